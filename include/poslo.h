@@ -1,0 +1,184 @@
+/*
+ * poslo.h - C ABI of the POSLO-F verifier library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library implements the verifier side of POSLO-F (Nouma and Yavuz,
+ * "Lightweight and High-Throughput Secure Logging for Internet of Things and
+ * Cold Cloud Continuum", arXiv 2506.08781): aggregate verification (AVer,
+ * paper section "Fine-grained public-key POSLO", which reuses steps 2-8 of
+ * POSLO-C.AVer), the GPU batch verifier of section "POSLO Parallel Batch
+ * Verification" (figure "Parallel POSLO signature verification algorithm"),
+ * and distillation / selective batch verification (Distill and SeBVer,
+ * section "POSLO-C Distillation and Selective Batch Verification", applied
+ * entry by entry as the POSLO-F text prescribes).  A host-side signer (Kg,
+ * Sig, Agg) produces test data.
+ *
+ * Conventions
+ *  - Every function returns 0 (POSLO_OK) or a negative POSLO_E_* code.
+ *  - A verification reject is NOT an error: it is status 0 with *accept = 0,
+ *    mirroring "return b = 0" in the paper.
+ *  - Pointers documented as "device" point to GPU memory (hipMalloc or a
+ *    torch CUDA tensor) on the context's device; "host" pointers point to
+ *    CPU memory.  All buffers are owned by the caller unless a *_free call
+ *    is named.
+ *  - Work is issued on the caller's stream (a hipStream_t passed as void*;
+ *    NULL means the default stream).  Calls that return a verdict
+ *    synchronize that stream before returning.
+ *  - A poslo_ctx is not thread-safe; use one per host thread.
+ *
+ * Byte formats (readings of the paper, which fixes no encodings)
+ *  - entry index t is 0-based; epoch i = t >> log2_n2, j = t & (n2 - 1).
+ *  - signature sigma_t: 80 bytes = LE32B(s_t) || enc(R_t) || x_t
+ *    (|sigma| = 2|q| + kappa, paper table "Private/public key and signature
+ *    sizes").
+ *  - aggregate tag: 64 bytes = LE32B(s) || enc(R).
+ *  - public key: 32 bytes = enc(Y).  enc() is the RFC 8032 point encoding
+ *    of edwards25519 (y little-endian, parity of x in bit 255).
+ *  - ds (disclosed seeds stack, section "POSLO Data Types and Seed
+ *    Management"): 1 count byte, then per node {u8 depth; u8 pad[3] = 0;
+ *    u32 LE index; u8 value[16]}, bottom of the stack first, at most 32
+ *    nodes.
+ */
+#ifndef POSLO_H
+#define POSLO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    POSLO_OK = 0,
+    POSLO_E_INVAL = -1,     /* bad argument, size or parameter */
+    POSLO_E_NOMEM = -2,     /* host or device allocation failed */
+    POSLO_E_DEVICE = -3,    /* a HIP call failed */
+    POSLO_E_SEED = -4,      /* SR returned bottom: ds does not cover an epoch */
+    POSLO_E_ENCODING = -5,  /* a public key or commitment is not a point */
+    POSLO_E_EXHAUSTED = -6, /* signer state reached t = n */
+    POSLO_E_BUSY = -7       /* resource temporarily unavailable */
+};
+
+enum {
+    POSLO_INST_SHA256 = 0, /* POSLO: PRF and H from SHA-256 */
+    POSLO_INST_AES = 1     /* POSLO+: PRF from MMO-AES-128, H = MDC-2-AES-128 */
+};
+
+/* Public parameters I (paper, POSLO-F.Kg): instantiation, n1 = 2^log2_n1
+ * epochs of n2 = 2^log2_n2 entries each, kappa = 128.  BPV parameters (v, k)
+ * are used by the signer only; v must be a power of two <= 65536. */
+typedef struct poslo_params {
+    uint32_t inst;
+    uint32_t log2_n1; /* 0..31 */
+    uint32_t log2_n2; /* 0..31; log2_n1 + log2_n2 <= 40 */
+    uint32_t bpv_v;   /* 1024 in the paper */
+    uint32_t bpv_k;   /* 16 in the paper */
+} poslo_params;
+
+/* A batch of consecutive log entries t0 .. t0+n-1 in device memory.
+ * Fixed length: offsets == NULL, entry p occupies data[p*msg_len ..
+ * (p+1)*msg_len).  Variable length: offsets (device, n+1 u64) gives entry p
+ * as data[offsets[p] .. offsets[p+1]), msg_len is ignored. */
+typedef struct poslo_msgs {
+    const uint8_t* data;     /* device */
+    const uint64_t* offsets; /* device or NULL */
+    uint64_t msg_len;
+    uint64_t n;
+    uint64_t t0;
+} poslo_msgs;
+
+/* Library version string. */
+const char* poslo_version(void);
+
+/* Human-readable text for a status code. */
+const char* poslo_strerror(int status);
+
+/* ---------------------------------------------------------------- signer */
+
+typedef struct poslo_signer poslo_signer;
+
+/* POSLO-F.Kg (paper, figure "Fine-grained public-key POSLO"): y, root seed
+ * x_D[0] and the BPV table derived deterministically from a 32-byte seed
+ * with the scheme's PRF_0.  pk: host, 32 bytes out.  *sk is freed with
+ * poslo_signer_free.  E_INVAL on bad params. */
+int poslo_kg(const poslo_params* params, const uint8_t seed[32], poslo_signer** sk, uint8_t pk[32]);
+
+void poslo_signer_free(poslo_signer* sk);
+
+/* POSLO-F.Sig of the next entry t = St.t: sigma_t = (s_t, R_t, x_t) with
+ * SSO at the first entry of each epoch and BPV.Online commitments.
+ * m: host, len bytes.  sig: host, 80 bytes out.  E_EXHAUSTED at t = n. */
+int poslo_sig(poslo_signer* sk, const uint8_t* m, size_t len, uint8_t sig[80]);
+
+/* Sign n consecutive entries (host buffers; offsets has n+1 entries, or is
+ * NULL for fixed msg_len) with up to nthreads host threads (0 = all cores).
+ * Produces the same bytes as n calls of poslo_sig. sigs: host, 80*n out. */
+int poslo_sig_batch(poslo_signer* sk, const uint8_t* msgs, const uint64_t* offsets, uint64_t msg_len,
+                    uint64_t n, uint8_t* sigs, int nthreads);
+
+/* Current state index t (number of entries signed). */
+uint64_t poslo_signer_count(const poslo_signer* sk);
+
+/* The signer's current disclosed-seed stack ds in the wire format above
+ * (buf: host, cap bytes; *len gets the size).  E_INVAL if cap is too small. */
+int poslo_ds_export(const poslo_signer* sk, uint8_t* buf, size_t cap, size_t* len);
+
+/* POSLO-C.Agg as used by POSLO-F (paper, figure "Digital signature
+ * algorithms"): s = sum s_t mod q, R = sum R_t.  sigs: host, count records
+ * of stride bytes (>= 80).  tag: host, 64 bytes out.  E_ENCODING if an R_t
+ * does not decode. */
+int poslo_agg(const uint8_t* sigs, size_t stride, uint64_t count, uint8_t tag[64]);
+
+/* Host reference of the instantiated functions, for tooling and tests:
+ * out16 = PRF_b(in) (b in {0,1}); out32 = H(in). */
+int poslo_prf_host(uint32_t inst, uint32_t b, const uint8_t* in, size_t len, uint8_t out16[16]);
+int poslo_hash_host(uint32_t inst, const uint8_t* in, size_t len, uint8_t out32[32]);
+
+/* ------------------------------------------------------------- verifier */
+
+typedef struct poslo_ctx poslo_ctx;
+
+/* A verifier context on one device: owns scratch buffers, cached key
+ * tables and result staging.  E_DEVICE if the device cannot be used. */
+int poslo_ctx_create(int device, poslo_ctx** ctx);
+void poslo_ctx_destroy(poslo_ctx* ctx);
+
+/* POSLO-F.AVer over a batch (the parallel verifier POSLO.PAVer: per entry
+ * x_t = PRF_0(SR(ds, i) || j) and e_t = H(m_t || x_t), e = sum e_t mod q,
+ * then the check R = e*Y + s*G).  pk, ds, tag: host.  *accept gets 1 or 0.
+ * If e_out is not NULL it receives e mod q (32 bytes LE, host).
+ * E_SEED if ds does not cover an epoch of the batch; E_ENCODING if pk is not
+ * a point encoding; a non-canonical tag gives *accept = 0. */
+int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
+               const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
+               uint8_t e_out[32]);
+
+/* Kernel timing (opt-in): while enabled, the context records HIP events on
+ * the launch stream around each kernel below and accumulates their elapsed
+ * time.  poslo_ctx_kernel_time returns the accumulated milliseconds and the
+ * number of timed launches of one kernel (and clears them if reset != 0). */
+enum {
+    POSLO_KT_SEED = 0,   /* per-epoch seed table (SR / SC, hoisted PRF state) */
+    POSLO_KT_AGG = 1,    /* fused PRF + digest + lazy aggregate (the hot loop) */
+    POSLO_KT_FINAL = 2,  /* fold of partial sums, mod q, aggregate check */
+    POSLO_KT_EKEYS = 3,  /* per-entry digests */
+    POSLO_KT_VERIFY = 4, /* per-entry individual verification (Distill) */
+    POSLO_KT_COMPACT = 5 /* invalid-index compaction and CCD aggregates */
+};
+int poslo_ctx_profile(poslo_ctx* ctx, int enable);
+int poslo_ctx_kernel_time(poslo_ctx* ctx, int kernel, int reset, double* total_ms, uint64_t* launches);
+
+/* Per-entry digests e_t mod q (32 bytes LE each) of a batch into e_dev
+ * (device, 32*n bytes) and the one-time seeds x_t (16 bytes each) into
+ * x_dev (device, 16*n bytes, may be NULL): the per-entry stage of AVer,
+ * exposed for distillation tooling and sampled checks.  Asynchronous on
+ * stream, except for the seed-coverage check. */
+int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* msgs, const uint8_t* ds,
+                size_t ds_len, uint8_t* e_dev, uint8_t* x_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POSLO_H */

@@ -1,0 +1,293 @@
+"""Python binding of libposlo, the POSLO-F verifier library for MI355X.
+
+Argument marshalling only: every step of signing and verification runs in
+the native library (HIP kernels on the GPU, C++ on the host).  Functions keep
+the C ABI's names (include/poslo.h).  Device buffers are torch CUDA tensors;
+streams are torch streams.  The library must be built (``_build.build()``);
+importing the functions without it raises, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libposlo.so")
+
+INST_SHA256 = 0
+INST_AES = 1
+
+POSLO_OK = 0
+POSLO_E_SEED = -4
+POSLO_E_ENCODING = -5
+
+
+class PosloError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_strerror(status)} ({status})")
+
+
+class poslo_params(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_uint32), ("log2_n1", ctypes.c_uint32), ("log2_n2", ctypes.c_uint32),
+                ("bpv_v", ctypes.c_uint32), ("bpv_k", ctypes.c_uint32)]
+
+
+class poslo_msgs(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("msg_len", ctypes.c_uint64),
+                ("n", ctypes.c_uint64), ("t0", ctypes.c_uint64)]
+
+
+def make_params(inst: int, log2_n1: int, log2_n2: int, bpv_v: int = 1024, bpv_k: int = 16) -> poslo_params:
+    return poslo_params(inst, log2_n1, log2_n2, bpv_v, bpv_k)
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_U8P = ctypes.c_char_p
+_SZ = ctypes.c_size_t
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_I = ctypes.c_int
+
+
+def lib():
+    """The loaded native library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libposlo.so is not built at {LIB_PATH}; run paper_2506_08781_amd._build.build()")
+        # torch ships its own HIP runtime and asks for it by an unversioned
+        # name; loading torch first lets this library bind to that same
+        # runtime (same soname) instead of bringing up a second one.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        sigs = {
+            "poslo_version": ([], ctypes.c_char_p),
+            "poslo_strerror": ([_I], ctypes.c_char_p),
+            "poslo_kg": ([P(poslo_params), _U8P, P(_VP), _VP], _I),
+            "poslo_signer_free": ([_VP], None),
+            "poslo_sig": ([_VP, _U8P, _SZ, _VP], _I),
+            "poslo_sig_batch": ([_VP, _VP, _VP, _U64, _U64, _VP, _I], _I),
+            "poslo_signer_count": ([_VP], _U64),
+            "poslo_ds_export": ([_VP, _VP, _SZ, P(_SZ)], _I),
+            "poslo_agg": ([_VP, _SZ, _U64, _VP], _I),
+            "poslo_prf_host": ([_U32, _U32, _U8P, _SZ, _VP], _I),
+            "poslo_hash_host": ([_U32, _U8P, _SZ, _VP], _I),
+            "poslo_ctx_create": ([_I, P(_VP)], _I),
+            "poslo_ctx_destroy": ([_VP], None),
+            "poslo_aver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _U8P, _SZ, _U8P, _VP, P(_I), _VP], _I),
+            "poslo_ekeys": ([_VP, P(poslo_params), P(poslo_msgs), _U8P, _SZ, _VP, _VP, _VP], _I),
+            "poslo_ctx_profile": ([_VP, _I], _I),
+            "poslo_ctx_kernel_time": ([_VP, _I, _I, P(ctypes.c_double), P(_U64)], _I),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    """Names of the C ABI functions declared in include/poslo.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "poslo.h")
+    with open(hdr) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(poslo_[a-z0-9_]+)\s*\(", text)))
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().poslo_strerror(status).decode()
+    except Exception:
+        return "error"
+
+
+def _check(status: int, where: str):
+    if status != POSLO_OK:
+        raise PosloError(status, where)
+
+
+def poslo_version() -> str:
+    return lib().poslo_version().decode()
+
+
+# ----------------------------------------------------------------- signer
+
+class Signer:
+    """Owns a poslo_signer*."""
+
+    def __init__(self, handle: int, params: poslo_params):
+        self.handle = ctypes.c_void_p(handle)
+        self.params = params
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and h.value and _lib is not None:
+            _lib.poslo_signer_free(h)
+            self.handle = None
+
+
+def poslo_kg(params: poslo_params, seed: bytes):
+    if len(seed) != 32:
+        raise ValueError("seed must be 32 bytes")
+    h = ctypes.c_void_p()
+    pk = ctypes.create_string_buffer(32)
+    _check(lib().poslo_kg(ctypes.byref(params), seed, ctypes.byref(h), pk), "poslo_kg")
+    return Signer(h.value, params), pk.raw
+
+
+def poslo_sig(sk: Signer, m: bytes) -> bytes:
+    out = ctypes.create_string_buffer(80)
+    _check(lib().poslo_sig(sk.handle, bytes(m), len(m), out), "poslo_sig")
+    return out.raw
+
+
+def poslo_sig_batch(sk: Signer, msgs: np.ndarray, offsets: np.ndarray | None = None, nthreads: int = 0) -> np.ndarray:
+    """Sign consecutive entries.  msgs: uint8 (n, L) array, or a flat uint8
+    array with offsets (n+1 uint64).  Returns a uint8 (n, 80) array."""
+    if offsets is None:
+        msgs = np.ascontiguousarray(msgs, dtype=np.uint8)
+        n, L = msgs.shape
+        off_ptr = None
+    else:
+        msgs = np.ascontiguousarray(msgs, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n, L = offsets.size - 1, 0
+        off_ptr = offsets.ctypes.data
+    sigs = np.empty((n, 80), dtype=np.uint8)
+    _check(lib().poslo_sig_batch(sk.handle, msgs.ctypes.data if msgs.size else None, off_ptr, L, n,
+                                 sigs.ctypes.data if n else None, nthreads), "poslo_sig_batch")
+    return sigs
+
+
+def poslo_signer_count(sk: Signer) -> int:
+    return lib().poslo_signer_count(sk.handle)
+
+
+def poslo_ds_export(sk: Signer) -> bytes:
+    buf = ctypes.create_string_buffer(1 + 24 * 32)
+    ln = ctypes.c_size_t()
+    _check(lib().poslo_ds_export(sk.handle, buf, len(buf), ctypes.byref(ln)), "poslo_ds_export")
+    return buf.raw[:ln.value]
+
+
+def poslo_agg(sigs) -> bytes:
+    arr = np.ascontiguousarray(np.frombuffer(bytes(sigs), dtype=np.uint8) if isinstance(sigs, (bytes, bytearray))
+                               else sigs, dtype=np.uint8).reshape(-1, 80)
+    tag = ctypes.create_string_buffer(64)
+    _check(lib().poslo_agg(arr.ctypes.data if arr.size else None, 80, arr.shape[0], tag), "poslo_agg")
+    return tag.raw
+
+
+def poslo_prf_host(inst: int, b: int, data: bytes) -> bytes:
+    out = ctypes.create_string_buffer(16)
+    _check(lib().poslo_prf_host(inst, b, bytes(data), len(data), out), "poslo_prf_host")
+    return out.raw
+
+
+def poslo_hash_host(inst: int, data: bytes) -> bytes:
+    out = ctypes.create_string_buffer(32)
+    _check(lib().poslo_hash_host(inst, bytes(data), len(data), out), "poslo_hash_host")
+    return out.raw
+
+
+# --------------------------------------------------------------- verifier
+
+class Ctx:
+    """Owns a poslo_ctx* on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().poslo_ctx_create(device, ctypes.byref(h)), "poslo_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle and self.handle.value:
+            lib().poslo_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def poslo_ctx_create(device: int = 0) -> Ctx:
+    return Ctx(device)
+
+
+POSLO_KT_SEED, POSLO_KT_AGG, POSLO_KT_FINAL, POSLO_KT_EKEYS, POSLO_KT_VERIFY, POSLO_KT_COMPACT = range(6)
+
+
+def poslo_ctx_profile(ctx: Ctx, enable: bool) -> None:
+    _check(lib().poslo_ctx_profile(ctx.handle, 1 if enable else 0), "poslo_ctx_profile")
+
+
+def poslo_ctx_kernel_time(ctx: Ctx, kernel: int, reset: bool = False) -> tuple[float, int]:
+    """(accumulated milliseconds, timed launches) of one kernel."""
+    ms = ctypes.c_double()
+    n = ctypes.c_uint64()
+    _check(lib().poslo_ctx_kernel_time(ctx.handle, kernel, 1 if reset else 0, ctypes.byref(ms), ctypes.byref(n)),
+           "poslo_ctx_kernel_time")
+    return ms.value, n.value
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_msgs(data, offsets=None, msg_len: int = 0, n: int | None = None, t0: int = 0) -> poslo_msgs:
+    """Batch descriptor over torch CUDA tensors: data uint8 (n, L) or flat,
+    offsets uint64 (int64) (n+1) or None."""
+    if offsets is None:
+        if data.dim() == 2:
+            n_, L = data.shape
+        else:
+            if n is None:
+                raise ValueError("n is required for a flat fixed-length buffer")
+            n_, L = n, msg_len
+        return poslo_msgs(data.data_ptr() if data.numel() else None, None, L, n_, t0)
+    n_ = offsets.numel() - 1
+    return poslo_msgs(data.data_ptr() if data.numel() else None, offsets.data_ptr(), 0, n_, t0)
+
+
+def poslo_aver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ds: bytes, tag: bytes,
+               stream=None) -> tuple[bool, bytes]:
+    """Aggregate verification of a device-resident batch.
+    Returns (accept, e mod q as 32 LE bytes)."""
+    acc = ctypes.c_int()
+    e = ctypes.create_string_buffer(32)
+    st = lib().poslo_aver(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs), bytes(ds), len(ds),
+                          bytes(tag), _stream_ptr(stream), ctypes.byref(acc), e)
+    _check(st, "poslo_aver")
+    return bool(acc.value), e.raw
+
+
+def poslo_ekeys(ctx: Ctx, params: poslo_params, msgs: poslo_msgs, ds: bytes, stream=None):
+    """Per-entry e_t mod q (uint8 (n, 32)) and x_t (uint8 (n, 16)) as CUDA tensors."""
+    import torch
+    n = msgs.n
+    dev = torch.device("cuda", ctx.device)
+    e = torch.empty((max(n, 1), 32), dtype=torch.uint8, device=dev)
+    x = torch.empty((max(n, 1), 16), dtype=torch.uint8, device=dev)
+    st = lib().poslo_ekeys(ctx.handle, ctypes.byref(params), ctypes.byref(msgs), bytes(ds), len(ds),
+                           e.data_ptr(), x.data_ptr(), _stream_ptr(stream))
+    _check(st, "poslo_ekeys")
+    return e[:n], x[:n]

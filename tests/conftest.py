@@ -28,3 +28,14 @@ def O():
     from oracle import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def P():
+    """The native library binding; builds it only if nothing is built."""
+    import paper_2506_08781_amd as lib
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2506_08781_amd import _build
+        _build.build()
+    lib.lib()
+    return lib

@@ -1,0 +1,182 @@
+"""GPU parity of aggregate verification (AVer) and per-entry digests against
+the oracle, through the C ABI.
+
+Inputs are seeded synthetic messages; keys, signatures, ds and tags for the
+small cases come from the oracle's own signer.  At the full 2^20 x 256-byte
+size the oracle checks sampled entries one by one, and the accept bit is
+checked on an honest batch (signed by the library's host signer, whose
+output equals the oracle's byte for byte in the CPU tests) and on a batch
+with one flipped message bit."""
+
+import functools
+import random
+
+import numpy as np
+import pytest
+
+import synthlog
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu(P):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    ctx = P.poslo_ctx_create(0)
+    yield torch, ctx
+    ctx.close()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(inst, n, lens, log2_n1, log2_n2, key_first, msg_seed):
+    """Oracle-signed batch.  lens: an int (fixed) or a tuple (variable)."""
+    from oracle import oracle as O
+    prm = O.Params(inst, log2_n1, log2_n2)
+    if isinstance(lens, int):
+        arr = synthlog.messages_fixed(msg_seed, n, lens)
+        msgs = [bytes(r) for r in arr]
+    else:
+        data, off = synthlog.messages_var(msg_seed, np.array(lens))
+        msgs = [bytes(data[off[k]:off[k + 1]]) for k in range(n)]
+    pk, sigs, ds, tag, _ = O.sign_batch(prm, synthlog.key_seed_bytes(key_first), msgs)
+    return prm, msgs, pk, sigs, ds, tag
+
+
+def upload(torch, msgs, fixed):
+    if fixed:
+        L = len(msgs[0]) if msgs else 0
+        arr = np.frombuffer(b"".join(msgs), dtype=np.uint8).reshape(len(msgs), L)
+        return torch.from_numpy(arr.copy()).cuda(), None
+    flat = np.frombuffer(b"".join(msgs), dtype=np.uint8) if msgs else np.zeros(0, np.uint8)
+    off = np.zeros(len(msgs) + 1, dtype=np.int64)
+    np.cumsum([len(m) for m in msgs], out=off[1:])
+    return torch.from_numpy(flat.copy()).cuda(), torch.from_numpy(off).cuda()
+
+
+CASES = [
+    # inst, n, lens, log2_n1, log2_n2 : the first two are the 1,024 x 32-byte
+    # configuration at n2 = 256 (both instantiations)
+    (1, 1024, 32, 2, 8),
+    (0, 1024, 32, 2, 8),
+    (1, 777, 48, 4, 6),    # ragged tail, multi-node ds, fast AES path
+    (1, 300, 37, 4, 5),    # length not a multiple of 16: generic path
+    (0, 300, 37, 4, 5),    # length not a multiple of 4: generic SHA path
+    (0, 519, 64, 6, 4),    # SHA fast path, several SHA blocks
+    (1, 1, 256, 1, 0),     # single entry, n2 = 1
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"inst{c[0]}-n{c[1]}-L{c[2]}-n1_{c[3]}-n2_{c[4]}")
+def test_aver_and_ekeys_parity(P, gpu, case):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    inst, n, L, l1, l2 = case
+    prm, msgs, pk, sigs, ds, tag = oracle_case(inst, n, L, l1, l2, 0, 1)
+    params = P.make_params(inst, l1, l2)
+    d, off = upload(torch, msgs, True)
+    m = P.make_msgs(d)
+    print(f"case {case}: aver", flush=True)
+    acc, e = P.poslo_aver(ctx, params, pk, m, ds, tag)
+    assert acc
+    assert int.from_bytes(e, "little") == O.ekeys_sum(prm, msgs, 0, ds)
+    # per-entry digests and one-time seeds
+    eg, xg = P.poslo_ekeys(ctx, params, m, ds)
+    eg, xg = eg.cpu().numpy(), xg.cpu().numpy()
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), 0, n)
+    for t in range(n):
+        x = O.one_time_seed(inst, seeds[t >> l2], t & ((1 << l2) - 1))
+        assert bytes(xg[t]) == x == sigs[t][64:80], t
+        assert int.from_bytes(bytes(eg[t]), "little") == O.digest_int(inst, msgs[t], x) % O.Q, t
+    # a flipped tag bit and a flipped message bit are rejected
+    bad = bytearray(tag)
+    bad[40] ^= 0x10
+    assert not P.poslo_aver(ctx, params, pk, m, ds, bytes(bad))[0]
+    mm = list(msgs)
+    k = n // 2
+    mm[k] = bytes([mm[k][0] ^ 1]) + mm[k][1:]
+    d2, _ = upload(torch, mm, True)
+    assert not P.poslo_aver(ctx, params, pk, P.make_msgs(d2), ds, tag)[0]
+
+
+@pytest.mark.parametrize("inst", [0, 1])
+def test_variable_length_and_slices(P, gpu, inst):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    lens = tuple(synthlog.uniform_ints(31, 0, 203, 0, 90))
+    prm, msgs, pk, sigs, ds, tag = oracle_case(inst, 203, lens, 4, 4, 3, 5)
+    params = P.make_params(inst, 4, 4)
+    d, off = upload(torch, msgs, False)
+    acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(d, off), ds, tag)
+    assert acc and int.from_bytes(e, "little") == O.ekeys_sum(prm, msgs, 0, ds)
+    # a slice starting mid-epoch verifies against its own aggregate
+    a, b = 37, 160
+    sub = msgs[a:b]
+    d3, off3 = upload(torch, sub, False)
+    acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(d3, off3, t0=a), ds, O.agg(sigs[a:b]))
+    assert acc and int.from_bytes(e, "little") == O.ekeys_sum(prm, sub, a, ds)
+
+
+def test_empty_batch_and_errors(P, gpu):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = oracle_case(1, 777, 48, 4, 6, 0, 1)
+    params = P.make_params(1, 4, 6)
+    empty = torch.zeros((0, 48), dtype=torch.uint8, device="cuda")
+    acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(empty), ds, O.agg([]))
+    assert acc and e == bytes(32)
+    # ds after entry 776 covers epochs 0..12; entries of epoch 13 are not covered
+    d, _ = upload(torch, msgs[:64], True)
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_aver(ctx, params, pk, P.make_msgs(d, t0=13 * 64), ds, tag)
+    assert ei.value.status == P.POSLO_E_SEED
+    # a public key that is not a point encoding is an error, not a reject
+    badpk = (2 ** 255 - 19 + 3).to_bytes(32, "little")
+    d, _ = upload(torch, msgs, True)
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_aver(ctx, params, badpk, P.make_msgs(d), ds, tag)
+    assert ei.value.status == P.POSLO_E_ENCODING
+    # a malformed ds is an invalid argument
+    with pytest.raises(P.PosloError):
+        P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds + b"\0", tag)
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_full_size_2p20_x_256(P, gpu, inst):
+    """2^20 entries of 256-byte messages, n2 = 256, n1 = 4096: the large
+    plain configuration, in the launch configuration the benchmark times."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    n, L, l1, l2 = 1 << 20, 256, 12, 8
+    print(f"full size inst {inst}: generate", flush=True)
+    arr = synthlog.messages_fixed(2, n, L)
+    params = P.make_params(inst, l1, l2)
+    sk, pk = P.poslo_kg(params, synthlog.key_seed_bytes(0x20))
+    sigs = P.poslo_sig_batch(sk, arr)
+    ds = P.poslo_ds_export(sk)
+    tag = P.poslo_agg(sigs)
+    d = torch.from_numpy(arr).cuda()
+    print("full size: aver", flush=True)
+    acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)
+    assert acc
+    eg, xg = P.poslo_ekeys(ctx, params, P.make_msgs(d), ds)
+    # property: the lazy aggregate equals the sum of per-entry residues
+    ev = eg.cpu().numpy()
+    total = 0
+    for w in range(4):
+        limb = ev[:, 8 * w:8 * w + 8].copy().view("<u8")[:, 0]
+        total += int(limb.astype(object).sum()) << (64 * w)
+    assert total % O.Q == int.from_bytes(e, "little")
+    # sampled entries against the oracle, one by one
+    prm = O.Params(inst, l1, l2)
+    rng = random.Random(99)
+    sample = sorted({0, 255, 256, n - 1} | {rng.randrange(n) for _ in range(252)})
+    xv = xg.cpu().numpy()
+    dsn = O.ds_decode(ds)
+    for t in sample:
+        x = O.one_time_seed(inst, O.SR(inst, dsn, t >> l2), t & 255)
+        assert bytes(xv[t]) == x == bytes(sigs[t][64:80])
+        assert int.from_bytes(bytes(ev[t]), "little") == O.digest_int(inst, bytes(arr[t]), x) % O.Q
+    # one flipped message bit makes the aggregate reject
+    d[n // 3, 17] ^= 4
+    assert not P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)[0]

@@ -1,0 +1,79 @@
+"""The native library without a GPU: it loads, exports every symbol its
+header declares, and its host-side signer and hash functions produce the
+oracle's bytes."""
+
+import ctypes
+import os
+import random
+
+import numpy as np
+import pytest
+
+import synthlog
+
+
+def test_exports_every_declared_symbol(P):
+    names = P.exported_symbols()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_errors_and_version(P):
+    assert P.poslo_version().startswith("poslo")
+    assert "seed" in P._strerror(P.POSLO_E_SEED)
+
+
+@pytest.mark.parametrize("inst", [0, 1])
+def test_host_prf_and_hash_match_oracle(P, O, inst):
+    rng = random.Random(inst)
+    for n in list(range(0, 70)) + [100, 255, 256, 257, 300, 528]:
+        d = bytes(rng.randrange(256) for _ in range(n))
+        assert P.poslo_hash_host(inst, d) == O.H(inst, d), n
+        for b in (0, 1):
+            assert P.poslo_prf_host(inst, b, d) == O.prf(inst, b, d), (n, b)
+
+
+@pytest.mark.parametrize("inst", [0, 1])
+def test_host_signer_matches_oracle(P, O, inst):
+    seed = synthlog.key_seed_bytes(0x40)
+    prm = P.make_params(inst, 3, 2)
+    sk, pk = P.poslo_kg(prm, seed)
+    osk, opk = O.kg(O.Params(inst, 3, 2), seed)
+    assert pk == opk
+    lens = [0, 5, 16, 17, 31, 32, 48, 64, 3, 100, 7, 12, 9]
+    data, off = synthlog.messages_var(9, np.array(lens))
+    msgs = [bytes(data[off[k]:off[k + 1]]) for k in range(len(lens))]
+    sigs = [P.poslo_sig(sk, m) for m in msgs]
+    for k, m in enumerate(msgs):
+        assert sigs[k] == O.sig(osk, m), k
+    assert P.poslo_ds_export(sk) == O.ds_encode(osk.ds)
+    assert P.poslo_agg(b"".join(sigs)) == O.agg(sigs)
+    # the threaded batch signer gives the same bytes, variable or fixed length
+    sk2, _ = P.poslo_kg(prm, seed)
+    batch = P.poslo_sig_batch(sk2, data, offsets=off, nthreads=4)
+    assert batch.tobytes() == b"".join(sigs)
+    assert P.poslo_signer_count(sk2) == len(lens)
+
+
+def test_signer_exhaustion_and_bad_params(P):
+    prm = P.make_params(1, 1, 1)
+    sk, pk = P.poslo_kg(prm, bytes(32))
+    for _ in range(4):
+        P.poslo_sig(sk, b"m")
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_sig(sk, b"m")
+    assert ei.value.status == -6
+    with pytest.raises(P.PosloError):
+        P.poslo_kg(P.make_params(7, 1, 1), bytes(32))
+    with pytest.raises(P.PosloError):
+        P.poslo_kg(P.make_params(1, 1, 1, bpv_v=1000), bytes(32))
+
+
+def test_agg_rejects_undecodable_commitment(P):
+    bad = bytearray(80)
+    bad[32:64] = (2 ** 255 - 19 + 1).to_bytes(32, "little")  # y >= p
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_agg(bytes(bad))
+    assert ei.value.status == -5

@@ -41,24 +41,34 @@ CONFIGS = {
 
 
 # ---------------------------------------------------------------------------
-# algorithmic work model (32-bit integer operations of the FIPS formulations)
+# algorithmic work model: 32-bit integer VALU operations of the formulation
+# the kernels implement on gfx950 (loads, loop control and address
+# arithmetic for message pointers are not counted, so this is a lower bound
+# of the executed instruction count; rocprof's SQ_INSTS_VALU cross-checks it)
 # ---------------------------------------------------------------------------
-# AES-128, T-table form: a full round is 16 byte extractions, 16 lookups and
-# 16 xors (48); the final round adds 16 byte masks and 12 ors (64); the
-# initial key addition is 4.  A key-schedule round is 4 extractions, 4
-# lookups, 4 masks, 3 ors, 1 Rcon xor and 4 chained xors (20).
-AES_RK = 4 + 9 * 48 + 64          # encryption under a precomputed schedule
-AES_OTF = AES_RK + 10 * 20        # with the schedule expanded on the fly
-# SHA-256 compression: 64 rounds of 24 ops, 48 schedule words of 13, 8 adds
-SHA_COMP = 64 * 24 + 48 * 13 + 8
+# AES-128 over byte-addressed T-tables: a full round is 16 table-address
+# v_perm, 8 rotations of the odd tables and 8 three-input xors (32); the
+# final round is 16 address v_perm, 8 byte-merge v_perm, 4 ors, 4 xors (32);
+# a key-schedule round is 4 address v_perm, 2 merge v_perm, 1 or, 1 xor3 and
+# 3 xors (11); the initial key addition is 4.
+AES_RK = 4 + 9 * 32 + 32          # encryption under a precomputed schedule
+AES_OTF = AES_RK + 10 * 11        # with the schedule expanded on the fly
+# SHA-256 compression: a round is 3+1 for each Sigma (rotations, xor3), 1 Ch,
+# 1 Maj, 2 three-input adds for T1, 1 for a, 1 for e (14); a schedule word is
+# 4 for each sigma and 2 adds (10); the feed-forward is 8 adds.
+SHA_COMP = 64 * 14 + 48 * 10 + 8
 
 
 def ops_per_entry(inst: int, L: int) -> int:
     if inst == 1:
         B = (L + 16 + 15) // 16
+        # PRF (one AES + 1 xor), MDC-2 block 0 under the constant IV schedules,
+        # blocks 1.. with two on-the-fly schedules, 8 xors per block, 9-limb sum
         return (AES_RK + 1) + (2 * AES_RK + 8) + (B - 1) * (2 * AES_OTF + 8) + 9
     nb = (L + 16 + 9 + 63) // 64
-    return (1 + nb) * SHA_COMP + 17
+    # PRF compression + message compressions, byte swaps of the message words
+    # and of the digest, 9-limb sum
+    return (1 + nb) * SHA_COMP + (L + 3) // 4 + 8 + 9
 
 
 def hash_calls_per_entry(inst: int, L: int) -> int:
@@ -110,6 +120,9 @@ def main():
     ap.add_argument("--inst", default="aes", choices=["aes", "sha"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy the message buffer once (a plain copy of known size "
+                         "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -149,6 +162,9 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     P.poslo_ctx_profile(ctx, False)
+    if args.calib_copy:
+        d.clone()
+        torch.cuda.synchronize()
     kt = {name: P.poslo_ctx_kernel_time(ctx, k) for name, k in
           (("seed", P.POSLO_KT_SEED), ("agg", P.POSLO_KT_AGG), ("final", P.POSLO_KT_FINAL))}
 

@@ -169,6 +169,16 @@ enum {
 int poslo_ctx_profile(poslo_ctx* ctx, int enable);
 int poslo_ctx_kernel_time(poslo_ctx* ctx, int kernel, int reset, double* total_ms, uint64_t* launches);
 
+/* Kernel tuning.  The POSLO+ hot kernel exists in several variants (number
+ * of rotated T-tables held in LDS, bank-replicated copies of each, threads
+ * per workgroup); poslo_agg_variant_name(v) describes variant v.
+ * poslo_ctx_set_tuning selects a variant (-1: library default) and the
+ * number of resident workgroups per compute unit (0: derived from the
+ * variant's LDS footprint).  Results do not depend on the tuning. */
+int poslo_agg_variant_count(void);
+const char* poslo_agg_variant_name(int v);
+int poslo_ctx_set_tuning(poslo_ctx* ctx, int agg_variant, int wg_per_cu);
+
 /* Per-entry digests e_t mod q (32 bytes LE each) of a batch into e_dev
  * (device, 32*n bytes) and the one-time seeds x_t (16 bytes each) into
  * x_dev (device, 16*n bytes, may be NULL): the per-entry stage of AVer,
@@ -176,6 +186,45 @@ int poslo_ctx_kernel_time(poslo_ctx* ctx, int kernel, int reset, double* total_m
  * stream, except for the seed-coverage check. */
 int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* msgs, const uint8_t* ds,
                 size_t ds_len, uint8_t* e_dev, uint8_t* x_dev, void* stream);
+
+/* ------------------------------------------------- distill and sebver */
+
+/* Cold cryptographic data (paper, system model and section "POSLO-C
+ * Distillation and Selective Batch Verification"): the valid aggregate
+ * CCD^v, umbrella aggregates CCD^u over spans of U = ceil(n / n_umbrella)
+ * entries, the invalid entries CCD^i with their signatures, and ds. */
+typedef struct poslo_ccd poslo_ccd;
+
+/* POSLO-F Distill over a batch: every entry is verified individually (x_t
+ * equals PRF_0(x_0[i] || j), s_t < q, enc(e_t*Y + s_t*G) equals the R_t
+ * bytes); valid entries are aggregated into CCD^v and their umbrella,
+ * invalid ones are listed (sorted) with their signatures.  sigs: device,
+ * 80*n bytes, 4-byte aligned, entry p at 80*p.  n_umbrella >= 1.  *out is
+ * freed with poslo_ccd_free.  Errors as poslo_aver. */
+int poslo_distill(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
+                  const uint8_t* sigs, const uint8_t* ds, size_t ds_len, uint32_t n_umbrella, void* stream,
+                  poslo_ccd** out);
+
+/* CCD accessors (host memory owned by the CCD; valid until poslo_ccd_free). */
+int poslo_ccd_invalid(const poslo_ccd* ccd, const uint64_t** idx, uint64_t* n);
+int poslo_ccd_invalid_sig(const poslo_ccd* ccd, uint64_t k, uint8_t sig[80]);
+int poslo_ccd_valid_tag(const poslo_ccd* ccd, uint8_t tag[64]);
+/* umbrella tags (64 bytes each, in order) into tags (cap bytes, may be NULL
+ * to query *n_umb and *span) */
+int poslo_ccd_umbrellas(const poslo_ccd* ccd, uint8_t* tags, size_t cap, uint64_t* n_umb, uint64_t* span);
+/* byte serialization for cold storage: *len gets the size; E_INVAL when cap
+ * is too small or the input is malformed */
+int poslo_ccd_export(const poslo_ccd* ccd, uint8_t* buf, size_t cap, size_t* len);
+int poslo_ccd_import(const uint8_t* buf, size_t len, poslo_ccd** out);
+void poslo_ccd_free(poslo_ccd* ccd);
+
+/* SeBVer over distilled data (the same batch: msgs t0 and n must match the
+ * CCD).  mode 'V': one bit, AVer of all entries not in CCD^i against CCD^v.
+ * 'U': one bit per umbrella, AVer of its range minus CCD^i against its tag.
+ * 'I': one bit per CCD^i entry, its individual verification (1 = valid).
+ * bits: host, cap bytes; *n_bits gets the count. */
+int poslo_sebver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
+                 const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,19 @@ def lib():
             "poslo_ekeys": ([_VP, P(poslo_params), P(poslo_msgs), _U8P, _SZ, _VP, _VP, _VP], _I),
             "poslo_ctx_profile": ([_VP, _I], _I),
             "poslo_ctx_kernel_time": ([_VP, _I, _I, P(ctypes.c_double), P(_U64)], _I),
+            "poslo_agg_variant_count": ([], _I),
+            "poslo_agg_variant_name": ([_I], ctypes.c_char_p),
+            "poslo_ctx_set_tuning": ([_VP, _I, _I], _I),
+            "poslo_distill": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _VP, _U8P, _SZ, _U32, _VP, P(_VP)], _I),
+            "poslo_ccd_invalid": ([_VP, P(P(_U64)), P(_U64)], _I),
+            "poslo_ccd_invalid_sig": ([_VP, _U64, _VP], _I),
+            "poslo_ccd_valid_tag": ([_VP, _VP], _I),
+            "poslo_ccd_umbrellas": ([_VP, _VP, _SZ, P(_U64), P(_U64)], _I),
+            "poslo_ccd_export": ([_VP, _VP, _SZ, P(_SZ)], _I),
+            "poslo_ccd_import": ([_U8P, _SZ, P(_VP)], _I),
+            "poslo_ccd_free": ([_VP], None),
+            "poslo_sebver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _VP, ctypes.c_char, _VP, _SZ, P(_SZ),
+                              _VP], _I),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(L, name)
@@ -231,6 +244,21 @@ def poslo_ctx_create(device: int = 0) -> Ctx:
 POSLO_KT_SEED, POSLO_KT_AGG, POSLO_KT_FINAL, POSLO_KT_EKEYS, POSLO_KT_VERIFY, POSLO_KT_COMPACT = range(6)
 
 
+def poslo_agg_variant_count() -> int:
+    return lib().poslo_agg_variant_count()
+
+
+def poslo_agg_variant_name(v: int) -> str:
+    r = lib().poslo_agg_variant_name(v)
+    if r is None:
+        raise IndexError(v)
+    return r.decode()
+
+
+def poslo_ctx_set_tuning(ctx: Ctx, agg_variant: int = -1, wg_per_cu: int = 0) -> None:
+    _check(lib().poslo_ctx_set_tuning(ctx.handle, agg_variant, wg_per_cu), "poslo_ctx_set_tuning")
+
+
 def poslo_ctx_profile(ctx: Ctx, enable: bool) -> None:
     _check(lib().poslo_ctx_profile(ctx.handle, 1 if enable else 0), "poslo_ctx_profile")
 
@@ -291,3 +319,79 @@ def poslo_ekeys(ctx: Ctx, params: poslo_params, msgs: poslo_msgs, ds: bytes, str
                            e.data_ptr(), x.data_ptr(), _stream_ptr(stream))
     _check(st, "poslo_ekeys")
     return e[:n], x[:n]
+
+
+# ------------------------------------------------------ distill / sebver
+
+class CCD:
+    """Owns a poslo_ccd* (cold cryptographic data of a distilled batch)."""
+
+    def __init__(self, handle):
+        self.handle = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and h.value and _lib is not None:
+            _lib.poslo_ccd_free(h)
+            self.handle = None
+
+    def invalid(self) -> list[int]:
+        p = ctypes.POINTER(ctypes.c_uint64)()
+        n = ctypes.c_uint64()
+        _check(lib().poslo_ccd_invalid(self.handle, ctypes.byref(p), ctypes.byref(n)), "poslo_ccd_invalid")
+        return [p[k] for k in range(n.value)]
+
+    def invalid_sig(self, k: int) -> bytes:
+        out = ctypes.create_string_buffer(80)
+        _check(lib().poslo_ccd_invalid_sig(self.handle, k, out), "poslo_ccd_invalid_sig")
+        return out.raw
+
+    def valid_tag(self) -> bytes:
+        out = ctypes.create_string_buffer(64)
+        _check(lib().poslo_ccd_valid_tag(self.handle, out), "poslo_ccd_valid_tag")
+        return out.raw
+
+    def umbrellas(self) -> tuple[list[bytes], int]:
+        n = ctypes.c_uint64()
+        span = ctypes.c_uint64()
+        _check(lib().poslo_ccd_umbrellas(self.handle, None, 0, ctypes.byref(n), ctypes.byref(span)),
+               "poslo_ccd_umbrellas")
+        buf = ctypes.create_string_buffer(max(1, 64 * n.value))
+        _check(lib().poslo_ccd_umbrellas(self.handle, buf, len(buf), ctypes.byref(n), ctypes.byref(span)),
+               "poslo_ccd_umbrellas")
+        return [buf.raw[64 * k:64 * k + 64] for k in range(n.value)], span.value
+
+    def export(self) -> bytes:
+        ln = ctypes.c_size_t()
+        lib().poslo_ccd_export(self.handle, None, 0, ctypes.byref(ln))
+        buf = ctypes.create_string_buffer(ln.value)
+        _check(lib().poslo_ccd_export(self.handle, buf, len(buf), ctypes.byref(ln)), "poslo_ccd_export")
+        return buf.raw[:ln.value]
+
+
+def poslo_ccd_import(data: bytes) -> CCD:
+    h = ctypes.c_void_p()
+    _check(lib().poslo_ccd_import(bytes(data), len(data), ctypes.byref(h)), "poslo_ccd_import")
+    return CCD(h.value)
+
+
+def poslo_distill(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, sigs, ds: bytes,
+                  n_umbrella: int, stream=None) -> CCD:
+    """Distill a device-resident batch; sigs is a CUDA uint8 tensor of 80*n bytes."""
+    h = ctypes.c_void_p()
+    st = lib().poslo_distill(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs),
+                             sigs.data_ptr() if sigs.numel() else None, bytes(ds), len(ds), n_umbrella,
+                             _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "poslo_distill")
+    return CCD(h.value)
+
+
+def poslo_sebver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ccd: CCD, mode: str,
+                 stream=None) -> list[bool]:
+    cap = max(1, len(ccd.invalid()), len(ccd.umbrellas()[0]))
+    bits = ctypes.create_string_buffer(cap)
+    nb = ctypes.c_size_t()
+    st = lib().poslo_sebver(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs), ccd.handle,
+                            mode.encode(), bits, cap, ctypes.byref(nb), _stream_ptr(stream))
+    _check(st, "poslo_sebver")
+    return [bool(b) for b in bits.raw[:nb.value]]

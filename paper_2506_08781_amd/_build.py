@@ -1,16 +1,20 @@
-"""Build the HIP library libposlo.so in-tree for gfx950 with hipcc."""
+"""Build the HIP library libposlo.so in-tree for gfx950 with hipcc.
+
+Each translation unit is compiled to an object in parallel, then linked."""
 
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposlo.so")
 
-SOURCES = ["verifier.hip", "distill.hip", "batched.hip", "server.hip", "signer.hip"]
+SOURCES = ["verifier.hip", "agg_aes.hip", "distill.hip", "batched.hip", "server.hip", "signer.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POSLO_OFFLOAD_ARCH", "gfx950")
@@ -22,7 +26,6 @@ def flags() -> list[str]:
         "-O3",
         "-std=c++17",
         "-fPIC",
-        "-shared",
         # packed fp32 instructions stay off for every HIP translation unit
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wno-unused-command-line-argument",
@@ -35,16 +38,32 @@ def sources() -> list[str]:
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libposlo.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *flags(), "-o", tmp, *sources(), "-lpthread"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _compile(src: str, obj: str, extra: list[str]) -> None:
+    cmd = [HIPCC, *flags(), *extra, "-c", "-o", obj, src]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n" + res.stdout + res.stderr)
+
+
+def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None) -> str:
+    """Compile every HIP source and link libposlo.so (always recompiles)."""
+    extra = list(extra or [])
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="poslo_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in srcs]
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            futs = [ex.submit(_compile, s, o, extra) for s, o in zip(srcs, objs)]
+            for f in futs:
+                f.result()
+        out = LIB + ".tmp"
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out, *objs, "-lpthread"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
+        os.replace(out, LIB)
     return LIB
 
 

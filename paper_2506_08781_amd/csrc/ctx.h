@@ -1,0 +1,101 @@
+// The verifier context shared by the library's translation units: device
+// scratch buffers, cached per-key tables, tuning state and kernel timing.
+#pragma once
+
+#include <stdint.h>
+#include <string.h>
+
+#include <list>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/poslo.h"
+#include "common.h"
+#include "ge25519.h"
+
+namespace poslo {
+
+constexpr int kKtCount = 8;
+constexpr int kCombWindows = 64;              // 4-bit windows of a 256-bit scalar
+constexpr int kCombWords = kCombWindows * 16 * 32;  // 16 points per window, 32 words each
+
+// AES hot-kernel variants (T-table layout x LDS replication x block size)
+struct AggVariant {
+    const char* name;
+    int nt;      // distinct rotated tables held in LDS
+    int copies;  // bank-replicated copies of each table
+    int block;   // threads per workgroup
+    int perm;    // byte-addressed layout (64 copies, v_perm_b32 addressing)
+};
+int agg_aes_variant_count();
+const AggVariant& agg_aes_variant(int v);
+int agg_aes_default_variant();
+// launch variant v (fast layout) or the generic-layout kernel
+int launch_agg_aes(int v, bool fast, uint32_t grid, const void* batch_args, uint32_t* partials, hipStream_t s);
+size_t agg_aes_lds_bytes(int v);
+
+struct KeyEntry {
+    std::string pk;
+    uint32_t* d_table = nullptr;  // comb table of Y on the device
+    ge Y;
+};
+
+}  // namespace poslo
+
+struct poslo_ctx {
+    int device = 0;
+    int num_cu = 256;
+    // tuning: AES kernel variant and workgroups per CU (0 = derived)
+    int agg_variant = -1;
+    int wg_per_cu = 0;
+    // per-kernel timing with HIP events on the launch stream (opt-in)
+    bool profile = false;
+    hipEvent_t ev[poslo::kKtCount][2] = {};
+    bool ev_pending[poslo::kKtCount] = {};
+    double kt_ms[poslo::kKtCount] = {};
+    uint64_t kt_launches[poslo::kKtCount] = {};
+    // scratch
+    uint32_t* d_tab = nullptr;
+    size_t tab_words = 0;
+    uint32_t* d_part = nullptr;
+    size_t part_words = 0;
+    uint32_t* d_result = nullptr;
+    uint32_t* h_result = nullptr;  // pinned
+    // comb tables: G (static) and per-key Y, LRU-bounded
+    uint32_t* d_gtable = nullptr;
+    size_t key_cap = 4096;
+    std::list<poslo::KeyEntry> keys;  // front = most recent
+    std::unordered_map<std::string, std::list<poslo::KeyEntry>::iterator> key_index;
+    // scratch slots of the Distill / SeBVer / batched entry points
+    uint32_t* xbuf[16] = {};
+    size_t xbuf_words[16] = {};
+};
+
+namespace poslo {
+
+int ctx_ensure(uint32_t** buf, size_t* have, size_t words);
+// device scratch slot of at least `bytes` bytes (grown on demand, kept until
+// the context is destroyed)
+int ctx_scratch(poslo_ctx* c, int slot, size_t bytes, void** out);
+void prof_begin(poslo_ctx* c, int k, hipStream_t s);
+void prof_end(poslo_ctx* c, int k, hipStream_t s);
+void prof_collect(poslo_ctx* c);
+// device comb table of the key (built on the host on first use); nullptr and
+// *status = POSLO_E_ENCODING if pk is not a point encoding
+const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
+// host comb table: t[w][d] = d * 16^w * P as 32-word points
+void build_comb_table(const ge& P, std::vector<uint32_t>& out);
+
+struct BatchArgs;
+struct DsArg;
+bool params_ok(const poslo_params* p);
+// host-side checks of a batch (parameters, ds parse, SR coverage of every
+// epoch); fills the kernel argument block and the by-value ds, sizes the
+// epoch table
+int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds, size_t ds_len,
+                  BatchArgs& a, DsArg& dsa, uint32_t& n_epochs);
+bool fast_layout(const poslo_msgs* m, uint64_t align);
+int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s);
+
+}  // namespace poslo

@@ -29,8 +29,10 @@ struct ConstTables {
 };
 
 // Table reader over bank-replicated copies in LDS.  NT = 4 keeps the four
-// rotated tables; NT = 1 keeps te0 and rotates.  C copies are interleaved so
-// that copy c of entry x sits at word x*C + c; a lane reads copy (lane mod C).
+// rotated tables, NT = 2 keeps te0 and te0 rotated by 16 (the other two are
+// one rotation away), NT = 1 keeps te0 and rotates.  C copies are interleaved
+// so that copy c of entry x sits at word x*C + c; a lane reads copy
+// (lane mod C), which spreads a wave's random lookups over more banks.
 template <int NT, int C>
 struct LdsTables {
     const uint32_t* p;
@@ -41,10 +43,12 @@ struct LdsTables {
     }
     __device__ __forceinline__ uint32_t t2(uint32_t x) const {
         if constexpr (NT == 4) return p[(512 + x) * C];
+        else if constexpr (NT == 2) return p[(256 + x) * C];
         else return rotl32(p[x * C], 16);
     }
     __device__ __forceinline__ uint32_t t3(uint32_t x) const {
         if constexpr (NT == 4) return p[(768 + x) * C];
+        else if constexpr (NT == 2) return rotl32(p[(256 + x) * C], 8);
         else return rotl32(p[x * C], 24);
     }
 };
@@ -53,7 +57,8 @@ template <int NT, int C>
 __device__ __forceinline__ void lds_tables_fill(uint32_t* lds) {
     for (int k = threadIdx.x; k < NT * 256 * C; k += blockDim.x) {
         int e = k / C;
-        lds[k] = rotl32(c_aes.te0[e & 255], 8 * (e >> 8));
+        int rot = NT == 2 ? 16 * (e >> 8) : 8 * (e >> 8);
+        lds[k] = rotl32(c_aes.te0[e & 255], rot);
     }
 }
 

@@ -1,0 +1,746 @@
+// POSLO-F distillation and selective batch verification on gfx950.
+//
+// Paper: section "POSLO-C Distillation and Selective Batch Verification"
+// (figure "Distillation and selective batch verification"), applied entry by
+// entry as the "Fine-grained public-key POSLO" text prescribes: every entry is
+// verified individually; valid entries are aggregated into the overall tag
+// CCD^v and into umbrella tags CCD^u; invalid entries are kept with their
+// signatures in CCD^i.  SeBVer checks CCD^v (mode V), each umbrella (mode U)
+// or each invalid entry (mode I).
+//
+// Entry validity: x_t equals the re-derived PRF_0(x_0[i] || j), s_t < q, and
+// encode(e_t*Y + s_t*G) equals the R_t bytes.
+//
+// Aggregates: for a valid entry R_t = e_t*Y + s_t*G exactly, so the sum of the
+// valid R_t of a range equals (sum e_t)*Y + (sum s_t)*G.  The kernels
+// therefore sum e_t and s_t lazily over valid entries (as AVer does) and do
+// one double-scalar multiplication per umbrella instead of one point addition
+// per entry; the result is the same group element, hence the same bytes.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "ctx.h"
+#include "device_ec.h"
+#include "device_entry.h"
+#include "scheme_host.h"
+
+namespace poslo {
+
+constexpr int kTile = 256;  // entries per verification tile (one workgroup)
+
+// tiles never straddle an umbrella: umbrella l covers [l*span, min(n, (l+1)*span))
+struct TileGeom {
+    uint64_t n;
+    uint64_t span;
+    uint32_t tiles_per_umb;
+};
+
+__device__ __forceinline__ bool tile_range(const TileGeom& g, uint32_t tile, uint64_t& start, uint64_t& end) {
+    uint64_t l = tile / g.tiles_per_umb, k = tile % g.tiles_per_umb;
+    uint64_t u0 = l * g.span, u1 = u0 + g.span < g.n ? u0 + g.span : g.n;
+    start = u0 + k * kTile;
+    end = start + kTile < u1 ? start + kTile : u1;
+    return start < end;
+}
+
+struct VerifyArgs {
+    BatchArgs a;
+    TileGeom g;
+    uint32_t inst;
+    const uint8_t* sigs;   // 80 bytes per entry (tile mode) or per list item (list mode)
+    const uint64_t* list;  // list mode: batch positions
+    uint64_t list_n;
+    const uint32_t* ty;
+    const uint32_t* tg;
+    uint8_t* flags;        // 1 = invalid, per batch position (tile mode) or list item
+    uint32_t* tile_part;   // 18 words per tile: lazy sums of e_t and s_t over valid entries
+};
+
+// individual verification of the entry at batch position pos; on success
+// e (mod q) and s are returned for the aggregates
+__device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const VerifyArgs& v, uint64_t pos,
+                                             const uint8_t* sg, uint32_t e[8], uint32_t s[8]) {
+    const BatchArgs& a = v.a;
+    uint32_t x[4], xs[4];
+    for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
+    EntryView ev = entry_view(a, pos);
+    uint32_t dig[8];
+    if (v.inst == INST_AES) {
+        one_time_seed_aes(tb, a, pos, x);
+        if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
+        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+        if (!sc_is_canonical(s)) return false;
+        digest_mdc2<false>(tb, ev, x, dig);
+    } else {
+        one_time_seed_sha(a, pos, x);  // big-endian words of the bytes of x_t
+        if ((bswap32(x[0]) ^ xs[0]) | (bswap32(x[1]) ^ xs[1]) | (bswap32(x[2]) ^ xs[2]) | (bswap32(x[3]) ^ xs[3]))
+            return false;
+        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+        if (!sc_is_canonical(s)) return false;
+        digest_sha<false>(ev, x, dig);
+    }
+    sc_reduce256(e, dig);
+    ge P;
+    lane_double_scalar(P, v.ty, v.tg, e, s);
+    uint32_t r[8];
+    for (int k = 0; k < 8; k++) r[k] = load_le32(sg + 32 + 4 * k);
+    return ge_encodes_to(P, r);
+}
+
+__global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    uint64_t start, end;
+    bool any = tile_range(v.g, blockIdx.x, start, end);
+    uint64_t pos = start + threadIdx.x;
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (any && pos < end) {
+        uint32_t e[8], s[8];
+        bool ok = verify_entry(tb, v, pos, v.sigs + 80 * pos, e, s);
+        v.flags[pos] = ok ? 0 : 1;
+        if (ok) {
+            acc288_add256(ae, e);
+            acc288_add256(as, s);
+        }
+    }
+    uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
+    block_reduce288_store<kTile>(ae, out);
+    __syncthreads();
+    block_reduce288_store<kTile>(as, out + 9);
+}
+
+// list mode (SeBVer I): flags[i] = 1 when list item i is invalid
+__global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    uint64_t i = (uint64_t)blockIdx.x * kTile + threadIdx.x;
+    if (i >= v.list_n) return;
+    uint32_t e[8], s[8];
+    bool ok = verify_entry(tb, v, v.list[i], v.sigs + 80 * i, e, s);
+    v.flags[i] = ok ? 0 : 1;
+}
+
+// per-tile lazy sums of e_t over non-skipped entries (SeBVer U)
+__global__ __launch_bounds__(kTile) void k_ekeys_tiles(BatchArgs a, TileGeom g, uint32_t inst, uint32_t* tile_part) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    uint64_t start, end;
+    bool any = tile_range(g, blockIdx.x, start, end);
+    uint64_t pos = start + threadIdx.x;
+    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (any && pos < end && !skipped(a, pos)) {
+        uint32_t x[4], dig[8];
+        EntryView ev = entry_view(a, pos);
+        if (inst == INST_AES) {
+            one_time_seed_aes(tb, a, pos, x);
+            digest_mdc2<false>(tb, ev, x, dig);
+        } else {
+            one_time_seed_sha(a, pos, x);
+            digest_sha<false>(ev, x, dig);
+        }
+        acc288_add256(acc, dig);
+    }
+    block_reduce288_store<kTile>(acc, tile_part + (uint64_t)blockIdx.x * 18);
+}
+
+// Per umbrella: fold the tiles' partials, reduce mod q, then
+//   mode 0 (Distill): tag = LE32B(s) || enc(e*Y + s*G), and e, s mod q kept
+//   mode 1 (SeBVer U): bit = [host checks ok] and e*Y + s*G == R of the tag
+struct FoldArgs {
+    const uint32_t* tile_part;
+    uint32_t tiles_per_umb;
+    uint32_t mode;
+    const uint32_t* ty;
+    const uint32_t* tg;
+    const uint32_t* chk;  // mode 1: per umbrella 25 words: s[8], x_R[8], y_R[8], ok
+    uint32_t* umb_es;     // mode 0: per umbrella e mod q [8], s mod q [8]
+    uint8_t* umb_tags;    // mode 0: 64 bytes per umbrella
+    uint32_t* umb_bits;   // mode 1: accept per umbrella
+};
+
+__global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
+    __shared__ uint32_t tot_e[9], tot_s[9];
+    __shared__ uint32_t sh[16];
+    const uint32_t l = blockIdx.x;
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t k = threadIdx.x; k < f.tiles_per_umb; k += kTile) {
+        const uint32_t* tp = f.tile_part + ((uint64_t)l * f.tiles_per_umb + k) * 18;
+        acc288_add(ae, tp);
+        acc288_add(as, tp + 9);
+    }
+    block_reduce288_store<kTile>(ae, tot_e);
+    __syncthreads();
+    block_reduce288_store<kTile>(as, tot_s);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t e[8], s[8];
+        sc_reduce288(e, tot_e);
+        if (f.mode == 0) {
+            sc_reduce288(s, tot_s);
+        } else {
+            for (int k = 0; k < 8; k++) s[k] = f.chk[l * 25 + k];
+        }
+        for (int k = 0; k < 8; k++) {
+            sh[k] = e[k];
+            sh[8 + k] = s[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t e[8], s[8];
+        for (int k = 0; k < 8; k++) {
+            e[k] = sh[k];
+            s[k] = sh[8 + k];
+        }
+        ge P;
+        wave_double_scalar(P, f.ty, f.tg, e, s);
+        if (threadIdx.x == 0) {
+            if (f.mode == 0) {
+                uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
+                for (int k = 0; k < 8; k++) {
+                    store_le32(tag + 4 * k, s[k]);
+                    f.umb_es[l * 16 + k] = e[k];
+                    f.umb_es[l * 16 + 8 + k] = s[k];
+                }
+                ge_encode(tag + 32, P);
+            } else {
+                const uint32_t* c = f.chk + l * 25;
+                fe rx, ry, t0, t1;
+                for (int k = 0; k < 8; k++) {
+                    rx.v[k] = c[8 + k];
+                    ry.v[k] = c[16 + k];
+                }
+                fe_mul(t0, rx, P.Z);
+                fe_mul(t1, ry, P.Z);
+                f.umb_bits[l] = (c[24] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
+            }
+        }
+    }
+}
+
+// CCD^v: fold the umbrellas' (e, s) mod q and encode e*Y + s*G
+__global__ __launch_bounds__(kTile) void k_valid_fold(const uint32_t* umb_es, uint32_t n_umb, const uint32_t* ty,
+                                                      const uint32_t* tg, uint8_t* tag) {
+    __shared__ uint32_t tot_e[9], tot_s[9];
+    __shared__ uint32_t sh[16];
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t l = threadIdx.x; l < n_umb; l += kTile) {
+        acc288_add256(ae, umb_es + l * 16);
+        acc288_add256(as, umb_es + l * 16 + 8);
+    }
+    block_reduce288_store<kTile>(ae, tot_e);
+    __syncthreads();
+    block_reduce288_store<kTile>(as, tot_s);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t e[8], s[8];
+        sc_reduce288(e, tot_e);
+        sc_reduce288(s, tot_s);
+        for (int k = 0; k < 8; k++) {
+            sh[k] = e[k];
+            sh[8 + k] = s[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t e[8], s[8];
+        for (int k = 0; k < 8; k++) {
+            e[k] = sh[k];
+            s[k] = sh[8 + k];
+        }
+        ge P;
+        wave_double_scalar(P, ty, tg, e, s);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 8; k++) store_le32(tag + 4 * k, s[k]);
+            ge_encode(tag + 32, P);
+        }
+    }
+}
+
+// sorted list of invalid entries: per-thread counts over contiguous chunks,
+// a workgroup exclusive scan, then ordered writes.  out_idx gets t0 + pos.
+constexpr int kCompact = 1024;
+
+__global__ __launch_bounds__(kCompact) void k_compact(const uint8_t* flags, uint64_t n, uint64_t t0, uint64_t* out_idx,
+                                                      uint64_t* out_count) {
+    __shared__ uint64_t scan[kCompact];
+    uint64_t chunk = (n + kCompact - 1) / kCompact;
+    uint64_t a = (uint64_t)threadIdx.x * chunk, b = a + chunk < n ? a + chunk : n;
+    uint64_t cnt = 0;
+    for (uint64_t p = a; p < b; p++) cnt += flags[p];
+    scan[threadIdx.x] = cnt;
+    __syncthreads();
+    // Hillis-Steele inclusive scan
+    for (int off = 1; off < kCompact; off <<= 1) {
+        uint64_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t o = scan[threadIdx.x] - cnt;
+    for (uint64_t p = a; p < b; p++)
+        if (flags[p]) out_idx[o++] = t0 + p;
+    if (threadIdx.x == kCompact - 1) *out_count = scan[kCompact - 1];
+}
+
+__global__ void k_gather_sigs(const uint64_t* idx, uint64_t count, uint64_t t0, const uint8_t* sigs, uint8_t* out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count * 20) return;
+    uint64_t k = i / 20, w = i % 20;
+    const uint8_t* src = sigs + (idx[k] - t0) * 80 + 4 * w;
+    uint8_t* dst = out + k * 80 + 4 * w;
+    for (int b = 0; b < 4; b++) dst[b] = src[b];
+}
+
+}  // namespace poslo
+
+// ===========================================================================
+// host side
+// ===========================================================================
+
+using namespace poslo;
+
+struct poslo_ccd {
+    uint32_t inst = 0, log2_n1 = 0, log2_n2 = 0;
+    uint64_t t0 = 0, n = 0, span = 0;
+    std::vector<uint8_t> ds;
+    uint8_t valid_tag[64] = {};
+    std::vector<uint8_t> umb_tags;      // 64 bytes per umbrella
+    std::vector<uint64_t> invalid;      // sorted global indices t
+    std::vector<uint8_t> invalid_sigs;  // 80 bytes per invalid entry
+};
+
+namespace {
+
+#define HIP_TRY(x)                                     \
+    do {                                               \
+        if ((x) != hipSuccess) return POSLO_E_DEVICE;  \
+    } while (0)
+
+int scratch(poslo_ctx* c, int slot, size_t bytes, void** out) { return ctx_scratch(c, slot, bytes, out); }
+
+enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX };
+
+int checked_sigs(const uint8_t* sigs, uint64_t n) {
+    if (n && !sigs) return POSLO_E_INVAL;
+    if ((uintptr_t)sigs % 4) return POSLO_E_INVAL;
+    return POSLO_OK;
+}
+
+}  // namespace
+
+extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
+                             const uint8_t* sigs, const uint8_t* ds, size_t ds_len, uint32_t n_umbrella, void* stream,
+                             poslo_ccd** out) {
+    if (!out || !pk || n_umbrella == 0) return POSLO_E_INVAL;
+    *out = nullptr;
+    BatchArgs a;
+    DsArg dsa;
+    uint32_t n_epochs;
+    int st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs);
+    if (st) return st;
+    if ((st = checked_sigs(sigs, m->n))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(c->device));
+    const KeyEntry* key = ctx_key(c, pk, &st);
+    if (!key) return st;
+
+    poslo_ccd* ccd = new (std::nothrow) poslo_ccd();
+    if (!ccd) return POSLO_E_NOMEM;
+    ccd->inst = prm->inst;
+    ccd->log2_n1 = prm->log2_n1;
+    ccd->log2_n2 = prm->log2_n2;
+    ccd->t0 = m->t0;
+    ccd->n = m->n;
+    ccd->ds.assign(ds, ds + ds_len);
+    uint64_t n = m->n;
+    uint64_t span = std::max<uint64_t>(1, (n + n_umbrella - 1) / n_umbrella);
+    uint64_t n_umb = n ? (n + span - 1) / span : 0;
+    ccd->span = span;
+
+    void *flags, *tiles, *umb_es, *umb_tags, *idx, *misc, *gsigs;
+    uint32_t tpu = (uint32_t)((span + kTile - 1) / kTile);
+    uint64_t n_tiles = n_umb * tpu;
+    if (n_tiles > 0x7fffffffull) {
+        delete ccd;
+        return POSLO_E_INVAL;
+    }
+    if ((st = scratch(c, S_FLAGS, std::max<uint64_t>(n, 1), &flags)) ||
+        (st = scratch(c, S_TILES, std::max<uint64_t>(n_tiles, 1) * 72, &tiles)) ||
+        (st = scratch(c, S_UMB_ES, std::max<uint64_t>(n_umb, 1) * 64, &umb_es)) ||
+        (st = scratch(c, S_UMB_TAGS, std::max<uint64_t>(n_umb, 1) * 64, &umb_tags)) ||
+        (st = scratch(c, S_IDX, std::max<uint64_t>(n, 1) * 8, &idx)) || (st = scratch(c, S_MISC, 256, &misc))) {
+        delete ccd;
+        return st;
+    }
+    uint8_t* d_valid_tag = (uint8_t*)misc;
+    uint64_t* d_count = (uint64_t*)((uint8_t*)misc + 128);
+    auto fail = [&](int code) {
+        delete ccd;
+        return code;
+    };
+    if (n) {
+        prof_begin(c, POSLO_KT_SEED, s);
+        if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return fail(st);
+        prof_end(c, POSLO_KT_SEED, s);
+        VerifyArgs v;
+        v.a = a;
+        v.g = TileGeom{n, span, tpu};
+        v.inst = prm->inst;
+        v.sigs = sigs;
+        v.list = nullptr;
+        v.list_n = 0;
+        v.ty = key->d_table;
+        v.tg = c->d_gtable;
+        v.flags = (uint8_t*)flags;
+        v.tile_part = (uint32_t*)tiles;
+        prof_begin(c, POSLO_KT_VERIFY, s);
+        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v);
+        if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
+        prof_end(c, POSLO_KT_VERIFY, s);
+        FoldArgs f;
+        f.tile_part = (uint32_t*)tiles;
+        f.tiles_per_umb = tpu;
+        f.mode = 0;
+        f.ty = key->d_table;
+        f.tg = c->d_gtable;
+        f.chk = nullptr;
+        f.umb_es = (uint32_t*)umb_es;
+        f.umb_tags = (uint8_t*)umb_tags;
+        f.umb_bits = nullptr;
+        prof_begin(c, POSLO_KT_COMPACT, s);
+        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
+        hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompact), 0, s, (const uint8_t*)flags, n, m->t0, (uint64_t*)idx,
+                           d_count);
+        if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
+    } else {
+        prof_begin(c, POSLO_KT_COMPACT, s);
+    }
+    hipLaunchKernelGGL(k_valid_fold, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es, (uint32_t)n_umb,
+                       key->d_table, c->d_gtable, d_valid_tag);
+    if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
+    prof_end(c, POSLO_KT_COMPACT, s);
+    uint64_t count = 0;
+    if ((n && hipMemcpyAsync(&count, d_count, 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        hipMemcpyAsync(ccd->valid_tag, d_valid_tag, 64, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(POSLO_E_DEVICE);
+    ccd->umb_tags.resize(n_umb * 64);
+    if (n_umb && hipMemcpyAsync(ccd->umb_tags.data(), umb_tags, n_umb * 64, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(POSLO_E_DEVICE);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(POSLO_E_DEVICE);
+    prof_collect(c);
+    ccd->invalid.resize(count);
+    ccd->invalid_sigs.resize(count * 80);
+    if (count) {
+        if ((st = scratch(c, S_SIGS, count * 80, &gsigs))) return fail(st);
+        uint64_t threads = count * 20;
+        hipLaunchKernelGGL(k_gather_sigs, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
+                           (const uint64_t*)idx, count, m->t0, sigs, (uint8_t*)gsigs);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(ccd->invalid.data(), idx, count * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(ccd->invalid_sigs.data(), gsigs, count * 80, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(POSLO_E_DEVICE);
+    }
+    *out = ccd;
+    return POSLO_OK;
+}
+
+extern "C" void poslo_ccd_free(poslo_ccd* ccd) { delete ccd; }
+
+extern "C" int poslo_ccd_invalid(const poslo_ccd* ccd, const uint64_t** idx, uint64_t* n) {
+    if (!ccd || !idx || !n) return POSLO_E_INVAL;
+    *idx = ccd->invalid.data();
+    *n = ccd->invalid.size();
+    return POSLO_OK;
+}
+
+extern "C" int poslo_ccd_invalid_sig(const poslo_ccd* ccd, uint64_t k, uint8_t sig[80]) {
+    if (!ccd || !sig || k >= ccd->invalid.size()) return POSLO_E_INVAL;
+    memcpy(sig, ccd->invalid_sigs.data() + 80 * k, 80);
+    return POSLO_OK;
+}
+
+extern "C" int poslo_ccd_valid_tag(const poslo_ccd* ccd, uint8_t tag[64]) {
+    if (!ccd || !tag) return POSLO_E_INVAL;
+    memcpy(tag, ccd->valid_tag, 64);
+    return POSLO_OK;
+}
+
+extern "C" int poslo_ccd_umbrellas(const poslo_ccd* ccd, uint8_t* tags, size_t cap, uint64_t* n_umb, uint64_t* span) {
+    if (!ccd) return POSLO_E_INVAL;
+    uint64_t k = ccd->umb_tags.size() / 64;
+    if (n_umb) *n_umb = k;
+    if (span) *span = ccd->span;
+    if (tags) {
+        if (cap < ccd->umb_tags.size()) return POSLO_E_INVAL;
+        memcpy(tags, ccd->umb_tags.data(), ccd->umb_tags.size());
+    }
+    return POSLO_OK;
+}
+
+// Serialized CCD (for cold storage): magic "PCCD", u32 version 1, u32 inst,
+// log2_n1, log2_n2, u64 t0, n, span, u32 ds_len, ds, valid tag (64), u64
+// n_umb, tags (64 each), u64 n_inv, per invalid entry u64 t and sigma (80).
+namespace {
+void put32(std::vector<uint8_t>& o, uint32_t v) {
+    uint8_t b[4];
+    store_le32(b, v);
+    o.insert(o.end(), b, b + 4);
+}
+void put64(std::vector<uint8_t>& o, uint64_t v) {
+    put32(o, (uint32_t)v);
+    put32(o, (uint32_t)(v >> 32));
+}
+struct Reader {
+    const uint8_t* p;
+    size_t left;
+    bool ok = true;
+    uint32_t u32() {
+        if (left < 4) {
+            ok = false;
+            return 0;
+        }
+        uint32_t v = load_le32(p);
+        p += 4;
+        left -= 4;
+        return v;
+    }
+    uint64_t u64() {
+        uint64_t lo = u32();
+        return lo | ((uint64_t)u32() << 32);
+    }
+    bool bytes(uint8_t* dst, size_t n) {
+        if (left < n) return ok = false;
+        memcpy(dst, p, n);
+        p += n;
+        left -= n;
+        return true;
+    }
+};
+}  // namespace
+
+extern "C" int poslo_ccd_export(const poslo_ccd* ccd, uint8_t* buf, size_t cap, size_t* len) {
+    if (!ccd || !len) return POSLO_E_INVAL;
+    std::vector<uint8_t> o;
+    o.insert(o.end(), {'P', 'C', 'C', 'D'});
+    put32(o, 1);
+    put32(o, ccd->inst);
+    put32(o, ccd->log2_n1);
+    put32(o, ccd->log2_n2);
+    put64(o, ccd->t0);
+    put64(o, ccd->n);
+    put64(o, ccd->span);
+    put32(o, (uint32_t)ccd->ds.size());
+    o.insert(o.end(), ccd->ds.begin(), ccd->ds.end());
+    o.insert(o.end(), ccd->valid_tag, ccd->valid_tag + 64);
+    put64(o, ccd->umb_tags.size() / 64);
+    o.insert(o.end(), ccd->umb_tags.begin(), ccd->umb_tags.end());
+    put64(o, ccd->invalid.size());
+    for (size_t k = 0; k < ccd->invalid.size(); k++) {
+        put64(o, ccd->invalid[k]);
+        o.insert(o.end(), ccd->invalid_sigs.begin() + 80 * k, ccd->invalid_sigs.begin() + 80 * (k + 1));
+    }
+    *len = o.size();
+    if (!buf || cap < o.size()) return POSLO_E_INVAL;
+    memcpy(buf, o.data(), o.size());
+    return POSLO_OK;
+}
+
+extern "C" int poslo_ccd_import(const uint8_t* buf, size_t len, poslo_ccd** out) {
+    if (!buf || !out) return POSLO_E_INVAL;
+    *out = nullptr;
+    Reader r{buf, len};
+    uint8_t magic[4];
+    if (!r.bytes(magic, 4) || memcmp(magic, "PCCD", 4) != 0 || r.u32() != 1) return POSLO_E_INVAL;
+    poslo_ccd* c = new (std::nothrow) poslo_ccd();
+    if (!c) return POSLO_E_NOMEM;
+    c->inst = r.u32();
+    c->log2_n1 = r.u32();
+    c->log2_n2 = r.u32();
+    c->t0 = r.u64();
+    c->n = r.u64();
+    c->span = r.u64();
+    uint32_t dl = r.u32();
+    if (!r.ok || dl > 1 + 24 * 32) {
+        delete c;
+        return POSLO_E_INVAL;
+    }
+    c->ds.resize(dl);
+    r.bytes(c->ds.data(), dl);
+    r.bytes(c->valid_tag, 64);
+    uint64_t nu = r.u64();
+    if (!r.ok || nu > r.left / 64) {
+        delete c;
+        return POSLO_E_INVAL;
+    }
+    c->umb_tags.resize(nu * 64);
+    r.bytes(c->umb_tags.data(), nu * 64);
+    uint64_t ni = r.u64();
+    if (!r.ok || ni > r.left / 88) {
+        delete c;
+        return POSLO_E_INVAL;
+    }
+    c->invalid.resize(ni);
+    c->invalid_sigs.resize(ni * 80);
+    for (uint64_t k = 0; k < ni; k++) {
+        c->invalid[k] = r.u64();
+        r.bytes(c->invalid_sigs.data() + 80 * k, 80);
+    }
+    if (!r.ok || r.left != 0) {
+        delete c;
+        return POSLO_E_INVAL;
+    }
+    *out = c;
+    return POSLO_OK;
+}
+
+// skip bitmap of the CCD's invalid entries over batch positions (device)
+static int upload_skip(poslo_ctx* c, const poslo_ccd* ccd, hipStream_t s, const uint32_t** out) {
+    uint64_t words = (ccd->n + 31) / 32;
+    std::vector<uint32_t> bm(std::max<uint64_t>(words, 1), 0);
+    for (uint64_t t : ccd->invalid) {
+        uint64_t p = t - ccd->t0;
+        bm[p >> 5] |= 1u << (p & 31);
+    }
+    void* d;
+    int st = scratch(c, S_AUX, bm.size() * 4, &d);
+    if (st) return st;
+    if (hipMemcpyAsync(d, bm.data(), bm.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return POSLO_E_DEVICE;
+    *out = (const uint32_t*)d;
+    return POSLO_OK;
+}
+
+namespace poslo {
+int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m, const uint8_t* ds,
+              size_t ds_len, const uint8_t tag[64], void* stream, const uint32_t* skip, int* accept,
+              uint8_t e_out[32]);
+}
+
+extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
+                            const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream) {
+    if (!c || !prm || !pk || !m || !ccd || !n_bits) return POSLO_E_INVAL;
+    if (m->t0 != ccd->t0 || m->n != ccd->n || prm->inst != ccd->inst || prm->log2_n2 != ccd->log2_n2 ||
+        prm->log2_n1 != ccd->log2_n1)
+        return POSLO_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(c->device));
+    int st;
+    if (mode == 'V') {
+        *n_bits = 1;
+        if (!bits || cap < 1) return POSLO_E_INVAL;
+        const uint32_t* skip = nullptr;
+        if (!ccd->invalid.empty() && (st = upload_skip(c, ccd, s, &skip))) return st;
+        int acc = 0;
+        st = aver_impl(c, prm, pk, m, ccd->ds.data(), ccd->ds.size(), ccd->valid_tag, stream, skip, &acc, nullptr);
+        if (st) return st;
+        bits[0] = (uint8_t)acc;
+        return POSLO_OK;
+    }
+    BatchArgs a;
+    DsArg dsa;
+    uint32_t n_epochs;
+    if ((st = prepare_batch(c, prm, m, ccd->ds.data(), ccd->ds.size(), a, dsa, n_epochs))) return st;
+    const KeyEntry* key = ctx_key(c, pk, &st);
+    if (!key) return st;
+    if (mode == 'U') {
+        uint64_t n_umb = ccd->umb_tags.size() / 64;
+        *n_bits = n_umb;
+        if (!bits || cap < n_umb) return POSLO_E_INVAL;
+        if (n_umb == 0) return POSLO_OK;
+        uint64_t span = ccd->span;
+        if (span == 0 || (m->n + span - 1) / span != n_umb) return POSLO_E_INVAL;
+        const uint32_t* skip = nullptr;
+        if (!ccd->invalid.empty() && (st = upload_skip(c, ccd, s, &skip))) return st;
+        a.skip = skip;
+        uint32_t tpu = (uint32_t)((span + kTile - 1) / kTile);
+        uint64_t n_tiles = n_umb * tpu;
+        // host checks of each umbrella tag: s < q and R decodes
+        std::vector<uint32_t> chk(n_umb * 25);
+        for (uint64_t l = 0; l < n_umb; l++) {
+            const uint8_t* tg = ccd->umb_tags.data() + 64 * l;
+            uint32_t* ck = &chk[l * 25];
+            for (int k = 0; k < 8; k++) ck[k] = load_le32(tg + 4 * k);
+            ge R;
+            bool ok = sc_is_canonical(ck) && ge_decode(R, tg + 32);
+            for (int k = 0; k < 8; k++) {
+                ck[8 + k] = ok ? R.X.v[k] : 0;
+                ck[16 + k] = ok ? R.Y.v[k] : 0;
+            }
+            ck[24] = ok ? 1 : 0;
+        }
+        void *tiles, *dchk, *dbits;
+        if ((st = scratch(c, S_TILES, n_tiles * 72, &tiles)) || (st = scratch(c, S_UMB_ES, chk.size() * 4, &dchk)) ||
+            (st = scratch(c, S_UMB_TAGS, n_umb * 4, &dbits)))
+            return st;
+        HIP_TRY(hipMemcpyAsync(dchk, chk.data(), chk.size() * 4, hipMemcpyHostToDevice, s));
+        if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
+        hipLaunchKernelGGL(k_ekeys_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, a, TileGeom{m->n, span, tpu},
+                           prm->inst, (uint32_t*)tiles);
+        FoldArgs f;
+        f.tile_part = (uint32_t*)tiles;
+        f.tiles_per_umb = tpu;
+        f.mode = 1;
+        f.ty = key->d_table;
+        f.tg = c->d_gtable;
+        f.chk = (const uint32_t*)dchk;
+        f.umb_es = nullptr;
+        f.umb_tags = nullptr;
+        f.umb_bits = (uint32_t*)dbits;
+        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
+        HIP_TRY(hipGetLastError());
+        std::vector<uint32_t> hb(n_umb);
+        HIP_TRY(hipMemcpyAsync(hb.data(), dbits, n_umb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (uint64_t l = 0; l < n_umb; l++) bits[l] = (uint8_t)hb[l];
+        return POSLO_OK;
+    }
+    if (mode == 'I') {
+        uint64_t ni = ccd->invalid.size();
+        *n_bits = ni;
+        if (!bits || cap < ni) return POSLO_E_INVAL;
+        if (ni == 0) return POSLO_OK;
+        std::vector<uint64_t> pos(ni);
+        for (uint64_t k = 0; k < ni; k++) {
+            if (ccd->invalid[k] < m->t0 || ccd->invalid[k] - m->t0 >= m->n) return POSLO_E_INVAL;
+            pos[k] = ccd->invalid[k] - m->t0;
+        }
+        void *dpos, *dsig, *dflags;
+        if ((st = scratch(c, S_IDX, ni * 8, &dpos)) || (st = scratch(c, S_SIGS, ni * 80, &dsig)) ||
+            (st = scratch(c, S_FLAGS, ni, &dflags)))
+            return st;
+        HIP_TRY(hipMemcpyAsync(dpos, pos.data(), ni * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(dsig, ccd->invalid_sigs.data(), ni * 80, hipMemcpyHostToDevice, s));
+        if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
+        VerifyArgs v;
+        v.a = a;
+        v.g = TileGeom{m->n, 1, 1};
+        v.inst = prm->inst;
+        v.sigs = (const uint8_t*)dsig;
+        v.list = (const uint64_t*)dpos;
+        v.list_n = ni;
+        v.ty = key->d_table;
+        v.tg = c->d_gtable;
+        v.flags = (uint8_t*)dflags;
+        v.tile_part = nullptr;
+        hipLaunchKernelGGL(k_verify_list, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);
+        HIP_TRY(hipGetLastError());
+        std::vector<uint8_t> hf(ni);
+        HIP_TRY(hipMemcpyAsync(hf.data(), dflags, ni, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (uint64_t k = 0; k < ni; k++) bits[k] = hf[k] ? 0 : 1;
+        return POSLO_OK;
+    }
+    return POSLO_E_INVAL;
+}

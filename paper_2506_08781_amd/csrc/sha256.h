@@ -22,12 +22,24 @@ inline constexpr Sha256Consts kSha256 = {
      0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u, 0xc67178f2u},
     {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au, 0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u}};
 
+// three-input xor and majority: one v_bitop3_b32 each on the device (both
+// functions are symmetric in their inputs, so the truth table does not
+// depend on operand order), plain C on the host
+__device__ __forceinline__ uint32_t xor3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__host__ inline uint32_t xor3_u32(uint32_t a, uint32_t b, uint32_t c) { return a ^ b ^ c; }
+__device__ __forceinline__ uint32_t maj3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xe8);
+}
+__host__ inline uint32_t maj3_u32(uint32_t a, uint32_t b, uint32_t c) { return (a & b) | (c & (a | b)); }
+
 PD uint32_t sha_ch(uint32_t e, uint32_t f, uint32_t g) { return g ^ (e & (f ^ g)); }
-PD uint32_t sha_maj(uint32_t a, uint32_t b, uint32_t c) { return (a & b) | (c & (a | b)); }
-PD uint32_t sha_S0(uint32_t a) { return rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22); }
-PD uint32_t sha_S1(uint32_t e) { return rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25); }
-PD uint32_t sha_s0(uint32_t w) { return rotr32(w, 7) ^ rotr32(w, 18) ^ (w >> 3); }
-PD uint32_t sha_s1(uint32_t w) { return rotr32(w, 17) ^ rotr32(w, 19) ^ (w >> 10); }
+PD uint32_t sha_maj(uint32_t a, uint32_t b, uint32_t c) { return maj3_u32(a, b, c); }
+PD uint32_t sha_S0(uint32_t a) { return xor3_u32(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22)); }
+PD uint32_t sha_S1(uint32_t e) { return xor3_u32(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25)); }
+PD uint32_t sha_s0(uint32_t w) { return xor3_u32(rotr32(w, 7), rotr32(w, 18), w >> 3); }
+PD uint32_t sha_s1(uint32_t w) { return xor3_u32(rotr32(w, 17), rotr32(w, 19), w >> 10); }
 
 // H <- compress(H, W[0..15]); W is consumed as a 16-word rolling schedule
 PD void sha256_compress(uint32_t H[8], uint32_t W[16]) {

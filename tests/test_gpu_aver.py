@@ -180,3 +180,22 @@ def test_full_size_2p20_x_256(P, gpu, inst):
     # one flipped message bit makes the aggregate reject
     d[n // 3, 17] ^= 4
     assert not P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)[0]
+
+
+def test_every_tuning_variant_agrees(P, gpu):
+    """Every hot-kernel variant and grid shape gives the same aggregate."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = oracle_case(1, 777, 48, 4, 6, 0, 1)
+    params = P.make_params(1, 4, 6)
+    d, _ = upload(torch, msgs, True)
+    want = O.ekeys_sum(prm, msgs, 0, ds)
+    try:
+        for v in range(P.poslo_agg_variant_count()):
+            for wg in (0, 1):
+                print(f"variant {P.poslo_agg_variant_name(v)} wg {wg}", flush=True)
+                P.poslo_ctx_set_tuning(ctx, v, wg)
+                acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)
+                assert acc and int.from_bytes(e, "little") == want, P.poslo_agg_variant_name(v)
+    finally:
+        P.poslo_ctx_set_tuning(ctx, -1, 0)

@@ -1,0 +1,160 @@
+"""GPU parity of Distill and SeBVer against the oracle, through the C ABI.
+
+Small batches are signed by the oracle and corrupted at seeded single-bit
+positions of m_t || sigma_t; the GPU's CCD (sorted invalid set, invalid
+signatures, valid tag, umbrella tags) must equal the oracle's byte for byte,
+and SeBVer's bits must equal the oracle's.  At the full 2^20 x 256-byte size
+with 1% corruption the invalid set must equal the injected set, sampled
+entries are re-verified by the oracle one by one, and the valid tag must
+equal the aggregate of the untouched signatures."""
+
+import functools
+import random
+
+import numpy as np
+import pytest
+
+import synthlog
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu(P):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    ctx = P.poslo_ctx_create(0)
+    yield torch, ctx
+    ctx.close()
+
+
+def corrupt(msgs, sigs, plan):
+    msgs, sigs = list(msgs), list(sigs)
+    for e, bit in plan:
+        L = len(msgs[e])
+        blob = bytearray(msgs[e] + sigs[e])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        msgs[e], sigs[e] = bytes(blob[:L]), bytes(blob[L:])
+    return msgs, sigs
+
+
+@functools.lru_cache(maxsize=None)
+def signed(inst, n, L, l1, l2, key_first, msg_seed):
+    from oracle import oracle as O
+    prm = O.Params(inst, l1, l2)
+    msgs = [bytes(r) for r in synthlog.messages_fixed(msg_seed, n, L)]
+    pk, sigs, ds, tag, _ = O.sign_batch(prm, synthlog.key_seed_bytes(key_first), msgs)
+    return prm, msgs, pk, sigs, ds, tag
+
+
+def to_dev(torch, msgs, sigs):
+    L = len(msgs[0])
+    m = torch.from_numpy(np.frombuffer(b"".join(msgs), dtype=np.uint8).reshape(len(msgs), L).copy()).cuda()
+    s = torch.from_numpy(np.frombuffer(b"".join(sigs), dtype=np.uint8).copy()).cuda()
+    return m, s
+
+
+CASES = [
+    # inst, n, L, log2_n1, log2_n2, corrupted, umbrellas
+    (1, 200, 40, 4, 4, 7, 5),
+    (0, 200, 40, 4, 4, 7, 5),
+    (1, 300, 32, 5, 4, 0, 3),     # nothing to find
+    (0, 64, 16, 3, 3, 11, 64),    # one entry per umbrella
+    (1, 129, 48, 4, 4, 129, 1),   # every entry corrupted, one umbrella
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"inst{c[0]}-n{c[1]}-L{c[2]}-k{c[5]}-u{c[6]}")
+def test_distill_and_sebver_match_oracle(P, gpu, case):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    inst, n, L, l1, l2, k, nu = case
+    prm, msgs, pk, sigs, ds, tag = signed(inst, n, L, l1, l2, 0x11, 8)
+    plan = synthlog.corruption_plan(40 + k, n, k, 8 * (L + 80))
+    cm, cs = corrupt(msgs, sigs, plan)
+    params = P.make_params(inst, l1, l2)
+    dm, dsig = to_dev(torch, cm, cs)
+    print(f"case {case}: distill", flush=True)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, nu)
+    want = O.distill(prm, pk, cm, cs, 0, ds, nu)
+    got_inv = ccd.invalid()
+    assert got_inv == [t for t, _ in want.invalid]
+    assert got_inv == sorted(e for e, _ in plan)
+    for i, (t, sg) in enumerate(want.invalid):
+        assert ccd.invalid_sig(i) == sg
+    assert ccd.valid_tag() == want.valid_tag
+    tags, span = ccd.umbrellas()
+    assert span == want.span and tags == [t for t, _ in want.umbrellas]
+    m = P.make_msgs(dm)
+    for mode in "VUI":
+        assert P.poslo_sebver(ctx, params, pk, m, ccd, mode) == O.sebver(prm, pk, cm, want, mode), mode
+    # the serialized CCD verifies the same way after a round trip
+    ccd2 = P.poslo_ccd_import(ccd.export())
+    assert ccd2.invalid() == got_inv and ccd2.valid_tag() == ccd.valid_tag()
+    assert P.poslo_sebver(ctx, params, pk, m, ccd2, "V") == [True]
+
+
+def test_sebver_detects_tampered_ccd(P, gpu):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = signed(1, 200, 40, 4, 4, 0x11, 8)
+    params = P.make_params(1, 4, 4)
+    plan = synthlog.corruption_plan(47, 200, 7, 8 * 120)
+    cm, cs = corrupt(msgs, sigs, plan)
+    dm, dsig = to_dev(torch, cm, cs)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 5)
+    blob = bytearray(ccd.export())
+    # flip a bit of the first umbrella tag's R: that umbrella must fail
+    hdr = 4 + 4 + 4 * 3 + 8 * 3
+    ds_len = int.from_bytes(blob[hdr:hdr + 4], "little")
+    umb0 = hdr + 4 + ds_len + 64 + 8
+    blob[umb0 + 40] ^= 1
+    bad = P.poslo_ccd_import(bytes(blob))
+    bits = P.poslo_sebver(ctx, params, pk, P.make_msgs(dm), bad, "U")
+    assert bits[0] is False and all(bits[1:])
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_full_size_distill_1pct(P, gpu, inst):
+    """2^20 entries of 256 bytes, 1% of entries with one flipped bit of
+    m_t || sigma_t, umbrellas of 2^14 entries."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    n, L, l1, l2 = 1 << 20, 256, 12, 8
+    print(f"full distill inst {inst}: generate", flush=True)
+    arr = synthlog.messages_fixed(2, n, L)
+    params = P.make_params(inst, l1, l2)
+    sk, pk = P.poslo_kg(params, synthlog.key_seed_bytes(0x20))
+    sigs = P.poslo_sig_batch(sk, arr)
+    ds = P.poslo_ds_export(sk)
+    k = n // 100
+    plan = synthlog.corruption_plan(3, n, k, 8 * (L + 80))
+    carr, csig = arr.copy(), sigs.copy()
+    for e, bit in plan:
+        if bit < 8 * L:
+            carr[e, bit // 8] ^= 1 << (bit % 8)
+        else:
+            b = bit - 8 * L
+            csig[e, b // 8] ^= 1 << (b % 8)
+    dm = torch.from_numpy(carr).cuda()
+    dsig = torch.from_numpy(csig.reshape(-1)).cuda()
+    print("full distill: run", flush=True)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 64)
+    inv = ccd.invalid()
+    assert inv == [e for e, _ in plan]
+    # the valid tag is the aggregate of the untouched signatures
+    bad = np.zeros(n, dtype=bool)
+    bad[inv] = True
+    assert ccd.valid_tag() == P.poslo_agg(sigs[~bad])
+    # sampled entries against the oracle's individual verification
+    prm = O.Params(inst, l1, l2)
+    dsn = O.ds_decode(ds)
+    rng = random.Random(5)
+    sample = rng.sample(inv, 24) + rng.sample(range(n), 24)
+    for t in sample:
+        x0 = O.SR(inst, dsn, t >> l2)
+        assert O.entry_valid(prm, pk, bytes(carr[t]), t, bytes(csig[t]), x0) == (not bad[t]), t
+    m = P.make_msgs(dm)
+    assert P.poslo_sebver(ctx, params, pk, m, ccd, "V") == [True]
+    assert all(P.poslo_sebver(ctx, params, pk, m, ccd, "U"))
+    assert not any(P.poslo_sebver(ctx, params, pk, m, ccd, "I"))

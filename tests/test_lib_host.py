@@ -77,3 +77,30 @@ def test_agg_rejects_undecodable_commitment(P):
     with pytest.raises(P.PosloError) as ei:
         P.poslo_agg(bytes(bad))
     assert ei.value.status == -5
+
+
+def _ccd_blob(ds=b"\x00", n_umb=2, invalid=((5, b"\x07" * 80),)):
+    out = bytearray(b"PCCD") + (1).to_bytes(4, "little")
+    for v in (1, 3, 4):
+        out += v.to_bytes(4, "little")
+    for v in (0, 100, 50):
+        out += v.to_bytes(8, "little")
+    out += len(ds).to_bytes(4, "little") + ds + b"\x01" * 64
+    out += n_umb.to_bytes(8, "little") + b"\x02" * (64 * n_umb)
+    out += len(invalid).to_bytes(8, "little")
+    for t, sg in invalid:
+        out += t.to_bytes(8, "little") + sg
+    return bytes(out)
+
+
+def test_ccd_serialization_roundtrip_and_strictness(P):
+    blob = _ccd_blob()
+    ccd = P.poslo_ccd_import(blob)
+    assert ccd.invalid() == [5] and ccd.invalid_sig(0) == b"\x07" * 80
+    assert ccd.valid_tag() == b"\x01" * 64
+    tags, span = ccd.umbrellas()
+    assert span == 50 and tags == [b"\x02" * 64] * 2
+    assert ccd.export() == blob
+    for bad in (blob[:-1], blob + b"\0", b"XCCD" + blob[4:]):
+        with pytest.raises(P.PosloError):
+            P.poslo_ccd_import(bad)

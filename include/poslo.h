@@ -79,13 +79,16 @@ typedef struct poslo_params {
 /* A batch of consecutive log entries t0 .. t0+n-1 in device memory.
  * Fixed length: offsets == NULL, entry p occupies data[p*msg_len ..
  * (p+1)*msg_len).  Variable length: offsets (device, n+1 u64) gives entry p
- * as data[offsets[p] .. offsets[p+1]), msg_len is ignored. */
+ * as data[offsets[p] .. offsets[p+1]), msg_len is ignored.  data_bytes is the
+ * size of the data buffer (0 = unknown); when known, unaligned messages are
+ * read with aligned word loads that stay inside it. */
 typedef struct poslo_msgs {
     const uint8_t* data;     /* device */
     const uint64_t* offsets; /* device or NULL */
     uint64_t msg_len;
     uint64_t n;
     uint64_t t0;
+    uint64_t data_bytes;
 } poslo_msgs;
 
 /* Library version string. */
@@ -225,6 +228,121 @@ void poslo_ccd_free(poslo_ccd* ccd);
  * bits: host, cap bytes; *n_bits gets the count. */
 int poslo_sebver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
                  const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream);
+
+/* ------------------------------------------- synthetic data on the device */
+
+/* Seeded message bytes generated on the device for benchmarks and tests:
+ * entry p of the batch takes its bytes from xoshiro256** stream (seed, t0+p)
+ * (splitmix64-seeded from (seed << 32) | (t0 + p)), little-endian, truncated
+ * to its length; m->data is ignored, out (device) receives the bytes at the
+ * layout m describes.  t0 + n must stay below 2^32. */
+int poslo_synth_messages(uint32_t seed, const poslo_msgs* m, uint8_t* out, void* stream);
+
+/* Keys held on the device for large-scale signing (test data): y, x_D[0]
+ * and the public key derived on the host as poslo_kg does, the BPV table
+ * derived on the device.  seeds: host, 32*nkeys; pks: host, 32*nkeys out.
+ * bpv_k <= 16.  Freed with poslo_gpu_keys_free. */
+typedef struct poslo_gpu_keys poslo_gpu_keys;
+int poslo_gpu_keys_create(poslo_ctx* ctx, const poslo_params* params, const uint8_t* seeds, uint32_t nkeys,
+                          poslo_gpu_keys** out, uint8_t* pks);
+void poslo_gpu_keys_free(poslo_gpu_keys* keys);
+
+/* One signing (or verification) job: entries t0 .. t0+n-1 of a signer whose
+ * messages are entries entry_base .. entry_base+n-1 of a global batch. */
+typedef struct poslo_sign_job {
+    uint32_t key;
+    uint32_t reserved;
+    uint64_t t0;
+    uint64_t n;
+    uint64_t entry_base;
+} poslo_sign_job;
+
+/* Sign every job's entries as poslo_sig_batch would (same bytes).  With
+ * n_total = max over jobs of entry_base + n: data (offsets[n_total] bytes),
+ * offsets (n_total + 1 u64), sigs (80 per global entry): device.  tags
+ * (64*njobs) and ds_out (ds_stride >= 769 bytes per job, may be NULL): host,
+ * the aggregate tag of each job and the ds after its last entry.
+ * Synchronous. */
+int poslo_gpu_sign(poslo_gpu_keys* keys, const poslo_sign_job* jobs, uint32_t njobs, const uint8_t* data,
+                   const uint64_t* offsets, uint8_t* sigs, uint8_t* tags, uint8_t* ds_out, size_t ds_stride,
+                   void* stream);
+
+/* ------------------------------------------------ many signers per launch */
+
+/* Load public keys into the context's device-resident key cache (comb
+ * tables built on the device, 128 KiB per key), so that later calls with
+ * these keys start without a host-side table build.  pks: host, 32*n.
+ * *n_bad (may be NULL) gets the number of keys that are not point
+ * encodings; those are skipped and the call returns POSLO_E_ENCODING.
+ * The cache holds at least the keys of the largest batch seen and evicts
+ * the least recently used beyond that.  Synchronous. */
+int poslo_ctx_keys_load(poslo_ctx* ctx, const uint8_t* pks, size_t n, size_t* n_bad);
+
+/* One signer's batch inside a multi-signer verification: entries t0 ..
+ * t0+n-1 of the signer with public key pk, whose messages are entries
+ * entry_base .. entry_base+n-1 of the global (offsets) layout, with the
+ * signer's ds after its last entry and its aggregate tag.  pk, ds and tag:
+ * host.  Jobs may use the same key; their entry ranges must not overlap. */
+typedef struct poslo_batch_job {
+    const uint8_t* pk;
+    const uint8_t* ds;
+    size_t ds_len;
+    const uint8_t* tag;
+    uint64_t t0;
+    uint64_t n;
+    uint64_t entry_base;
+} poslo_batch_job;
+
+/* Launch parameters of the multi-signer path: variant (see
+ * poslo_batch_variant_name: instantiation, LDS table copies, workgroup size,
+ * entries per work item, length sort), workgroups per CU of the persistent
+ * grid (0 = derived from LDS and wave budget), and whether to capture the
+ * launch sequence in a hipGraph that is replayed for identical shapes. */
+typedef struct poslo_tuning {
+    int variant;
+    int wg_per_cu;
+    int use_graph;
+    int reserved;
+} poslo_tuning;
+
+int poslo_batch_variant_count(void);
+const char* poslo_batch_variant_name(int v);
+
+/* AVer of every job in one persistent launch (section "POSLO Parallel Batch
+ * Verification", extended to many signers: per-epoch seeds of all jobs, one
+ * persistent hashing kernel that pulls fixed-size work items of any job from
+ * a queue, then one aggregate check per job).  data (device, data_bytes
+ * bytes or 0 if unknown) and offsets (device, u64, covering every job's
+ * entries) hold the messages.  accept: host, njobs bytes.  tuning may be
+ * NULL: the autotuner's choice for this shape class if one was made, else
+ * the default.
+ * distill: 0 = AVer only (sigs, invalid and n_invalid unused); 1 = the
+ * entries of rejected jobs are verified individually (Distill's check);
+ * 2 = the entries of every job are (AVer reads only messages, ds and tag,
+ * so a corrupted signature in an accepted job is found by mode 2 only).
+ * sigs: device, 80 bytes per global entry.  The invalid entries are
+ * returned as sorted (job, t) pairs in invalid (host, 2*cap u64);
+ * *n_invalid gets the count even when it exceeds cap (the pairs are then
+ * not written).  Accept bits equal poslo_aver per job; the pairs of a job
+ * equal poslo_distill's invalid list for it.  Errors: E_INVAL (bad job or
+ * argument), E_SEED (a ds does not cover an epoch), E_ENCODING (a pk is not
+ * a point).  Synchronous. */
+int poslo_verify_batch(poslo_ctx* ctx, const poslo_params* params, const poslo_batch_job* jobs, uint32_t njobs,
+                       const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes, const uint8_t* sigs,
+                       int distill, const poslo_tuning* tuning, void* stream, uint8_t* accept, uint64_t* invalid,
+                       size_t cap, size_t* n_invalid);
+
+/* Time every applicable variant and grid size on this batch (reps timed
+ * runs each, after one untimed run whose verdicts must match the first
+ * candidate's), cache the fastest for the batch's shape class (instantiation,
+ * log2 mean message length, log2 entry count) and return it.  E_DEVICE if
+ * two candidates disagree on a verdict. */
+int poslo_autotune_batch(poslo_ctx* ctx, const poslo_params* params, const poslo_batch_job* jobs, uint32_t njobs,
+                         const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes, int reps, void* stream,
+                         poslo_tuning* best, double* best_ms);
+
+/* Drop the context's captured graphs and tuning cache. */
+int poslo_batch_forget(poslo_ctx* ctx);
 
 #ifdef __cplusplus
 }

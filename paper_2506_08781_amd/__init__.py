@@ -38,7 +38,23 @@ class poslo_params(ctypes.Structure):
 
 class poslo_msgs(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("msg_len", ctypes.c_uint64),
-                ("n", ctypes.c_uint64), ("t0", ctypes.c_uint64)]
+                ("n", ctypes.c_uint64), ("t0", ctypes.c_uint64), ("data_bytes", ctypes.c_uint64)]
+
+
+class poslo_sign_job(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("t0", ctypes.c_uint64),
+                ("n", ctypes.c_uint64), ("entry_base", ctypes.c_uint64)]
+
+
+class poslo_batch_job(ctypes.Structure):
+    _fields_ = [("pk", ctypes.c_void_p), ("ds", ctypes.c_void_p), ("ds_len", ctypes.c_size_t),
+                ("tag", ctypes.c_void_p), ("t0", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("entry_base", ctypes.c_uint64)]
+
+
+class poslo_tuning(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
 
 def make_params(inst: int, log2_n1: int, log2_n2: int, bpv_v: int = 1024, bpv_k: int = 16) -> poslo_params:
@@ -100,6 +116,18 @@ def lib():
             "poslo_ccd_free": ([_VP], None),
             "poslo_sebver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _VP, ctypes.c_char, _VP, _SZ, P(_SZ),
                               _VP], _I),
+            "poslo_synth_messages": ([_U32, P(poslo_msgs), _VP, _VP], _I),
+            "poslo_gpu_keys_create": ([_VP, P(poslo_params), _U8P, _U32, P(_VP), _VP], _I),
+            "poslo_gpu_keys_free": ([_VP], None),
+            "poslo_gpu_sign": ([_VP, P(poslo_sign_job), _U32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
+            "poslo_ctx_keys_load": ([_VP, _U8P, _SZ, P(_SZ)], _I),
+            "poslo_batch_variant_count": ([], _I),
+            "poslo_batch_variant_name": ([_I], ctypes.c_char_p),
+            "poslo_verify_batch": ([_VP, P(poslo_params), P(poslo_batch_job), _U32, _VP, _VP, _U64, _VP, _I,
+                                    P(poslo_tuning), _VP, _VP, _VP, _SZ, P(_SZ)], _I),
+            "poslo_autotune_batch": ([_VP, P(poslo_params), P(poslo_batch_job), _U32, _VP, _VP, _U64, _I, _VP,
+                                      P(poslo_tuning), P(ctypes.c_double)], _I),
+            "poslo_batch_forget": ([_VP], _I),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(L, name)
@@ -291,9 +319,9 @@ def make_msgs(data, offsets=None, msg_len: int = 0, n: int | None = None, t0: in
             if n is None:
                 raise ValueError("n is required for a flat fixed-length buffer")
             n_, L = n, msg_len
-        return poslo_msgs(data.data_ptr() if data.numel() else None, None, L, n_, t0)
+        return poslo_msgs(data.data_ptr() if data.numel() else None, None, L, n_, t0, data.numel())
     n_ = offsets.numel() - 1
-    return poslo_msgs(data.data_ptr() if data.numel() else None, offsets.data_ptr(), 0, n_, t0)
+    return poslo_msgs(data.data_ptr() if data.numel() else None, offsets.data_ptr(), 0, n_, t0, data.numel())
 
 
 def poslo_aver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ds: bytes, tag: bytes,
@@ -395,3 +423,154 @@ def poslo_sebver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, cc
                             mode.encode(), bits, cap, ctypes.byref(nb), _stream_ptr(stream))
     _check(st, "poslo_sebver")
     return [bool(b) for b in bits.raw[:nb.value]]
+
+
+# --------------------------------------------------- device-side test data
+
+def poslo_synth_messages(seed: int, msgs: poslo_msgs, out, stream=None) -> None:
+    """Fill out (CUDA uint8 tensor at the layout msgs describes) with the
+    seeded message bytes of entries t0 .. t0+n-1."""
+    _check(lib().poslo_synth_messages(seed, ctypes.byref(msgs), out.data_ptr() if out.numel() else None,
+                                      _stream_ptr(stream)), "poslo_synth_messages")
+
+
+class GpuKeys:
+    """Owns a poslo_gpu_keys* (signing keys held on the device)."""
+
+    def __init__(self, handle, pks: list[bytes]):
+        self.handle = ctypes.c_void_p(handle)
+        self.pks = pks
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.poslo_gpu_keys_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
+def poslo_gpu_keys_create(ctx: Ctx, params: poslo_params, seeds: list[bytes]) -> GpuKeys:
+    n = len(seeds)
+    blob = b"".join(bytes(s) for s in seeds)
+    if len(blob) != 32 * n:
+        raise ValueError("seeds must be 32 bytes each")
+    pks = ctypes.create_string_buffer(max(1, 32 * n))
+    h = ctypes.c_void_p()
+    _check(lib().poslo_gpu_keys_create(ctx.handle, ctypes.byref(params), blob, n, ctypes.byref(h), pks),
+           "poslo_gpu_keys_create")
+    return GpuKeys(h.value, [pks.raw[32 * k:32 * k + 32] for k in range(n)])
+
+
+DS_STRIDE = 1 + 32 * 24
+
+
+def poslo_gpu_sign(keys: GpuKeys, jobs: list[tuple[int, int, int, int]], data, offsets, sigs,
+                   want_ds: bool = True, stream=None):
+    """Sign jobs (key, t0, n, entry_base) on the device.  data/offsets/sigs:
+    CUDA tensors (sigs: uint8, 80 per global entry).  Returns (tags, ds)
+    lists of bytes, one per job."""
+    nj = len(jobs)
+    arr = (poslo_sign_job * max(1, nj))()
+    for k, (key, t0, n, base) in enumerate(jobs):
+        arr[k] = poslo_sign_job(key, 0, t0, n, base)
+    tags = ctypes.create_string_buffer(max(1, 64 * nj))
+    ds = ctypes.create_string_buffer(max(1, DS_STRIDE * nj)) if want_ds else None
+    st = lib().poslo_gpu_sign(keys.handle, arr, nj, data.data_ptr() if data.numel() else None,
+                              offsets.data_ptr(), sigs.data_ptr() if sigs.numel() else None, tags, ds,
+                              DS_STRIDE, _stream_ptr(stream))
+    _check(st, "poslo_gpu_sign")
+    out_tags = [tags.raw[64 * k:64 * k + 64] for k in range(nj)]
+    out_ds = None
+    if want_ds:
+        raw = ds.raw
+        out_ds = []
+        for k in range(nj):
+            rec = raw[DS_STRIDE * k:DS_STRIDE * (k + 1)]
+            out_ds.append(rec[:1 + 24 * rec[0]])
+    return out_tags, out_ds
+
+
+# --------------------------------------------------- many signers per launch
+
+def poslo_ctx_keys_load(ctx: Ctx, pks: list[bytes]) -> int:
+    """Make the keys device-resident; returns the number of non-point keys."""
+    blob = b"".join(bytes(p) for p in pks)
+    bad = ctypes.c_size_t()
+    st = lib().poslo_ctx_keys_load(ctx.handle, blob, len(pks), ctypes.byref(bad))
+    if st not in (POSLO_OK, POSLO_E_ENCODING):
+        _check(st, "poslo_ctx_keys_load")
+    return bad.value
+
+
+def poslo_batch_variant_count() -> int:
+    return lib().poslo_batch_variant_count()
+
+
+def poslo_batch_variant_name(v: int) -> str:
+    r = lib().poslo_batch_variant_name(v)
+    if r is None:
+        raise ValueError(f"no batch variant {v}")
+    return r.decode()
+
+
+class BatchJobs:
+    """A ctypes job table plus the host buffers it points into."""
+
+    def __init__(self, jobs: list[dict]):
+        self._keep = []
+        self.n = len(jobs)
+        self.arr = (poslo_batch_job * max(1, self.n))()
+        for k, j in enumerate(jobs):
+            pk = ctypes.create_string_buffer(bytes(j["pk"]), 32)
+            tag = ctypes.create_string_buffer(bytes(j["tag"]), 64)
+            dsb = bytes(j["ds"])
+            ds = ctypes.create_string_buffer(dsb, max(1, len(dsb)))
+            self._keep += [pk, tag, ds]
+            self.arr[k] = poslo_batch_job(ctypes.addressof(pk), ctypes.addressof(ds), len(dsb),
+                                          ctypes.addressof(tag), j["t0"], j["n"], j["entry_base"])
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, poslo_tuning):
+        return ctypes.byref(t)
+    variant, wg, graph = t
+    return ctypes.byref(poslo_tuning(variant, wg, 1 if graph else 0, 0))
+
+
+def poslo_verify_batch(ctx: Ctx, params: poslo_params, jobs: BatchJobs, data, offsets, sigs=None,
+                       distill: int = 1, tuning=None, stream=None, cap: int | None = None):
+    """AVer of every job in one launch.  With sigs, distill = 1 verifies the
+    entries of rejected jobs individually, 2 those of every job.  Returns
+    (accept list, sorted invalid (job, t) list, or None without sigs)."""
+    acc = ctypes.create_string_buffer(max(1, jobs.n))
+    n_inv = ctypes.c_size_t()
+    mode = distill if sigs is not None else 0
+    cap = (4096 if cap is None else cap) if mode else 0
+    inv = (ctypes.c_uint64 * max(2, 2 * cap))()
+    st = lib().poslo_verify_batch(ctx.handle, ctypes.byref(params), jobs.arr, jobs.n,
+                                  data.data_ptr() if data.numel() else None, offsets.data_ptr(), data.numel(),
+                                  sigs.data_ptr() if mode and sigs.numel() else None, mode,
+                                  _tuning(tuning), _stream_ptr(stream), acc, inv, cap,
+                                  ctypes.byref(n_inv) if mode else None)
+    _check(st, "poslo_verify_batch")
+    accept = [bool(b) for b in acc.raw[:jobs.n]]
+    if not mode:
+        return accept, None
+    if n_inv.value > cap:
+        return poslo_verify_batch(ctx, params, jobs, data, offsets, sigs, distill, tuning, stream, cap=n_inv.value)
+    return accept, [(int(inv[2 * k]), int(inv[2 * k + 1])) for k in range(n_inv.value)]
+
+
+def poslo_autotune_batch(ctx: Ctx, params: poslo_params, jobs: BatchJobs, data, offsets, reps: int = 3,
+                         stream=None) -> tuple[poslo_tuning, float]:
+    best = poslo_tuning()
+    ms = ctypes.c_double()
+    st = lib().poslo_autotune_batch(ctx.handle, ctypes.byref(params), jobs.arr, jobs.n,
+                                    data.data_ptr() if data.numel() else None, offsets.data_ptr(), data.numel(),
+                                    reps, _stream_ptr(stream), ctypes.byref(best), ctypes.byref(ms))
+    _check(st, "poslo_autotune_batch")
+    return best, ms.value
+
+
+def poslo_batch_forget(ctx: Ctx) -> None:
+    _check(lib().poslo_batch_forget(ctx.handle), "poslo_batch_forget")

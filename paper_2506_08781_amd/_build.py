@@ -14,7 +14,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposlo.so")
 
-SOURCES = ["verifier.hip", "agg_aes.hip", "distill.hip", "batched.hip", "server.hip", "signer.hip"]
+SOURCES = [
+    "verifier.hip", "agg_aes.hip", "distill.hip", "keys.hip", "batched.hip", "server.hip", "signer.hip",
+    "signer_gpu.hip", "synth_gen.hip",
+]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POSLO_OFFLOAD_ARCH", "gfx950")

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <list>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -38,7 +39,7 @@ size_t agg_aes_lds_bytes(int v);
 struct KeyEntry {
     std::string pk;
     uint32_t* d_table = nullptr;  // comb table of Y on the device
-    ge Y;
+    std::shared_ptr<void> slab;   // allocation holding d_table (shared by a bulk load)
 };
 
 }  // namespace poslo
@@ -68,8 +69,8 @@ struct poslo_ctx {
     std::list<poslo::KeyEntry> keys;  // front = most recent
     std::unordered_map<std::string, std::list<poslo::KeyEntry>::iterator> key_index;
     // scratch slots of the Distill / SeBVer / batched entry points
-    uint32_t* xbuf[16] = {};
-    size_t xbuf_words[16] = {};
+    uint32_t* xbuf[32] = {};
+    size_t xbuf_words[32] = {};
 };
 
 namespace poslo {
@@ -84,6 +85,13 @@ void prof_collect(poslo_ctx* c);
 // device comb table of the key (built on the host on first use); nullptr and
 // *status = POSLO_E_ENCODING if pk is not a point encoding
 const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
+// device comb tables of many keys (built on the device for the missing
+// ones); tables[k] is key k's table.  Keys that are not point encodings get
+// nullptr and are counted in *n_bad (the call then returns E_ENCODING).
+// Keys of one call are never evicted by that call.
+int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad);
+// per-context state of the multi-signer path, released with the context
+void batch_release(poslo_ctx* c);
 // host comb table: t[w][d] = d * 16^w * P as 32-word points
 void build_comb_table(const ge& P, std::vector<uint32_t>& out);
 

@@ -19,6 +19,7 @@ struct BatchArgs {
     uint32_t log2_n2;
     const uint32_t* tab;   // per-epoch table, kEpochWords each
     const uint32_t* skip;  // optional bitmap over batch positions
+    const uint8_t* end;    // end of the data buffer, or nullptr when unknown
 };
 
 struct EntryView {

@@ -1,0 +1,145 @@
+// Per-entry work for variable-length, arbitrarily aligned messages, and the
+// individual verification of one entry (the Distill / SeBVer check).
+#pragma once
+
+#include "device_ec.h"
+#include "device_entry.h"
+
+namespace poslo {
+
+// Message bytes [o, o + 4*nw) of an entry as little-endian words (o + 4*nw
+// <= L).  Aligned words are loaded directly; otherwise nw + 1 aligned words
+// are funnel-shifted with v_alignbyte_b32.  `end` bounds the buffer, so no
+// load reaches past it.
+template <int NW>
+__device__ __forceinline__ void load_msg_words(const uint8_t* m, uint64_t o, const uint8_t* end, uint32_t w[NW]) {
+    const uint8_t* A = m + o;
+    uintptr_t a = (uintptr_t)A;
+    uint32_t sh = (uint32_t)(a & 3u);
+    const uint32_t* base = reinterpret_cast<const uint32_t*>(a - sh);
+    if (sh == 0) {
+#pragma unroll
+        for (int k = 0; k < NW; k++) w[k] = base[k];
+    } else if (reinterpret_cast<const uint8_t*>(base + NW + 1) <= end) {
+        uint32_t d[NW + 1];
+#pragma unroll
+        for (int k = 0; k <= NW; k++) d[k] = base[k];
+#pragma unroll
+        for (int k = 0; k < NW; k++) w[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; k++) w[k] = load_le32(A + 4 * k);
+    }
+}
+
+// MDC-2 over m || x for any length and alignment, with a table reader T
+template <class T, class AesBlock>
+__device__ __forceinline__ void digest_mdc2_any(const T& tb, const EntryView& v, const uint8_t* end,
+                                                const uint32_t x[4], uint32_t dig[8], AesBlock blockfn) {
+    uint32_t h[4], hp[4];
+    uint64_t nfull = v.L / 16, b = 0;
+    for (; b < nfull; b++) {
+        uint32_t m[4];
+        load_msg_words<4>(v.m, 16 * b, end, m);
+        blockfn(tb, h, hp, m, b == 0);
+    }
+    uint64_t nb = (v.L + 16 + 15) / 16;
+    for (; b < nb; b++) {
+        uint32_t m[4];
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) word |= stream_byte_aes(v, x, 16 * b + 4 * w + k) << (8 * k);
+            m[w] = word;
+        }
+        blockfn(tb, h, hp, m, b == 0);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        dig[w] = h[w];
+        dig[4 + w] = hp[w];
+    }
+}
+
+// one MDC-2 block with the generic T-table reader
+struct Mdc2BlockGeneric {
+    template <class T>
+    __device__ __forceinline__ void operator()(const T& tb, uint32_t h[4], uint32_t hp[4], const uint32_t m[4],
+                                               bool first) const {
+        uint32_t sa[4] = {m[0], m[1], m[2], m[3]}, sb[4] = {m[0], m[1], m[2], m[3]};
+        if (first) {
+            aes128_encrypt_rk(tb, c_iv.a, sa);
+            aes128_encrypt_rk(tb, c_iv.b, sb);
+        } else {
+            aes128_encrypt2_otf(tb, h, sa, hp, sb);
+        }
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            sa[w] ^= m[w];
+            sb[w] ^= m[w];
+        }
+        h[0] = sa[0], h[1] = sa[1], h[2] = sb[2], h[3] = sb[3];
+        hp[0] = sb[0], hp[1] = sb[1], hp[2] = sa[2], hp[3] = sa[3];
+    }
+};
+
+// SHA-256(m || x) for any length and alignment (xw: big-endian words of x_t)
+__device__ __forceinline__ void digest_sha_any(const EntryView& v, const uint8_t* end, const uint32_t xw[4],
+                                               uint32_t dig[8]) {
+    uint64_t total = ((v.L + 16 + 9 + 63) / 64) * 64;
+    uint32_t H[8];
+    sha256_init(H);
+    uint64_t off = 0;
+    for (; off + 64 <= v.L; off += 64) {
+        uint32_t W[16];
+        load_msg_words<16>(v.m, off, end, W);
+#pragma unroll
+        for (int w = 0; w < 16; w++) W[w] = bswap32(W[w]);
+        sha256_compress(H, W);
+    }
+    for (; off < total; off += 64) {
+        uint32_t W[16];
+#pragma unroll
+        for (int w = 0; w < 16; w++) W[w] = sha_stream_word<false>(v, xw, off + 4 * w, total);
+        sha256_compress(H, W);
+    }
+#pragma unroll
+    for (int w = 0; w < 8; w++) dig[w] = bswap32(H[w]);
+}
+
+// Individual verification of the entry at batch position pos with signature
+// bytes sg (80): x_t equals the re-derived one-time seed, s_t < q, and
+// encode(e_t*Y + s_t*G) equals the R_t bytes.  On success e (mod q) and s are
+// returned.
+template <class T>
+__device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
+                                           uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg,
+                                           uint32_t e[8], uint32_t s[8]) {
+    uint32_t x[4], xs[4];
+    for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
+    EntryView ev = entry_view(a, pos);
+    uint32_t dig[8];
+    if (inst == INST_AES) {
+        one_time_seed_aes(tb, a, pos, x);
+        if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
+        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+        if (!sc_is_canonical(s)) return false;
+        digest_mdc2_any(tb, ev, end, x, dig, Mdc2BlockGeneric{});
+    } else {
+        one_time_seed_sha(a, pos, x);  // big-endian words of the bytes of x_t
+        if ((bswap32(x[0]) ^ xs[0]) | (bswap32(x[1]) ^ xs[1]) | (bswap32(x[2]) ^ xs[2]) | (bswap32(x[3]) ^ xs[3]))
+            return false;
+        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+        if (!sc_is_canonical(s)) return false;
+        digest_sha_any(ev, end, x, dig);
+    }
+    sc_reduce256(e, dig);
+    ge P;
+    lane_double_scalar(P, ty, tg, e, s);
+    uint32_t r[8];
+    for (int k = 0; k < 8; k++) r[k] = load_le32(sg + 32 + 4 * k);
+    return ge_encodes_to(P, r);
+}
+
+}  // namespace poslo

@@ -25,6 +25,7 @@
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
+#include "device_verify.h"
 #include "scheme_host.h"
 
 namespace poslo {
@@ -59,35 +60,10 @@ struct VerifyArgs {
     uint32_t* tile_part;   // 18 words per tile: lazy sums of e_t and s_t over valid entries
 };
 
-// individual verification of the entry at batch position pos; on success
-// e (mod q) and s are returned for the aggregates
+// individual verification of the entry at batch position pos (device_verify.h)
 __device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const VerifyArgs& v, uint64_t pos,
                                              const uint8_t* sg, uint32_t e[8], uint32_t s[8]) {
-    const BatchArgs& a = v.a;
-    uint32_t x[4], xs[4];
-    for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
-    EntryView ev = entry_view(a, pos);
-    uint32_t dig[8];
-    if (v.inst == INST_AES) {
-        one_time_seed_aes(tb, a, pos, x);
-        if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
-        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
-        if (!sc_is_canonical(s)) return false;
-        digest_mdc2<false>(tb, ev, x, dig);
-    } else {
-        one_time_seed_sha(a, pos, x);  // big-endian words of the bytes of x_t
-        if ((bswap32(x[0]) ^ xs[0]) | (bswap32(x[1]) ^ xs[1]) | (bswap32(x[2]) ^ xs[2]) | (bswap32(x[3]) ^ xs[3]))
-            return false;
-        for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
-        if (!sc_is_canonical(s)) return false;
-        digest_sha<false>(ev, x, dig);
-    }
-    sc_reduce256(e, dig);
-    ge P;
-    lane_double_scalar(P, v.ty, v.tg, e, s);
-    uint32_t r[8];
-    for (int k = 0; k < 8; k++) r[k] = load_le32(sg + 32 + 4 * k);
-    return ge_encodes_to(P, r);
+    return verify_one(tb, v.a, v.a.end, v.inst, pos, sg, v.ty, v.tg, e, s);
 }
 
 __global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v) {
@@ -142,10 +118,10 @@ __global__ __launch_bounds__(kTile) void k_ekeys_tiles(BatchArgs a, TileGeom g, 
         EntryView ev = entry_view(a, pos);
         if (inst == INST_AES) {
             one_time_seed_aes(tb, a, pos, x);
-            digest_mdc2<false>(tb, ev, x, dig);
+            digest_mdc2_any(tb, ev, a.end, x, dig, Mdc2BlockGeneric{});
         } else {
             one_time_seed_sha(a, pos, x);
-            digest_sha<false>(ev, x, dig);
+            digest_sha_any(ev, a.end, x, dig);
         }
         acc288_add256(acc, dig);
     }

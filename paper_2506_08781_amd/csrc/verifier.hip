@@ -188,7 +188,7 @@ int ctx_ensure(uint32_t** buf, size_t* have, size_t words) {
 }
 
 int ctx_scratch(poslo_ctx* c, int slot, size_t bytes, void** out) {
-    if (slot < 0 || slot >= 16) return POSLO_E_INVAL;
+    if (slot < 0 || slot >= 32) return POSLO_E_INVAL;
     int st = ctx_ensure(&c->xbuf[slot], &c->xbuf_words[slot], (bytes + 3) / 4);
     if (st) return st;
     *out = c->xbuf[slot];
@@ -256,27 +256,28 @@ const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status) {
     }
     KeyEntry ke;
     ke.pk = id;
-    if (!ge_decode(ke.Y, pk)) {
+    ge Y;
+    if (!ge_decode(Y, pk)) {
         *status = POSLO_E_ENCODING;
         return nullptr;
     }
     std::vector<uint32_t> tab;
-    build_comb_table(ke.Y, tab);
+    build_comb_table(Y, tab);
     if (c->keys.size() >= c->key_cap) {
         // evict the least recently used key; its table may still be read by
         // queued work, so wait for the device first
         hipDeviceSynchronize();
-        KeyEntry& old = c->keys.back();
-        hipFree(old.d_table);
-        c->key_index.erase(old.pk);
+        c->key_index.erase(c->keys.back().pk);
         c->keys.pop_back();
     }
-    if (hipMalloc((void**)&ke.d_table, tab.size() * 4) != hipSuccess) {
+    void* d = nullptr;
+    if (hipMalloc(&d, tab.size() * 4) != hipSuccess) {
         *status = POSLO_E_NOMEM;
         return nullptr;
     }
+    ke.slab = std::shared_ptr<void>(d, [](void* q) { hipFree(q); });
+    ke.d_table = (uint32_t*)d;
     if (hipMemcpy(ke.d_table, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(ke.d_table);
         *status = POSLO_E_DEVICE;
         return nullptr;
     }
@@ -337,8 +338,10 @@ extern "C" void poslo_ctx_destroy(poslo_ctx* c) {
     if (c->d_result) hipFree(c->d_result);
     if (c->h_result) hipHostFree(c->h_result);
     if (c->d_gtable) hipFree(c->d_gtable);
-    for (auto& k : c->keys) hipFree(k.d_table);
-    for (int k = 0; k < 16; k++)
+    batch_release(c);
+    c->key_index.clear();
+    c->keys.clear();
+    for (int k = 0; k < 32; k++)
         if (c->xbuf[k]) hipFree(c->xbuf[k]);
     for (int k = 0; k < kKtCount; k++)
         for (int e = 0; e < 2; e++)
@@ -412,6 +415,12 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     a.log2_n2 = prm->log2_n2;
     a.skip = nullptr;
     a.tab = nullptr;
+    if (m->data_bytes)
+        a.end = m->data + m->data_bytes;
+    else if (!m->offsets)
+        a.end = m->data + m->n * m->msg_len;
+    else
+        a.end = nullptr;
     n_epochs = 0;
     a.epoch_first = m->t0 >> prm->log2_n2;
     if (m->n == 0) return POSLO_OK;

@@ -1,0 +1,111 @@
+"""Seeded synthetic workloads built on the device through the C ABI.
+
+Messages come from the device generator (same bytes as ``synthlog``),
+signatures, tags and ds from the device signer (same bytes as the host
+signer), corruption positions from ``synthlog``'s seeded plans.  Used by the
+benchmark and the large GPU tests; nothing here verifies anything.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import synthlog
+
+from . import (BatchJobs, make_params, poslo_gpu_keys_create, poslo_gpu_sign, poslo_msgs,
+               poslo_synth_messages)
+
+
+@dataclass
+class MultiSignerLog:
+    params: object
+    counts: list[int]               # entries per signer
+    lengths: np.ndarray             # message length per global entry
+    offsets: np.ndarray             # uint64, total + 1
+    data: object                    # CUDA uint8 tensor (message bytes)
+    d_offsets: object               # CUDA int64 tensor
+    sigs: object                    # CUDA uint8 tensor, 80 per entry
+    pks: list[bytes]
+    jobs: list[dict]                # pk, ds, tag, t0, n, entry_base, key
+    plan: list[tuple[int, int]] = field(default_factory=list)  # (entry, bit) flips applied
+
+    @property
+    def total(self) -> int:
+        return int(self.offsets.size - 1)
+
+    def batch_jobs(self) -> BatchJobs:
+        return BatchJobs(self.jobs)
+
+    def job_of_entry(self, e: int) -> int:
+        return int(np.searchsorted(self.bases, e, side="right") - 1)
+
+    @property
+    def bases(self) -> np.ndarray:
+        return np.array([j["entry_base"] for j in self.jobs], dtype=np.int64)
+
+
+def _flip(torch, log: MultiSignerLog, plan):
+    """Flip one bit of m_t || sigma_t per planned entry, on the device."""
+    if not plan:
+        return
+    msg_idx, msg_mask, sig_idx, sig_mask = [], [], [], []
+    for e, bit in plan:
+        L = int(log.lengths[e])
+        if bit < 8 * L:
+            msg_idx.append(int(log.offsets[e]) + bit // 8)
+            msg_mask.append(1 << (bit % 8))
+        else:
+            b = bit - 8 * L
+            sig_idx.append(80 * e + b // 8)
+            sig_mask.append(1 << (b % 8))
+    dev = log.data.device
+    for buf, idx, mask in ((log.data, msg_idx, msg_mask), (log.sigs, sig_idx, sig_mask)):
+        if idx:
+            it = torch.tensor(idx, dtype=torch.int64, device=dev)
+            mt = torch.tensor(mask, dtype=torch.uint8, device=dev)
+            buf[it] = buf[it] ^ mt
+
+
+def multi_signer(ctx, inst: int, n_signers: int, max_batch: int, len_lo: int, len_hi: int,
+                 corrupt_frac: float, seed: int, log2_n1: int = 8, log2_n2: int = 8,
+                 counts: list[int] | None = None) -> MultiSignerLog:
+    """n_signers fresh signers, signer k with a log-uniform [1, max_batch]
+    entry count (or counts[k]), messages of uniform [len_lo, len_hi] bytes,
+    each signer's batch signed from t = 0 and aggregated into one tag; then
+    round(corrupt_frac * total) distinct entries get one flipped bit,
+    uniform over the 8 (L + 80) bits of m_t || sigma_t."""
+    import torch
+
+    params = make_params(inst, log2_n1, log2_n2)
+    if counts is None:
+        counts = synthlog.log_uniform_counts(seed, 0, n_signers, max_batch)
+    counts = [int(c) for c in counts]
+    total = sum(counts)
+    lengths = synthlog.uniform_per_stream(seed + 1, np.arange(total), len_lo, len_hi)
+    offsets = np.zeros(total + 1, dtype=np.uint64)
+    np.cumsum(lengths, out=offsets[1:])
+    nbytes = int(offsets[-1])
+    dev = torch.device("cuda", ctx.device)
+    d_off = torch.from_numpy(offsets.view(np.int64)).to(dev)
+    data = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
+    poslo_synth_messages(seed + 2, poslo_msgs(data.data_ptr(), d_off.data_ptr(), 0, total, 0, nbytes), data)
+    seeds = [synthlog.derived_key_seed(seed + 3, k) for k in range(n_signers)]
+    keys = poslo_gpu_keys_create(ctx, params, seeds)
+    bases = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64) if counts else np.zeros(0, np.int64)
+    sjobs = [(k, 0, counts[k], int(bases[k])) for k in range(n_signers)]
+    sigs = torch.empty(max(1, 80 * total), dtype=torch.uint8, device=dev)
+    tags, ds = poslo_gpu_sign(keys, sjobs, data[:nbytes], d_off, sigs)
+    jobs = [dict(key=k, pk=keys.pks[k], ds=ds[k], tag=tags[k], t0=0, n=counts[k], entry_base=int(bases[k]))
+            for k in range(n_signers)]
+    del keys
+    log = MultiSignerLog(params=params, counts=counts, lengths=lengths, offsets=offsets, data=data[:nbytes],
+                         d_offsets=d_off, sigs=sigs[:80 * total], pks=[j["pk"] for j in jobs], jobs=jobs)
+    k = int(round(corrupt_frac * total))
+    if k:
+        bits = 8 * (lengths.astype(np.int64) + 80)
+        log.plan = synthlog.corruption_plan_var(seed + 4, total, k, bits)
+        _flip(torch, log, log.plan)
+    torch.cuda.synchronize(dev)
+    return log

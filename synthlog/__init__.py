@@ -184,6 +184,16 @@ def messages_var(seed: int, lengths: np.ndarray, t0: int = 0):
     return data, offsets
 
 
+def uniform_per_stream(seed: int, sids: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """One integer in [lo, hi] per stream: lo + floor(u * (hi - lo + 1)) with
+    u = (first output >> 11) * 2^-53 of stream (seed, sid).  Vectorised; each
+    value depends only on its own stream, so any entry's value can be drawn
+    independently (the device generator computes the same values)."""
+    w = stream_words(seed, np.asarray(sids, dtype=np.uint64), 1)[:, 0]
+    u = (w >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    return (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
+
+
 def uniform_ints(seed: int, sid: int, n: int, lo: int, hi: int) -> list[int]:
     """n uniform integers in [lo, hi] from stream (seed, sid)."""
     g = Xoshiro256ss(stream_seed(seed, sid))
@@ -225,6 +235,16 @@ def corruption_plan(seed: int, n: int, k: int, bits_per_entry: int):
     entries = sample_distinct(seed, 0, n, k)
     g = Xoshiro256ss(stream_seed(seed, 1))
     plan = [(e, g.below(bits_per_entry)) for e in entries]
+    plan.sort()
+    return plan
+
+
+def corruption_plan_var(seed: int, n: int, k: int, bits) -> list[tuple[int, int]]:
+    """As corruption_plan, with entry e's bit drawn uniform over bits[e] bits
+    (entries of different lengths)."""
+    entries = sample_distinct(seed, 0, n, k)
+    g = Xoshiro256ss(stream_seed(seed, 1))
+    plan = [(e, g.below(int(bits[e]))) for e in entries]
     plan.sort()
     return plan
 

@@ -1,0 +1,285 @@
+"""GPU parity of the multi-signer path (many signers' batches in one
+persistent launch), the device signer and the device message generator,
+through the C ABI.
+
+Small cases: several signers with jobs of uneven sizes (including empty and
+single-entry jobs, jobs starting mid-epoch and jobs of one key at different
+t), variable-length messages (0 to 100 bytes, any alignment), signed by the
+oracle.  The device signer must reproduce the oracle's signatures, tags and
+ds byte for byte; the batch verifier's accept bits must equal the oracle's
+AVer per job and its invalid (job, t) pairs the oracle's Distill on every
+rejected job, for every kernel variant, with and without graph replay.
+Large case: 4,096 signers with log-uniform [1, 65,536] entries of [64, 512]
+bytes and 0.1% corrupted entries; accept bits and the invalid set must equal
+what the injected corruption fixes, and sampled entries are re-verified one
+by one by the oracle."""
+
+import functools
+
+import numpy as np
+import pytest
+
+import synthlog
+
+pytestmark = pytest.mark.gpu
+
+KEYS = 3
+L1, L2 = 4, 3
+# (key, t0, n); each key's jobs are consecutive in t
+JOBS = [(0, 0, 37), (1, 0, 1), (2, 20, 50), (0, 37, 0), (0, 37, 26), (1, 1, 90)]
+
+
+@pytest.fixture(scope="module")
+def gpu(P):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    ctx = P.poslo_ctx_create(0)
+    yield torch, ctx
+    ctx.close()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_jobs(inst):
+    """Messages, keys and the oracle's signatures, tags and ds of JOBS."""
+    from oracle import oracle as O
+    prm = O.Params(inst, L1, L2)
+    total = sum(n for _, _, n in JOBS)
+    lens = synthlog.uniform_per_stream(31, np.arange(total), 0, 100)
+    data, off = synthlog.messages_var(32, lens)
+    msgs = [bytes(data[off[e]:off[e + 1]]) for e in range(total)]
+    seeds = [synthlog.derived_key_seed(50, k) for k in range(KEYS)]
+    signers, pks = {}, {}
+    for k in range(KEYS):
+        signers[k], pks[k] = O.kg(prm, seeds[k])
+    out, base = [], 0
+    for key, t0, n in JOBS:
+        s = signers[key]
+        while s.t < t0:
+            O.sig(s, b"")
+        assert s.t == t0
+        sg = [O.sig(s, msgs[base + p]) for p in range(n)]
+        out.append(dict(key=key, t0=t0, n=n, entry_base=base, pk=pks[key], sigs=sg, tag=O.agg(sg),
+                        ds=O.ds_encode(s.ds)))
+        base += n
+    return prm, seeds, data, off, msgs, out
+
+
+def to_dev(torch, data, off, sigs=b""):
+    d = torch.from_numpy(np.frombuffer(bytes(data), dtype=np.uint8).copy()).cuda()
+    o = torch.from_numpy(np.asarray(off, dtype=np.uint64).view(np.int64).copy()).cuda()
+    s = torch.from_numpy(np.frombuffer(bytes(sigs), dtype=np.uint8).copy()).cuda() if sigs else None
+    return d, o, s
+
+
+def test_device_messages_equal_generator(P, gpu):
+    torch, ctx = gpu
+    rng = np.random.default_rng(3)
+    lens = rng.integers(0, 300, 257)
+    lens[5], lens[6], lens[7] = 0, 1, 8
+    data, off = synthlog.messages_var(77, lens, t0=5)
+    out = torch.zeros(data.size, dtype=torch.uint8, device="cuda")
+    offs = torch.from_numpy(off.view(np.int64).copy()).cuda()
+    print("device generator: variable layout", flush=True)
+    P.poslo_synth_messages(77, P.poslo_msgs(None, offs.data_ptr(), 0, lens.size, 5, data.size), out)
+    assert out.cpu().numpy().tobytes() == data.tobytes()
+    want = synthlog.messages_fixed(78, 1000, 40, t0=3)
+    out2 = torch.zeros((1000, 40), dtype=torch.uint8, device="cuda")
+    print("device generator: fixed layout", flush=True)
+    P.poslo_synth_messages(78, P.poslo_msgs(None, None, 40, 1000, 3, 40000), out2)
+    assert np.array_equal(out2.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_gpu_signer_equals_oracle(P, gpu, inst):
+    torch, ctx = gpu
+    prm, seeds, data, off, msgs, jobs = oracle_jobs(inst)
+    params = P.make_params(inst, L1, L2)
+    print(f"inst {inst}: device keys", flush=True)
+    keys = P.poslo_gpu_keys_create(ctx, params, seeds)
+    for j in jobs:
+        assert keys.pks[j["key"]] == j["pk"]
+    d, o, _ = to_dev(torch, data, off)
+    total = len(msgs)
+    sigs = torch.zeros(80 * total, dtype=torch.uint8, device="cuda")
+    print(f"inst {inst}: device signer over {len(jobs)} jobs", flush=True)
+    tags, ds = P.poslo_gpu_sign(keys, [(j["key"], j["t0"], j["n"], j["entry_base"]) for j in jobs], d, o, sigs)
+    hs = sigs.cpu().numpy().tobytes()
+    for k, j in enumerate(jobs):
+        b = j["entry_base"]
+        got = [hs[80 * (b + p):80 * (b + p + 1)] for p in range(j["n"])]
+        assert got == j["sigs"], f"job {k}"
+        assert tags[k] == j["tag"], f"job {k}"
+        assert ds[k] == j["ds"], f"job {k}"
+
+
+def corrupted_inputs(inst, n_flips=6, tamper_tag_of=4):
+    """JOBS with seeded single-bit flips of m_t || sigma_t and one tampered
+    tag; returns the oracle's expected accept bits and (job, t) pairs."""
+    from oracle import oracle as O
+    prm, seeds, data, off, msgs, jobs = oracle_jobs(inst)
+    total = len(msgs)
+    sigs = [sg for j in jobs for sg in j["sigs"]]
+    lens = np.array([len(m) for m in msgs])
+    plan = synthlog.corruption_plan_var(90 + inst, total, n_flips, 8 * (lens + 80))
+    msgs, sigs = list(msgs), list(sigs)
+    for e, bit in plan:
+        blob = bytearray(msgs[e] + sigs[e])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        msgs[e], sigs[e] = bytes(blob[:lens[e]]), bytes(blob[lens[e]:])
+    jobs = [dict(j) for j in jobs]
+    if tamper_tag_of is not None:
+        t = bytearray(jobs[tamper_tag_of]["tag"])
+        t[5] ^= 0x10
+        jobs[tamper_tag_of]["tag"] = bytes(t)
+    want_acc, want_inv, want_all = [], [], []
+    for k, j in enumerate(jobs):
+        b, n = j["entry_base"], j["n"]
+        jm, js = msgs[b:b + n], sigs[b:b + n]
+        ok = O.aver(prm, j["pk"], jm, j["t0"], j["ds"], j["tag"])
+        want_acc.append(ok)
+        bad = [(k, t) for t, _ in O.distill(prm, j["pk"], jm, js, j["t0"], j["ds"], 1).invalid]
+        want_all += bad
+        if not ok:
+            want_inv += bad
+    return jobs, b"".join(msgs), off, b"".join(sigs), want_acc, sorted(want_inv), sorted(want_all), plan
+
+
+@functools.lru_cache(maxsize=None)
+def corrupted_case(inst):
+    return corrupted_inputs(inst)
+
+
+def variants_of(P, inst):
+    pre = "aes" if inst == 1 else "sha"
+    return [v for v in range(P.poslo_batch_variant_count()) if P.poslo_batch_variant_name(v).startswith(pre)]
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_verify_batch_equals_oracle(P, gpu, inst):
+    torch, ctx = gpu
+    jobs, data, off, sigs, want_acc, want_inv, want_all, plan = corrupted_case(inst)
+    # every flipped entry is invalid; only rejected jobs are distilled in mode 1
+    assert {e for e, _ in plan} == {jobs[k]["entry_base"] + (t - jobs[k]["t0"]) for k, t in want_all}
+    assert set(want_inv) <= set(want_all) and want_acc.count(False) >= 2
+    params = P.make_params(inst, L1, L2)
+    d, o, s = to_dev(torch, data, off, sigs)
+    bj = P.BatchJobs(jobs)
+    for v in variants_of(P, inst):
+        for graph in (False, True):
+            print(f"inst {inst}: variant {P.poslo_batch_variant_name(v)} graph {graph}", flush=True)
+            acc, inv = P.poslo_verify_batch(ctx, params, bj, d, o, s, tuning=(v, 0, graph))
+            assert acc == want_acc
+            assert inv == want_inv
+            acc2, inv2 = P.poslo_verify_batch(ctx, params, bj, d, o, None, tuning=(v, 0, graph))
+            assert acc2 == want_acc and inv2 is None
+            acc3, inv3 = P.poslo_verify_batch(ctx, params, bj, d, o, s, distill=2, tuning=(v, 0, graph))
+            assert acc3 == want_acc and inv3 == want_all
+    print(f"inst {inst}: default tuning", flush=True)
+    assert P.poslo_verify_batch(ctx, params, bj, d, o, s) == (want_acc, want_inv)
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_graph_replays_and_honest_jobs(P, gpu, inst):
+    """Replays of one captured graph, with unrelated eager work and
+    synchronizations between them, give the eager result every time; the
+    honest jobs all accept."""
+    torch, ctx = gpu
+    prm, seeds, data, off, msgs, jobs = oracle_jobs(inst)
+    sigs = b"".join(sg for j in jobs for sg in j["sigs"])
+    params = P.make_params(inst, L1, L2)
+    d, o, s = to_dev(torch, data, off, sigs)
+    bj = P.BatchJobs(jobs)
+    v = variants_of(P, inst)[0]
+    eager = P.poslo_verify_batch(ctx, params, bj, d, o, s, tuning=(v, 0, False))
+    assert eager == ([True] * len(jobs), [])
+    x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+    for r in range(4):
+        print(f"inst {inst}: graph replay {r}", flush=True)
+        assert P.poslo_verify_batch(ctx, params, bj, d, o, s, tuning=(v, 0, True)) == eager
+        x = (x * 1.0001).sin()
+        torch.cuda.synchronize()
+    # a tampered tag in a replayed shape flips only that job
+    jobs2 = [dict(j) for j in jobs]
+    t = bytearray(jobs2[2]["tag"])
+    t[0] ^= 1
+    jobs2[2]["tag"] = bytes(t)
+    acc, inv = P.poslo_verify_batch(ctx, params, P.BatchJobs(jobs2), d, o, s, tuning=(v, 0, True))
+    assert acc == [k != 2 for k in range(len(jobs))] and inv == []
+
+
+def test_autotune_picks_a_parity_variant(P, gpu):
+    torch, ctx = gpu
+    for inst in (1, 0):
+        jobs, data, off, sigs, want_acc, want_inv, _, _ = corrupted_case(inst)
+        params = P.make_params(inst, L1, L2)
+        d, o, s = to_dev(torch, data, off, sigs)
+        bj = P.BatchJobs(jobs)
+        print(f"inst {inst}: autotune", flush=True)
+        best, ms = P.poslo_autotune_batch(ctx, params, bj, d, o, reps=2)
+        assert best.variant in variants_of(P, inst) and ms > 0
+        assert P.poslo_verify_batch(ctx, params, bj, d, o, s) == (want_acc, want_inv)
+    P.poslo_batch_forget(ctx)
+
+
+def test_verify_batch_errors(P, gpu):
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, seeds, data, off, msgs, jobs = oracle_jobs(1)
+    params = P.make_params(1, L1, L2)
+    d, o, s = to_dev(torch, data, off, b"".join(sg for j in jobs for sg in j["sigs"]))
+    # a ds that does not cover the job's epochs
+    bad = [dict(j) for j in jobs]
+    bad[4]["ds"] = jobs[0]["ds"][:1 + 24 * 1]
+    bad[4]["ds"] = bytes([1]) + bad[4]["ds"][1:]
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_verify_batch(ctx, params, P.BatchJobs(bad), d, o, s)
+    assert ei.value.status == P.POSLO_E_SEED
+    # a public key that is not a point
+    y = 2
+    while O.decode(y.to_bytes(32, "little")) is not None:
+        y += 1
+    bad = [dict(j) for j in jobs]
+    bad[1]["pk"] = y.to_bytes(32, "little")
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_verify_batch(ctx, params, P.BatchJobs(bad), d, o, s)
+    assert ei.value.status == P.POSLO_E_ENCODING
+    assert P.poslo_ctx_keys_load(ctx, [jobs[0]["pk"], y.to_bytes(32, "little")]) == 1
+    # no jobs at all
+    assert P.poslo_verify_batch(ctx, params, P.BatchJobs([]), d, o, s) == ([], [])
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_full_size_multi_signer(P, gpu, inst):
+    """4,096 signers, log-uniform [1, 65,536] entries each, messages of
+    [64, 512] bytes, 0.1% of entries with one flipped bit."""
+    from oracle import oracle as O
+    from paper_2506_08781_amd import workloads
+    torch, ctx = gpu
+    print(f"inst {inst}: building the 4096-signer log on the device", flush=True)
+    log = workloads.multi_signer(ctx, inst, 4096, 65536, 64, 512, 0.001, seed=7000 + inst)
+    print(f"inst {inst}: {log.total} entries, {len(log.plan)} flips", flush=True)
+    bases = log.bases
+    flipped, msg_flipped = {}, set()
+    for e, bit in log.plan:
+        k = int(np.searchsorted(bases, e, side="right") - 1)
+        flipped.setdefault(k, []).append(e - int(bases[k]))
+        if bit < 8 * int(log.lengths[e]):
+            msg_flipped.add(k)
+    bj = log.batch_jobs()
+    acc, inv = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2)
+    print(f"inst {inst}: verified, {acc.count(False)} rejected, {len(inv)} invalid", flush=True)
+    # AVer reads messages, ds and tags: a job is rejected iff a message bit flipped
+    assert acc == [k not in msg_flipped for k in range(4096)]
+    assert inv == sorted((k, t) for k, ts in flipped.items() for t in ts)
+    # sampled entries re-verified one by one by the oracle
+    prm = O.Params(inst, 8, 8)
+    hs_idx = [e for e, _ in log.plan[:3]] + [int(bases[k]) for k in (0, 1, 4095) if k not in flipped]
+    for e in hs_idx:
+        k = int(np.searchsorted(bases, e, side="right") - 1)
+        j = log.jobs[k]
+        t = e - j["entry_base"]
+        L0, L1_ = int(log.offsets[e]), int(log.offsets[e + 1])
+        m = log.data[L0:L1_].cpu().numpy().tobytes()
+        sg = log.sigs[80 * e:80 * e + 80].cpu().numpy().tobytes()
+        x0 = O.SR(inst, O.ds_decode(j["ds"]), t >> 8)
+        assert O.entry_valid(prm, j["pk"], m, t, sg, x0) == (k not in flipped or t not in flipped[k])

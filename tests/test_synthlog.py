@@ -39,3 +39,21 @@ def test_sampling_helpers():
     assert min(c) >= 1 and max(c) <= 65536
     u = synthlog.uniform_ints(6, 0, 500, 64, 512)
     assert min(u) >= 64 and max(u) <= 512
+
+
+def test_uniform_per_stream():
+    v = synthlog.uniform_per_stream(9, np.arange(20000), 64, 512)
+    assert v.min() >= 64 and v.max() <= 512 and abs(v.mean() - 288) < 3
+    g = synthlog.Xoshiro256ss(synthlog.stream_seed(9, 17))
+    u = (g.next() >> 11) * (1.0 / (1 << 53))
+    assert v[17] == 64 + int(u * 449)
+
+
+def test_corruption_plan_var():
+    bits = np.array([8 * (L + 80) for L in range(1, 501)])
+    plan = synthlog.corruption_plan_var(12, 500, 40, bits)
+    assert len({e for e, _ in plan}) == 40
+    assert all(0 <= b < bits[e] for e, b in plan)
+    assert plan == sorted(plan)
+    # fixed bit counts reduce to the fixed-length plan
+    assert synthlog.corruption_plan_var(4, 1000, 10, np.full(1000, 64)) == synthlog.corruption_plan(4, 1000, 10, 64)

@@ -1,14 +1,22 @@
 #!/usr/bin/env python3
-"""Benchmark of POSLO-F batch verification on one MI355X.
+"""Benchmark of POSLO-F verification on one MI355X.
 
-A step is one aggregate verification (AVer) of a device-resident batch:
-seed table (SR/SC and the hoisted PRF state), the fused per-entry PRF +
-digest + lazy-sum kernel, and the final fold with the curve check.
+A step of the headline workload is one aggregate verification (AVer) of a
+device-resident batch: seed table (SR/SC and the hoisted PRF state), the
+fused per-entry PRF + digest + lazy-sum kernel, and the final fold with the
+curve check.  Headline workload: plain POSLO-F at the 128-bit parameter set,
+one signer, 2^20 entries of 256-byte messages (seeded xoshiro256** bytes),
+n2 = 256, n1 = 4096, POSLO+ instantiation (MMO-AES-128 PRF, MDC-2-AES-128
+hash), one aggregate tag over honest signatures.
 
-Default workload: plain POSLO-F at the 128-bit parameter set, one signer,
-2^20 entries of 256-byte messages (seeded xoshiro256** bytes), n2 = 256,
-n1 = 4096, POSLO+ instantiation (MMO-AES-128 PRF, MDC-2-AES-128 hash), one
-aggregate tag over honest signatures.  Prints one JSON line.
+The same run also measures, each on its own synthetic log:
+ - distill: Distill of 2^20 x 256-byte entries with 1% of entries carrying
+   one flipped bit of m_t || sigma_t (exact invalid set, CCD);
+ - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
+   [64, 512]-byte messages, 0.1% flipped entries, verified in one persistent
+   launch (autotuned) against the plain path (one AVer call per signer),
+   plus the invalid set of every signer (AVer + individual checks).
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -24,8 +32,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-import synthlog  # noqa: E402
-
 METRIC = "verified log entries/sec on 1 MI355X + p99 verify latency, batched vs plain"
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU work
@@ -33,11 +39,13 @@ INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 CONFIGS = {
-    "c1": dict(n=1024, L=32, log2_n1=2, log2_n2=8, key_first=0x00, msg_seed=1,
+    "c1": dict(n=1024, L=32, log2_n1=2, log2_n2=8, seed=1,
                name="plain AVer, 1,024 entries x 32 B, n2=256, n1=4"),
-    "c2": dict(n=1 << 20, L=256, log2_n1=12, log2_n2=8, key_first=0x20, msg_seed=2,
+    "c2": dict(n=1 << 20, L=256, log2_n1=12, log2_n2=8, seed=2,
                name="plain AVer, 2^20 entries x 256 B, n2=256, n1=4096"),
 }
+DISTILL = dict(n=1 << 20, L=256, log2_n1=12, log2_n2=8, seed=3, frac=0.01, umbrellas=64)
+BATCHED = dict(signers=4096, max_batch=65536, len_lo=64, len_hi=512, frac=0.001, seed=4, log2_n1=8, log2_n2=8)
 
 
 # ---------------------------------------------------------------------------
@@ -59,7 +67,8 @@ AES_OTF = AES_RK + 10 * 11        # with the schedule expanded on the fly
 SHA_COMP = 64 * 14 + 48 * 10 + 8
 
 
-def ops_per_entry(inst: int, L: int) -> int:
+def ops_per_entry(inst: int, L):
+    """Works on ints and numpy arrays of lengths."""
     if inst == 1:
         B = (L + 16 + 15) // 16
         # PRF (one AES + 1 xor), MDC-2 block 0 under the constant IV schedules,
@@ -71,44 +80,234 @@ def ops_per_entry(inst: int, L: int) -> int:
     return (1 + nb) * SHA_COMP + (L + 3) // 4 + 8 + 9
 
 
-def hash_calls_per_entry(inst: int, L: int) -> int:
+def hash_calls_per_entry(inst: int, L):
     """AES-128 block encryptions (POSLO+) or SHA-256 compressions (POSLO)."""
     if inst == 1:
         return 1 + 2 * ((L + 16 + 15) // 16)
     return 1 + (L + 16 + 9 + 63) // 64
 
 
+def pct(xs, p):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(p / 100 * (len(xs) - 1))))]
+
+
+def lat_summary(lat_s):
+    ms = [1e3 * x for x in lat_s]
+    return {"p50": pct(ms, 50), "p99": pct(ms, 99), "max": max(ms), "samples": len(ms)}
+
+
+def kernel_ms(P, ctx, k):
+    tot, n = P.poslo_ctx_kernel_time(ctx, k)
+    return tot / max(n, 1)
+
+
+def reset_times(P, ctx):
+    for k in range(8):
+        P.poslo_ctx_kernel_time(ctx, k, reset=True)
+
+
 # ---------------------------------------------------------------------------
 
 
-def build_inputs(P, cfg, inst):
-    arr = synthlog.messages_fixed(cfg["msg_seed"], cfg["n"], cfg["L"])
-    params = P.make_params(inst, cfg["log2_n1"], cfg["log2_n2"])
-    sk, pk = P.poslo_kg(params, synthlog.key_seed_bytes(cfg["key_first"]))
-    sigs = P.poslo_sig_batch(sk, arr)
-    ds = P.poslo_ds_export(sk)
-    tag = P.poslo_agg(sigs)
-    return arr, params, pk, sigs, ds, tag
-
-
-def cpu_baseline(cfg, inst, arr, pk, sigs, ds, P, target_s: float):
+def cpu_baseline(cfg, inst, log, target_s: float):
     """The oracle's AVer timed on host cores over a bounded leading slice of
     the same batch (same key, messages, ds), single-threaded."""
     from oracle import oracle as O
     prm = O.Params(inst, cfg["log2_n1"], cfg["log2_n2"])
-    # calibrate on 64 entries
-    cal = [bytes(r) for r in arr[:64]]
+    cal = [bytes(r) for r in log.data[:64].cpu().numpy()]
     t = time.perf_counter()
-    O.ekeys_sum(prm, cal, 0, ds)
+    O.ekeys_sum(prm, cal, 0, log.ds)
     per = (time.perf_counter() - t) / 64
     ns = int(max(64, min(cfg["n"], target_s / max(per, 1e-9))))
-    sample = [bytes(r) for r in arr[:ns]]
-    tag = P.poslo_agg(sigs[:ns])
+    sample = [bytes(r) for r in log.data[:ns].cpu().numpy()]
+    sg = log.sigs[:80 * ns].cpu().numpy().tobytes()
+    tag = O.agg([sg[80 * k:80 * k + 80] for k in range(ns)])
     t = time.perf_counter()
-    ok = O.aver(prm, pk, sample, 0, ds, tag)
+    ok = O.aver(prm, log.pk, sample, 0, log.ds, tag)
     dt = time.perf_counter() - t
     return {"value": ns / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle AVer over the first {ns} entries of the same batch ({dt:.1f} s, accept={ok})"}
+
+
+def bench_plain(P, torch, ctx, cfg, inst, steps, warmup, calib_copy):
+    from paper_2506_08781_amd import workloads
+    t = time.perf_counter()
+    log = workloads.single_signer_fixed(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
+    print(f"# plain: inputs ready in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    msgs = P.make_msgs(log.data)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ok, _ = P.poslo_aver(ctx, log.params, log.pk, msgs, log.ds, log.tag, stream)
+        assert ok, "honest batch rejected"
+    P.poslo_ctx_profile(ctx, True)
+    reset_times(P, ctx)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        ok, _ = P.poslo_aver(ctx, log.params, log.pk, msgs, log.ds, log.tag, stream)
+        lat.append(time.perf_counter() - s)
+        assert ok
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    P.poslo_ctx_profile(ctx, False)
+    if calib_copy:
+        log.data.clone()
+        torch.cuda.synchronize()
+    kt = {name: kernel_ms(P, ctx, k) for name, k in
+          (("seed", P.POSLO_KT_SEED), ("agg", P.POSLO_KT_AGG), ("final", P.POSLO_KT_FINAL))}
+    return log, total, lat, kt
+
+
+def bench_distill(P, torch, ctx, inst, steps):
+    from paper_2506_08781_amd import workloads
+    c = DISTILL
+    t = time.perf_counter()
+    log = workloads.single_signer_fixed(ctx, inst, c["n"], c["L"], c["log2_n1"], c["log2_n2"], c["seed"],
+                                        corrupt_frac=c["frac"])
+    print(f"# distill: inputs ready in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    msgs = P.make_msgs(log.data)
+    want = sorted(e for e, _ in log.plan)
+    ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
+    assert ccd.invalid() == want, "invalid set differs from the injected flips"
+    del ccd
+    P.poslo_ctx_profile(ctx, True)
+    reset_times(P, ctx)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
+        lat.append(time.perf_counter() - s)
+        del ccd
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    P.poslo_ctx_profile(ctx, False)
+    n = c["n"]
+    return {
+        "workload": f"Distill, 2^20 entries x 256 B, {int(c['frac'] * 100)}% entries with one flipped bit, "
+                    f"{c['umbrellas']} umbrellas",
+        "entries_per_s": n * steps / total,
+        "ms_per_step": 1e3 * total / steps,
+        "latency_ms": lat_summary(lat),
+        "invalid": len(want),
+        "kernel_ms": {"verify": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
+                      "compact": kernel_ms(P, ctx, P.POSLO_KT_COMPACT)},
+    }
+
+
+def bench_batched(P, torch, ctx, inst, steps):
+    from paper_2506_08781_amd import workloads
+    c = BATCHED
+    t = time.perf_counter()
+    log = workloads.multi_signer(ctx, inst, c["signers"], c["max_batch"], c["len_lo"], c["len_hi"], c["frac"],
+                                 seed=c["seed"], log2_n1=c["log2_n1"], log2_n2=c["log2_n2"])
+    print(f"# batched: {log.total} entries of {c['signers']} signers ready in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    total_entries = log.total
+    bases = log.bases
+    flipped, msg_flipped = {}, set()
+    for e, bit in log.plan:
+        k = int(np.searchsorted(bases, e, side="right") - 1)
+        flipped.setdefault(k, []).append(e - int(bases[k]))
+        if bit < 8 * int(log.lengths[e]):
+            msg_flipped.add(k)
+    want_acc = [k not in msg_flipped for k in range(c["signers"])]
+    want_inv = sorted((k, t) for k, ts in flipped.items() for t in ts)
+    bj = log.batch_jobs()
+    P.poslo_ctx_keys_load(ctx, log.pks)  # keys resident before timing
+
+    # autotune the persistent launch on this batch (AVer only)
+    t = time.perf_counter()
+    tuning, tuned_ms = P.poslo_autotune_batch(ctx, log.params, bj, log.data, log.d_offsets, reps=2)
+    tune_s = time.perf_counter() - t
+    tuned = (tuning.variant, tuning.wg_per_cu, False)
+    acc, _ = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, tuning=tuned)
+    assert acc == want_acc, "batched accept bits differ from the injected flips"
+
+    # batched AVer, eager launches, kernel events on
+    P.poslo_ctx_profile(ctx, True)
+    reset_times(P, ctx)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, tuning=tuned)
+        lat.append(time.perf_counter() - s)
+    torch.cuda.synchronize()
+    eager_total = time.perf_counter() - t0
+    P.poslo_ctx_profile(ctx, False)
+    hot_ms = kernel_ms(P, ctx, P.POSLO_KT_BATCH_HOT)
+    pipe_ms = kernel_ms(P, ctx, P.POSLO_KT_BATCH)
+
+    # the same with the launch sequence replayed from a captured graph
+    graph = (tuning.variant, tuning.wg_per_cu, True)
+    P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, tuning=graph)
+    glat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        acc, _ = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, tuning=graph)
+        glat.append(time.perf_counter() - s)
+    torch.cuda.synchronize()
+    graph_total = time.perf_counter() - t0
+    assert acc == want_acc
+
+    # AVer plus the exact invalid set of every signer (SeBVer's input)
+    t0 = time.perf_counter()
+    acc, inv = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2,
+                                    tuning=graph, cap=len(want_inv) + 16)
+    distill_s = time.perf_counter() - t0
+    assert acc == want_acc and inv == want_inv, "batched invalid set differs from the injected flips"
+
+    # plain path: one AVer call per signer on the same device buffers
+    plain_lat = []
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, j in enumerate(log.jobs):
+        m = P.poslo_msgs(log.data.data_ptr(), log.d_offsets.data_ptr() + 8 * j["entry_base"], 0, j["n"], j["t0"],
+                         log.data.numel())
+        s = time.perf_counter()
+        ok, _ = P.poslo_aver(ctx, log.params, j["pk"], m, j["ds"], j["tag"], stream)
+        plain_lat.append(time.perf_counter() - s)
+        assert ok == want_acc[k]
+    torch.cuda.synchronize()
+    plain_total = time.perf_counter() - t0
+
+    ops = int(np.sum(ops_per_entry(inst, log.lengths.astype(np.int64))))
+    hashes = int(np.sum(hash_calls_per_entry(inst, log.lengths.astype(np.int64))))
+    achieved = ops / (hot_ms / 1e3) / 1e12
+    graph_eps = total_entries * steps / graph_total
+    return {
+        "workload": f"{c['signers']} signers, log-uniform [1, {c['max_batch']}] entries each "
+                    f"({total_entries} total), messages uniform [{c['len_lo']}, {c['len_hi']}] B, "
+                    f"{c['frac'] * 100:.1f}% entries with one flipped bit, n2={1 << c['log2_n2']}, "
+                    f"n1={1 << c['log2_n1']}",
+        "entries": total_entries,
+        "msg_bytes": int(log.offsets[-1]),
+        "tuning": {"variant": P.poslo_batch_variant_name(tuning.variant), "wg_per_cu": tuning.wg_per_cu,
+                   "autotune_s": tune_s, "tuned_ms": tuned_ms},
+        "batched": {"entries_per_s": graph_eps, "ms_per_step": 1e3 * graph_total / steps,
+                    "latency_ms": lat_summary(glat), "launch": "hipGraph replay",
+                    "eager_entries_per_s": total_entries * steps / eager_total,
+                    "eager_latency_ms": lat_summary(lat),
+                    "hashes_per_s": hashes * steps / graph_total},
+        "batched_with_invalid_sets": {"entries_per_s": total_entries / distill_s, "ms": 1e3 * distill_s,
+                                      "rejected": acc.count(False), "invalid": len(inv)},
+        "plain": {"entries_per_s": total_entries / plain_total, "ms_per_pass": 1e3 * plain_total,
+                  "per_signer_latency_ms": lat_summary(plain_lat)},
+        "speedup_vs_plain": graph_eps / (total_entries / plain_total),
+        "kernel_ms": {"hot": hot_ms, "pipeline": pipe_ms},
+        "roofline": {"bound": "alu", "kernel": "k_batch_hot", "achieved": achieved, "peak": INT32_PEAK_TOPS,
+                     "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops": ops, "traffic": None,
+                     "hbm_GBs": int(log.offsets[-1]) / (hot_ms / 1e3) / 1e9},
+    }
 
 
 def main():
@@ -118,6 +317,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--inst", default="aes", choices=["aes", "sha"])
+    ap.add_argument("--sections", default="plain,distill,batched",
+                    help="comma list of plain, distill, batched (plain always runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -137,48 +338,16 @@ def main():
 
     cfg = CONFIGS[args.config]
     inst = 1 if args.inst == "aes" else 0
-    t = time.perf_counter()
-    arr, params, pk, sigs, ds, tag = build_inputs(P, cfg, inst)
-    print(f"# inputs ready in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
-    d = torch.from_numpy(arr).cuda()
-    msgs = P.make_msgs(d)
+    sections = set(args.sections.split(","))
     ctx = P.poslo_ctx_create(0)
-    stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        ok, _ = P.poslo_aver(ctx, params, pk, msgs, ds, tag, stream)
-        assert ok, "honest batch rejected"
-    P.poslo_ctx_profile(ctx, True)
-    for k in (P.POSLO_KT_SEED, P.POSLO_KT_AGG, P.POSLO_KT_FINAL):
-        P.poslo_ctx_kernel_time(ctx, k, reset=True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s = time.perf_counter()
-        ok, _ = P.poslo_aver(ctx, params, pk, msgs, ds, tag, stream)
-        lat.append(time.perf_counter() - s)
-        assert ok
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    P.poslo_ctx_profile(ctx, False)
-    if args.calib_copy:
-        d.clone()
-        torch.cuda.synchronize()
-    kt = {name: P.poslo_ctx_kernel_time(ctx, k) for name, k in
-          (("seed", P.POSLO_KT_SEED), ("agg", P.POSLO_KT_AGG), ("final", P.POSLO_KT_FINAL))}
-
+    log, total, lat, kt = bench_plain(P, torch, ctx, cfg, inst, args.steps, args.warmup, args.calib_copy)
     n = cfg["n"]
     ms_step = 1e3 * total / args.steps
     value = n / (total / args.steps)
-    agg_ms = kt["agg"][0] / max(kt["agg"][1], 1)
+    agg_ms = kt["agg"]
     ope = ops_per_entry(inst, cfg["L"])
     achieved = n * ope / (agg_ms / 1e3) / 1e12
-    lat_ms = sorted(1e3 * x for x in lat)
-
-    def pct(p):
-        return lat_ms[min(len(lat_ms) - 1, int(round(p / 100 * (len(lat_ms) - 1))))]
-
     out = {
         "metric": METRIC,
         "value": value,
@@ -195,17 +364,26 @@ def main():
         "config": {"workload": cfg["name"] + (", POSLO+ (MMO/MDC-2 over AES-128)" if inst else ", POSLO (SHA-256)"),
                    "entries": n, "msg_bytes": cfg["L"], "n2": 1 << cfg["log2_n2"], "n1": 1 << cfg["log2_n1"],
                    "instantiation": args.inst, "path": "plain"},
-        "latency_ms": {"p50": pct(50), "p99": pct(99), "max": lat_ms[-1]},
+        "latency_ms": lat_summary(lat),
         "hashes_per_s": value * hash_calls_per_entry(inst, cfg["L"]),
         "hash_unit": "AES-128 blocks/s" if inst else "SHA-256 compressions/s",
-        "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "kernel_ms": kt,
         "roofline": {"bound": "alu", "kernel": "k_agg_ekeys_" + args.inst, "achieved": achieved,
                      "peak": INT32_PEAK_TOPS, "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS,
                      "ops_per_entry": ope, "traffic": None,
                      "hbm_GBs": n * cfg["L"] / (agg_ms / 1e3) / 1e9},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, inst, arr, pk, sigs, ds, P, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, inst, log, args.cpu_seconds)
+    del log
+    torch.cuda.empty_cache()
+    if "distill" in sections:
+        out["distill"] = bench_distill(P, torch, ctx, inst, max(2, args.steps // 4))
+        torch.cuda.empty_cache()
+    if "batched" in sections:
+        out["multi_signer"] = bench_batched(P, torch, ctx, inst, max(3, args.steps // 2))
+        torch.cuda.empty_cache()
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

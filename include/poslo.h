@@ -167,7 +167,9 @@ enum {
     POSLO_KT_FINAL = 2,  /* fold of partial sums, mod q, aggregate check */
     POSLO_KT_EKEYS = 3,  /* per-entry digests */
     POSLO_KT_VERIFY = 4, /* per-entry individual verification (Distill) */
-    POSLO_KT_COMPACT = 5 /* invalid-index compaction and CCD aggregates */
+    POSLO_KT_COMPACT = 5, /* invalid-index compaction and CCD aggregates */
+    POSLO_KT_BATCH_HOT = 6, /* multi-signer persistent hashing kernel (eager launches only) */
+    POSLO_KT_BATCH = 7      /* multi-signer pipeline: seeds, hashing, per-job checks */
 };
 int poslo_ctx_profile(poslo_ctx* ctx, int enable);
 int poslo_ctx_kernel_time(poslo_ctx* ctx, int kernel, int reset, double* total_ms, uint64_t* launches);

@@ -269,7 +269,8 @@ def poslo_ctx_create(device: int = 0) -> Ctx:
     return Ctx(device)
 
 
-POSLO_KT_SEED, POSLO_KT_AGG, POSLO_KT_FINAL, POSLO_KT_EKEYS, POSLO_KT_VERIFY, POSLO_KT_COMPACT = range(6)
+(POSLO_KT_SEED, POSLO_KT_AGG, POSLO_KT_FINAL, POSLO_KT_EKEYS, POSLO_KT_VERIFY, POSLO_KT_COMPACT,
+ POSLO_KT_BATCH_HOT, POSLO_KT_BATCH) = range(8)
 
 
 def poslo_agg_variant_count() -> int:

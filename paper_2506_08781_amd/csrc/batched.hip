@@ -564,16 +564,18 @@ int run_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs
     A.tab = (const uint32_t*)d_tab;
     A.counter = (uint32_t*)d_misc;
     A.partials = (uint32_t*)d_part;
-    auto launch_all = [&](hipStream_t q) -> int {
+    auto launch_all = [&](hipStream_t q, bool timed) -> int {
         hipLaunchKernelGGL(k_batch_seeds, dim3(seed_grid), dim3(256), 0, q, S);
+        if (timed) prof_begin(c, POSLO_KT_BATCH_HOT, q);
         int r = launch_hot(tune.variant, grid, A, q);
+        if (timed) prof_end(c, POSLO_KT_BATCH_HOT, q);
         if (r) return r;
         if (njobs)
             hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs,
                                (const uint32_t*)d_part, c->d_gtable, (const uint32_t*)d_rdec, (uint32_t*)d_res);
         return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
     };
-    prof_begin(c, POSLO_KT_AGG, s);
+    prof_begin(c, POSLO_KT_BATCH, s);
     if (tune.use_graph) {
         std::string gk;
         key_bytes(gk, S);
@@ -596,7 +598,7 @@ int run_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs
             }
             if (!bs.capture) HIP_TRY(hipStreamCreateWithFlags(&bs.capture, hipStreamNonBlocking));
             HIP_TRY(hipStreamBeginCapture(bs.capture, hipStreamCaptureModeThreadLocal));
-            int r = launch_all(bs.capture);
+            int r = launch_all(bs.capture, false);
             hipGraph_t g = nullptr;
             hipError_t ec = hipStreamEndCapture(bs.capture, &g);
             if (r || ec != hipSuccess) {
@@ -610,9 +612,9 @@ int run_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs
         }
         HIP_TRY(hipGraphLaunch(exec, s));
     } else {
-        if ((st = launch_all(s))) return st;
+        if ((st = launch_all(s, true))) return st;
     }
-    prof_end(c, POSLO_KT_AGG, s);
+    prof_end(c, POSLO_KT_BATCH, s);
     std::vector<uint32_t> res(std::max<uint32_t>(njobs, 1));
     if (njobs) HIP_TRY(hipMemcpyAsync(res.data(), d_res, njobs * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -109,3 +109,43 @@ def multi_signer(ctx, inst: int, n_signers: int, max_batch: int, len_lo: int, le
         _flip(torch, log, log.plan)
     torch.cuda.synchronize(dev)
     return log
+
+
+@dataclass
+class SingleSignerLog:
+    params: object
+    data: object        # CUDA uint8 tensor (n, L)
+    sigs: object        # CUDA uint8 tensor (80 n)
+    pk: bytes
+    ds: bytes
+    tag: bytes
+    plan: list[tuple[int, int]] = field(default_factory=list)
+
+
+def single_signer_fixed(ctx, inst: int, n: int, L: int, log2_n1: int, log2_n2: int, seed: int,
+                        corrupt_frac: float = 0.0) -> SingleSignerLog:
+    """One fresh signer, n entries of L-byte messages from stream seed, all
+    signed from t = 0 into one tag; optionally round(corrupt_frac * n)
+    entries with one flipped bit of m_t || sigma_t (the tag stays the honest
+    one)."""
+    import torch
+
+    params = make_params(inst, log2_n1, log2_n2)
+    dev = torch.device("cuda", ctx.device)
+    data = torch.empty((n, L), dtype=torch.uint8, device=dev)
+    poslo_synth_messages(seed, poslo_msgs(data.data_ptr(), None, L, n, 0, n * L), data)
+    offs = torch.arange(0, (n + 1) * L, L, dtype=torch.int64, device=dev)
+    keys = poslo_gpu_keys_create(ctx, params, [synthlog.derived_key_seed(seed + 3, 0)])
+    sigs = torch.empty(80 * n, dtype=torch.uint8, device=dev)
+    tags, ds = poslo_gpu_sign(keys, [(0, 0, n, 0)], data, offs, sigs)
+    log = SingleSignerLog(params=params, data=data, sigs=sigs, pk=keys.pks[0], ds=ds[0], tag=tags[0])
+    del keys
+    k = int(round(corrupt_frac * n))
+    if k:
+        log.plan = synthlog.corruption_plan(seed + 4, n, k, 8 * (L + 80))
+        flat = data.view(-1)
+        view = MultiSignerLog(params=params, counts=[n], lengths=np.full(n, L), offsets=np.arange(n + 1) * L,
+                              data=flat, d_offsets=offs, sigs=sigs, pks=[log.pk], jobs=[])
+        _flip(torch, view, log.plan)
+    torch.cuda.synchronize(dev)
+    return log

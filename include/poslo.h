@@ -346,6 +346,94 @@ int poslo_autotune_batch(poslo_ctx* ctx, const poslo_params* params, const poslo
 /* Drop the context's captured graphs and tuning cache. */
 int poslo_batch_forget(poslo_ctx* ctx);
 
+/* ------------------------------------------------------------ serving loop */
+
+/* A verification server: requests (one signer's batch each) are submitted
+ * from any thread as they arrive and verified by a worker thread that
+ * admits them while device memory and launch slots allow, groups the
+ * admitted requests into multi-signer launches and keeps several launches
+ * in flight on separate streams (a request that arrives while others are on
+ * the GPU joins the next group).  Public keys stay resident on the device
+ * (comb tables) with a per-key aggregate state: the sum of the tags of the
+ * key's accepted requests and the number of entries they covered.  A
+ * request's result does not depend on what it was grouped with. */
+typedef struct poslo_server poslo_server;
+
+typedef struct poslo_server_cfg {
+    poslo_params params;
+    uint32_t n_streams;   /* launch groups in flight (0: 4) */
+    uint32_t max_group;   /* requests per launch group (0: 256) */
+    uint64_t mem_bytes;   /* device budget for admitted requests: staging copies of host
+                             buffers and per-request scratch (0: 8 GiB) */
+    int distill;          /* 0: accept bit only; 1: invalid entries of rejected requests;
+                             2: invalid entries of every request */
+    int variant;          /* hot-kernel variant (-1: the default of the instantiation) */
+} poslo_server_cfg;
+
+typedef struct poslo_request {
+    uint32_t key_id;      /* a registered key */
+    uint32_t on_device;   /* 1: data, offsets and sigs are device pointers; 0: host pointers,
+                             copied to the device when the request is launched.  Either way
+                             they stay valid and unchanged until the result is polled. */
+    uint64_t t0, n;       /* entries t0 .. t0+n-1 */
+    const uint8_t* data;
+    const uint64_t* offsets;  /* n + 1 offsets into data, or NULL: fixed msg_len */
+    uint64_t msg_len;
+    uint64_t data_bytes;      /* bytes of data (0: offsets[n], or n * msg_len) */
+    const uint8_t* sigs;      /* 80 per entry, or NULL when the server does not distill */
+    const uint8_t* ds;        /* host, copied at submit */
+    size_t ds_len;
+    const uint8_t* tag;       /* host, 64 bytes, copied at submit */
+    uint64_t user;            /* returned with the result */
+} poslo_request;
+
+typedef struct poslo_result {
+    uint64_t ticket;
+    uint64_t user;
+    int status;           /* POSLO_OK, or the error this request failed with */
+    int accept;
+    uint64_t n_invalid;   /* invalid entries found (poslo_server_take_invalid) */
+    uint64_t entries;
+    double t_submit_ms;   /* times since the server was created */
+    double t_admit_ms;
+    double t_launch_ms;
+    double t_done_ms;
+} poslo_result;
+
+typedef struct poslo_server_stats {
+    uint64_t submitted, completed, queued, in_flight;
+    uint64_t entries_completed, groups_launched;
+    uint64_t bytes_in_use, bytes_peak;
+    double latency_p50_ms, latency_p99_ms; /* submit to done, over completed requests */
+    double elapsed_ms;                     /* since the server was created */
+} poslo_server_stats;
+
+/* device: HIP device index.  E_INVAL on a bad configuration. */
+int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out);
+/* Register n keys (ids and 32-byte encodings, host).  E_ENCODING if one is
+ * not a point (none is registered then); an id registered again is
+ * replaced (requests already queued keep the key they were submitted
+ * with).  Synchronous.  E_BUSY when the key-state array must grow while
+ * requests are queued or in flight: register keys before serving. */
+int poslo_server_register_keys(poslo_server* srv, const uint32_t* ids, const uint8_t* pks, size_t n);
+/* Queue a request; never waits for the device.  *ticket identifies its
+ * result.  The request's own inputs are checked here: E_INVAL for an
+ * unknown key, inconsistent sizes or a malformed ds, E_SEED when the ds
+ * does not cover one of its epochs. */
+int poslo_server_submit(poslo_server* srv, const poslo_request* req, uint64_t* ticket);
+/* Move up to cap finished results to out (in completion order); *n gets
+ * the count.  timeout_ms > 0 waits that long for at least one. */
+int poslo_server_poll(poslo_server* srv, poslo_result* out, size_t cap, size_t* n, double timeout_ms);
+/* The sorted invalid entry indices t of a polled result; the list is
+ * released by this call.  E_INVAL if the ticket has none pending. */
+int poslo_server_take_invalid(poslo_server* srv, uint64_t ticket, uint64_t* out, size_t cap, size_t* n);
+/* The key's device-resident aggregate state: the tag sum of its accepted
+ * requests (64 bytes, the Agg format) and the entries they covered. */
+int poslo_server_key_state(poslo_server* srv, uint32_t key_id, uint8_t tag[64], uint64_t* entries);
+int poslo_server_stats_get(poslo_server* srv, poslo_server_stats* out);
+/* Waits for every submitted request to finish, then frees the server. */
+void poslo_server_destroy(poslo_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

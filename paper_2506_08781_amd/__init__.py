@@ -21,8 +21,13 @@ INST_SHA256 = 0
 INST_AES = 1
 
 POSLO_OK = 0
+POSLO_E_INVAL = -1
+POSLO_E_NOMEM = -2
+POSLO_E_DEVICE = -3
 POSLO_E_SEED = -4
 POSLO_E_ENCODING = -5
+POSLO_E_EXHAUSTED = -6
+POSLO_E_BUSY = -7
 
 
 class PosloError(RuntimeError):
@@ -55,6 +60,34 @@ class poslo_batch_job(ctypes.Structure):
 class poslo_tuning(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("reserved", ctypes.c_int)]
+
+
+class poslo_server_cfg(ctypes.Structure):
+    _fields_ = [("params", poslo_params), ("n_streams", ctypes.c_uint32), ("max_group", ctypes.c_uint32),
+                ("mem_bytes", ctypes.c_uint64), ("distill", ctypes.c_int), ("variant", ctypes.c_int)]
+
+
+class poslo_request(ctypes.Structure):
+    _fields_ = [("key_id", ctypes.c_uint32), ("on_device", ctypes.c_uint32), ("t0", ctypes.c_uint64),
+                ("n", ctypes.c_uint64), ("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("msg_len", ctypes.c_uint64), ("data_bytes", ctypes.c_uint64), ("sigs", ctypes.c_void_p),
+                ("ds", ctypes.c_void_p), ("ds_len", ctypes.c_size_t), ("tag", ctypes.c_void_p),
+                ("user", ctypes.c_uint64)]
+
+
+class poslo_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("user", ctypes.c_uint64), ("status", ctypes.c_int),
+                ("accept", ctypes.c_int), ("n_invalid", ctypes.c_uint64), ("entries", ctypes.c_uint64),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_launch_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+class poslo_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("in_flight", ctypes.c_uint64), ("entries_completed", ctypes.c_uint64),
+                ("groups_launched", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("bytes_peak", ctypes.c_uint64), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("elapsed_ms", ctypes.c_double)]
 
 
 def make_params(inst: int, log2_n1: int, log2_n2: int, bpv_v: int = 1024, bpv_k: int = 16) -> poslo_params:
@@ -128,6 +161,14 @@ def lib():
             "poslo_autotune_batch": ([_VP, P(poslo_params), P(poslo_batch_job), _U32, _VP, _VP, _U64, _I, _VP,
                                       P(poslo_tuning), P(ctypes.c_double)], _I),
             "poslo_batch_forget": ([_VP], _I),
+            "poslo_server_create": ([_I, P(poslo_server_cfg), P(_VP)], _I),
+            "poslo_server_register_keys": ([_VP, _VP, _U8P, _SZ], _I),
+            "poslo_server_submit": ([_VP, P(poslo_request), P(_U64)], _I),
+            "poslo_server_poll": ([_VP, P(poslo_result), _SZ, P(_SZ), ctypes.c_double], _I),
+            "poslo_server_take_invalid": ([_VP, _U64, _VP, _SZ, P(_SZ)], _I),
+            "poslo_server_key_state": ([_VP, _U32, _VP, P(_U64)], _I),
+            "poslo_server_stats_get": ([_VP, P(poslo_server_stats)], _I),
+            "poslo_server_destroy": ([_VP], None),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(L, name)
@@ -575,3 +616,94 @@ def poslo_autotune_batch(ctx: Ctx, params: poslo_params, jobs: BatchJobs, data, 
 
 def poslo_batch_forget(ctx: Ctx) -> None:
     _check(lib().poslo_batch_forget(ctx.handle), "poslo_batch_forget")
+
+
+# ------------------------------------------------------------- serving loop
+
+class Request:
+    """A poslo_request plus the host buffers it points into (ds, tag, and
+    host message buffers when on_device is 0)."""
+
+    def __init__(self, key_id: int, t0: int, n: int, data, offsets, msg_len: int, sigs, ds: bytes, tag: bytes,
+                 user: int = 0, data_bytes: int | None = None):
+        self._ds = ctypes.create_string_buffer(bytes(ds), max(1, len(ds)))
+        self._tag = ctypes.create_string_buffer(bytes(tag), 64)
+        self._keep = []
+
+        def ptr(x):
+            if x is None:
+                return None, True
+            if hasattr(x, "data_ptr"):  # CUDA tensor, kept alive with the request
+                self._keep.append(x)
+                return (x.data_ptr() if x.numel() else None), True
+            arr = np.ascontiguousarray(x)
+            self._keep.append(arr)
+            return (arr.ctypes.data if arr.size else None), False
+
+        dp, dev = ptr(data)
+        op, _ = ptr(offsets)
+        sp, _ = ptr(sigs)
+        if data_bytes is None:
+            data_bytes = 0 if data is None else (data.numel() if hasattr(data, "numel") else np.asarray(data).nbytes)
+        self.req = poslo_request(key_id, 1 if dev else 0, t0, n, dp, op, msg_len, data_bytes, sp,
+                                 ctypes.addressof(self._ds), len(ds), ctypes.addressof(self._tag), user)
+
+
+class Server:
+    """Owns a poslo_server*."""
+
+    def __init__(self, device: int, params: poslo_params, n_streams: int = 4, max_group: int = 256,
+                 mem_bytes: int = 0, distill: int = 1, variant: int = -1):
+        cfg = poslo_server_cfg(params, n_streams, max_group, mem_bytes, distill, variant)
+        h = ctypes.c_void_p()
+        _check(lib().poslo_server_create(device, ctypes.byref(cfg), ctypes.byref(h)), "poslo_server_create")
+        self.handle = h
+        self._live = {}
+
+    def register_keys(self, ids: list[int], pks: list[bytes]) -> None:
+        arr = (ctypes.c_uint32 * max(1, len(ids)))(*ids)
+        _check(lib().poslo_server_register_keys(self.handle, arr, b"".join(bytes(p) for p in pks), len(ids)),
+               "poslo_server_register_keys")
+
+    def submit(self, req: Request) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().poslo_server_submit(self.handle, ctypes.byref(req.req), ctypes.byref(t)), "poslo_server_submit")
+        self._live[t.value] = req  # keep its buffers alive until polled
+        return t.value
+
+    def poll(self, cap: int = 1024, timeout_ms: float = 0.0) -> list[poslo_result]:
+        buf = (poslo_result * cap)()
+        n = ctypes.c_size_t()
+        _check(lib().poslo_server_poll(self.handle, buf, cap, ctypes.byref(n), timeout_ms), "poslo_server_poll")
+        out = [buf[k] for k in range(n.value)]
+        for r in out:
+            self._live.pop(r.ticket, None)
+        return out
+
+    def take_invalid(self, ticket: int, n: int) -> list[int]:
+        arr = (ctypes.c_uint64 * max(1, n))()
+        got = ctypes.c_size_t()
+        _check(lib().poslo_server_take_invalid(self.handle, ticket, arr, n, ctypes.byref(got)),
+               "poslo_server_take_invalid")
+        return [int(arr[k]) for k in range(got.value)]
+
+    def key_state(self, key_id: int) -> tuple[bytes, int]:
+        tag = ctypes.create_string_buffer(64)
+        e = ctypes.c_uint64()
+        _check(lib().poslo_server_key_state(self.handle, key_id, tag, ctypes.byref(e)), "poslo_server_key_state")
+        return tag.raw, e.value
+
+    def stats(self) -> poslo_server_stats:
+        st = poslo_server_stats()
+        _check(lib().poslo_server_stats_get(self.handle, ctypes.byref(st)), "poslo_server_stats_get")
+        return st
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().poslo_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()

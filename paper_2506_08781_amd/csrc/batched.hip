@@ -1,7 +1,7 @@
 // Batched verification of many signers' batches in one persistent launch.
 //
-// Each signer's batch is a job: its own key, entry range, ds and tag (the
-// paper verifies one batch per launch; section "POSLO Parallel Batch
+// Each signer's batch is a job: its own key, entries, ds and tag (the paper
+// verifies one batch per launch; section "POSLO Parallel Batch
 // Verification").  Jobs are cut into work items of up to CHUNK entries that
 // never straddle a job.  A persistent grid of workgroups pulls items from an
 // atomic counter until the queue is empty; each item's entries are sorted
@@ -9,12 +9,13 @@
 // that the 64 lanes of a wave hash messages of similar length; digests are
 // summed lazily into one 288-bit partial per item.  A second kernel folds
 // each job's partials, reduces mod q and checks the job's tag with one wave
-// (comb tables).  Jobs that fail can be distilled: their entries are verified
-// individually and the invalid ones reported as (job, t) pairs.
+// (comb tables).  Entries of chosen jobs can then be verified individually
+// (Distill's check); invalid ones are appended to a list with one atomic per
+// wave (ballot + popcount) and sorted on the host.
 //
-// The sequence (seed rows -> persistent hashing -> per-job checks -> result
-// copy) can be captured in a hipGraph and replayed; an autotuner times the
-// kernel variants on the caller's batch and caches the fastest per shape.
+// The kernel sequence can be captured in a hipGraph and replayed; an
+// autotuner times the kernel variants on the caller's batch and caches the
+// fastest per shape class.
 #include <string.h>
 
 #include <algorithm>
@@ -24,39 +25,25 @@
 #include <vector>
 
 #include "aes_perm.h"
-#include "ctx.h"
+#include "batch_run.h"
 #include "device_verify.h"
-#include "scheme_host.h"
 
 namespace poslo {
 
-struct BJob {
-    const uint32_t* ty;  // comb table of the job's key
-    uint64_t t0, n;
-    uint64_t entry_base;  // first entry in the global offsets array
-    uint64_t epoch_base;  // first row of the epoch table
-    uint64_t item_base, item_end;
-    uint32_t tag[16];     // LE words: s[8] || R bytes[8]
-};
-
-struct BItem {
-    uint32_t job;
-    uint32_t count;
-    uint64_t first;  // entry offset within the job
-};
-
-struct BHot {
-    const BJob* jobs;
-    const BItem* items;
-    uint32_t n_items;
-    uint32_t log2_n2;
-    const uint8_t* data;
-    const uint64_t* offsets;
-    const uint8_t* end;
-    const uint32_t* tab;
-    uint32_t* counter;
-    uint32_t* partials;  // 9 words per item
-};
+__device__ __forceinline__ BatchArgs job_args(const BJob& J, uint32_t log2_n2, const uint32_t* tab) {
+    BatchArgs a;
+    a.data = J.data;
+    a.offsets = J.offsets;
+    a.msg_len = J.msg_len;
+    a.n = J.n;
+    a.t0 = J.t0;
+    a.epoch_first = J.t0 >> log2_n2;
+    a.log2_n2 = log2_n2;
+    a.tab = tab + J.epoch_base * kEpochWords;
+    a.skip = nullptr;
+    a.end = J.end;
+    return a;
+}
 
 // ---- seed rows: one lane per (job, epoch); row 0 resets the queue ---------
 // Blocks past the rows decode each job's tag (one lane per job): s < q and
@@ -133,20 +120,15 @@ __global__ __launch_bounds__(256) void k_batch_seeds(BSeeds S) {
 
 // ---- the persistent hashing kernel ------------------------------------------
 
-__device__ __forceinline__ BatchArgs job_args(const BHot& A, const BJob& J) {
-    BatchArgs a;
-    a.data = A.data;
-    a.offsets = A.offsets + J.entry_base;
-    a.msg_len = 0;
-    a.n = J.n;
-    a.t0 = J.t0;
-    a.epoch_first = J.t0 >> A.log2_n2;
-    a.log2_n2 = A.log2_n2;
-    a.tab = A.tab + J.epoch_base * kEpochWords;
-    a.skip = nullptr;
-    a.end = A.end;
-    return a;
-}
+struct BHot {
+    const BJob* jobs;
+    const BItem* items;
+    uint32_t n_items;
+    uint32_t log2_n2;
+    const uint32_t* tab;
+    uint32_t* counter;
+    uint32_t* partials;  // 9 words per item
+};
 
 // one MDC-2 block with the byte-addressed LDS tables
 struct Mdc2BlockPerm {
@@ -178,10 +160,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     if constexpr (INST == INST_AES) {
         perm_tables_fill<NT>(lds);
     }
-    uint32_t* counts = lds + TW;                                   // 64 bucket counters
-    uint32_t* misc = counts + 64;                                  // [0] item id
-    uint16_t* order = reinterpret_cast<uint16_t*>(misc + 16);      // CHUNK slots
-    uint8_t* keys = reinterpret_cast<uint8_t*>(order + CHUNK);     // CHUNK block counts
+    uint32_t* counts = lds + TW;                                // 64 bucket counters
+    uint32_t* misc = counts + 64;                               // [0] item id
+    uint16_t* order = reinterpret_cast<uint16_t*>(misc + 16);   // CHUNK slots
+    uint8_t* keys = reinterpret_cast<uint8_t*>(order + CHUNK);  // CHUNK block counts
     uint32_t* red = lds + TW + SW;
     const PermTables<NT> tb = perm_tables<NT>(lds);
     for (;;) {
@@ -193,12 +175,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         if (item >= A.n_items) break;
         const BItem it = A.items[item];
         const BJob J = A.jobs[it.job];
-        const BatchArgs a = job_args(A, J);
+        const BatchArgs a = job_args(J, A.log2_n2, A.tab);
         if (SORT) {
             // counting sort of the item's slots by block count
             for (uint32_t s = threadIdx.x; s < it.count; s += BLOCK) {
                 uint64_t p = it.first + s;
-                uint64_t L = a.offsets[p + 1] - a.offsets[p];
+                uint64_t L = a.offsets ? a.offsets[p + 1] - a.offsets[p] : a.msg_len;
                 uint64_t nb = INST == INST_AES ? (L + 31) / 16 : (L + 25 + 63) / 64;
                 uint32_t key = nb < 63 ? (uint32_t)nb : 63u;
                 keys[s] = (uint8_t)key;
@@ -270,20 +252,17 @@ __global__ __launch_bounds__(64) void k_batch_final(const BJob* jobs, const uint
     }
 }
 
-// ---- individual verification of the entries of failing jobs ----------------
+// ---- individual verification of the entries of chosen jobs ----------------
 
 struct BVerify {
     const BJob* jobs;
     const BItem* tiles;  // up to 256 entries each
-    const uint8_t* sigs;  // 80 bytes per global entry
     const uint32_t* tg;
     uint32_t inst;
     uint32_t log2_n2;
-    const uint8_t* data;
-    const uint64_t* offsets;
-    const uint8_t* end;
     const uint32_t* tab;
-    uint8_t* flags;  // per global entry, 1 = invalid (entries of verified jobs only)
+    uint64_t* idx;    // appended slots (job's vbase + entry offset) of invalid entries
+    uint32_t* count;  // number appended
 };
 
 __global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
@@ -292,55 +271,32 @@ __global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
     __syncthreads();
     LdsTables<4, 1> tb{lds};
     const BItem it = V.tiles[blockIdx.x];
-    if (threadIdx.x >= it.count) return;
-    const BJob J = V.jobs[it.job];
-    BHot A;
-    A.data = V.data;
-    A.offsets = V.offsets;
-    A.end = V.end;
-    A.tab = V.tab;
-    A.log2_n2 = V.log2_n2;
-    BatchArgs a = job_args(A, J);
-    uint64_t p = it.first + threadIdx.x;
-    uint64_t g = J.entry_base + p;
-    uint32_t e[8], s[8];
-    bool ok = verify_one(tb, a, a.end, V.inst, p, V.sigs + g * 80, J.ty, V.tg, e, s);
-    V.flags[g] = ok ? 0 : 1;
-}
-
-__global__ void k_fill_u8(uint8_t* p, uint64_t n) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-// global entries flagged invalid, in order (per-thread counts, a scan, writes)
-__global__ __launch_bounds__(1024) void k_batch_compact(const uint8_t* flags, uint64_t n, uint64_t* out_idx,
-                                                        uint64_t* out_count) {
-    __shared__ uint64_t scan[1024];
-    uint64_t chunk = (n + 1023) / 1024;
-    uint64_t a = (uint64_t)threadIdx.x * chunk, b = a + chunk < n ? a + chunk : n;
-    uint64_t cnt = 0;
-    for (uint64_t p = a; p < b; p++) cnt += flags[p];
-    scan[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint64_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += v;
-        __syncthreads();
+    const BJob& J = V.jobs[it.job];
+    bool bad = false;
+    uint64_t slot = 0;
+    if (threadIdx.x < it.count) {
+        BatchArgs a = job_args(J, V.log2_n2, V.tab);
+        uint64_t p = it.first + threadIdx.x;
+        uint32_t e[8], s[8];
+        bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
+        slot = J.vbase + p;
     }
-    uint64_t o = scan[threadIdx.x] - cnt;
-    for (uint64_t p = a; p < b; p++)
-        if (flags[p]) out_idx[o++] = p;
-    if (threadIdx.x == 1023) *out_count = scan[1023];
+    // one atomic per wave: ballot, the lowest set lane adds the popcount,
+    // every set lane takes its rank among the set lanes below it
+    const uint64_t mask = __ballot(bad);
+    if (mask) {
+        const uint32_t lane = threadIdx.x & 63;
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(V.count, (uint32_t)__popcll(mask));
+        base = __shfl(base, (int)leader);
+        if (bad) V.idx[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = slot;
+    }
 }
+
+__global__ void k_zero_u32(uint32_t* p) { p[0] = 0; }
 
 // ---- tuning --------------------------------------------------------------------
-
-struct HotVariant {
-    const char* name;
-    int inst, nt, block, chunk, sort, waves_per_simd;
-};
 
 static const HotVariant kHot[] = {
     {"aes_perm2_b1024_c1024_sorted", 1, 2, 1024, 1024, 1, 4}, {"aes_perm2_b1024_c2048_sorted", 1, 2, 1024, 2048, 1, 4},
@@ -351,7 +307,11 @@ static const HotVariant kHot[] = {
 };
 constexpr int kNumHot = sizeof kHot / sizeof kHot[0];
 
-static size_t hot_lds_bytes(const HotVariant& v) {
+int batch_variant_count() { return kNumHot; }
+const HotVariant& batch_variant(int v) { return kHot[v]; }
+int batch_default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 0 : 5; }
+
+size_t hot_lds_bytes(const HotVariant& v) {
     size_t tw = v.inst == 1 ? (size_t)v.nt * 256 * 64 : 0;
     return 4 * (tw + 64 + 16 + v.chunk / 2 + v.chunk / 4 + (v.block / 64) * 9);
 }
@@ -384,56 +344,86 @@ static uint32_t hot_wg_per_cu(const HotVariant& v, int override_wg) {
     return std::max<uint32_t>(1, std::min(by_lds, by_waves));
 }
 
-}  // namespace poslo
+// ---- the runner ----------------------------------------------------------------
 
-// ===========================================================================
-// host side
-// ===========================================================================
-
-using namespace poslo;
-using namespace poslo::hostside;
-
-namespace {
+using namespace hostside;
 
 #define HIP_TRY(x)                                     \
     do {                                               \
         if ((x) != hipSuccess) return POSLO_E_DEVICE;  \
     } while (0)
 
-enum { X_JOBS = 16, X_DS, X_ROWS, X_ITEMS, X_TAB, X_PART, X_RESULT, X_TILES, X_FLAGS, X_IDX, X_MISC, X_RDEC };
+BatchRunner::~BatchRunner() {
+    forget_graphs();
+    if (capture_) hipStreamDestroy(capture_);
+    for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_})
+        if (p) hipFree(p);
+    if (h_res_) hipHostFree(h_res_);
+    if (h_misc_) hipHostFree(h_misc_);
+}
 
-struct Plan {
-    std::vector<BJob> jobs;
-    std::vector<DsArg> ds;
-    std::vector<uint32_t> job_of_row;
-    std::vector<BItem> items;
-    uint64_t n_total = 0;
-};
-
-// job table, per-epoch rows and work items on the host
-int make_plan(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs, uint32_t njobs, uint32_t chunk,
-              Plan& P) {
-    P.jobs.resize(njobs);
-    P.ds.resize(njobs);
-    P.job_of_row.clear();
-    P.items.clear();
-    P.n_total = 0;
-    uint64_t nmax = 1ull << (prm->log2_n1 + prm->log2_n2);
-    std::vector<uint8_t> pks((size_t)njobs * 32);
-    for (uint32_t j = 0; j < njobs; j++) {
-        const poslo_batch_job& in = jobs[j];
-        if (!in.pk || !in.tag || in.t0 > nmax || in.n > nmax - in.t0 || in.n >= (1ull << 32)) return POSLO_E_INVAL;
-        if (in.entry_base > UINT64_MAX - in.n) return POSLO_E_INVAL;
-        memcpy(&pks[(size_t)j * 32], in.pk, 32);
+void BatchRunner::forget_graphs() {
+    if (!graphs_.empty()) {
+        hipDeviceSynchronize();
+        for (auto& g : graphs_) hipGraphExecDestroy(g.second);
+        graphs_.clear();
     }
-    std::vector<const uint32_t*> tables;
-    int st = ctx_keys_bulk(c, pks.data(), njobs, tables, nullptr);
-    if (st) return st;
+}
+
+int BatchRunner::grow(void** p, size_t* have, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (*have >= bytes) return POSLO_OK;
+    // the old buffer may be read by queued work or baked into captured graphs
+    forget_graphs();
+    hipDeviceSynchronize();
+    if (*p) hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(p, want) != hipSuccess) return POSLO_E_NOMEM;
+    *have = want;
+    return POSLO_OK;
+}
+
+int BatchRunner::grow_pinned(void** p, size_t* have, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (*have >= bytes) return POSLO_OK;
+    forget_graphs();
+    hipDeviceSynchronize();
+    if (*p) hipHostFree(*p);
+    *p = nullptr;
+    *have = 0;
+    size_t want = bytes + bytes / 4;
+    if (hipHostMalloc(p, want, hipHostMallocDefault) != hipSuccess) return POSLO_E_NOMEM;
+    *have = want;
+    return POSLO_OK;
+}
+
+int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njobs, const poslo_tuning& t,
+                      int num_cu) {
+    if (!params_ok(prm) || (njobs && !jobs)) return POSLO_E_INVAL;
+    if (t.variant < 0 || t.variant >= kNumHot || kHot[t.variant].inst != (int)prm->inst || t.wg_per_cu < 0 ||
+        t.wg_per_cu > 64)
+        return POSLO_E_INVAL;
+    prm_ = *prm;
+    tune_ = t;
+    num_cu_ = num_cu;
+    vtiles_.clear();
+    vbase_.clear();
+    const uint32_t chunk = (uint32_t)kHot[t.variant].chunk;
+    jobs_.assign(njobs, BJob{});
+    ds_.resize(njobs);
+    job_of_row_.clear();
+    items_.clear();
+    uint64_t nmax = 1ull << (prm->log2_n1 + prm->log2_n2), total = 0;
     std::vector<DsNode> nodes;
     for (uint32_t j = 0; j < njobs; j++) {
-        const poslo_batch_job& in = jobs[j];
+        const JobSpec& in = jobs[j];
+        if (!in.ty || !in.tag || in.t0 > nmax || in.n > nmax - in.t0 || (in.n && !in.data)) return POSLO_E_INVAL;
+        total += in.n;
+        if (total >= (1ull << 32)) return POSLO_E_INVAL;
         if (!ds_parse(in.ds, in.ds_len, nodes)) return POSLO_E_INVAL;
-        DsArg& d = P.ds[j];
+        DsArg& d = ds_[j];
         memset(&d, 0, sizeof d);
         d.count = (uint32_t)nodes.size();
         for (size_t k = 0; k < nodes.size(); k++) {
@@ -441,44 +431,214 @@ int make_plan(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs
             d.index[k] = nodes[k].index;
             for (int w = 0; w < 4; w++) d.v[k][w] = load_le32(nodes[k].v + 4 * w);
         }
-        BJob& J = P.jobs[j];
-        J.ty = tables[j];
+        BJob& J = jobs_[j];
+        J.ty = in.ty;
+        J.data = in.data;
+        J.offsets = in.offsets;
+        J.msg_len = in.offsets ? 0 : in.msg_len;
+        J.end = in.data_bytes ? in.data + in.data_bytes : (in.offsets ? nullptr : in.data + in.n * in.msg_len);
+        J.sigs = in.sigs;
         J.t0 = in.t0;
         J.n = in.n;
-        J.entry_base = in.entry_base;
-        J.epoch_base = P.job_of_row.size();
-        J.item_base = P.items.size();
+        J.epoch_base = job_of_row_.size();
+        J.item_base = items_.size();
+        J.vbase = 0;
         for (int k = 0; k < 16; k++) J.tag[k] = load_le32(in.tag + 4 * k);
         if (in.n) {
             uint64_t e0 = in.t0 >> prm->log2_n2, e1 = (in.t0 + in.n - 1) >> prm->log2_n2;
             for (uint64_t e = e0; e <= e1; e++) {
                 if (sr_node(nodes.data(), (int)nodes.size(), e) < 0) return POSLO_E_SEED;
-                P.job_of_row.push_back(j);
+                job_of_row_.push_back(j);
             }
             for (uint64_t f = 0; f < in.n; f += chunk)
-                P.items.push_back(BItem{j, (uint32_t)std::min<uint64_t>(chunk, in.n - f), f});
+                items_.push_back(BItem{j, (uint32_t)std::min<uint64_t>(chunk, in.n - f), f});
         }
-        J.item_end = P.items.size();
-        P.n_total = std::max(P.n_total, in.entry_base + in.n);
+        J.item_end = items_.size();
     }
-    if (P.job_of_row.size() >= (1ull << 32) || P.items.size() >= (1ull << 32)) return POSLO_E_INVAL;
     return POSLO_OK;
 }
 
-template <class V>
-int upload(poslo_ctx* c, int slot, const V& v, hipStream_t s, void** out) {
-    size_t bytes = std::max<size_t>(v.size() * sizeof(v[0]), 16);
-    int st = ctx_scratch(c, slot, bytes, out);
-    if (st) return st;
-    if (!v.empty() && hipMemcpyAsync(*out, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s) != hipSuccess)
-        return POSLO_E_DEVICE;
+template <class T>
+static void key_bytes(std::string& k, const T& v) {
+    k.append(reinterpret_cast<const char*>(&v), sizeof v);
+}
+
+int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof) {
+    if (!prof || !prof->d_gtable) return POSLO_E_INVAL;
+    const uint32_t njobs = (uint32_t)jobs_.size();
+    const uint64_t rows = job_of_row_.size();
+    int st;
+    if ((st = grow(&d_jobs_, &n_jobs_b_, njobs * sizeof(BJob))) ||
+        (st = grow(&d_ds_, &n_ds_b_, njobs * sizeof(DsArg))) || (st = grow(&d_rows_, &n_rows_b_, rows * 4)) ||
+        (st = grow(&d_items_, &n_items_b_, items_.size() * sizeof(BItem))) ||
+        (st = grow(&d_tab_, &n_tab_b_, rows * kEpochWords * 4)) ||
+        (st = grow(&d_part_, &n_part_b_, items_.size() * 36)) || (st = grow(&d_res_, &n_res_b_, njobs * 4)) ||
+        (st = grow(&d_misc_, &n_misc_b_, 256)) || (st = grow(&d_rdec_, &n_rdec_b_, njobs * 17 * 4)) ||
+        (st = grow_pinned((void**)&h_res_, &h_res_b_, njobs * 4)))
+        return st;
+    if (njobs) {
+        HIP_TRY(hipMemcpyAsync(d_jobs_, jobs_.data(), njobs * sizeof(BJob), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_ds_, ds_.data(), njobs * sizeof(DsArg), hipMemcpyHostToDevice, s));
+    }
+    if (rows) HIP_TRY(hipMemcpyAsync(d_rows_, job_of_row_.data(), rows * 4, hipMemcpyHostToDevice, s));
+    if (!items_.empty())
+        HIP_TRY(hipMemcpyAsync(d_items_, items_.data(), items_.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
+    const HotVariant& hv = kHot[tune_.variant];
+    BSeeds S;
+    memset(&S, 0, sizeof S);
+    S.jobs = (const BJob*)d_jobs_;
+    S.ds = (const DsArg*)d_ds_;
+    S.job_of_row = (const uint32_t*)d_rows_;
+    S.n_rows = rows;
+    S.row_blocks = (uint32_t)std::max<uint64_t>(1, (rows + 255) / 256);
+    S.njobs = njobs;
+    S.log2_n2 = prm_.log2_n2;
+    S.inst = prm_.inst;
+    S.tab = (uint32_t*)d_tab_;
+    S.counter = (uint32_t*)d_misc_;
+    S.rdec = (uint32_t*)d_rdec_;
+    const uint32_t seed_grid = S.row_blocks + (njobs + 255) / 256;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(items_.size(), (uint64_t)num_cu_ * hot_wg_per_cu(hv, tune_.wg_per_cu)));
+    BHot A;
+    memset(&A, 0, sizeof A);
+    A.jobs = (const BJob*)d_jobs_;
+    A.items = (const BItem*)d_items_;
+    A.n_items = (uint32_t)items_.size();
+    A.log2_n2 = prm_.log2_n2;
+    A.tab = (const uint32_t*)d_tab_;
+    A.counter = (uint32_t*)d_misc_;
+    A.partials = (uint32_t*)d_part_;
+    const uint32_t* tg = prof->d_gtable;
+    auto launch_all = [&](hipStream_t q, bool timed) -> int {
+        hipLaunchKernelGGL(k_batch_seeds, dim3(seed_grid), dim3(256), 0, q, S);
+        if (timed) prof_begin(prof, POSLO_KT_BATCH_HOT, q);
+        int r = launch_hot(tune_.variant, grid, A, q);
+        if (timed) prof_end(prof, POSLO_KT_BATCH_HOT, q);
+        if (r) return r;
+        if (njobs)
+            hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs_,
+                               (const uint32_t*)d_part_, tg, (const uint32_t*)d_rdec_, (uint32_t*)d_res_);
+        return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
+    };
+    prof_begin(prof, POSLO_KT_BATCH, s);
+    if (use_graph) {
+        std::string gk;
+        key_bytes(gk, S);
+        key_bytes(gk, A);
+        key_bytes(gk, seed_grid);
+        key_bytes(gk, grid);
+        key_bytes(gk, tune_.variant);
+        key_bytes(gk, tg);
+        key_bytes(gk, d_res_);
+        auto it = graphs_.find(gk);
+        hipGraphExec_t exec = nullptr;
+        if (it != graphs_.end()) {
+            exec = it->second;
+        } else {
+            if (graphs_.size() >= 64) {
+                HIP_TRY(hipStreamSynchronize(s));
+                forget_graphs();
+            }
+            if (!capture_) HIP_TRY(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal));
+            int r = launch_all(capture_, false);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(capture_, &g);
+            if (r || ec != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return r ? r : POSLO_E_DEVICE;
+            }
+            hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ei != hipSuccess) return POSLO_E_DEVICE;
+            graphs_[gk] = exec;
+        }
+        HIP_TRY(hipGraphLaunch(exec, s));
+    } else {
+        if ((st = launch_all(s, prof->profile))) return st;
+    }
+    prof_end(prof, POSLO_KT_BATCH, s);
+    if (njobs) HIP_TRY(hipMemcpyAsync(h_res_, d_res_, njobs * 4, hipMemcpyDeviceToHost, s));
     return POSLO_OK;
 }
+
+int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s, poslo_ctx* prof) {
+    if (!prof || !prof->d_gtable) return POSLO_E_INVAL;
+    vtiles_.clear();
+    vbase_.clear();
+    n_checked_ = 0;
+    for (uint32_t j : which) {
+        if (j >= jobs_.size()) return POSLO_E_INVAL;
+        BJob& J = jobs_[j];
+        if (J.n && !J.sigs) return POSLO_E_INVAL;
+        J.vbase = n_checked_;
+        vbase_.push_back({n_checked_, j});
+        for (uint64_t f = 0; f < J.n; f += 256)
+            vtiles_.push_back(BItem{j, (uint32_t)std::min<uint64_t>(256, J.n - f), f});
+        n_checked_ += J.n;
+    }
+    if (n_checked_ >= (1ull << 32)) return POSLO_E_INVAL;
+    int st;
+    if ((st = grow(&d_vtiles_, &n_vtiles_b_, vtiles_.size() * sizeof(BItem))) ||
+        (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)))
+        return st;
+    h_misc_[0] = 0;
+    if (vtiles_.empty()) return POSLO_OK;
+    HIP_TRY(hipMemcpyAsync(d_jobs_, jobs_.data(), jobs_.size() * sizeof(BJob), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_vtiles_, vtiles_.data(), vtiles_.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
+    uint32_t* cnt = (uint32_t*)d_misc_ + 4;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cnt);
+    BVerify V;
+    V.jobs = (const BJob*)d_jobs_;
+    V.tiles = (const BItem*)d_vtiles_;
+    V.tg = prof->d_gtable;
+    V.inst = prm_.inst;
+    V.log2_n2 = prm_.log2_n2;
+    V.tab = (const uint32_t*)d_tab_;
+    V.idx = (uint64_t*)d_idx_;
+    V.count = cnt;
+    prof_begin(prof, POSLO_KT_VERIFY, s);
+    hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+    prof_end(prof, POSLO_KT_VERIFY, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h_misc_, cnt, 4, hipMemcpyDeviceToHost, s));
+    return POSLO_OK;
+}
+
+int BatchRunner::invalid(std::vector<std::pair<uint32_t, uint64_t>>& out, hipStream_t s) {
+    out.clear();
+    if (vtiles_.empty()) return POSLO_OK;
+    uint64_t count = (uint32_t)h_misc_[0];
+    if (count > n_checked_) return POSLO_E_DEVICE;
+    std::vector<uint64_t> slots(count);
+    if (count) {
+        HIP_TRY(hipMemcpyAsync(slots.data(), d_idx_, count * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::sort(slots.begin(), slots.end());
+    out.reserve(count);
+    for (uint64_t sl : slots) {
+        auto it = std::upper_bound(vbase_.begin(), vbase_.end(), std::make_pair(sl, UINT32_MAX));
+        uint32_t j = std::prev(it)->second;
+        out.push_back({j, jobs_[j].t0 + (sl - jobs_[j].vbase)});
+    }
+    std::sort(out.begin(), out.end());
+    return POSLO_OK;
+}
+
+}  // namespace poslo
+
+// ===========================================================================
+// synchronous entry points over a global entry layout
+// ===========================================================================
+
+using namespace poslo;
+
+namespace {
 
 struct BatchState {
-    // instantiated graphs keyed by the bytes of every launch argument
-    std::map<std::string, hipGraphExec_t> graphs;
-    hipStream_t capture = nullptr;  // private stream that graphs are captured on
+    BatchRunner runner;
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, poslo_tuning> tuned;  // (inst, log2 mean L, log2 n)
 };
 
@@ -496,11 +656,6 @@ BatchState& state_of(poslo_ctx* c) {
     return *s;
 }
 
-template <class T>
-void key_bytes(std::string& k, const T& v) {
-    k.append(reinterpret_cast<const char*>(&v), sizeof v);
-}
-
 uint32_t ilog2(uint64_t v) {
     uint32_t r = 0;
     while (v > 1) {
@@ -515,115 +670,63 @@ std::tuple<uint32_t, uint32_t, uint32_t> shape_class(const poslo_params* prm, ui
     return {prm->inst, ilog2(mean + 1), ilog2(n_total + 1)};
 }
 
-int default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 0 : 5; }
-
-// the pipeline: seeds and tag decode -> persistent hashing -> per-job checks
-int run_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs, uint32_t njobs, const uint8_t* data,
-              const uint64_t* offsets, uint64_t data_bytes, const poslo_tuning& tune, hipStream_t s, uint8_t* accept,
-              Plan& P, void** d_jobs_out, void** d_tab_out) {
-    const HotVariant& hv = kHot[tune.variant];
-    if ((uint32_t)hv.inst != prm->inst) return POSLO_E_INVAL;
-    int st = make_plan(c, prm, jobs, njobs, (uint32_t)hv.chunk, P);
-    if (st) return st;
-    void *d_jobs, *d_ds, *d_rows, *d_items, *d_tab, *d_part, *d_res, *d_misc, *d_rdec;
-    if ((st = upload(c, X_JOBS, P.jobs, s, &d_jobs)) || (st = upload(c, X_DS, P.ds, s, &d_ds)) ||
-        (st = upload(c, X_ROWS, P.job_of_row, s, &d_rows)) || (st = upload(c, X_ITEMS, P.items, s, &d_items)) ||
-        (st = ctx_scratch(c, X_TAB, std::max<size_t>(P.job_of_row.size(), 1) * kEpochWords * 4, &d_tab)) ||
-        (st = ctx_scratch(c, X_PART, std::max<size_t>(P.items.size(), 1) * 36, &d_part)) ||
-        (st = ctx_scratch(c, X_RESULT, std::max<size_t>(njobs, 1) * 4, &d_res)) ||
-        (st = ctx_scratch(c, X_MISC, 256, &d_misc)) ||
-        (st = ctx_scratch(c, X_RDEC, std::max<size_t>(njobs, 1) * 17 * 4, &d_rdec)))
-        return st;
-    *d_jobs_out = d_jobs;
-    *d_tab_out = d_tab;
-    BSeeds S;
-    memset(&S, 0, sizeof S);
-    S.jobs = (const BJob*)d_jobs;
-    S.ds = (const DsArg*)d_ds;
-    S.job_of_row = (const uint32_t*)d_rows;
-    S.n_rows = P.job_of_row.size();
-    S.row_blocks = (uint32_t)std::max<uint64_t>(1, (S.n_rows + 255) / 256);
-    S.njobs = njobs;
-    S.log2_n2 = prm->log2_n2;
-    S.inst = prm->inst;
-    S.tab = (uint32_t*)d_tab;
-    S.counter = (uint32_t*)d_misc;
-    S.rdec = (uint32_t*)d_rdec;
-    uint32_t seed_grid = S.row_blocks + (njobs + 255) / 256;
-    uint32_t grid = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>(P.items.size(), (uint64_t)c->num_cu * hot_wg_per_cu(hv, tune.wg_per_cu)));
-    BHot A;
-    memset(&A, 0, sizeof A);
-    A.jobs = (const BJob*)d_jobs;
-    A.items = (const BItem*)d_items;
-    A.n_items = (uint32_t)P.items.size();
-    A.log2_n2 = prm->log2_n2;
-    A.data = data;
-    A.offsets = offsets;
-    A.end = data_bytes ? data + data_bytes : nullptr;
-    A.tab = (const uint32_t*)d_tab;
-    A.counter = (uint32_t*)d_misc;
-    A.partials = (uint32_t*)d_part;
-    auto launch_all = [&](hipStream_t q, bool timed) -> int {
-        hipLaunchKernelGGL(k_batch_seeds, dim3(seed_grid), dim3(256), 0, q, S);
-        if (timed) prof_begin(c, POSLO_KT_BATCH_HOT, q);
-        int r = launch_hot(tune.variant, grid, A, q);
-        if (timed) prof_end(c, POSLO_KT_BATCH_HOT, q);
-        if (r) return r;
-        if (njobs)
-            hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs,
-                               (const uint32_t*)d_part, c->d_gtable, (const uint32_t*)d_rdec, (uint32_t*)d_res);
-        return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
-    };
-    prof_begin(c, POSLO_KT_BATCH, s);
-    if (tune.use_graph) {
-        std::string gk;
-        key_bytes(gk, S);
-        key_bytes(gk, A);
-        key_bytes(gk, seed_grid);
-        key_bytes(gk, grid);
-        key_bytes(gk, tune.variant);
-        key_bytes(gk, c->d_gtable);
-        key_bytes(gk, d_res);
-        BatchState& bs = state_of(c);
-        auto it = bs.graphs.find(gk);
-        hipGraphExec_t exec = nullptr;
-        if (it != bs.graphs.end()) {
-            exec = it->second;
-        } else {
-            if (bs.graphs.size() >= 64) {
-                HIP_TRY(hipStreamSynchronize(s));
-                for (auto& g : bs.graphs) hipGraphExecDestroy(g.second);
-                bs.graphs.clear();
-            }
-            if (!bs.capture) HIP_TRY(hipStreamCreateWithFlags(&bs.capture, hipStreamNonBlocking));
-            HIP_TRY(hipStreamBeginCapture(bs.capture, hipStreamCaptureModeThreadLocal));
-            int r = launch_all(bs.capture, false);
-            hipGraph_t g = nullptr;
-            hipError_t ec = hipStreamEndCapture(bs.capture, &g);
-            if (r || ec != hipSuccess) {
-                if (g) hipGraphDestroy(g);
-                return r ? r : POSLO_E_DEVICE;
-            }
-            hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            if (ei != hipSuccess) return POSLO_E_DEVICE;
-            bs.graphs[gk] = exec;
-        }
-        HIP_TRY(hipGraphLaunch(exec, s));
-    } else {
-        if ((st = launch_all(s, true))) return st;
+// resolve keys and express the global layout as per-job views
+int make_specs(poslo_ctx* c, const poslo_batch_job* jobs, uint32_t njobs, const uint8_t* data,
+               const uint64_t* offsets, uint64_t data_bytes, const uint8_t* sigs, std::vector<JobSpec>& specs) {
+    std::vector<uint8_t> pks((size_t)njobs * 32);
+    for (uint32_t j = 0; j < njobs; j++) {
+        if (!jobs[j].pk || !jobs[j].tag) return POSLO_E_INVAL;
+        if (jobs[j].n && (!data || !offsets)) return POSLO_E_INVAL;
+        if (jobs[j].entry_base > UINT64_MAX / 80 - jobs[j].n) return POSLO_E_INVAL;
+        memcpy(&pks[(size_t)j * 32], jobs[j].pk, 32);
     }
-    prof_end(c, POSLO_KT_BATCH, s);
-    std::vector<uint32_t> res(std::max<uint32_t>(njobs, 1));
-    if (njobs) HIP_TRY(hipMemcpyAsync(res.data(), d_res, njobs * 4, hipMemcpyDeviceToHost, s));
+    std::vector<const uint32_t*> tables;
+    int st = ctx_keys_bulk(c, pks.data(), njobs, tables, nullptr);
+    if (st) return st;
+    specs.resize(njobs);
+    for (uint32_t j = 0; j < njobs; j++) {
+        const poslo_batch_job& in = jobs[j];
+        JobSpec& sp = specs[j];
+        sp.ty = tables[j];
+        sp.data = data;
+        sp.offsets = offsets ? offsets + in.entry_base : nullptr;
+        sp.msg_len = 0;
+        sp.data_bytes = data_bytes;
+        sp.sigs = sigs ? sigs + 80 * in.entry_base : nullptr;
+        sp.t0 = in.t0;
+        sp.n = in.n;
+        sp.ds = in.ds;
+        sp.ds_len = in.ds_len;
+        sp.tag = in.tag;
+    }
+    return POSLO_OK;
+}
+
+int run_sync(poslo_ctx* c, BatchRunner& R, const poslo_params* prm, const std::vector<JobSpec>& specs,
+             const poslo_tuning& t, hipStream_t s, uint8_t* accept) {
+    int st = R.plan(prm, specs.data(), (uint32_t)specs.size(), t, c->num_cu);
+    if (st) return st;
+    if ((st = R.launch(s, t.use_graph != 0, c))) return st;
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
-    for (uint32_t j = 0; j < njobs; j++) accept[j] = (uint8_t)res[j];
+    for (uint32_t j = 0; j < R.njobs(); j++) accept[j] = (uint8_t)R.accept(j);
     return POSLO_OK;
 }
 
 }  // namespace
+
+namespace poslo {
+
+void batch_release(poslo_ctx* c) {
+    auto& m = states();
+    auto it = m.find(c);
+    if (it == m.end()) return;
+    hipDeviceSynchronize();
+    delete it->second;
+    m.erase(it);
+}
+
+}  // namespace poslo
 
 extern "C" int poslo_batch_variant_count(void) { return kNumHot; }
 
@@ -633,8 +736,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
                                   const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes,
                                   const uint8_t* sigs, int distill, const poslo_tuning* tuning, void* stream,
                                   uint8_t* accept, uint64_t* invalid, size_t cap, size_t* n_invalid) {
-    if (!c || !params_ok(prm) || (njobs && (!jobs || !accept)) || !offsets || distill < 0 || distill > 2)
-        return POSLO_E_INVAL;
+    if (!c || !params_ok(prm) || (njobs && (!jobs || !accept)) || distill < 0 || distill > 2) return POSLO_E_INVAL;
     if (distill && (!sigs || !n_invalid || (cap && !invalid))) return POSLO_E_INVAL;
     if (n_invalid) *n_invalid = 0;
     hipStream_t s = (hipStream_t)stream;
@@ -644,77 +746,32 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
     if (tuning) {
         t = *tuning;
     } else {
-        t.variant = default_variant(prm->inst);
+        t.variant = batch_default_variant(prm->inst);
         t.wg_per_cu = 0;
         t.use_graph = 0;
+        t.reserved = 0;
         uint64_t n_total = 0;
         for (uint32_t j = 0; j < njobs; j++) n_total += jobs[j].n;
         auto& tuned = state_of(c).tuned;
         auto it = tuned.find(shape_class(prm, n_total, data_bytes));
         if (it != tuned.end()) t = it->second;
     }
-    if (t.variant < 0 || t.variant >= kNumHot || kHot[t.variant].inst != (int)prm->inst) return POSLO_E_INVAL;
-    Plan P;
-    void *d_jobs, *d_tab;
-    int st = run_batch(c, prm, jobs, njobs, data, offsets, data_bytes, t, s, accept, P, &d_jobs, &d_tab);
+    std::vector<JobSpec> specs;
+    int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, sigs, specs);
     if (st) return st;
+    BatchRunner& R = state_of(c).runner;
+    if ((st = run_sync(c, R, prm, specs, t, s, accept))) return st;
     if (!distill) return POSLO_OK;
-    // individual verification of the entries of the rejected jobs (mode 1)
-    // or of every job (mode 2)
-    std::vector<BItem> tiles;
-    for (uint32_t j = 0; j < njobs; j++) {
-        if (accept[j] && distill == 1) continue;
-        for (uint64_t f = 0; f < jobs[j].n; f += 256)
-            tiles.push_back(BItem{j, (uint32_t)std::min<uint64_t>(256, jobs[j].n - f), f});
-    }
-    if (tiles.empty()) return POSLO_OK;
-    void *d_tiles, *d_flags, *d_idx, *d_misc;
-    uint64_t nt = P.n_total;
-    if ((st = upload(c, X_TILES, tiles, s, &d_tiles)) || (st = ctx_scratch(c, X_FLAGS, std::max<uint64_t>(nt, 1), &d_flags)) ||
-        (st = ctx_scratch(c, X_IDX, std::max<uint64_t>(nt, 1) * 8, &d_idx)) || (st = ctx_scratch(c, X_MISC, 256, &d_misc)))
-        return st;
-    hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, s, (uint8_t*)d_flags, nt);
-    BVerify V;
-    V.jobs = (const BJob*)d_jobs;
-    V.tiles = (const BItem*)d_tiles;
-    V.sigs = sigs;
-    V.tg = c->d_gtable;
-    V.inst = prm->inst;
-    V.log2_n2 = prm->log2_n2;
-    V.data = data;
-    V.offsets = offsets;
-    V.end = data_bytes ? data + data_bytes : nullptr;
-    V.tab = (const uint32_t*)d_tab;
-    V.flags = (uint8_t*)d_flags;
-    prof_begin(c, POSLO_KT_VERIFY, s);
-    hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)tiles.size()), dim3(256), 0, s, V);
-    hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(1024), 0, s, (const uint8_t*)d_flags, nt, (uint64_t*)d_idx,
-                       (uint64_t*)d_misc + 8);
-    HIP_TRY(hipGetLastError());
-    prof_end(c, POSLO_KT_VERIFY, s);
-    uint64_t count = 0;
-    HIP_TRY(hipMemcpyAsync(&count, (uint64_t*)d_misc + 8, 8, hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> which;
+    for (uint32_t j = 0; j < njobs; j++)
+        if (!accept[j] || distill == 2) which.push_back(j);
+    if ((st = R.launch_verify(which, s, c))) return st;
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
-    *n_invalid = count;
-    if (count > cap) return POSLO_OK;  // caller sees the count and may retry with room
-    std::vector<uint64_t> g(count);
-    if (count) {
-        HIP_TRY(hipMemcpyAsync(g.data(), d_idx, count * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
-    // global entry -> (job, t): jobs' entry ranges may come in any order
-    std::vector<std::pair<uint64_t, uint32_t>> starts(njobs);
-    for (uint32_t j = 0; j < njobs; j++) starts[j] = {jobs[j].entry_base, j};
-    std::sort(starts.begin(), starts.end());
     std::vector<std::pair<uint32_t, uint64_t>> out;
-    out.reserve(count);
-    for (uint64_t gi : g) {
-        auto it = std::upper_bound(starts.begin(), starts.end(), std::make_pair(gi, UINT32_MAX));
-        uint32_t j = std::prev(it)->second;
-        out.push_back({j, jobs[j].t0 + (gi - jobs[j].entry_base)});
-    }
-    std::sort(out.begin(), out.end());
+    if ((st = R.invalid(out, s))) return st;
+    *n_invalid = out.size();
+    if (out.size() > cap) return POSLO_OK;  // caller sees the count and may retry with room
     for (size_t k = 0; k < out.size(); k++) {
         invalid[2 * k] = out[k].first;
         invalid[2 * k + 1] = out[k].second;
@@ -725,10 +782,14 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
 extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs, uint32_t njobs,
                                     const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes, int reps,
                                     void* stream, poslo_tuning* best, double* best_ms) {
-    if (!c || !params_ok(prm) || !best || njobs == 0) return POSLO_E_INVAL;
+    if (!c || !params_ok(prm) || !best || njobs == 0 || !jobs) return POSLO_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if (reps < 1) reps = 3;
+    std::vector<JobSpec> specs;
+    int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, nullptr, specs);
+    if (st) return st;
+    BatchRunner& R = state_of(c).runner;
     std::vector<uint8_t> acc_ref(njobs), acc(njobs);
     double best_t = 1e30;
     poslo_tuning bt{-1, 0, 0, 0};
@@ -736,37 +797,29 @@ extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    auto done = [&](int code) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return code;
+    };
     for (int v = 0; v < kNumHot; v++) {
         if (kHot[v].inst != (int)prm->inst) continue;
         for (int wg : {0, 1, 2, 4}) {
             if (wg > 0 && wg * (kHot[v].block / 64) > 4 * kHot[v].waves_per_simd) continue;
             if (wg > 0 && (size_t)wg * (hot_lds_bytes(kHot[v]) + 512) > 160 * 1024) continue;
             poslo_tuning t{v, wg, 0, 0};
-            Plan P;
-            void *dj, *dt;
-            int st = run_batch(c, prm, jobs, njobs, data, offsets, data_bytes, t, s, acc.data(), P, &dj, &dt);
-            if (st) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-                return st;
-            }
+            if ((st = run_sync(c, R, prm, specs, t, s, acc.data()))) return done(st);
             // every candidate must agree on every job's verdict
             if (!have_ref) {
                 acc_ref = acc;
                 have_ref = true;
             } else if (acc != acc_ref) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-                return POSLO_E_DEVICE;
+                return done(POSLO_E_DEVICE);
             }
             double total = 0;
             for (int r = 0; r < reps; r++) {
                 hipEventRecord(e0, s);
-                if ((st = run_batch(c, prm, jobs, njobs, data, offsets, data_bytes, t, s, acc.data(), P, &dj, &dt))) {
-                    hipEventDestroy(e0);
-                    hipEventDestroy(e1);
-                    return st;
-                }
+                if ((st = run_sync(c, R, prm, specs, t, s, acc.data()))) return done(st);
                 hipEventRecord(e1, s);
                 hipEventSynchronize(e1);
                 float ms = 0;
@@ -779,8 +832,7 @@ extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    done(0);
     uint64_t n_total = 0;
     for (uint32_t j = 0; j < njobs; j++) n_total += jobs[j].n;
     state_of(c).tuned[shape_class(prm, n_total, data_bytes)] = bt;
@@ -788,21 +840,6 @@ extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const
     if (best_ms) *best_ms = best_t;
     return POSLO_OK;
 }
-
-namespace poslo {
-
-void batch_release(poslo_ctx* c) {
-    auto& m = states();
-    auto it = m.find(c);
-    if (it == m.end()) return;
-    hipDeviceSynchronize();
-    for (auto& g : it->second->graphs) hipGraphExecDestroy(g.second);
-    if (it->second->capture) hipStreamDestroy(it->second->capture);
-    delete it->second;
-    m.erase(it);
-}
-
-}  // namespace poslo
 
 extern "C" int poslo_batch_forget(poslo_ctx* c) {
     if (!c) return POSLO_E_INVAL;

@@ -149,3 +149,76 @@ def single_signer_fixed(ctx, inst: int, n: int, L: int, log2_n1: int, log2_n2: i
         _flip(torch, view, log.plan)
     torch.cuda.synchronize(dev)
     return log
+
+
+@dataclass
+class ServingLog:
+    params: object
+    L: int
+    data: object          # CUDA uint8 tensor (total, L)
+    sigs: object          # CUDA uint8 tensor (80 total)
+    pks: list[bytes]      # by key id
+    requests: list[dict]  # key, t0, n, base, ds, tag, flip: (entry in request, bit) or None
+
+    def expected(self, r: int, distill: int):
+        """(accept, invalid t list) the flips fix for request r."""
+        q = self.requests[r]
+        if q["flip"] is None:
+            return True, []
+        e, bit = q["flip"]
+        msg = bit < 8 * self.L
+        inv = [q["t0"] + e] if (distill == 2 or msg) else []
+        return not msg, inv
+
+
+def serving_requests(ctx, inst: int, n_keys: int, n_requests: int, max_batch: int, L: int, p_corrupt: float,
+                     seed: int, log2_n1: int = 12, log2_n2: int = 8) -> ServingLog:
+    """n_requests requests over n_keys signers: request r is for key
+    uniform in [0, n_keys), with a log-uniform [1, max_batch] entry count,
+    continuing that key's log (t0 = the entries its earlier requests
+    covered); L-byte messages; with probability p_corrupt a request gets one
+    flipped bit in one uniform entry, uniform over the 8 (L + 80) bits of
+    m_t || sigma_t (its tag stays the honest one)."""
+    import torch
+
+    params = make_params(inst, log2_n1, log2_n2)
+    keys_of = synthlog.uniform_ints(seed, 0, n_requests, 0, n_keys - 1)
+    counts = synthlog.log_uniform_counts(seed, 1, n_requests, max_batch)
+    g = synthlog.Xoshiro256ss(synthlog.stream_seed(seed, 2))
+    next_t = [0] * n_keys
+    reqs, base = [], 0
+    cap = 1 << (log2_n1 + log2_n2)
+    for r in range(n_requests):
+        k, n = keys_of[r], counts[r]
+        if next_t[k] + n > cap:
+            raise ValueError("a key's log outgrew its parameter set")
+        flip = None
+        if g.uniform01() < p_corrupt:
+            flip = (g.below(n), g.below(8 * (L + 80)))
+        reqs.append(dict(key=k, t0=next_t[k], n=n, base=base, flip=flip))
+        next_t[k] += n
+        base += n
+    total = base
+    dev = torch.device("cuda", ctx.device)
+    data = torch.empty((max(1, total), L), dtype=torch.uint8, device=dev)
+    poslo_synth_messages(seed + 1, poslo_msgs(data.data_ptr(), None, L, total, 0, total * L), data)
+    offs = torch.arange(0, (total + 1) * L, L, dtype=torch.int64, device=dev)
+    keys = poslo_gpu_keys_create(ctx, params, [synthlog.derived_key_seed(seed + 3, k) for k in range(n_keys)])
+    sigs = torch.empty(max(1, 80 * total), dtype=torch.uint8, device=dev)
+    tags, ds = poslo_gpu_sign(keys, [(q["key"], q["t0"], q["n"], q["base"]) for q in reqs], data, offs, sigs)
+    for q, t, d in zip(reqs, tags, ds):
+        q["tag"], q["ds"] = t, d
+    log = ServingLog(params=params, L=L, data=data[:total], sigs=sigs[:80 * total], pks=list(keys.pks),
+                     requests=reqs)
+    del keys
+    plan = []
+    for q in reqs:
+        if q["flip"] is not None:
+            plan.append((q["base"] + q["flip"][0], q["flip"][1]))
+    if plan:
+        view = MultiSignerLog(params=params, counts=[total], lengths=np.full(total, L),
+                              offsets=np.arange(total + 1) * L, data=log.data.view(-1), d_offsets=offs,
+                              sigs=log.sigs, pks=[], jobs=[])
+        _flip(torch, view, sorted(plan))
+    torch.cuda.synchronize(dev)
+    return log

@@ -104,3 +104,31 @@ def test_ccd_serialization_roundtrip_and_strictness(P):
     for bad in (blob[:-1], blob + b"\0", b"XCCD" + blob[4:]):
         with pytest.raises(P.PosloError):
             P.poslo_ccd_import(bad)
+
+
+def test_request_keeps_device_buffers_alive(P):
+    """A queued request's device buffers must outlive the caller's
+    references: the server reads them when the request is launched."""
+    import gc
+    import weakref
+
+    class DeviceBuffer:  # stands in for a CUDA tensor (data_ptr, numel)
+        def __init__(self, n):
+            self.n = n
+
+        def data_ptr(self):
+            return 0x10000
+
+        def numel(self):
+            return self.n
+
+    bufs = [DeviceBuffer(16), DeviceBuffer(2), DeviceBuffer(80)]
+    refs = [weakref.ref(b) for b in bufs]
+    q = P.Request(0, 0, 1, bufs[0], bufs[1], 0, bufs[2], b"\x00", bytes(64))
+    assert q.req.on_device == 1 and q.req.data_bytes == 16
+    del bufs
+    gc.collect()
+    assert all(r() is not None for r in refs)
+    del q
+    gc.collect()
+    assert all(r() is None for r in refs)

@@ -15,7 +15,11 @@ The same run also measures, each on its own synthetic log:
  - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
    [64, 512]-byte messages, 0.1% flipped entries, verified in one persistent
    launch (autotuned) against the plain path (one AVer call per signer),
-   plus the invalid set of every signer (AVer + individual checks).
+   plus the invalid set of every signer (AVer + individual checks);
+ - serving: requests from 10,000 resident keys with log-uniform [1, 2^18]
+   entries of 128-byte messages, 0.5% of requests with a flipped bit,
+   submitted at Poisson arrival times of fixed rates and in one burst to the
+   serving loop; p50/p99 submit-to-result latency and entries/s.
 Prints one JSON line.
 """
 
@@ -46,6 +50,8 @@ CONFIGS = {
 }
 DISTILL = dict(n=1 << 20, L=256, log2_n1=12, log2_n2=8, seed=3, frac=0.01, umbrellas=64)
 BATCHED = dict(signers=4096, max_batch=65536, len_lo=64, len_hi=512, frac=0.001, seed=4, log2_n1=8, log2_n2=8)
+SERVING = dict(keys=10000, distinct=1500, max_batch=1 << 18, L=128, p_corrupt=0.005, seed=5, submissions=4000,
+               qps=(2000, 10000, 40000))
 
 
 # ---------------------------------------------------------------------------
@@ -310,6 +316,83 @@ def bench_batched(P, torch, ctx, inst, steps):
     }
 
 
+def serve_run(P, srv, reqs, order, qps):
+    """Submit reqs[order[k]] at Poisson times of rate qps (all at once when
+    qps is 0) from this thread; returns the results and the wall time from
+    the first submission to the last result."""
+    import random
+    rng = random.Random(11)
+    results = {}
+    t_first = time.perf_counter()
+    t_next = t_first
+    for k in order:
+        if qps:
+            t_next += rng.expovariate(qps)
+            while time.perf_counter() < t_next:
+                pass
+        srv.submit(reqs[k])
+        for r in srv.poll(256):
+            results[r.ticket] = r
+    while len(results) < len(order):
+        for r in srv.poll(1024, timeout_ms=20):
+            results[r.ticket] = r
+    wall = time.perf_counter() - t_first
+    return list(results.values()), wall
+
+
+def bench_serving(P, torch, ctx, inst):
+    from paper_2506_08781_amd import workloads
+    c = SERVING
+    t = time.perf_counter()
+    log = workloads.serving_requests(ctx, inst, c["keys"], c["distinct"], c["max_batch"], c["L"], c["p_corrupt"],
+                                     seed=c["seed"])
+    n_entries = [q["n"] for q in log.requests]
+    print(f"# serving: {len(log.requests)} distinct requests, {sum(n_entries)} entries, ready in "
+          f"{time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    srv = P.Server(0, log.params, n_streams=4, max_group=256, distill=1)
+    srv.register_keys(list(range(c["keys"])), log.pks)
+    L = log.L
+    reqs = []
+    for r, q in enumerate(log.requests):
+        b, n = q["base"], q["n"]
+        reqs.append(P.Request(q["key"], q["t0"], n, log.data[b:b + n], None, L, log.sigs[80 * b:80 * (b + n)],
+                              q["ds"], q["tag"], user=r, data_bytes=n * L))
+    import random
+    rng = random.Random(3)
+    # warm the streams' buffers with one pass over every distinct request
+    res, _ = serve_run(P, srv, reqs, list(range(len(reqs))), 0)
+    for r in res:
+        acc, inv = log.expected(r.user, 1)
+        assert r.status == P.POSLO_OK and bool(r.accept) == acc and r.n_invalid == len(inv), f"request {r.user}"
+        if r.n_invalid:
+            assert srv.take_invalid(r.ticket, r.n_invalid) == inv
+    runs = []
+    for qps in list(c["qps"]) + [0]:
+        order = [rng.randrange(len(reqs)) for _ in range(c["submissions"])]
+        res, wall = serve_run(P, srv, reqs, order, qps)
+        ok = all(r.status == P.POSLO_OK and bool(r.accept) == log.expected(r.user, 1)[0] for r in res)
+        for r in res:
+            if r.n_invalid:
+                srv.take_invalid(r.ticket, r.n_invalid)
+        lat = [r.t_done_ms - r.t_submit_ms for r in res]
+        ent = sum(r.entries for r in res)
+        runs.append({"qps": qps if qps else "burst", "requests": len(res), "entries": ent,
+                     "entries_per_s": ent / wall, "wall_s": wall, "correct": ok,
+                     "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)}})
+        assert ok, "a served result differs from what its flips fix"
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": f"serving: Poisson arrivals from {c['keys']} resident keys, requests of log-uniform "
+                    f"[1, 2^18] entries of {L}-byte messages, {c['p_corrupt'] * 100:.1f}% of requests with one "
+                    f"flipped bit, {len(reqs)} distinct requests resubmitted, invalid entries of rejected "
+                    f"requests reported",
+        "runs": runs,
+        "groups_launched": st.groups_launched,
+        "device_bytes_peak": st.bytes_peak,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,8 +400,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--inst", default="aes", choices=["aes", "sha"])
-    ap.add_argument("--sections", default="plain,distill,batched",
-                    help="comma list of plain, distill, batched (plain always runs)")
+    ap.add_argument("--sections", default="plain,distill,batched,serving",
+                    help="comma list of plain, distill, batched, serving (plain always runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -382,6 +465,9 @@ def main():
         torch.cuda.empty_cache()
     if "batched" in sections:
         out["multi_signer"] = bench_batched(P, torch, ctx, inst, max(3, args.steps // 2))
+        torch.cuda.empty_cache()
+    if "serving" in sections:
+        out["serving"] = bench_serving(P, torch, ctx, inst)
         torch.cuda.empty_cache()
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -264,12 +264,21 @@ def bench_batched(P, torch, ctx, inst, steps):
     graph_total = time.perf_counter() - t0
     assert acc == want_acc
 
-    # AVer plus the exact invalid set of every signer (SeBVer's input)
-    t0 = time.perf_counter()
-    acc, inv = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2,
-                                    tuning=graph, cap=len(want_inv) + 16)
-    distill_s = time.perf_counter() - t0
-    assert acc == want_acc and inv == want_inv, "batched invalid set differs from the injected flips"
+    # AVer plus the exact invalid set of every signer (SeBVer's input), with
+    # one individual check per entry and with the group schedule
+    sets = {}
+    for name, mode in (("per_entry", 2), ("groups", 2 | P.POSLO_DISTILL_GROUPS)):
+        P.poslo_ctx_profile(ctx, True)
+        reset_times(P, ctx)
+        t0 = time.perf_counter()
+        acc, inv = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=mode,
+                                        tuning=graph, cap=len(want_inv) + 16)
+        dt = time.perf_counter() - t0
+        P.poslo_ctx_profile(ctx, False)
+        assert acc == want_acc and inv == want_inv, "batched invalid set differs from the injected flips"
+        sets[name] = {"entries_per_s": total_entries / dt, "ms": 1e3 * dt,
+                      "check_kernels_ms": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
+                      "rejected": acc.count(False), "invalid": len(inv)}
 
     # plain path: one AVer call per signer on the same device buffers
     plain_lat = []
@@ -304,8 +313,7 @@ def bench_batched(P, torch, ctx, inst, steps):
                     "eager_entries_per_s": total_entries * steps / eager_total,
                     "eager_latency_ms": lat_summary(lat),
                     "hashes_per_s": hashes * steps / graph_total},
-        "batched_with_invalid_sets": {"entries_per_s": total_entries / distill_s, "ms": 1e3 * distill_s,
-                                      "rejected": acc.count(False), "invalid": len(inv)},
+        "batched_with_invalid_sets": sets,
         "plain": {"entries_per_s": total_entries / plain_total, "ms_per_pass": 1e3 * plain_total,
                   "per_signer_latency_ms": lat_summary(plain_lat)},
         "speedup_vs_plain": graph_eps / (total_entries / plain_total),

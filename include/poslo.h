@@ -300,6 +300,8 @@ typedef struct poslo_batch_job {
  * entries per work item, length sort), workgroups per CU of the persistent
  * grid (0 = derived from LDS and wave budget), and whether to capture the
  * launch sequence in a hipGraph that is replayed for identical shapes. */
+#define POSLO_DISTILL_GROUPS 4
+
 typedef struct poslo_tuning {
     int variant;
     int wg_per_cu;
@@ -322,6 +324,14 @@ const char* poslo_batch_variant_name(int v);
  * entries of rejected jobs are verified individually (Distill's check);
  * 2 = the entries of every job are (AVer reads only messages, ds and tag,
  * so a corrupted signature in an accepted job is found by mode 2 only).
+ * Or-ing POSLO_DISTILL_GROUPS into the mode selects the group schedule:
+ * every entry is screened (x check, s < q, strict R decode), the sums of
+ * groups of 8 entries are checked against (sum e)*Y + (sum s)*G, and only
+ * the entries of failing groups are verified one by one.  Both schedules
+ * return the same set unless the errors of several invalid entries of one
+ * group cancel exactly (for independent corruptions, probability about 1/q
+ * per pair; a forger can arrange it, so audits of adversarial logs use the
+ * plain schedule).
  * sigs: device, 80 bytes per global entry.  The invalid entries are
  * returned as sorted (job, t) pairs in invalid (host, 2*cap u64);
  * *n_invalid gets the count even when it exceeds cap (the pairs are then
@@ -366,7 +376,8 @@ typedef struct poslo_server_cfg {
     uint64_t mem_bytes;   /* device budget for admitted requests: staging copies of host
                              buffers and per-request scratch (0: 8 GiB) */
     int distill;          /* 0: accept bit only; 1: invalid entries of rejected requests;
-                             2: invalid entries of every request */
+                             2: invalid entries of every request; | POSLO_DISTILL_GROUPS:
+                             group schedule (see poslo_verify_batch) */
     int variant;          /* hot-kernel variant (-1: the default of the instantiation) */
 } poslo_server_cfg;
 

@@ -28,6 +28,7 @@ POSLO_E_SEED = -4
 POSLO_E_ENCODING = -5
 POSLO_E_EXHAUSTED = -6
 POSLO_E_BUSY = -7
+POSLO_DISTILL_GROUPS = 4
 
 
 class PosloError(RuntimeError):

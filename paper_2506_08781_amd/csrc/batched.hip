@@ -294,7 +294,164 @@ __global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
     }
 }
 
+// ---- group-check schedule of the individual checks --------------------------
+// Each wave screens 64 entries of one job (x check, s < q, strict R decode,
+// e_t); entries failing the screen are invalid.  The others are summed in
+// groups of 8 lanes, (sum e)*Y + (sum s)*G == sum R is checked per group
+// with the whole wave, and only the entries of failing groups are verified
+// one by one afterwards (k_batch_leaf).  One invalid entry makes its group's
+// sums differ, so a passing group holds no invalid entry unless the errors
+// of several invalid entries cancel (for independent corruptions, with
+// probability about 1/q per pair).
+
+struct BScreen {
+    const BJob* jobs;
+    const BItem* tiles;
+    const uint32_t* tg;
+    uint32_t inst;
+    uint32_t log2_n2;
+    const uint32_t* tab;
+    uint64_t* idx;       // invalid slots
+    uint32_t* count;
+    uint64_t* sus;       // suspects: job << 32 | entry offset
+    uint32_t* sus_count;
+};
+
+__device__ __forceinline__ void shfl_xor_point(ge& Q, const ge& P, int m) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        Q.X.v[k] = __shfl_xor(P.X.v[k], m);
+        Q.Y.v[k] = __shfl_xor(P.Y.v[k], m);
+        Q.Z.v[k] = __shfl_xor(P.Z.v[k], m);
+        Q.T.v[k] = __shfl_xor(P.T.v[k], m);
+    }
+}
+
+__device__ __forceinline__ void shfl_point(ge& Q, const ge& P, int src) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        Q.X.v[k] = __shfl(P.X.v[k], src);
+        Q.Y.v[k] = __shfl(P.Y.v[k], src);
+        Q.Z.v[k] = __shfl(P.Z.v[k], src);
+        Q.T.v[k] = __shfl(P.T.v[k], src);
+    }
+}
+
+// append `value` for every lane with `flag` set: one atomic per wave
+__device__ __forceinline__ void wave_append(bool flag, uint64_t value, uint64_t* list, uint32_t* count) {
+    const uint64_t mask = __ballot(flag);
+    if (!mask) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)leader);
+    if (flag) list[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = value;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_screen(BScreen V) {
+    __shared__ uint32_t lds[4 * 256];
+    __shared__ uint32_t gsum[4][8][48];  // per wave and group: e, s, R (X, Y, Z, T)
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    const BItem it = V.tiles[blockIdx.x];
+    const bool active = threadIdx.x < it.count;
+    if (__ballot(active) == 0) return;  // whole wave past the tile's end
+    const BJob& J = V.jobs[it.job];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t p = it.first + threadIdx.x;
+    uint32_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    ge R;
+    ge_identity(R);
+    bool ok = false;
+    if (active) {
+        BatchArgs a = job_args(J, V.log2_n2, V.tab);
+        ok = screen_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, e, s, R);
+        if (!ok) {
+            for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
+            ge_identity(R);
+        }
+    }
+    const bool pre_bad = active && !ok;
+    // sums over groups of 8 lanes (every lane of a group ends with the sum)
+#pragma unroll 1
+    for (int m = 1; m < 8; m <<= 1) {
+        uint32_t oe[8], os[8];
+        for (int k = 0; k < 8; k++) {
+            oe[k] = __shfl_xor(e[k], m);
+            os[k] = __shfl_xor(s[k], m);
+        }
+        sc_add(e, e, oe);
+        sc_add(s, s, os);
+        ge Q;
+        shfl_xor_point(Q, R, m);
+        ge_add(R, R, Q);
+    }
+    // park the group sums in LDS, then one check per group by the whole wave
+    uint32_t (*gs)[48] = gsum[threadIdx.x >> 6];
+    if ((lane & 7) == 0) {
+        uint32_t* o = gs[lane >> 3];
+        for (int k = 0; k < 8; k++) {
+            o[k] = e[k];
+            o[8 + k] = s[k];
+        }
+        store_point(o + 16, R);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t fail = 0;
+#pragma unroll 1
+    for (int g = 0; g < 8; g++) {
+        uint32_t eg[8], sg[8];
+        for (int k = 0; k < 8; k++) {
+            eg[k] = gs[g][k];
+            sg[k] = gs[g][8 + k];
+        }
+        ge Rg, P;
+        load_point(Rg, gs[g] + 16);
+        wave_double_scalar(P, J.ty, V.tg, eg, sg);
+        uint32_t eq = 0;
+        if (lane == 0) {
+            fe a1, b1, a2, b2;
+            fe_mul(a1, P.X, Rg.Z);
+            fe_mul(b1, Rg.X, P.Z);
+            fe_mul(a2, P.Y, Rg.Z);
+            fe_mul(b2, Rg.Y, P.Z);
+            eq = (fe_equal(a1, b1) && fe_equal(a2, b2)) ? 1u : 0u;
+        }
+        eq = __shfl(eq, 0);
+        if (!eq) fail |= 1u << g;
+    }
+    const bool suspect = active && ok && ((fail >> (lane >> 3)) & 1u);
+    wave_append(pre_bad, J.vbase + p, V.idx, V.count);
+    wave_append(suspect, ((uint64_t)it.job << 32) | p, V.sus, V.sus_count);
+}
+
+// individual checks of the suspects, grid-stride over the device count
+__global__ __launch_bounds__(256) void k_batch_leaf(BVerify V, const uint64_t* sus, const uint32_t* sus_count) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    const uint32_t n = *sus_count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t w = sus[i];
+        const BJob& J = V.jobs[(uint32_t)(w >> 32)];
+        const uint64_t p = (uint32_t)w;
+        BatchArgs a = job_args(J, V.log2_n2, V.tab);
+        uint32_t e[8], s[8];
+        const bool bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
+        wave_append(bad, J.vbase + p, V.idx, V.count);
+    }
+}
+
 __global__ void k_zero_u32(uint32_t* p) { p[0] = 0; }
+__global__ void k_zero2_u32(uint32_t* p, uint32_t* q) {
+    p[0] = 0;
+    q[0] = 0;
+}
 
 // ---- tuning --------------------------------------------------------------------
 
@@ -356,7 +513,8 @@ using namespace hostside;
 BatchRunner::~BatchRunner() {
     forget_graphs();
     if (capture_) hipStreamDestroy(capture_);
-    for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_})
+    for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_,
+                    d_sus_})
         if (p) hipFree(p);
     if (h_res_) hipHostFree(h_res_);
     if (h_misc_) hipHostFree(h_misc_);
@@ -563,7 +721,7 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof) {
     return POSLO_OK;
 }
 
-int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s, poslo_ctx* prof) {
+int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s, poslo_ctx* prof, bool groups) {
     if (!prof || !prof->d_gtable) return POSLO_E_INVAL;
     vtiles_.clear();
     vbase_.clear();
@@ -581,14 +739,16 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     if (n_checked_ >= (1ull << 32)) return POSLO_E_INVAL;
     int st;
     if ((st = grow(&d_vtiles_, &n_vtiles_b_, vtiles_.size() * sizeof(BItem))) ||
-        (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)))
+        (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)) ||
+        (groups && (st = grow(&d_sus_, &n_sus_b_, n_checked_ * 8))))
         return st;
     h_misc_[0] = 0;
     if (vtiles_.empty()) return POSLO_OK;
     HIP_TRY(hipMemcpyAsync(d_jobs_, jobs_.data(), jobs_.size() * sizeof(BJob), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_vtiles_, vtiles_.data(), vtiles_.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
     uint32_t* cnt = (uint32_t*)d_misc_ + 4;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cnt);
+    uint32_t* sus_cnt = (uint32_t*)d_misc_ + 5;
+    hipLaunchKernelGGL(k_zero2_u32, dim3(1), dim3(1), 0, s, cnt, sus_cnt);
     BVerify V;
     V.jobs = (const BJob*)d_jobs_;
     V.tiles = (const BItem*)d_vtiles_;
@@ -599,7 +759,25 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.idx = (uint64_t*)d_idx_;
     V.count = cnt;
     prof_begin(prof, POSLO_KT_VERIFY, s);
-    hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+    if (groups) {
+        BScreen G;
+        G.jobs = V.jobs;
+        G.tiles = V.tiles;
+        G.tg = V.tg;
+        G.inst = V.inst;
+        G.log2_n2 = V.log2_n2;
+        G.tab = V.tab;
+        G.idx = V.idx;
+        G.count = cnt;
+        G.sus = (uint64_t*)d_sus_;
+        G.sus_count = sus_cnt;
+        hipLaunchKernelGGL(k_batch_screen, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
+        uint32_t leaf_grid = (uint32_t)std::min<uint64_t>((n_checked_ + 255) / 256, (uint64_t)num_cu_ * 8);
+        hipLaunchKernelGGL(k_batch_leaf, dim3(std::max<uint32_t>(leaf_grid, 1)), dim3(256), 0, s, V,
+                           (const uint64_t*)d_sus_, (const uint32_t*)sus_cnt);
+    } else {
+        hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+    }
     prof_end(prof, POSLO_KT_VERIFY, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h_misc_, cnt, 4, hipMemcpyDeviceToHost, s));
@@ -736,6 +914,8 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
                                   const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes,
                                   const uint8_t* sigs, int distill, const poslo_tuning* tuning, void* stream,
                                   uint8_t* accept, uint64_t* invalid, size_t cap, size_t* n_invalid) {
+    const bool groups = (distill & POSLO_DISTILL_GROUPS) != 0;
+    distill &= ~POSLO_DISTILL_GROUPS;
     if (!c || !params_ok(prm) || (njobs && (!jobs || !accept)) || distill < 0 || distill > 2) return POSLO_E_INVAL;
     if (distill && (!sigs || !n_invalid || (cap && !invalid))) return POSLO_E_INVAL;
     if (n_invalid) *n_invalid = 0;
@@ -765,7 +945,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
     std::vector<uint32_t> which;
     for (uint32_t j = 0; j < njobs; j++)
         if (!accept[j] || distill == 2) which.push_back(j);
-    if ((st = R.launch_verify(which, s, c))) return st;
+    if ((st = R.launch_verify(which, s, c, groups))) return st;
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
     std::vector<std::pair<uint32_t, uint64_t>> out;

@@ -142,4 +142,36 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
     return ge_encodes_to(P, r);
 }
 
+// The per-entry part of a group check: x_t equals the re-derived one-time
+// seed, s_t < q and the R_t bytes decode (strictly, so that a decoded R_t
+// encodes back to the same bytes).  On success e_t (mod q), s_t and R_t are
+// returned; the entry is then valid exactly when e_t*Y + s_t*G == R_t.
+template <class T>
+__device__ __forceinline__ bool screen_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
+                                           uint64_t pos, const uint8_t* sg, uint32_t e[8], uint32_t s[8], ge& R) {
+    uint32_t x[4], xs[4];
+    for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
+    EntryView ev = entry_view(a, pos);
+    uint32_t dig[8];
+    if (inst == INST_AES) {
+        one_time_seed_aes(tb, a, pos, x);
+        if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
+    } else {
+        one_time_seed_sha(a, pos, x);
+        if ((bswap32(x[0]) ^ xs[0]) | (bswap32(x[1]) ^ xs[1]) | (bswap32(x[2]) ^ xs[2]) | (bswap32(x[3]) ^ xs[3]))
+            return false;
+    }
+    for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+    if (!sc_is_canonical(s)) return false;
+    uint8_t rb[32];
+    for (int k = 0; k < 8; k++) store_le32(rb + 4 * k, load_le32(sg + 32 + 4 * k));
+    if (!ge_decode(R, rb)) return false;
+    if (inst == INST_AES)
+        digest_mdc2_any(tb, ev, end, x, dig, Mdc2BlockGeneric{});
+    else
+        digest_sha_any(ev, end, x, dig);
+    sc_reduce256(e, dig);
+    return true;
+}
+
 }  // namespace poslo

@@ -101,7 +101,59 @@ PD void fe_mul(fe& r, const fe& a, const fe& b) {
     r.v[0] += (uint32_t)c * 38u;
 }
 
-PD void fe_sq(fe& r, const fe& a) { fe_mul(r, a, a); }
+// a^2 with 36 limb products: the 28 cross products once, doubled by a
+// shift, plus the 8 squares
+PD void fe_sq(fe& r, const fe& a) {
+    uint32_t t[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) t[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+        uint64_t c = 0;
+#pragma unroll
+        for (int j = i + 1; j < 8; j++) {
+            c += (uint64_t)a.v[i] * a.v[j] + t[i + j];
+            t[i + j] = (uint32_t)c;
+            c >>= 32;
+        }
+        t[i + 8] = (uint32_t)c;
+    }
+    uint32_t top = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        uint32_t nt = (t[k] << 1) | top;
+        top = t[k] >> 31;
+        t[k] = nt;
+    }
+    uint64_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        uint64_t sq = (uint64_t)a.v[i] * a.v[i];
+        c += (uint64_t)t[2 * i] + (uint32_t)sq;
+        t[2 * i] = (uint32_t)c;
+        c >>= 32;
+        c += (uint64_t)t[2 * i + 1] + (sq >> 32);
+        t[2 * i + 1] = (uint32_t)c;
+        c >>= 32;
+    }
+    // fold the high half: t_lo + 38 * t_hi
+    uint32_t u[8];
+    c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        c += (uint64_t)t[i + 8] * 38u + t[i];
+        u[i] = (uint32_t)c;
+        c >>= 32;
+    }
+    c *= 38;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        c += u[i];
+        r.v[i] = (uint32_t)c;
+        c >>= 32;
+    }
+    r.v[0] += (uint32_t)c * 38u;
+}
 
 PD void fe_sqn(fe& r, const fe& a, int n) {
     fe_sq(r, a);

@@ -304,11 +304,12 @@ void poslo_server::finish_group(Slot& sl, const std::vector<std::vector<uint64_t
 
 void poslo_server::complete(Slot& sl) {
     if (sl.phase == 1) {
+        const int mode = cfg.distill & ~POSLO_DISTILL_GROUPS;
         std::vector<uint32_t> which;
         for (uint32_t k = 0; k < sl.group.size(); k++)
-            if (cfg.distill == 2 || (cfg.distill == 1 && !sl.runner.accept(k))) which.push_back(k);
+            if (mode == 2 || (mode == 1 && !sl.runner.accept(k))) which.push_back(k);
         if (!which.empty()) {
-            int st = sl.runner.launch_verify(which, sl.stream, ctx);
+            int st = sl.runner.launch_verify(which, sl.stream, ctx, (cfg.distill & POSLO_DISTILL_GROUPS) != 0);
             if (st == POSLO_OK && hipEventRecord(sl.ev, sl.stream) == hipSuccess) {
                 sl.phase = 2;
                 return;
@@ -425,7 +426,9 @@ void poslo_server::run() {
 }
 
 extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out) {
-    if (!cfg || !out || !params_ok(&cfg->params) || cfg->distill < 0 || cfg->distill > 2) return POSLO_E_INVAL;
+    if (!cfg || !out || !params_ok(&cfg->params)) return POSLO_E_INVAL;
+    const int mode = cfg->distill & ~POSLO_DISTILL_GROUPS;
+    if (mode < 0 || mode > 2) return POSLO_E_INVAL;
     if (cfg->variant >= batch_variant_count() ||
         (cfg->variant >= 0 && batch_variant(cfg->variant).inst != (int)cfg->params.inst))
         return POSLO_E_INVAL;

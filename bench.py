@@ -179,30 +179,36 @@ def bench_distill(P, torch, ctx, inst, steps):
     ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
     assert ccd.invalid() == want, "invalid set differs from the injected flips"
     del ccd
-    P.poslo_ctx_profile(ctx, True)
-    reset_times(P, ctx)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        s = time.perf_counter()
-        ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
-        lat.append(time.perf_counter() - s)
-        del ccd
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    P.poslo_ctx_profile(ctx, False)
     n = c["n"]
-    return {
+    out = {
         "workload": f"Distill, 2^20 entries x 256 B, {int(c['frac'] * 100)}% entries with one flipped bit, "
                     f"{c['umbrellas']} umbrellas",
-        "entries_per_s": n * steps / total,
-        "ms_per_step": 1e3 * total / steps,
-        "latency_ms": lat_summary(lat),
         "invalid": len(want),
-        "kernel_ms": {"verify": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
-                      "compact": kernel_ms(P, ctx, P.POSLO_KT_COMPACT)},
     }
+    for name, groups in (("per_entry", False), ("groups", True)):
+        P.poslo_ctx_set_distill_schedule(ctx, groups)
+        ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
+        assert ccd.invalid() == want, "invalid set differs from the injected flips"
+        del ccd
+        P.poslo_ctx_profile(ctx, True)
+        reset_times(P, ctx)
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s = time.perf_counter()
+            ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
+            lat.append(time.perf_counter() - s)
+            del ccd
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        P.poslo_ctx_profile(ctx, False)
+        out[name] = {"entries_per_s": n * steps / total, "ms_per_step": 1e3 * total / steps,
+                     "latency_ms": lat_summary(lat),
+                     "kernel_ms": {"checks": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
+                                   "fold_and_compact": kernel_ms(P, ctx, P.POSLO_KT_COMPACT)}}
+    P.poslo_ctx_set_distill_schedule(ctx, False)
+    return out
 
 
 def bench_batched(P, torch, ctx, inst, steps):

@@ -194,6 +194,13 @@ int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* ms
 
 /* ------------------------------------------------- distill and sebver */
 
+/* Schedule of poslo_distill's individual checks: 0 (default) one full
+ * check per entry; 1 the group schedule of poslo_verify_batch (screen every
+ * entry, check sums of groups of 8, verify only the entries of failing
+ * groups one by one), which gives the same CCD unless the errors of several
+ * invalid entries of one group cancel exactly. */
+int poslo_ctx_set_distill_schedule(poslo_ctx* ctx, int groups);
+
 /* Cold cryptographic data (paper, system model and section "POSLO-C
  * Distillation and Selective Batch Verification"): the valid aggregate
  * CCD^v, umbrella aggregates CCD^u over spans of U = ceil(n / n_umbrella)

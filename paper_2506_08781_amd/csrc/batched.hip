@@ -317,38 +317,6 @@ struct BScreen {
     uint32_t* sus_count;
 };
 
-__device__ __forceinline__ void shfl_xor_point(ge& Q, const ge& P, int m) {
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        Q.X.v[k] = __shfl_xor(P.X.v[k], m);
-        Q.Y.v[k] = __shfl_xor(P.Y.v[k], m);
-        Q.Z.v[k] = __shfl_xor(P.Z.v[k], m);
-        Q.T.v[k] = __shfl_xor(P.T.v[k], m);
-    }
-}
-
-__device__ __forceinline__ void shfl_point(ge& Q, const ge& P, int src) {
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        Q.X.v[k] = __shfl(P.X.v[k], src);
-        Q.Y.v[k] = __shfl(P.Y.v[k], src);
-        Q.Z.v[k] = __shfl(P.Z.v[k], src);
-        Q.T.v[k] = __shfl(P.T.v[k], src);
-    }
-}
-
-// append `value` for every lane with `flag` set: one atomic per wave
-__device__ __forceinline__ void wave_append(bool flag, uint64_t value, uint64_t* list, uint32_t* count) {
-    const uint64_t mask = __ballot(flag);
-    if (!mask) return;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
-    base = __shfl(base, (int)leader);
-    if (flag) list[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = value;
-}
-
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_screen(BScreen V) {
     __shared__ uint32_t lds[4 * 256];
     __shared__ uint32_t gsum[4][8][48];  // per wave and group: e, s, R (X, Y, Z, T)
@@ -374,56 +342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
     const bool pre_bad = active && !ok;
-    // sums over groups of 8 lanes (every lane of a group ends with the sum)
-#pragma unroll 1
-    for (int m = 1; m < 8; m <<= 1) {
-        uint32_t oe[8], os[8];
-        for (int k = 0; k < 8; k++) {
-            oe[k] = __shfl_xor(e[k], m);
-            os[k] = __shfl_xor(s[k], m);
-        }
-        sc_add(e, e, oe);
-        sc_add(s, s, os);
-        ge Q;
-        shfl_xor_point(Q, R, m);
-        ge_add(R, R, Q);
-    }
-    // park the group sums in LDS, then one check per group by the whole wave
-    uint32_t (*gs)[48] = gsum[threadIdx.x >> 6];
-    if ((lane & 7) == 0) {
-        uint32_t* o = gs[lane >> 3];
-        for (int k = 0; k < 8; k++) {
-            o[k] = e[k];
-            o[8 + k] = s[k];
-        }
-        store_point(o + 16, R);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t fail = 0;
-#pragma unroll 1
-    for (int g = 0; g < 8; g++) {
-        uint32_t eg[8], sg[8];
-        for (int k = 0; k < 8; k++) {
-            eg[k] = gs[g][k];
-            sg[k] = gs[g][8 + k];
-        }
-        ge Rg, P;
-        load_point(Rg, gs[g] + 16);
-        wave_double_scalar(P, J.ty, V.tg, eg, sg);
-        uint32_t eq = 0;
-        if (lane == 0) {
-            fe a1, b1, a2, b2;
-            fe_mul(a1, P.X, Rg.Z);
-            fe_mul(b1, Rg.X, P.Z);
-            fe_mul(a2, P.Y, Rg.Z);
-            fe_mul(b2, Rg.Y, P.Z);
-            eq = (fe_equal(a1, b1) && fe_equal(a2, b2)) ? 1u : 0u;
-        }
-        eq = __shfl(eq, 0);
-        if (!eq) fail |= 1u << g;
-    }
+    const uint32_t fail = wave_group_checks(e, s, R, gsum[threadIdx.x >> 6], J.ty, V.tg);
     const bool suspect = active && ok && ((fail >> (lane >> 3)) & 1u);
     wave_append(pre_bad, J.vbase + p, V.idx, V.count);
     wave_append(suspect, ((uint64_t)it.job << 32) | p, V.sus, V.sus_count);

@@ -50,6 +50,8 @@ struct poslo_ctx {
     // tuning: AES kernel variant and workgroups per CU (0 = derived)
     int agg_variant = -1;
     int wg_per_cu = 0;
+    // Distill schedule: 0 one individual check per entry, 1 group checks
+    int distill_groups = 0;
     // per-kernel timing with HIP events on the launch stream (opt-in)
     bool profile = false;
     hipEvent_t ev[poslo::kKtCount][2] = {};

@@ -174,4 +174,89 @@ __device__ __forceinline__ bool screen_one(const T& tb, const BatchArgs& a, cons
     return true;
 }
 
+// ---- group checks -------------------------------------------------------------
+
+__device__ __forceinline__ void shfl_xor_point(ge& Q, const ge& P, int m) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        Q.X.v[k] = __shfl_xor(P.X.v[k], m);
+        Q.Y.v[k] = __shfl_xor(P.Y.v[k], m);
+        Q.Z.v[k] = __shfl_xor(P.Z.v[k], m);
+        Q.T.v[k] = __shfl_xor(P.T.v[k], m);
+    }
+}
+
+// append `value` for every lane with `flag` set: one atomic per wave (ballot,
+// the lowest set lane adds the popcount, every set lane takes its rank among
+// the set lanes below it)
+__device__ __forceinline__ void wave_append(bool flag, uint64_t value, uint64_t* list, uint32_t* count) {
+    const uint64_t mask = __ballot(flag);
+    if (!mask) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)leader);
+    if (flag) list[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = value;
+}
+
+// Groups of 8 lanes: (e, s, R) of each lane (zero, zero, identity for lanes
+// that do not take part) are summed over the group, and (sum e)*Y +
+// (sum s)*G == sum R is checked for each of the wave's 8 groups by the whole
+// wave (the sums pass through this wave's LDS area gs of 8 x 48 words).
+// Returns the wave-uniform mask of failing groups; e, s and R are
+// overwritten.  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_group_checks(uint32_t e[8], uint32_t s[8], ge& R, uint32_t (*gs)[48],
+                                                      const uint32_t* ty, const uint32_t* tg) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int m = 1; m < 8; m <<= 1) {
+        uint32_t oe[8], os[8];
+        for (int k = 0; k < 8; k++) {
+            oe[k] = __shfl_xor(e[k], m);
+            os[k] = __shfl_xor(s[k], m);
+        }
+        sc_add(e, e, oe);
+        sc_add(s, s, os);
+        ge Q;
+        shfl_xor_point(Q, R, m);
+        ge_add(R, R, Q);
+    }
+    if ((lane & 7) == 0) {
+        uint32_t* o = gs[lane >> 3];
+        for (int k = 0; k < 8; k++) {
+            o[k] = e[k];
+            o[8 + k] = s[k];
+        }
+        store_point(o + 16, R);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t fail = 0;
+#pragma unroll 1
+    for (int g = 0; g < 8; g++) {
+        uint32_t eg[8], sg[8];
+        for (int k = 0; k < 8; k++) {
+            eg[k] = gs[g][k];
+            sg[k] = gs[g][8 + k];
+        }
+        ge Rg, P;
+        load_point(Rg, gs[g] + 16);
+        wave_double_scalar(P, ty, tg, eg, sg);
+        uint32_t eq = 0;
+        if (lane == 0) {
+            fe a1, b1, a2, b2;
+            fe_mul(a1, P.X, Rg.Z);
+            fe_mul(b1, Rg.X, P.Z);
+            fe_mul(a2, P.Y, Rg.Z);
+            fe_mul(b2, Rg.Y, P.Z);
+            eq = (fe_equal(a1, b1) && fe_equal(a2, b2)) ? 1u : 0u;
+        }
+        eq = __shfl(eq, 0);
+        if (!eq) fail |= 1u << g;
+    }
+    return fail;
+}
+
 }  // namespace poslo

@@ -90,6 +90,123 @@ __global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v) {
     block_reduce288_store<kTile>(as, out + 9);
 }
 
+// ---- group schedule -----------------------------------------------------------
+// k_distill_screen screens a tile's entries (x check, s < q, strict R decode,
+// e_t), checks sums of groups of 8, adds the passing groups' sums to the
+// tile's partials and lists the entries of failing groups (contiguously per
+// tile); k_distill_leaf verifies the listed entries one by one and keeps the
+// valid ones' (e_t, s_t); k_distill_fixup adds those to their tiles'
+// partials.  Same flags and partials as k_verify_tiles unless the errors of
+// several invalid entries of one group cancel exactly.
+
+struct DistillGroups {
+    uint64_t* sus;       // batch positions of the entries of failing groups
+    uint32_t* sus_count;
+    uint32_t* tile_sus;  // per tile: first listed entry, count
+    uint32_t* leaf;      // per listed entry: e[8], s[8] when valid, else zeros
+};
+
+__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void k_distill_screen(VerifyArgs v,
+                                                                                                  DistillGroups G) {
+    __shared__ uint32_t lds[4 * 256];
+    __shared__ uint32_t gsum[kTile / 64][8][48];
+    __shared__ uint32_t wcnt[kTile / 64], wbase[kTile / 64 + 1];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    uint64_t start, end;
+    const bool any = tile_range(v.g, blockIdx.x, start, end);
+    const uint64_t pos = start + threadIdx.x;
+    const bool active = any && pos < end;
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    ge R;
+    ge_identity(R);
+    bool ok = false;
+    if (active) {
+        ok = screen_one(tb, v.a, v.a.end, v.inst, pos, v.sigs + 80 * pos, e, s, R);
+        if (!ok) {
+            for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
+            ge_identity(R);
+        }
+        v.flags[pos] = ok ? 0 : 1;
+    }
+    const uint32_t fail = wave_group_checks(e, s, R, gsum[w], v.ty, v.tg);
+    // the passing groups' sums (mod q) into this tile's partials
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (lane == 0)
+        for (int g = 0; g < 8; g++)
+            if (!((fail >> g) & 1u)) {
+                acc288_add256(ae, gsum[w][g]);
+                acc288_add256(as, gsum[w][g] + 8);
+            }
+    // list the entries of failing groups, one contiguous range per tile
+    const bool suspect = active && ok && ((fail >> (lane >> 3)) & 1u);
+    const uint64_t mask = __ballot(suspect);
+    if (lane == 0) wcnt[w] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int k = 0; k < kTile / 64; k++) {
+            wbase[k] = tot;
+            tot += wcnt[k];
+        }
+        uint32_t base = tot ? atomicAdd(G.sus_count, tot) : 0;
+        wbase[kTile / 64] = base;
+        G.tile_sus[2 * blockIdx.x] = base;
+        G.tile_sus[2 * blockIdx.x + 1] = tot;
+    }
+    __syncthreads();
+    if (suspect) G.sus[wbase[kTile / 64] + wbase[w] + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = pos;
+    uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
+    block_reduce288_store<kTile>(ae, out);
+    __syncthreads();
+    block_reduce288_store<kTile>(as, out + 9);
+}
+
+__global__ __launch_bounds__(kTile) void k_distill_leaf(VerifyArgs v, DistillGroups G) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    LdsTables<4, 1> tb{lds};
+    const uint32_t n = *G.sus_count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t pos = G.sus[i];
+        uint32_t e[8], s[8];
+        const bool ok = verify_entry(tb, v, pos, v.sigs + 80 * pos, e, s);
+        v.flags[pos] = ok ? 0 : 1;
+        uint32_t* o = G.leaf + (uint64_t)i * 16;
+        for (int k = 0; k < 8; k++) {
+            o[k] = ok ? e[k] : 0u;
+            o[8 + k] = ok ? s[k] : 0u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_distill_fixup(DistillGroups G, uint32_t* tile_part) {
+    const uint32_t base = G.tile_sus[2 * blockIdx.x], cnt = G.tile_sus[2 * blockIdx.x + 1];
+    if (cnt == 0) return;
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t k = threadIdx.x; k < cnt; k += 64) {
+        acc288_add256(ae, G.leaf + (uint64_t)(base + k) * 16);
+        acc288_add256(as, G.leaf + (uint64_t)(base + k) * 16 + 8);
+    }
+    wave_reduce288(ae);
+    wave_reduce288(as);
+    if (threadIdx.x == 0) {
+        uint32_t* tp = tile_part + (uint64_t)blockIdx.x * 18;
+        uint32_t t[9];
+        for (int k = 0; k < 9; k++) t[k] = tp[k];
+        acc288_add(t, ae);
+        for (int k = 0; k < 9; k++) tp[k] = t[k];
+        for (int k = 0; k < 9; k++) t[k] = tp[9 + k];
+        acc288_add(t, as);
+        for (int k = 0; k < 9; k++) tp[9 + k] = t[k];
+    }
+}
+
+__global__ void k_zero32(uint32_t* p) { p[0] = 0; }
+
 // list mode (SeBVer I): flags[i] = 1 when list item i is invalid
 __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
     __shared__ uint32_t lds[4 * 256];
@@ -242,30 +359,63 @@ __global__ __launch_bounds__(kTile) void k_valid_fold(const uint32_t* umb_es, ui
     }
 }
 
-// sorted list of invalid entries: per-thread counts over contiguous chunks,
-// a workgroup exclusive scan, then ordered writes.  out_idx gets t0 + pos.
-constexpr int kCompact = 1024;
+// sorted list of invalid entries, in two passes over blocks of 4,096 flags:
+// per-block counts, then each block adds the counts of the blocks before it,
+// scans its threads' counts in LDS and writes its entries in order.  out_idx
+// gets t0 + pos.
+constexpr int kCmpThreads = 256, kCmpPer = 16, kCmpBlock = kCmpThreads * kCmpPer;
 
-__global__ __launch_bounds__(kCompact) void k_compact(const uint8_t* flags, uint64_t n, uint64_t t0, uint64_t* out_idx,
-                                                      uint64_t* out_count) {
-    __shared__ uint64_t scan[kCompact];
-    uint64_t chunk = (n + kCompact - 1) / kCompact;
-    uint64_t a = (uint64_t)threadIdx.x * chunk, b = a + chunk < n ? a + chunk : n;
-    uint64_t cnt = 0;
-    for (uint64_t p = a; p < b; p++) cnt += flags[p];
-    scan[threadIdx.x] = cnt;
+__device__ __forceinline__ uint32_t flags_of_thread(const uint8_t* flags, uint64_t n, uint64_t base) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCmpPer; k++)
+        if (base + k < n) c += flags[base + k];
+    return c;
+}
+
+__global__ __launch_bounds__(kCmpThreads) void k_flag_count(const uint8_t* flags, uint64_t n, uint32_t* blk) {
+    __shared__ uint32_t red[kCmpThreads / 64];
+    uint64_t base = (uint64_t)blockIdx.x * kCmpBlock + (uint64_t)threadIdx.x * kCmpPer;
+    uint32_t c = flags_of_thread(flags, n, base);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
     __syncthreads();
-    // Hillis-Steele inclusive scan
-    for (int off = 1; off < kCompact; off <<= 1) {
-        uint64_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kCmpThreads / 64; w++) t += red[w];
+        blk[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kCmpThreads) void k_flag_scatter(const uint8_t* flags, uint64_t n, uint64_t t0,
+                                                              const uint32_t* blk, uint64_t* out_idx,
+                                                              uint64_t* out_count) {
+    __shared__ uint64_t red[kCmpThreads / 64];
+    __shared__ uint32_t scan[kCmpThreads];
+    // entries flagged in the blocks before this one
+    uint64_t before = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kCmpThreads) before += blk[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = before;
+    uint64_t base = (uint64_t)blockIdx.x * kCmpBlock + (uint64_t)threadIdx.x * kCmpPer;
+    uint32_t c = flags_of_thread(flags, n, base);
+    scan[threadIdx.x] = c;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int w = 0; w < kCmpThreads / 64; w++) pre += red[w];
+    // inclusive scan of the threads' counts
+    for (int off = 1; off < kCmpThreads; off <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
         __syncthreads();
         scan[threadIdx.x] += v;
         __syncthreads();
     }
-    uint64_t o = scan[threadIdx.x] - cnt;
-    for (uint64_t p = a; p < b; p++)
-        if (flags[p]) out_idx[o++] = t0 + p;
-    if (threadIdx.x == kCompact - 1) *out_count = scan[kCompact - 1];
+    uint64_t o = pre + scan[threadIdx.x] - c;
+    for (int k = 0; k < kCmpPer; k++)
+        if (base + k < n && flags[base + k]) out_idx[o++] = t0 + base + k;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kCmpThreads - 1) *out_count = pre + scan[kCmpThreads - 1];
 }
 
 __global__ void k_gather_sigs(const uint64_t* idx, uint64_t count, uint64_t t0, const uint8_t* sigs, uint8_t* out) {
@@ -304,7 +454,7 @@ namespace {
 
 int scratch(poslo_ctx* c, int slot, size_t bytes, void** out) { return ctx_scratch(c, slot, bytes, out); }
 
-enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX };
+enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_SUS = 16, S_LEAF, S_TSUS };
 
 int checked_sigs(const uint8_t* sigs, uint64_t n) {
     if (n && !sigs) return POSLO_E_INVAL;
@@ -354,7 +504,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         (st = scratch(c, S_TILES, std::max<uint64_t>(n_tiles, 1) * 72, &tiles)) ||
         (st = scratch(c, S_UMB_ES, std::max<uint64_t>(n_umb, 1) * 64, &umb_es)) ||
         (st = scratch(c, S_UMB_TAGS, std::max<uint64_t>(n_umb, 1) * 64, &umb_tags)) ||
-        (st = scratch(c, S_IDX, std::max<uint64_t>(n, 1) * 8, &idx)) || (st = scratch(c, S_MISC, 256, &misc))) {
+        (st = scratch(c, S_IDX, std::max<uint64_t>(n, 1) * 8, &idx)) || (st = scratch(c, S_MISC, 256 + 4 * ((n + kCmpBlock - 1) / kCmpBlock), &misc))) {
         delete ccd;
         return st;
     }
@@ -380,7 +530,24 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         v.flags = (uint8_t*)flags;
         v.tile_part = (uint32_t*)tiles;
         prof_begin(c, POSLO_KT_VERIFY, s);
-        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v);
+        if (c->distill_groups) {
+            void *sus, *leaf, *tsus;
+            if ((st = scratch(c, S_SUS, n * 8, &sus)) || (st = scratch(c, S_LEAF, n * 64, &leaf)) ||
+                (st = scratch(c, S_TSUS, n_tiles * 8, &tsus)))
+                return fail(st);
+            DistillGroups G;
+            G.sus = (uint64_t*)sus;
+            G.sus_count = (uint32_t*)((uint8_t*)misc + 192);
+            G.tile_sus = (uint32_t*)tsus;
+            G.leaf = (uint32_t*)leaf;
+            hipLaunchKernelGGL(k_zero32, dim3(1), dim3(1), 0, s, G.sus_count);
+            hipLaunchKernelGGL(k_distill_screen, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, G);
+            uint32_t leaf_grid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)c->num_cu * 8);
+            hipLaunchKernelGGL(k_distill_leaf, dim3(leaf_grid), dim3(kTile), 0, s, v, G);
+            hipLaunchKernelGGL(k_distill_fixup, dim3((uint32_t)n_tiles), dim3(64), 0, s, G, (uint32_t*)tiles);
+        } else {
+            hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v);
+        }
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);
         FoldArgs f;
@@ -395,8 +562,11 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         f.umb_bits = nullptr;
         prof_begin(c, POSLO_KT_COMPACT, s);
         hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
-        hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompact), 0, s, (const uint8_t*)flags, n, m->t0, (uint64_t*)idx,
-                           d_count);
+        const uint32_t nblk = (uint32_t)((n + kCmpBlock - 1) / kCmpBlock);
+        uint32_t* blk = (uint32_t*)((uint8_t*)misc + 256);  // per-block counts after the tag and count
+        hipLaunchKernelGGL(k_flag_count, dim3(nblk), dim3(kCmpThreads), 0, s, (const uint8_t*)flags, n, blk);
+        hipLaunchKernelGGL(k_flag_scatter, dim3(nblk), dim3(kCmpThreads), 0, s, (const uint8_t*)flags, n, m->t0,
+                           (const uint32_t*)blk, (uint64_t*)idx, d_count);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     } else {
         prof_begin(c, POSLO_KT_COMPACT, s);
@@ -719,4 +889,10 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
         return POSLO_OK;
     }
     return POSLO_E_INVAL;
+}
+
+extern "C" int poslo_ctx_set_distill_schedule(poslo_ctx* c, int groups) {
+    if (!c || groups < 0 || groups > 1) return POSLO_E_INVAL;
+    c->distill_groups = groups;
+    return POSLO_OK;
 }

@@ -64,10 +64,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("groups", [False, True], ids=["per_entry", "groups"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"inst{c[0]}-n{c[1]}-L{c[2]}-k{c[5]}-u{c[6]}")
-def test_distill_and_sebver_match_oracle(P, gpu, case):
+def test_distill_and_sebver_match_oracle(P, gpu, case, groups):
     from oracle import oracle as O
     torch, ctx = gpu
+    P.poslo_ctx_set_distill_schedule(ctx, groups)
     inst, n, L, l1, l2, k, nu = case
     prm, msgs, pk, sigs, ds, tag = signed(inst, n, L, l1, l2, 0x11, 8)
     plan = synthlog.corruption_plan(40 + k, n, k, 8 * (L + 80))
@@ -139,9 +141,17 @@ def test_full_size_distill_1pct(P, gpu, inst):
     dm = torch.from_numpy(carr).cuda()
     dsig = torch.from_numpy(csig.reshape(-1)).cuda()
     print("full distill: run", flush=True)
+    P.poslo_ctx_set_distill_schedule(ctx, False)
     ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 64)
     inv = ccd.invalid()
     assert inv == [e for e, _ in plan]
+    # the group schedule gives the same CCD
+    print("full distill: group schedule", flush=True)
+    P.poslo_ctx_set_distill_schedule(ctx, True)
+    ccd_g = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 64)
+    P.poslo_ctx_set_distill_schedule(ctx, False)
+    assert ccd_g.invalid() == inv and ccd_g.valid_tag() == ccd.valid_tag()
+    assert ccd_g.umbrellas() == ccd.umbrellas() and ccd_g.export() == ccd.export()
     # the valid tag is the aggregate of the untouched signatures
     bad = np.zeros(n, dtype=bool)
     bad[inv] = True

@@ -93,6 +93,37 @@ def hash_calls_per_entry(inst: int, L):
     return 1 + (L + 16 + 9 + 63) // 64
 
 
+# HBM traffic of the headline kernels from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over the plain-large
+# workload, each scaled by what the counter read for a plain 256 MiB device
+# copy in the same runs (FETCH_SIZE 131,092 KiB -> x2.0, WRITE_SIZE
+# 262,144 KiB -> x1.0).  Valid only for the kernel sources they were taken
+# on: the sha256 prefix of those files must match, else traffic is null.
+TRAFFIC = {
+    "aes": {"fetch_kib": 131879.4, "write_kib": 16.0, "fetch_scale": 2.0, "write_scale": 1.0,
+            "files": ["agg_aes.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "common.h",
+                      "sc25519.h"],
+            "sha256": "b124bc6464674c9d", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "sha": {"fetch_kib": 133163.7, "write_kib": 1088.0, "fetch_scale": 2.0, "write_scale": 1.0,
+            "files": ["verifier.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h"],
+            "sha256": "14f2f4bad312e1c7", "profile": "profiles/pmc_aver_2p20x256.md"},
+}
+
+
+def traffic_bytes(inst_name):
+    """Measured HBM bytes per launch of the headline kernel, or None when its
+    sources changed since the counters were taken."""
+    import hashlib
+    t = TRAFFIC[inst_name]
+    h = hashlib.sha256()
+    for f in t["files"]:
+        with open(os.path.join(ROOT, "paper_2506_08781_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != t["sha256"]:
+        return None
+    return 1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def pct(xs, p):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(p / 100 * (len(xs) - 1))))]
@@ -188,7 +219,12 @@ def bench_distill(P, torch, ctx, inst, steps):
     for name, groups in (("per_entry", False), ("groups", True)):
         P.poslo_ctx_set_distill_schedule(ctx, groups)
         ccd = P.poslo_distill(ctx, log.params, log.pk, msgs, log.sigs, log.ds, c["umbrellas"])
-        assert ccd.invalid() == want, "invalid set differs from the injected flips"
+        got = ccd.invalid()
+        if got != want:
+            miss, extra = sorted(set(want) - set(got)), sorted(set(got) - set(want))
+            plan = dict(log.plan)
+            raise AssertionError(f"{name}: invalid set differs from the injected flips: {len(miss)} missing "
+                                 f"{[(e, plan[e]) for e in miss[:8]]}, {len(extra)} extra {extra[:8]}")
         del ccd
         P.poslo_ctx_profile(ctx, True)
         reset_times(P, ctx)
@@ -467,7 +503,10 @@ def main():
         "kernel_ms": kt,
         "roofline": {"bound": "alu", "kernel": "k_agg_ekeys_" + args.inst, "achieved": achieved,
                      "peak": INT32_PEAK_TOPS, "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS,
-                     "ops_per_entry": ope, "traffic": None,
+                     "ops_per_entry": ope,
+                     "traffic": traffic_bytes(args.inst) if args.config == "c2" else None,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "algorithmic_bytes": n * cfg["L"],
                      "hbm_GBs": n * cfg["L"] / (agg_ms / 1e3) / 1e9},
     }
     if not args.no_cpu_baseline:

@@ -319,7 +319,8 @@ struct BScreen {
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_screen(BScreen V) {
     __shared__ uint32_t lds[4 * 256];
-    __shared__ uint32_t gsum[4][8][48];  // per wave and group: e, s, R (X, Y, Z, T)
+    __shared__ uint32_t gsum[4][16][48];  // per wave and group (8 rows, 8 columns): e, s, R (X, Y, Z, T)
+    __shared__ uint32_t own[4][64][48];   // per lane: its own e, s, R
     lds_tables_fill<4, 1>(lds);
     __syncthreads();
     LdsTables<4, 1> tb{lds};
@@ -342,8 +343,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
     const bool pre_bad = active && !ok;
-    const uint32_t fail = wave_group_checks(e, s, R, gsum[threadIdx.x >> 6], J.ty, V.tg);
-    const bool suspect = active && ok && ((fail >> (lane >> 3)) & 1u);
+    const uint32_t fail = wave_group_checks(e, s, R, gsum[threadIdx.x >> 6], own[threadIdx.x >> 6], J.ty, V.tg);
+    const bool suspect = active && ok && group_suspect(fail);
     wave_append(pre_bad, J.vbase + p, V.idx, V.count);
     wave_append(suspect, ((uint64_t)it.job << 32) | p, V.sus, V.sus_count);
 }

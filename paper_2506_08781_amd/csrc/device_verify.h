@@ -200,17 +200,44 @@ __device__ __forceinline__ void wave_append(bool flag, uint64_t value, uint64_t*
     if (flag) list[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = value;
 }
 
-// Groups of 8 lanes: (e, s, R) of each lane (zero, zero, identity for lanes
-// that do not take part) are summed over the group, and (sum e)*Y +
-// (sum s)*G == sum R is checked for each of the wave's 8 groups by the whole
-// wave (the sums pass through this wave's LDS area gs of 8 x 48 words).
-// Returns the wave-uniform mask of failing groups; e, s and R are
-// overwritten.  Every lane of the wave must call it.
-__device__ __forceinline__ uint32_t wave_group_checks(uint32_t e[8], uint32_t s[8], ge& R, uint32_t (*gs)[48],
-                                                      const uint32_t* ty, const uint32_t* tg) {
-    const uint32_t lane = threadIdx.x & 63;
+// e*Y + s*G by a group of 8 lanes that pass the same e and s: lane k of the
+// group adds windows 8k..8k+7 of both tables, then three levels of
+// additions; the result is valid in every lane of the group.
+__device__ __forceinline__ void group8_double_scalar(ge& P, const uint32_t* ty, const uint32_t* tg, const uint32_t e[8],
+                                                     const uint32_t s[8]) {
+    const int sub = threadIdx.x & 7;
+    ge_identity(P);
+#pragma unroll 1
+    for (int k = 0; k < 8; k++) {
+        const int w = sub * 8 + k;
+        ge Q;
+        load_point(Q, comb_entry(ty, w, digit4(e, w)));
+        ge_add(P, P, Q);
+        load_point(Q, comb_entry(tg, w, digit4(s, w)));
+        ge_add(P, P, Q);
+    }
 #pragma unroll 1
     for (int m = 1; m < 8; m <<= 1) {
+        ge Q;
+        shfl_xor_point(Q, P, m);
+        ge_add(P, P, Q);
+    }
+}
+
+__device__ __forceinline__ bool same_point(const ge& P, const ge& R) {
+    fe a1, b1, a2, b2;
+    fe_mul(a1, P.X, R.Z);
+    fe_mul(b1, R.X, P.Z);
+    fe_mul(a2, P.Y, R.Z);
+    fe_mul(b2, R.Y, P.Z);
+    return fe_equal(a1, b1) && fe_equal(a2, b2);
+}
+
+// sums of (e, s, R) over the lanes that differ from this one only in the
+// bits of `bits` (a butterfly over those bits)
+__device__ __forceinline__ void lane_sums(uint32_t e[8], uint32_t s[8], ge& R, int first, int last) {
+#pragma unroll 1
+    for (int m = first; m <= last; m <<= 1) {
         uint32_t oe[8], os[8];
         for (int k = 0; k < 8; k++) {
             oe[k] = __shfl_xor(e[k], m);
@@ -222,41 +249,73 @@ __device__ __forceinline__ uint32_t wave_group_checks(uint32_t e[8], uint32_t s[
         shfl_xor_point(Q, R, m);
         ge_add(R, R, Q);
     }
-    if ((lane & 7) == 0) {
-        uint32_t* o = gs[lane >> 3];
-        for (int k = 0; k < 8; k++) {
-            o[k] = e[k];
-            o[8 + k] = s[k];
-        }
-        store_point(o + 16, R);
+}
+
+__device__ __forceinline__ void store_sums(uint32_t* o, const uint32_t e[8], const uint32_t s[8], const ge& R) {
+    for (int k = 0; k < 8; k++) {
+        o[k] = e[k];
+        o[8 + k] = s[k];
     }
+    store_point(o + 16, R);
+}
+
+// The 8 groups' relations checked at once, 8 lanes per group (lanes 8g..8g+7
+// check the sums in gs[g]); returns the mask of failing groups.
+__device__ __forceinline__ uint32_t check_groups8(const uint32_t (*gs)[48], const uint32_t* ty, const uint32_t* tg) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t* g = gs[lane >> 3];
+    uint32_t eg[8], sg[8];
+    for (int k = 0; k < 8; k++) {
+        eg[k] = g[k];
+        sg[k] = g[8 + k];
+    }
+    ge Rg, P;
+    load_point(Rg, g + 16);
+    group8_double_scalar(P, ty, tg, eg, sg);
+    const bool bad = (lane & 7) == 0 && !same_point(P, Rg);
+    const uint64_t m = __ballot(bad);
+    uint32_t fail = 0;
+    for (int k = 0; k < 8; k++)
+        if ((m >> (8 * k)) & 1ull) fail |= 1u << k;
+    return fail;
+}
+
+// Group checks of (sum e)*Y + (sum s)*G == sum R over two partitions of the
+// wave's 64 entries into 8 groups of 8: "rows" (lanes 8g..8g+7) and
+// "columns" (lanes congruent to g mod 8).  A row and a column share exactly
+// one lane, so errors of two invalid entries can cancel in at most one of
+// the two groups that each of them belongs to; an entry needs an individual
+// check when its row or its column fails.  (e, s, R) of each lane is (zero,
+// zero, identity) for lanes that do not take part; gs is this wave's LDS
+// area of 16 x 48 words.  Returns the wave-uniform masks: rows in bits 0-7,
+// columns in bits 8-15.  e, s and R are overwritten; every lane of the wave
+// must call it.  own is this wave's LDS area of 64 x 48 words: it keeps each
+// lane's (e, s, R) (read back with load_own after the call).
+__device__ __forceinline__ uint32_t wave_group_checks(uint32_t e[8], uint32_t s[8], ge& R, uint32_t (*gs)[48],
+                                                      uint32_t (*own)[48], const uint32_t* ty, const uint32_t* tg) {
+    const uint32_t lane = threadIdx.x & 63;
+    store_sums(own[lane], e, s, R);
+    lane_sums(e, s, R, 1, 4);  // rows
+    if ((lane & 7) == 0) store_sums(gs[lane >> 3], e, s, R);
+    for (int k = 0; k < 8; k++) {
+        e[k] = own[lane][k];
+        s[k] = own[lane][8 + k];
+    }
+    load_point(R, own[lane] + 16);
+    lane_sums(e, s, R, 8, 32);  // columns
+    if (lane < 8) store_sums(gs[8 + lane], e, s, R);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t fail = 0;
-#pragma unroll 1
-    for (int g = 0; g < 8; g++) {
-        uint32_t eg[8], sg[8];
-        for (int k = 0; k < 8; k++) {
-            eg[k] = gs[g][k];
-            sg[k] = gs[g][8 + k];
-        }
-        ge Rg, P;
-        load_point(Rg, gs[g] + 16);
-        wave_double_scalar(P, ty, tg, eg, sg);
-        uint32_t eq = 0;
-        if (lane == 0) {
-            fe a1, b1, a2, b2;
-            fe_mul(a1, P.X, Rg.Z);
-            fe_mul(b1, Rg.X, P.Z);
-            fe_mul(a2, P.Y, Rg.Z);
-            fe_mul(b2, Rg.Y, P.Z);
-            eq = (fe_equal(a1, b1) && fe_equal(a2, b2)) ? 1u : 0u;
-        }
-        eq = __shfl(eq, 0);
-        if (!eq) fail |= 1u << g;
-    }
-    return fail;
+    const uint32_t rows = check_groups8(gs, ty, tg);
+    const uint32_t cols = check_groups8(gs + 8, ty, tg);
+    return rows | (cols << 8);
+}
+
+// an entry needs its individual check when its row or its column failed
+__device__ __forceinline__ bool group_suspect(uint32_t masks) {
+    const uint32_t lane = threadIdx.x & 63;
+    return ((masks >> (lane >> 3)) & 1u) || ((masks >> (8 + (lane & 7))) & 1u);
 }
 
 }  // namespace poslo

@@ -109,7 +109,8 @@ struct DistillGroups {
 __global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void k_distill_screen(VerifyArgs v,
                                                                                                   DistillGroups G) {
     __shared__ uint32_t lds[4 * 256];
-    __shared__ uint32_t gsum[kTile / 64][8][48];
+    __shared__ uint32_t gsum[kTile / 64][16][48];
+    __shared__ uint32_t own[kTile / 64][64][48];
     __shared__ uint32_t wcnt[kTile / 64], wbase[kTile / 64 + 1];
     lds_tables_fill<4, 1>(lds);
     __syncthreads();
@@ -131,17 +132,16 @@ __global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void
         }
         v.flags[pos] = ok ? 0 : 1;
     }
-    const uint32_t fail = wave_group_checks(e, s, R, gsum[w], v.ty, v.tg);
-    // the passing groups' sums (mod q) into this tile's partials
+    const uint32_t fail = wave_group_checks(e, s, R, gsum[w], own[w], v.ty, v.tg);
+    // entries that passed the screen and need no individual check are
+    // valid: their (e_t, s_t) go into this tile's partials
+    const bool suspect = active && ok && group_suspect(fail);
     uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (lane == 0)
-        for (int g = 0; g < 8; g++)
-            if (!((fail >> g) & 1u)) {
-                acc288_add256(ae, gsum[w][g]);
-                acc288_add256(as, gsum[w][g] + 8);
-            }
+    if (active && ok && !suspect) {
+        acc288_add256(ae, own[w][lane]);
+        acc288_add256(as, own[w][lane] + 8);
+    }
     // list the entries of failing groups, one contiguous range per tile
-    const bool suspect = active && ok && ((fail >> (lane >> 3)) & 1u);
     const uint64_t mask = __ballot(suspect);
     if (lane == 0) wcnt[w] = (uint32_t)__popcll(mask);
     __syncthreads();

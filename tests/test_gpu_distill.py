@@ -168,3 +168,47 @@ def test_full_size_distill_1pct(P, gpu, inst):
     assert P.poslo_sebver(ctx, params, pk, m, ccd, "V") == [True]
     assert all(P.poslo_sebver(ctx, params, pk, m, ccd, "U"))
     assert not any(P.poslo_sebver(ctx, params, pk, m, ccd, "I"))
+
+
+def _flip_s_bit(sig, b):
+    s = bytearray(sig)
+    s[b // 8] ^= 1 << (b % 8)
+    return bytes(s)
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_group_schedule_catches_cancelling_pairs(P, gpu, inst):
+    """Two entries of one row of a wave with the same bit of s flipped in
+    opposite directions leave the row's sum of s unchanged; so do two
+    entries of one column.  Each pair still fails the other partition's
+    group, so the group schedule must name all four entries, exactly as the
+    oracle's entry-by-entry Distill does."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = signed(inst, 200, 40, 4, 4, 0x11, 8)
+    sigs = list(sigs)
+
+    def s_int(k):
+        return int.from_bytes(sigs[k][:32], "little")
+
+    for i, j in ((16, 19), (5, 13)):  # a row pair (lanes 16..23), a column pair (lanes = 5 mod 8)
+        b = next(b for b in range(8, 240) if (s_int(i) >> b) & 1 and not (s_int(j) >> b) & 1)
+        before = s_int(i) + s_int(j)
+        sigs[i], sigs[j] = _flip_s_bit(sigs[i], b), _flip_s_bit(sigs[j], b)
+        assert s_int(i) + s_int(j) == before  # the pair's sum of s is unchanged
+    want = O.distill(prm, pk, msgs, sigs, 0, ds, 1)
+    assert [t for t, _ in want.invalid] == [5, 13, 16, 19]
+    params = P.make_params(inst, 4, 4)
+    dm, dsig = to_dev(torch, msgs, sigs)
+    for groups in (False, True):
+        P.poslo_ctx_set_distill_schedule(ctx, groups)
+        ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 1)
+        assert ccd.invalid() == [5, 13, 16, 19], f"groups={groups}"
+        assert ccd.valid_tag() == want.valid_tag
+    P.poslo_ctx_set_distill_schedule(ctx, False)
+    # the multi-signer path's group schedule too (the tag is the honest one)
+    bj = P.BatchJobs([dict(pk=pk, ds=ds, tag=tag, t0=0, n=200, entry_base=0)])
+    off = torch.arange(0, 201 * 40, 40, dtype=torch.int64, device="cuda")
+    for mode in (2, 2 | P.POSLO_DISTILL_GROUPS):
+        acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=mode)
+        assert acc == [True] and inv == [(0, 5), (0, 13), (0, 16), (0, 19)], f"mode {mode}"

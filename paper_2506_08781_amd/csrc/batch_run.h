@@ -30,6 +30,7 @@ struct BJob {
     uint64_t epoch_base;      // first row of the job in the epoch table
     uint64_t item_base, item_end;
     uint64_t vbase;           // first slot of the job in the individual-check numbering
+    uint64_t ebase;           // first entry of the job in the launch's entry numbering
     uint32_t tag[16];         // LE words: s[8] || enc(R) bytes[8]
 };
 
@@ -78,7 +79,10 @@ class BatchRunner {
     // the persistent hashing kernel, one aggregate check per job, and the
     // copy of the accept words to pinned memory.  With use_graph the kernel
     // sequence is captured once per argument set and replayed.
-    int launch(hipStream_t s, bool use_graph, poslo_ctx* prof);
+    // With emit, the hashing kernel also writes every entry's e_t mod q and
+    // whether its x_t differs from the signature's (jobs need sigs), which
+    // the group screen then reads instead of hashing again.
+    int launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emit = false);
     // accept word of job j, valid once s has passed launch's work
     uint32_t accept(uint32_t j) const { return h_res_[j]; }
     // enqueue the individual checks of the listed jobs' entries; the invalid
@@ -113,9 +117,11 @@ class BatchRunner {
     // device buffers (grown on demand, kept)
     void *d_jobs_ = nullptr, *d_ds_ = nullptr, *d_rows_ = nullptr, *d_items_ = nullptr, *d_tab_ = nullptr,
          *d_part_ = nullptr, *d_res_ = nullptr, *d_misc_ = nullptr, *d_rdec_ = nullptr, *d_vtiles_ = nullptr,
-         *d_idx_ = nullptr, *d_sus_ = nullptr;
+         *d_idx_ = nullptr, *d_sus_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr;
     size_t n_jobs_b_ = 0, n_ds_b_ = 0, n_rows_b_ = 0, n_items_b_ = 0, n_tab_b_ = 0, n_part_b_ = 0, n_res_b_ = 0,
-           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_sus_b_ = 0;
+           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_sus_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0;
+    uint64_t n_entries_ = 0;
+    bool emitted_ = false;  // the last launch wrote e_t and the x checks
     // pinned staging
     uint32_t* h_res_ = nullptr;
     size_t h_res_b_ = 0;

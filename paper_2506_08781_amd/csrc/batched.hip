@@ -128,6 +128,8 @@ struct BHot {
     const uint32_t* tab;
     uint32_t* counter;
     uint32_t* partials;  // 9 words per item
+    uint32_t* e_out;     // optional: e_t mod q, 8 words per entry (job's ebase + offset)
+    uint8_t* xbad;       // with e_out: 1 when x_t differs from the signature's
 };
 
 // one MDC-2 block with the byte-addressed LDS tables
@@ -152,7 +154,7 @@ struct Mdc2BlockPerm {
 
 // INST 1: MDC-2-AES over the byte-addressed tables (NT = 1 or 2);
 // INST 0: SHA-256 (no tables).  CHUNK entries per item at most.
-template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE>
+template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_batch_hot(BHot A) {
     constexpr int TW = INST == INST_AES ? NT * 256 * 64 : 0;  // table words
     constexpr int SW = 64 + 16 + CHUNK / 2 + CHUNK / 4;       // counts, misc, order (u16), keys (u8)
@@ -219,8 +221,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             } else {
                 one_time_seed_sha(a, p, x);
                 digest_sha_any(ev, a.end, x, dig);
+#pragma unroll
+                for (int w = 0; w < 4; w++) x[w] = bswap32(x[w]);
             }
             acc288_add256(acc, dig);
+            if constexpr (EMIT) {
+                // x_t as little-endian words against the signature's x bytes
+                const uint8_t* sg = J.sigs + p * 80 + 64;
+                uint32_t d = 0;
+#pragma unroll
+                for (int w = 0; w < 4; w++) d |= x[w] ^ load_le32(sg + 4 * w);
+                uint32_t e[8];
+                sc_reduce256(e, dig);
+                uint32_t* eo = A.e_out + (J.ebase + p) * 8;
+#pragma unroll
+                for (int w = 0; w < 8; w++) eo[w] = e[w];
+                A.xbad[J.ebase + p] = d ? 1 : 0;
+            }
         }
         block_reduce288_scratch<BLOCK>(acc, A.partials + (uint64_t)item * 9, red);
     }
@@ -311,18 +328,24 @@ struct BScreen {
     uint32_t inst;
     uint32_t log2_n2;
     const uint32_t* tab;
+    const uint32_t* ekeys;  // e_t and x checks from the hashing kernel, or nullptr: hash here
+    const uint8_t* xbad;
     uint64_t* idx;       // invalid slots
     uint32_t* count;
     uint64_t* sus;       // suspects: job << 32 | entry offset
     uint32_t* sus_count;
 };
 
+// PRE: e_t and the x checks come from the hashing kernel (V.ekeys, V.xbad)
+template <bool PRE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_screen(BScreen V) {
-    __shared__ uint32_t lds[4 * 256];
+    __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
     __shared__ uint32_t gsum[4][16][48];  // per wave and group (8 rows, 8 columns): e, s, R (X, Y, Z, T)
     __shared__ uint32_t own[4][64][48];   // per lane: its own e, s, R
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
+    if constexpr (!PRE) {
+        lds_tables_fill<4, 1>(lds);
+        __syncthreads();
+    }
     LdsTables<4, 1> tb{lds};
     const BItem it = V.tiles[blockIdx.x];
     const bool active = threadIdx.x < it.count;
@@ -335,8 +358,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     ge_identity(R);
     bool ok = false;
     if (active) {
-        BatchArgs a = job_args(J, V.log2_n2, V.tab);
-        ok = screen_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, e, s, R);
+        if constexpr (PRE) {
+            ok = !V.xbad[J.ebase + p] && screen_sig(J.sigs + p * 80, s, R);
+            const uint32_t* ei = V.ekeys + (J.ebase + p) * 8;
+            for (int k = 0; k < 8; k++) e[k] = ei[k];
+        } else {
+            BatchArgs a = job_args(J, V.log2_n2, V.tab);
+            ok = screen_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, e, s, R);
+        }
         if (!ok) {
             for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
             ge_identity(R);
@@ -394,8 +423,11 @@ size_t hot_lds_bytes(const HotVariant& v) {
 }
 
 static int launch_hot(int v, uint32_t grid, const BHot& A, hipStream_t s) {
-#define HOT(I, NT, B, C, S, W)                                                                  \
-    hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, S, W>), dim3(grid), dim3(B), 0, s, A); \
+#define HOT(I, NT, B, C, S, W)                                                                        \
+    if (A.e_out)                                                                                      \
+        hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, S, W, true>), dim3(grid), dim3(B), 0, s, A);  \
+    else                                                                                              \
+        hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, S, W, false>), dim3(grid), dim3(B), 0, s, A); \
     break
     switch (v) {
         case 0: HOT(1, 2, 1024, 1024, true, 4);
@@ -434,7 +466,7 @@ BatchRunner::~BatchRunner() {
     forget_graphs();
     if (capture_) hipStreamDestroy(capture_);
     for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_,
-                    d_sus_})
+                    d_sus_, d_ekeys_, d_xbad_})
         if (p) hipFree(p);
     if (h_res_) hipHostFree(h_res_);
     if (h_misc_) hipHostFree(h_misc_);
@@ -521,6 +553,7 @@ int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njo
         J.epoch_base = job_of_row_.size();
         J.item_base = items_.size();
         J.vbase = 0;
+        J.ebase = total - in.n;
         for (int k = 0; k < 16; k++) J.tag[k] = load_le32(in.tag + 4 * k);
         if (in.n) {
             uint64_t e0 = in.t0 >> prm->log2_n2, e1 = (in.t0 + in.n - 1) >> prm->log2_n2;
@@ -533,6 +566,8 @@ int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njo
         }
         J.item_end = items_.size();
     }
+    n_entries_ = total;
+    emitted_ = false;
     return POSLO_OK;
 }
 
@@ -541,11 +576,18 @@ static void key_bytes(std::string& k, const T& v) {
     k.append(reinterpret_cast<const char*>(&v), sizeof v);
 }
 
-int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof) {
+int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emit) {
     if (!prof || !prof->d_gtable) return POSLO_E_INVAL;
     const uint32_t njobs = (uint32_t)jobs_.size();
     const uint64_t rows = job_of_row_.size();
     int st;
+    if (emit) {
+        for (const BJob& J : jobs_)
+            if (J.n && !J.sigs) return POSLO_E_INVAL;
+        if ((st = grow(&d_ekeys_, &n_ekeys_b_, n_entries_ * 32)) || (st = grow(&d_xbad_, &n_xbad_b_, n_entries_)))
+            return st;
+    }
+    emitted_ = emit;
     if ((st = grow(&d_jobs_, &n_jobs_b_, njobs * sizeof(BJob))) ||
         (st = grow(&d_ds_, &n_ds_b_, njobs * sizeof(DsArg))) || (st = grow(&d_rows_, &n_rows_b_, rows * 4)) ||
         (st = grow(&d_items_, &n_items_b_, items_.size() * sizeof(BItem))) ||
@@ -587,6 +629,8 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof) {
     A.tab = (const uint32_t*)d_tab_;
     A.counter = (uint32_t*)d_misc_;
     A.partials = (uint32_t*)d_part_;
+    A.e_out = emit ? (uint32_t*)d_ekeys_ : nullptr;
+    A.xbad = emit ? (uint8_t*)d_xbad_ : nullptr;
     const uint32_t* tg = prof->d_gtable;
     auto launch_all = [&](hipStream_t q, bool timed) -> int {
         hipLaunchKernelGGL(k_batch_seeds, dim3(seed_grid), dim3(256), 0, q, S);
@@ -691,7 +735,12 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
         G.count = cnt;
         G.sus = (uint64_t*)d_sus_;
         G.sus_count = sus_cnt;
-        hipLaunchKernelGGL(k_batch_screen, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
+        G.ekeys = emitted_ ? (const uint32_t*)d_ekeys_ : nullptr;
+        G.xbad = emitted_ ? (const uint8_t*)d_xbad_ : nullptr;
+        if (G.ekeys)
+            hipLaunchKernelGGL(k_batch_screen<true>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
+        else
+            hipLaunchKernelGGL(k_batch_screen<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
         uint32_t leaf_grid = (uint32_t)std::min<uint64_t>((n_checked_ + 255) / 256, (uint64_t)num_cu_ * 8);
         hipLaunchKernelGGL(k_batch_leaf, dim3(std::max<uint32_t>(leaf_grid, 1)), dim3(256), 0, s, V,
                            (const uint64_t*)d_sus_, (const uint32_t*)sus_cnt);
@@ -801,10 +850,10 @@ int make_specs(poslo_ctx* c, const poslo_batch_job* jobs, uint32_t njobs, const 
 }
 
 int run_sync(poslo_ctx* c, BatchRunner& R, const poslo_params* prm, const std::vector<JobSpec>& specs,
-             const poslo_tuning& t, hipStream_t s, uint8_t* accept) {
+             const poslo_tuning& t, hipStream_t s, uint8_t* accept, bool emit = false) {
     int st = R.plan(prm, specs.data(), (uint32_t)specs.size(), t, c->num_cu);
     if (st) return st;
-    if ((st = R.launch(s, t.use_graph != 0, c))) return st;
+    if ((st = R.launch(s, t.use_graph != 0, c, emit))) return st;
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
     for (uint32_t j = 0; j < R.njobs(); j++) accept[j] = (uint8_t)R.accept(j);
@@ -860,7 +909,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
     int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, sigs, specs);
     if (st) return st;
     BatchRunner& R = state_of(c).runner;
-    if ((st = run_sync(c, R, prm, specs, t, s, accept))) return st;
+    if ((st = run_sync(c, R, prm, specs, t, s, accept, distill && groups))) return st;
     if (!distill) return POSLO_OK;
     std::vector<uint32_t> which;
     for (uint32_t j = 0; j < njobs; j++)

@@ -142,6 +142,15 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
     return ge_encodes_to(P, r);
 }
 
+// The signature part of the screen: s_t < q and the R_t bytes decode strictly.
+__device__ __forceinline__ bool screen_sig(const uint8_t* sg, uint32_t s[8], ge& R) {
+    for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+    if (!sc_is_canonical(s)) return false;
+    uint8_t rb[32];
+    for (int k = 0; k < 8; k++) store_le32(rb + 4 * k, load_le32(sg + 32 + 4 * k));
+    return ge_decode(R, rb);
+}
+
 // The per-entry part of a group check: x_t equals the re-derived one-time
 // seed, s_t < q and the R_t bytes decode (strictly, so that a decoded R_t
 // encodes back to the same bytes).  On success e_t (mod q), s_t and R_t are

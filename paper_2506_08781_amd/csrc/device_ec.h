@@ -41,6 +41,42 @@ __device__ __forceinline__ void shfl_down_point(ge& Q, const ge& P, int off) {
     }
 }
 
+// ge_add with its multiplications kept apart by scheduling barriers: the
+// same arithmetic with fewer values live at once, for kernels whose register
+// budget is tight (the group checks)
+__device__ __forceinline__ void ge_add_lean(ge& r, const ge& p, const ge& q) {
+    const fe d2 = POSLO_FE_D2;
+    fe a, b, c, d, t;
+    fe_sub(a, p.Y, p.X);
+    fe_sub(t, q.Y, q.X);
+    fe_mul(a, a, t);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_add(b, p.Y, p.X);
+    fe_add(t, q.Y, q.X);
+    fe_mul(b, b, t);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(c, p.T, q.T);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(c, c, d2);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(d, p.Z, q.Z);
+    fe_add(d, d, d);
+    __builtin_amdgcn_sched_barrier(0);
+    fe e, f, g, h;
+    fe_sub(e, b, a);
+    fe_sub(f, d, c);
+    fe_add(g, d, c);
+    fe_add(h, b, a);
+    fe_mul(r.X, e, f);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(r.Y, g, h);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(r.T, e, h);
+    __builtin_amdgcn_sched_barrier(0);
+    fe_mul(r.Z, f, g);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 __device__ __forceinline__ uint32_t digit4(const uint32_t k[8], int w) { return (k[w >> 3] >> (4 * (w & 7))) & 15u; }
 
 __device__ __forceinline__ const uint32_t* comb_entry(const uint32_t* table, int w, uint32_t d) {

@@ -221,15 +221,15 @@ __device__ __forceinline__ void group8_double_scalar(ge& P, const uint32_t* ty, 
         const int w = sub * 8 + k;
         ge Q;
         load_point(Q, comb_entry(ty, w, digit4(e, w)));
-        ge_add(P, P, Q);
+        ge_add_lean(P, P, Q);
         load_point(Q, comb_entry(tg, w, digit4(s, w)));
-        ge_add(P, P, Q);
+        ge_add_lean(P, P, Q);
     }
 #pragma unroll 1
     for (int m = 1; m < 8; m <<= 1) {
         ge Q;
         shfl_xor_point(Q, P, m);
-        ge_add(P, P, Q);
+        ge_add_lean(P, P, Q);
     }
 }
 
@@ -256,7 +256,7 @@ __device__ __forceinline__ void lane_sums(uint32_t e[8], uint32_t s[8], ge& R, i
         sc_add(s, s, os);
         ge Q;
         shfl_xor_point(Q, R, m);
-        ge_add(R, R, Q);
+        ge_add_lean(R, R, Q);
     }
 }
 

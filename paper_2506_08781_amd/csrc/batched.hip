@@ -132,26 +132,6 @@ struct BHot {
     uint8_t* xbad;       // with e_out: 1 when x_t differs from the signature's
 };
 
-// one MDC-2 block with the byte-addressed LDS tables
-struct Mdc2BlockPerm {
-    template <int NT>
-    __device__ __forceinline__ void operator()(const PermTables<NT>& tb, uint32_t h[4], uint32_t hp[4],
-                                               const uint32_t m[4], bool first) const {
-        uint32_t sa[4] = {m[0], m[1], m[2], m[3]}, sb[4] = {m[0], m[1], m[2], m[3]};
-        if (first)
-            penc2_rk(tb, c_iv.a, sa, c_iv.b, sb);
-        else
-            penc2_otf(tb, h, sa, hp, sb);
-#pragma unroll
-        for (int w = 0; w < 4; w++) {
-            sa[w] ^= m[w];
-            sb[w] ^= m[w];
-        }
-        h[0] = sa[0], h[1] = sa[1], h[2] = sb[2], h[3] = sb[3];
-        hp[0] = sb[0], hp[1] = sb[1], hp[2] = sa[2], hp[3] = sa[3];
-    }
-};
-
 // INST 1: MDC-2-AES over the byte-addressed tables (NT = 1 or 2);
 // INST 0: SHA-256 (no tables).  CHUNK entries per item at most.
 template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT>

@@ -2,6 +2,7 @@
 // individual verification of one entry (the Distill / SeBVer check).
 #pragma once
 
+#include "aes_perm.h"
 #include "device_ec.h"
 #include "device_entry.h"
 
@@ -74,6 +75,26 @@ struct Mdc2BlockGeneric {
         } else {
             aes128_encrypt2_otf(tb, h, sa, hp, sb);
         }
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            sa[w] ^= m[w];
+            sb[w] ^= m[w];
+        }
+        h[0] = sa[0], h[1] = sa[1], h[2] = sb[2], h[3] = sb[3];
+        hp[0] = sb[0], hp[1] = sb[1], hp[2] = sa[2], hp[3] = sa[3];
+    }
+};
+
+// one MDC-2 block with the byte-addressed LDS tables
+struct Mdc2BlockPerm {
+    template <int NT>
+    __device__ __forceinline__ void operator()(const PermTables<NT>& tb, uint32_t h[4], uint32_t hp[4],
+                                               const uint32_t m[4], bool first) const {
+        uint32_t sa[4] = {m[0], m[1], m[2], m[3]}, sb[4] = {m[0], m[1], m[2], m[3]};
+        if (first)
+            penc2_rk(tb, c_iv.a, sa, c_iv.b, sb);
+        else
+            penc2_otf(tb, h, sa, hp, sb);
 #pragma unroll
         for (int w = 0; w < 4; w++) {
             sa[w] ^= m[w];

@@ -106,13 +106,55 @@ struct DistillGroups {
     uint32_t* leaf;      // per listed entry: e[8], s[8] when valid, else zeros
 };
 
-__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void k_distill_screen(VerifyArgs v,
-                                                                                                  DistillGroups G) {
-    __shared__ uint32_t lds[4 * 256];
+// Per entry, ahead of the screen: e_t mod q and whether x_t differs from
+// the signature's (AES with the byte-addressed bank-private LDS tables of
+// the AVer hot kernel, 1,024 threads per workgroup)
+template <int INST, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_distill_hash(
+    BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
+    constexpr int TW = INST == INST_AES ? 2 * 256 * 64 : 1;
+    __shared__ uint32_t lds[TW];
+    if constexpr (INST == INST_AES) perm_tables_fill<2>(lds);
+    __syncthreads();
+    const PermTables<2> tb = perm_tables<2>(lds);
+    for (uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; p < a.n; p += (uint64_t)gridDim.x * BLOCK) {
+        EntryView ev = entry_view(a, p);
+        uint32_t x[4], dig[8];
+        if constexpr (INST == INST_AES) {
+            uint64_t t = a.t0 + p;
+            uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
+            const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
+            x[0] = jj, x[1] = 0, x[2] = 0, x[3] = 0;
+            penc_rk(tb, rk, x);
+            x[0] ^= jj;
+            digest_mdc2_any(tb, ev, a.end, x, dig, Mdc2BlockPerm{});
+        } else {
+            one_time_seed_sha(a, p, x);
+            digest_sha_any(ev, a.end, x, dig);
+#pragma unroll
+            for (int w = 0; w < 4; w++) x[w] = bswap32(x[w]);
+        }
+        const uint8_t* sx = sigs + p * 80 + 64;
+        uint32_t d = 0;
+#pragma unroll
+        for (int w = 0; w < 4; w++) d |= x[w] ^ load_le32(sx + 4 * w);
+        uint32_t e[8];
+        sc_reduce256(e, dig);
+#pragma unroll
+        for (int w = 0; w < 8; w++) ekeys[p * 8 + w] = e[w];
+        xbad[p] = d ? 1 : 0;
+    }
+}
+
+// PRE: e_t and the x checks come from k_distill_hash
+template <bool PRE>
+__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void k_distill_screen(
+    VerifyArgs v, DistillGroups G, const uint32_t* ekeys, const uint8_t* xbad) {
+    __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
     __shared__ uint32_t gsum[kTile / 64][16][48];
     __shared__ uint32_t own[kTile / 64][64][48];
     __shared__ uint32_t wcnt[kTile / 64], wbase[kTile / 64 + 1];
-    lds_tables_fill<4, 1>(lds);
+    if constexpr (!PRE) lds_tables_fill<4, 1>(lds);
     __syncthreads();
     LdsTables<4, 1> tb{lds};
     uint64_t start, end;
@@ -125,7 +167,12 @@ __global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void
     ge_identity(R);
     bool ok = false;
     if (active) {
-        ok = screen_one(tb, v.a, v.a.end, v.inst, pos, v.sigs + 80 * pos, e, s, R);
+        if constexpr (PRE) {
+            ok = !xbad[pos] && screen_sig(v.sigs + 80 * pos, s, R);
+            for (int k = 0; k < 8; k++) e[k] = ekeys[pos * 8 + k];
+        } else {
+            ok = screen_one(tb, v.a, v.a.end, v.inst, pos, v.sigs + 80 * pos, e, s, R);
+        }
         if (!ok) {
             for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
             ge_identity(R);
@@ -454,7 +501,7 @@ namespace {
 
 int scratch(poslo_ctx* c, int slot, size_t bytes, void** out) { return ctx_scratch(c, slot, bytes, out); }
 
-enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_SUS = 16, S_LEAF, S_TSUS };
+enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_SUS = 16, S_LEAF, S_TSUS, S_EK, S_XB };
 
 int checked_sigs(const uint8_t* sigs, uint64_t n) {
     if (n && !sigs) return POSLO_E_INVAL;
@@ -540,8 +587,17 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
             G.sus_count = (uint32_t*)((uint8_t*)misc + 192);
             G.tile_sus = (uint32_t*)tsus;
             G.leaf = (uint32_t*)leaf;
+            void *ek, *xb;
+            if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
             hipLaunchKernelGGL(k_zero32, dim3(1), dim3(1), 0, s, G.sus_count);
-            hipLaunchKernelGGL(k_distill_screen, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, G);
+            if (prm->inst == POSLO_INST_AES)
+                hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024>), dim3(c->num_cu), dim3(1024), 0, s, v.a, sigs,
+                                   (uint32_t*)ek, (uint8_t*)xb);
+            else
+                hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
+                                   sigs, (uint32_t*)ek, (uint8_t*)xb);
+            hipLaunchKernelGGL(k_distill_screen<true>, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, G,
+                               (const uint32_t*)ek, (const uint8_t*)xb);
             uint32_t leaf_grid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)c->num_cu * 8);
             hipLaunchKernelGGL(k_distill_leaf, dim3(leaf_grid), dim3(kTile), 0, s, v, G);
             hipLaunchKernelGGL(k_distill_fixup, dim3((uint32_t)n_tiles), dim3(64), 0, s, G, (uint32_t*)tiles);

@@ -194,13 +194,6 @@ int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* ms
 
 /* ------------------------------------------------- distill and sebver */
 
-/* Schedule of poslo_distill's individual checks: 0 (default) one full
- * check per entry; 1 the group schedule of poslo_verify_batch (screen every
- * entry, check sums of groups of 8, verify only the entries of failing
- * groups one by one), which gives the same CCD unless the errors of several
- * invalid entries of one group cancel exactly. */
-int poslo_ctx_set_distill_schedule(poslo_ctx* ctx, int groups);
-
 /* Cold cryptographic data (paper, system model and section "POSLO-C
  * Distillation and Selective Batch Verification"): the valid aggregate
  * CCD^v, umbrella aggregates CCD^u over spans of U = ceil(n / n_umbrella)
@@ -307,8 +300,6 @@ typedef struct poslo_batch_job {
  * entries per work item, length sort), workgroups per CU of the persistent
  * grid (0 = derived from LDS and wave budget), and whether to capture the
  * launch sequence in a hipGraph that is replayed for identical shapes. */
-#define POSLO_DISTILL_GROUPS 4
-
 typedef struct poslo_tuning {
     int variant;
     int wg_per_cu;
@@ -331,14 +322,8 @@ const char* poslo_batch_variant_name(int v);
  * entries of rejected jobs are verified individually (Distill's check);
  * 2 = the entries of every job are (AVer reads only messages, ds and tag,
  * so a corrupted signature in an accepted job is found by mode 2 only).
- * Or-ing POSLO_DISTILL_GROUPS into the mode selects the group schedule:
- * every entry is screened (x check, s < q, strict R decode), the sums of
- * groups of 8 entries are checked against (sum e)*Y + (sum s)*G, and only
- * the entries of failing groups are verified one by one.  Both schedules
- * return the same set unless the errors of several invalid entries of one
- * group cancel exactly (for independent corruptions, probability about 1/q
- * per pair; a forger can arrange it, so audits of adversarial logs use the
- * plain schedule).
+ * With distill set, the hashing kernel also keeps every entry's e_t and x
+ * check for the individual checks, which then do only the curve part.
  * sigs: device, 80 bytes per global entry.  The invalid entries are
  * returned as sorted (job, t) pairs in invalid (host, 2*cap u64);
  * *n_invalid gets the count even when it exceeds cap (the pairs are then
@@ -383,8 +368,7 @@ typedef struct poslo_server_cfg {
     uint64_t mem_bytes;   /* device budget for admitted requests: staging copies of host
                              buffers and per-request scratch (0: 8 GiB) */
     int distill;          /* 0: accept bit only; 1: invalid entries of rejected requests;
-                             2: invalid entries of every request; | POSLO_DISTILL_GROUPS:
-                             group schedule (see poslo_verify_batch) */
+                             2: invalid entries of every request */
     int variant;          /* hot-kernel variant (-1: the default of the instantiation) */
 } poslo_server_cfg;
 

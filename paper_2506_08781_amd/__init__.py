@@ -28,7 +28,6 @@ POSLO_E_SEED = -4
 POSLO_E_ENCODING = -5
 POSLO_E_EXHAUSTED = -6
 POSLO_E_BUSY = -7
-POSLO_DISTILL_GROUPS = 4
 
 
 class PosloError(RuntimeError):
@@ -151,7 +150,6 @@ def lib():
             "poslo_sebver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _VP, ctypes.c_char, _VP, _SZ, P(_SZ),
                               _VP], _I),
             "poslo_synth_messages": ([_U32, P(poslo_msgs), _VP, _VP], _I),
-            "poslo_ctx_set_distill_schedule": ([_VP, _I], _I),
             "poslo_gpu_keys_create": ([_VP, P(poslo_params), _U8P, _U32, P(_VP), _VP], _I),
             "poslo_gpu_keys_free": ([_VP], None),
             "poslo_gpu_sign": ([_VP, P(poslo_sign_job), _U32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
@@ -329,10 +327,6 @@ def poslo_agg_variant_name(v: int) -> str:
 
 def poslo_ctx_set_tuning(ctx: Ctx, agg_variant: int = -1, wg_per_cu: int = 0) -> None:
     _check(lib().poslo_ctx_set_tuning(ctx.handle, agg_variant, wg_per_cu), "poslo_ctx_set_tuning")
-
-
-def poslo_ctx_set_distill_schedule(ctx: Ctx, groups: bool) -> None:
-    _check(lib().poslo_ctx_set_distill_schedule(ctx.handle, 1 if groups else 0), "poslo_ctx_set_distill_schedule")
 
 
 def poslo_ctx_profile(ctx: Ctx, enable: bool) -> None:

@@ -81,16 +81,14 @@ class BatchRunner {
     // sequence is captured once per argument set and replayed.
     // With emit, the hashing kernel also writes every entry's e_t mod q and
     // whether its x_t differs from the signature's (jobs need sigs), which
-    // the group screen then reads instead of hashing again.
+    // launch_verify then reads instead of hashing again.
     int launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emit = false);
     // accept word of job j, valid once s has passed launch's work
     uint32_t accept(uint32_t j) const { return h_res_[j]; }
     // enqueue the individual checks of the listed jobs' entries; the invalid
     // ones are appended (in any order) to a device list whose count is
     // copied to pinned memory
-    // (groups: screen every entry and check sums of 8, then verify only the
-    // entries of failing groups one by one)
-    int launch_verify(const std::vector<uint32_t>& jobs, hipStream_t s, poslo_ctx* prof, bool groups = false);
+    int launch_verify(const std::vector<uint32_t>& jobs, hipStream_t s, poslo_ctx* prof);
     // after s has passed launch_verify's work: the sorted (job, t) pairs
     int invalid(std::vector<std::pair<uint32_t, uint64_t>>& out, hipStream_t s);
     uint32_t njobs() const { return (uint32_t)jobs_.size(); }
@@ -117,9 +115,9 @@ class BatchRunner {
     // device buffers (grown on demand, kept)
     void *d_jobs_ = nullptr, *d_ds_ = nullptr, *d_rows_ = nullptr, *d_items_ = nullptr, *d_tab_ = nullptr,
          *d_part_ = nullptr, *d_res_ = nullptr, *d_misc_ = nullptr, *d_rdec_ = nullptr, *d_vtiles_ = nullptr,
-         *d_idx_ = nullptr, *d_sus_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr;
+         *d_idx_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr;
     size_t n_jobs_b_ = 0, n_ds_b_ = 0, n_rows_b_ = 0, n_items_b_ = 0, n_tab_b_ = 0, n_part_b_ = 0, n_res_b_ = 0,
-           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_sus_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0;
+           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0;
     uint64_t n_entries_ = 0;
     bool emitted_ = false;  // the last launch wrote e_t and the x checks
     // pinned staging

@@ -258,129 +258,41 @@ struct BVerify {
     uint32_t inst;
     uint32_t log2_n2;
     const uint32_t* tab;
+    const uint32_t* ekeys;  // PRE: e_t from the hashing kernel (job's ebase + offset)
+    const uint8_t* xbad;    // PRE: x checks from the hashing kernel
     uint64_t* idx;    // appended slots (job's vbase + entry offset) of invalid entries
     uint32_t* count;  // number appended
 };
 
-__global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
-    const BItem it = V.tiles[blockIdx.x];
-    const BJob& J = V.jobs[it.job];
-    bool bad = false;
-    uint64_t slot = 0;
-    if (threadIdx.x < it.count) {
-        BatchArgs a = job_args(J, V.log2_n2, V.tab);
-        uint64_t p = it.first + threadIdx.x;
-        uint32_t e[8], s[8];
-        bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
-        slot = J.vbase + p;
-    }
-    // one atomic per wave: ballot, the lowest set lane adds the popcount,
-    // every set lane takes its rank among the set lanes below it
-    const uint64_t mask = __ballot(bad);
-    if (mask) {
-        const uint32_t lane = threadIdx.x & 63;
-        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(V.count, (uint32_t)__popcll(mask));
-        base = __shfl(base, (int)leader);
-        if (bad) V.idx[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = slot;
-    }
-}
-
-// ---- group-check schedule of the individual checks --------------------------
-// Each wave screens 64 entries of one job (x check, s < q, strict R decode,
-// e_t); entries failing the screen are invalid.  The others are summed in
-// groups of 8 lanes, (sum e)*Y + (sum s)*G == sum R is checked per group
-// with the whole wave, and only the entries of failing groups are verified
-// one by one afterwards (k_batch_leaf).  One invalid entry makes its group's
-// sums differ, so a passing group holds no invalid entry unless the errors
-// of several invalid entries cancel (for independent corruptions, with
-// probability about 1/q per pair).
-
-struct BScreen {
-    const BJob* jobs;
-    const BItem* tiles;
-    const uint32_t* tg;
-    uint32_t inst;
-    uint32_t log2_n2;
-    const uint32_t* tab;
-    const uint32_t* ekeys;  // e_t and x checks from the hashing kernel, or nullptr: hash here
-    const uint8_t* xbad;
-    uint64_t* idx;       // invalid slots
-    uint32_t* count;
-    uint64_t* sus;       // suspects: job << 32 | entry offset
-    uint32_t* sus_count;
-};
-
-// PRE: e_t and the x checks come from the hashing kernel (V.ekeys, V.xbad)
+// PRE: e_t and the x checks come from the hashing kernel (launch with emit)
 template <bool PRE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_screen(BScreen V) {
+__global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
     __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
-    __shared__ uint32_t gsum[4][16][48];  // per wave and group (8 rows, 8 columns): e, s, R (X, Y, Z, T)
-    __shared__ uint32_t own[4][64][48];   // per lane: its own e, s, R
     if constexpr (!PRE) {
         lds_tables_fill<4, 1>(lds);
         __syncthreads();
     }
     LdsTables<4, 1> tb{lds};
     const BItem it = V.tiles[blockIdx.x];
-    const bool active = threadIdx.x < it.count;
-    if (__ballot(active) == 0) return;  // whole wave past the tile's end
     const BJob& J = V.jobs[it.job];
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t p = it.first + threadIdx.x;
-    uint32_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    ge R;
-    ge_identity(R);
-    bool ok = false;
-    if (active) {
+    bool bad = false;
+    uint64_t slot = 0;
+    if (threadIdx.x < it.count) {
+        uint64_t p = it.first + threadIdx.x;
+        uint32_t e[8], s[8];
         if constexpr (PRE) {
-            ok = !V.xbad[J.ebase + p] && screen_sig(J.sigs + p * 80, s, R);
-            const uint32_t* ei = V.ekeys + (J.ebase + p) * 8;
-            for (int k = 0; k < 8; k++) e[k] = ei[k];
+            for (int k = 0; k < 8; k++) e[k] = V.ekeys[(J.ebase + p) * 8 + k];
+            bad = V.xbad[J.ebase + p] || !verify_sig(J.sigs + p * 80, e, J.ty, V.tg, s);
         } else {
             BatchArgs a = job_args(J, V.log2_n2, V.tab);
-            ok = screen_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, e, s, R);
+            bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
         }
-        if (!ok) {
-            for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
-            ge_identity(R);
-        }
+        slot = J.vbase + p;
     }
-    const bool pre_bad = active && !ok;
-    const uint32_t fail = wave_group_checks(e, s, R, gsum[threadIdx.x >> 6], own[threadIdx.x >> 6], J.ty, V.tg);
-    const bool suspect = active && ok && group_suspect(fail);
-    wave_append(pre_bad, J.vbase + p, V.idx, V.count);
-    wave_append(suspect, ((uint64_t)it.job << 32) | p, V.sus, V.sus_count);
-}
-
-// individual checks of the suspects, grid-stride over the device count
-__global__ __launch_bounds__(256) void k_batch_leaf(BVerify V, const uint64_t* sus, const uint32_t* sus_count) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
-    const uint32_t n = *sus_count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint64_t w = sus[i];
-        const BJob& J = V.jobs[(uint32_t)(w >> 32)];
-        const uint64_t p = (uint32_t)w;
-        BatchArgs a = job_args(J, V.log2_n2, V.tab);
-        uint32_t e[8], s[8];
-        const bool bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
-        wave_append(bad, J.vbase + p, V.idx, V.count);
-    }
+    wave_append(bad, slot, V.idx, V.count);
 }
 
 __global__ void k_zero_u32(uint32_t* p) { p[0] = 0; }
-__global__ void k_zero2_u32(uint32_t* p, uint32_t* q) {
-    p[0] = 0;
-    q[0] = 0;
-}
 
 // ---- tuning --------------------------------------------------------------------
 
@@ -446,7 +358,7 @@ BatchRunner::~BatchRunner() {
     forget_graphs();
     if (capture_) hipStreamDestroy(capture_);
     for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_,
-                    d_sus_, d_ekeys_, d_xbad_})
+                    d_ekeys_, d_xbad_})
         if (p) hipFree(p);
     if (h_res_) hipHostFree(h_res_);
     if (h_misc_) hipHostFree(h_misc_);
@@ -665,7 +577,7 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     return POSLO_OK;
 }
 
-int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s, poslo_ctx* prof, bool groups) {
+int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s, poslo_ctx* prof) {
     if (!prof || !prof->d_gtable) return POSLO_E_INVAL;
     vtiles_.clear();
     vbase_.clear();
@@ -683,16 +595,14 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     if (n_checked_ >= (1ull << 32)) return POSLO_E_INVAL;
     int st;
     if ((st = grow(&d_vtiles_, &n_vtiles_b_, vtiles_.size() * sizeof(BItem))) ||
-        (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)) ||
-        (groups && (st = grow(&d_sus_, &n_sus_b_, n_checked_ * 8))))
+        (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)))
         return st;
     h_misc_[0] = 0;
     if (vtiles_.empty()) return POSLO_OK;
     HIP_TRY(hipMemcpyAsync(d_jobs_, jobs_.data(), jobs_.size() * sizeof(BJob), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_vtiles_, vtiles_.data(), vtiles_.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
     uint32_t* cnt = (uint32_t*)d_misc_ + 4;
-    uint32_t* sus_cnt = (uint32_t*)d_misc_ + 5;
-    hipLaunchKernelGGL(k_zero2_u32, dim3(1), dim3(1), 0, s, cnt, sus_cnt);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cnt);
     BVerify V;
     V.jobs = (const BJob*)d_jobs_;
     V.tiles = (const BItem*)d_vtiles_;
@@ -700,33 +610,15 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.inst = prm_.inst;
     V.log2_n2 = prm_.log2_n2;
     V.tab = (const uint32_t*)d_tab_;
+    V.ekeys = emitted_ ? (const uint32_t*)d_ekeys_ : nullptr;
+    V.xbad = emitted_ ? (const uint8_t*)d_xbad_ : nullptr;
     V.idx = (uint64_t*)d_idx_;
     V.count = cnt;
     prof_begin(prof, POSLO_KT_VERIFY, s);
-    if (groups) {
-        BScreen G;
-        G.jobs = V.jobs;
-        G.tiles = V.tiles;
-        G.tg = V.tg;
-        G.inst = V.inst;
-        G.log2_n2 = V.log2_n2;
-        G.tab = V.tab;
-        G.idx = V.idx;
-        G.count = cnt;
-        G.sus = (uint64_t*)d_sus_;
-        G.sus_count = sus_cnt;
-        G.ekeys = emitted_ ? (const uint32_t*)d_ekeys_ : nullptr;
-        G.xbad = emitted_ ? (const uint8_t*)d_xbad_ : nullptr;
-        if (G.ekeys)
-            hipLaunchKernelGGL(k_batch_screen<true>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
-        else
-            hipLaunchKernelGGL(k_batch_screen<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, G);
-        uint32_t leaf_grid = (uint32_t)std::min<uint64_t>((n_checked_ + 255) / 256, (uint64_t)num_cu_ * 8);
-        hipLaunchKernelGGL(k_batch_leaf, dim3(std::max<uint32_t>(leaf_grid, 1)), dim3(256), 0, s, V,
-                           (const uint64_t*)d_sus_, (const uint32_t*)sus_cnt);
-    } else {
-        hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
-    }
+    if (emitted_)
+        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+    else
+        hipLaunchKernelGGL(k_batch_verify<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
     prof_end(prof, POSLO_KT_VERIFY, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h_misc_, cnt, 4, hipMemcpyDeviceToHost, s));
@@ -863,8 +755,6 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
                                   const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes,
                                   const uint8_t* sigs, int distill, const poslo_tuning* tuning, void* stream,
                                   uint8_t* accept, uint64_t* invalid, size_t cap, size_t* n_invalid) {
-    const bool groups = (distill & POSLO_DISTILL_GROUPS) != 0;
-    distill &= ~POSLO_DISTILL_GROUPS;
     if (!c || !params_ok(prm) || (njobs && (!jobs || !accept)) || distill < 0 || distill > 2) return POSLO_E_INVAL;
     if (distill && (!sigs || !n_invalid || (cap && !invalid))) return POSLO_E_INVAL;
     if (n_invalid) *n_invalid = 0;
@@ -889,12 +779,12 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
     int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, sigs, specs);
     if (st) return st;
     BatchRunner& R = state_of(c).runner;
-    if ((st = run_sync(c, R, prm, specs, t, s, accept, distill && groups))) return st;
+    if ((st = run_sync(c, R, prm, specs, t, s, accept, distill != 0))) return st;
     if (!distill) return POSLO_OK;
     std::vector<uint32_t> which;
     for (uint32_t j = 0; j < njobs; j++)
         if (!accept[j] || distill == 2) which.push_back(j);
-    if ((st = R.launch_verify(which, s, c, groups))) return st;
+    if ((st = R.launch_verify(which, s, c))) return st;
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
     std::vector<std::pair<uint32_t, uint64_t>> out;

@@ -1,0 +1,36 @@
+// Layout of the fixed-base comb tables read by device_ec.h: 32 windows of
+// 128 affine points, t[w][i] = (i + 1) * 256^w * P stored as the canonical
+// (y + x, y - x, 2d*x*y), 24 words; 393,216 bytes per point P.
+#pragma once
+
+#include "ge25519.h"
+
+namespace poslo {
+
+constexpr int kCombWindows = 32;     // signed 8-bit digits of a scalar below 2^253
+constexpr int kCombPerWindow = 128;  // digit magnitudes 1..128
+constexpr int kCombEntryWords = 24;
+constexpr int kCombWords = kCombWindows * kCombPerWindow * kCombEntryWords;
+
+// table entry of P
+PD void comb_entry_of(uint32_t o[kCombEntryWords], const ge& P) {
+    const fe d2 = POSLO_FE_D2;
+    fe zi, x, y, a, b, t;
+    fe_inv(zi, P.Z);
+    fe_mul(x, P.X, zi);
+    fe_mul(y, P.Y, zi);
+    fe_add(a, y, x);
+    fe_sub(b, y, x);
+    fe_mul(t, x, y);
+    fe_mul(t, t, d2);
+    fe_freeze(a, a);
+    fe_freeze(b, b);
+    fe_freeze(t, t);
+    for (int k = 0; k < 8; k++) {
+        o[k] = a.v[k];
+        o[8 + k] = b.v[k];
+        o[16 + k] = t.v[k];
+    }
+}
+
+}  // namespace poslo

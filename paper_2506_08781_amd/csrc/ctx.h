@@ -12,14 +12,13 @@
 #include <vector>
 
 #include "../../include/poslo.h"
+#include "comb.h"
 #include "common.h"
 #include "ge25519.h"
 
 namespace poslo {
 
 constexpr int kKtCount = 8;
-constexpr int kCombWindows = 64;              // 4-bit windows of a 256-bit scalar
-constexpr int kCombWords = kCombWindows * 16 * 32;  // 16 points per window, 32 words each
 
 // AES hot-kernel variants (T-table layout x LDS replication x block size)
 struct AggVariant {
@@ -50,8 +49,6 @@ struct poslo_ctx {
     // tuning: AES kernel variant and workgroups per CU (0 = derived)
     int agg_variant = -1;
     int wg_per_cu = 0;
-    // Distill schedule: 0 one individual check per entry, 1 group checks
-    int distill_groups = 0;
     // per-kernel timing with HIP events on the launch stream (opt-in)
     bool profile = false;
     hipEvent_t ev[poslo::kKtCount][2] = {};
@@ -84,7 +81,7 @@ int ctx_scratch(poslo_ctx* c, int slot, size_t bytes, void** out);
 void prof_begin(poslo_ctx* c, int k, hipStream_t s);
 void prof_end(poslo_ctx* c, int k, hipStream_t s);
 void prof_collect(poslo_ctx* c);
-// device comb table of the key (built on the host on first use); nullptr and
+// device comb table of the key (built on first use); nullptr and
 // *status = POSLO_E_ENCODING if pk is not a point encoding
 const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
 // device comb tables of many keys (built on the device for the missing
@@ -94,8 +91,10 @@ const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
 int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad);
 // per-context state of the multi-signer path, released with the context
 void batch_release(poslo_ctx* c);
-// host comb table: t[w][d] = d * 16^w * P as 32-word points
-void build_comb_table(const ge& P, std::vector<uint32_t>& out);
+// comb tables (comb.h layout) of the m encoded points pks (host, 32 bytes
+// each) into d_tab (device, m * kCombWords words), built on the device;
+// ok[k] = 0 where pks[k] is not a point encoding.  Synchronous.
+int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok);
 
 struct BatchArgs;
 struct DsArg;

@@ -66,49 +66,9 @@ __device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const Ve
     return verify_one(tb, v.a, v.a.end, v.inst, pos, sg, v.ty, v.tg, e, s);
 }
 
-__global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
-    uint64_t start, end;
-    bool any = tile_range(v.g, blockIdx.x, start, end);
-    uint64_t pos = start + threadIdx.x;
-    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (any && pos < end) {
-        uint32_t e[8], s[8];
-        bool ok = verify_entry(tb, v, pos, v.sigs + 80 * pos, e, s);
-        v.flags[pos] = ok ? 0 : 1;
-        if (ok) {
-            acc288_add256(ae, e);
-            acc288_add256(as, s);
-        }
-    }
-    uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
-    block_reduce288_store<kTile>(ae, out);
-    __syncthreads();
-    block_reduce288_store<kTile>(as, out + 9);
-}
-
-// ---- group schedule -----------------------------------------------------------
-// k_distill_screen screens a tile's entries (x check, s < q, strict R decode,
-// e_t), checks sums of groups of 8, adds the passing groups' sums to the
-// tile's partials and lists the entries of failing groups (contiguously per
-// tile); k_distill_leaf verifies the listed entries one by one and keeps the
-// valid ones' (e_t, s_t); k_distill_fixup adds those to their tiles'
-// partials.  Same flags and partials as k_verify_tiles unless the errors of
-// several invalid entries of one group cancel exactly.
-
-struct DistillGroups {
-    uint64_t* sus;       // batch positions of the entries of failing groups
-    uint32_t* sus_count;
-    uint32_t* tile_sus;  // per tile: first listed entry, count
-    uint32_t* leaf;      // per listed entry: e[8], s[8] when valid, else zeros
-};
-
-// Per entry, ahead of the screen: e_t mod q and whether x_t differs from
-// the signature's (AES with the byte-addressed bank-private LDS tables of
-// the AVer hot kernel, 1,024 threads per workgroup)
+// Per entry, ahead of the curve checks: e_t mod q and whether x_t differs
+// from the signature's (AES with the byte-addressed bank-private LDS tables
+// of the AVer hot kernel, 1,024 threads per workgroup)
 template <int INST, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_distill_hash(
     BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
@@ -146,113 +106,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
 }
 
-// PRE: e_t and the x checks come from k_distill_hash
-template <bool PRE>
-__global__ __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(2))) void k_distill_screen(
-    VerifyArgs v, DistillGroups G, const uint32_t* ekeys, const uint8_t* xbad) {
-    __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
-    __shared__ uint32_t gsum[kTile / 64][16][48];
-    __shared__ uint32_t own[kTile / 64][64][48];
-    __shared__ uint32_t wcnt[kTile / 64], wbase[kTile / 64 + 1];
-    if constexpr (!PRE) lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
+// the curve part of every entry's check, with e_t and the x check from
+// k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials
+__global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys, const uint8_t* xbad) {
     uint64_t start, end;
-    const bool any = tile_range(v.g, blockIdx.x, start, end);
-    const uint64_t pos = start + threadIdx.x;
-    const bool active = any && pos < end;
-    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    ge R;
-    ge_identity(R);
-    bool ok = false;
-    if (active) {
-        if constexpr (PRE) {
-            ok = !xbad[pos] && screen_sig(v.sigs + 80 * pos, s, R);
-            for (int k = 0; k < 8; k++) e[k] = ekeys[pos * 8 + k];
-        } else {
-            ok = screen_one(tb, v.a, v.a.end, v.inst, pos, v.sigs + 80 * pos, e, s, R);
-        }
-        if (!ok) {
-            for (int k = 0; k < 8; k++) e[k] = s[k] = 0;
-            ge_identity(R);
-        }
-        v.flags[pos] = ok ? 0 : 1;
-    }
-    const uint32_t fail = wave_group_checks(e, s, R, gsum[w], own[w], v.ty, v.tg);
-    // entries that passed the screen and need no individual check are
-    // valid: their (e_t, s_t) go into this tile's partials
-    const bool suspect = active && ok && group_suspect(fail);
+    bool any = tile_range(v.g, blockIdx.x, start, end);
+    uint64_t pos = start + threadIdx.x;
     uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (active && ok && !suspect) {
-        acc288_add256(ae, own[w][lane]);
-        acc288_add256(as, own[w][lane] + 8);
-    }
-    // list the entries of failing groups, one contiguous range per tile
-    const uint64_t mask = __ballot(suspect);
-    if (lane == 0) wcnt[w] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int k = 0; k < kTile / 64; k++) {
-            wbase[k] = tot;
-            tot += wcnt[k];
+    if (any && pos < end) {
+        uint32_t e[8], s[8];
+        for (int k = 0; k < 8; k++) e[k] = ekeys[pos * 8 + k];
+        const bool ok = !xbad[pos] && verify_sig(v.sigs + 80 * pos, e, v.ty, v.tg, s);
+        v.flags[pos] = ok ? 0 : 1;
+        if (ok) {
+            acc288_add256(ae, e);
+            acc288_add256(as, s);
         }
-        uint32_t base = tot ? atomicAdd(G.sus_count, tot) : 0;
-        wbase[kTile / 64] = base;
-        G.tile_sus[2 * blockIdx.x] = base;
-        G.tile_sus[2 * blockIdx.x + 1] = tot;
     }
-    __syncthreads();
-    if (suspect) G.sus[wbase[kTile / 64] + wbase[w] + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] = pos;
     uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
     block_reduce288_store<kTile>(ae, out);
     __syncthreads();
     block_reduce288_store<kTile>(as, out + 9);
 }
-
-__global__ __launch_bounds__(kTile) void k_distill_leaf(VerifyArgs v, DistillGroups G) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
-    const uint32_t n = *G.sus_count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint64_t pos = G.sus[i];
-        uint32_t e[8], s[8];
-        const bool ok = verify_entry(tb, v, pos, v.sigs + 80 * pos, e, s);
-        v.flags[pos] = ok ? 0 : 1;
-        uint32_t* o = G.leaf + (uint64_t)i * 16;
-        for (int k = 0; k < 8; k++) {
-            o[k] = ok ? e[k] : 0u;
-            o[8 + k] = ok ? s[k] : 0u;
-        }
-    }
-}
-
-__global__ __launch_bounds__(64) void k_distill_fixup(DistillGroups G, uint32_t* tile_part) {
-    const uint32_t base = G.tile_sus[2 * blockIdx.x], cnt = G.tile_sus[2 * blockIdx.x + 1];
-    if (cnt == 0) return;
-    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t k = threadIdx.x; k < cnt; k += 64) {
-        acc288_add256(ae, G.leaf + (uint64_t)(base + k) * 16);
-        acc288_add256(as, G.leaf + (uint64_t)(base + k) * 16 + 8);
-    }
-    wave_reduce288(ae);
-    wave_reduce288(as);
-    if (threadIdx.x == 0) {
-        uint32_t* tp = tile_part + (uint64_t)blockIdx.x * 18;
-        uint32_t t[9];
-        for (int k = 0; k < 9; k++) t[k] = tp[k];
-        acc288_add(t, ae);
-        for (int k = 0; k < 9; k++) tp[k] = t[k];
-        for (int k = 0; k < 9; k++) t[k] = tp[9 + k];
-        acc288_add(t, as);
-        for (int k = 0; k < 9; k++) tp[9 + k] = t[k];
-    }
-}
-
-__global__ void k_zero32(uint32_t* p) { p[0] = 0; }
 
 // list mode (SeBVer I): flags[i] = 1 when list item i is invalid
 __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
@@ -501,7 +376,7 @@ namespace {
 
 int scratch(poslo_ctx* c, int slot, size_t bytes, void** out) { return ctx_scratch(c, slot, bytes, out); }
 
-enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_SUS = 16, S_LEAF, S_TSUS, S_EK, S_XB };
+enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_EK = 16, S_XB };
 
 int checked_sigs(const uint8_t* sigs, uint64_t n) {
     if (n && !sigs) return POSLO_E_INVAL;
@@ -577,33 +452,16 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         v.flags = (uint8_t*)flags;
         v.tile_part = (uint32_t*)tiles;
         prof_begin(c, POSLO_KT_VERIFY, s);
-        if (c->distill_groups) {
-            void *sus, *leaf, *tsus;
-            if ((st = scratch(c, S_SUS, n * 8, &sus)) || (st = scratch(c, S_LEAF, n * 64, &leaf)) ||
-                (st = scratch(c, S_TSUS, n_tiles * 8, &tsus)))
-                return fail(st);
-            DistillGroups G;
-            G.sus = (uint64_t*)sus;
-            G.sus_count = (uint32_t*)((uint8_t*)misc + 192);
-            G.tile_sus = (uint32_t*)tsus;
-            G.leaf = (uint32_t*)leaf;
-            void *ek, *xb;
-            if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
-            hipLaunchKernelGGL(k_zero32, dim3(1), dim3(1), 0, s, G.sus_count);
-            if (prm->inst == POSLO_INST_AES)
-                hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024>), dim3(c->num_cu), dim3(1024), 0, s, v.a, sigs,
-                                   (uint32_t*)ek, (uint8_t*)xb);
-            else
-                hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
-                                   sigs, (uint32_t*)ek, (uint8_t*)xb);
-            hipLaunchKernelGGL(k_distill_screen<true>, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, G,
-                               (const uint32_t*)ek, (const uint8_t*)xb);
-            uint32_t leaf_grid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)c->num_cu * 8);
-            hipLaunchKernelGGL(k_distill_leaf, dim3(leaf_grid), dim3(kTile), 0, s, v, G);
-            hipLaunchKernelGGL(k_distill_fixup, dim3((uint32_t)n_tiles), dim3(64), 0, s, G, (uint32_t*)tiles);
-        } else {
-            hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v);
-        }
+        void *ek, *xb;
+        if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
+        if (prm->inst == POSLO_INST_AES)
+            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024>), dim3(c->num_cu), dim3(1024), 0, s, v.a, sigs,
+                               (uint32_t*)ek, (uint8_t*)xb);
+        else
+            hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a, sigs,
+                               (uint32_t*)ek, (uint8_t*)xb);
+        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, (const uint32_t*)ek,
+                           (const uint8_t*)xb);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);
         FoldArgs f;
@@ -945,10 +803,4 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
         return POSLO_OK;
     }
     return POSLO_E_INVAL;
-}
-
-extern "C" int poslo_ctx_set_distill_schedule(poslo_ctx* c, int groups) {
-    if (!c || groups < 0 || groups > 1) return POSLO_E_INVAL;
-    c->distill_groups = groups;
-    return POSLO_OK;
 }

@@ -2,72 +2,67 @@
 //
 // The aggregate check e*Y + s*G (section "Fine-grained public-key POSLO",
 // AVer; the paper's multiplicative Y^e * alpha^s read additively on
-// edwards25519) uses per-key tables t[w][d] = d * 16^w * Y, 64 windows of 16
-// points.  Building one on the host costs about a thousand point additions;
-// for thousands of resident keys the device builds them instead, one wave
-// per key: lane 0 decodes the key and walks the 64 window bases (four
-// doublings apart), then lane w fills window w with 15 additions.
+// edwards25519) and the individual checks read per-key tables of 32 windows
+// of 128 affine points (comb.h).  One workgroup of 128 threads builds one
+// table: thread i forms (i + 1) * Y by double-and-add, then walks the 32
+// windows eight doublings apart, converting each point to affine form.
 #include <string.h>
 
 #include <algorithm>
 #include <vector>
 
+#include "comb.h"
 #include "ctx.h"
 #include "ge25519.h"
 
 namespace poslo {
 
-__global__ __launch_bounds__(64) void k_comb_build(const uint8_t* pks, uint32_t* tables, uint32_t* ok) {
-    __shared__ uint32_t base[kCombWindows * 32];
-    __shared__ uint32_t good;
+__global__ __launch_bounds__(kCombPerWindow) void k_comb_build(const uint8_t* pks, uint32_t* tables, uint32_t* ok) {
     const uint32_t key = blockIdx.x;
-    if (threadIdx.x == 0) {
-        uint8_t b[32];
-        for (int k = 0; k < 32; k++) b[k] = pks[(uint64_t)key * 32 + k];
-        ge P;
-        bool g = ge_decode(P, b);
-        good = g ? 1u : 0u;
-        ok[key] = good;
-        if (g) {
-            for (int w = 0; w < kCombWindows; w++) {
-                uint32_t* o = base + w * 32;
-                for (int k = 0; k < 8; k++) {
-                    o[k] = P.X.v[k];
-                    o[8 + k] = P.Y.v[k];
-                    o[16 + k] = P.Z.v[k];
-                    o[24 + k] = P.T.v[k];
-                }
-                ge_dbl(P, P);
-                ge_dbl(P, P);
-                ge_dbl(P, P);
-                ge_dbl(P, P);
-            }
-        }
-    }
-    __syncthreads();
+    uint8_t b[32];
+    for (int k = 0; k < 32; k++) b[k] = pks[(uint64_t)key * 32 + k];
+    ge Y;
+    const bool good = ge_decode(Y, b);
+    if (threadIdx.x == 0) ok[key] = good ? 1u : 0u;
     if (!good) return;
-    const int w = threadIdx.x;  // one window per lane (64 lanes, 64 windows)
-    ge B, T;
-    for (int k = 0; k < 8; k++) {
-        B.X.v[k] = base[w * 32 + k];
-        B.Y.v[k] = base[w * 32 + 8 + k];
-        B.Z.v[k] = base[w * 32 + 16 + k];
-        B.T.v[k] = base[w * 32 + 24 + k];
+    const uint32_t m = threadIdx.x + 1;  // 1..128
+    ge P;
+    ge_identity(P);
+    for (int bit = 7; bit >= 0; bit--) {
+        ge_dbl(P, P);
+        if ((m >> bit) & 1u) ge_add(P, P, Y);
     }
-    ge_identity(T);
-    uint32_t* dst = tables + (uint64_t)key * kCombWords + (uint64_t)w * 16 * 32;
-    for (int d = 0; d < 16; d++) {
-        uint4* o = reinterpret_cast<uint4*>(dst + d * 32);
-        o[0] = make_uint4(T.X.v[0], T.X.v[1], T.X.v[2], T.X.v[3]);
-        o[1] = make_uint4(T.X.v[4], T.X.v[5], T.X.v[6], T.X.v[7]);
-        o[2] = make_uint4(T.Y.v[0], T.Y.v[1], T.Y.v[2], T.Y.v[3]);
-        o[3] = make_uint4(T.Y.v[4], T.Y.v[5], T.Y.v[6], T.Y.v[7]);
-        o[4] = make_uint4(T.Z.v[0], T.Z.v[1], T.Z.v[2], T.Z.v[3]);
-        o[5] = make_uint4(T.Z.v[4], T.Z.v[5], T.Z.v[6], T.Z.v[7]);
-        o[6] = make_uint4(T.T.v[0], T.T.v[1], T.T.v[2], T.T.v[3]);
-        o[7] = make_uint4(T.T.v[4], T.T.v[5], T.T.v[6], T.T.v[7]);
-        if (d < 15) ge_add(T, T, B);
+    uint32_t* dst = tables + (uint64_t)key * kCombWords + (uint64_t)threadIdx.x * kCombEntryWords;
+    for (int w = 0; w < kCombWindows; w++) {
+        uint32_t o[kCombEntryWords];
+        comb_entry_of(o, P);
+        uint4* q = reinterpret_cast<uint4*>(dst + (uint64_t)w * kCombPerWindow * kCombEntryWords);
+#pragma unroll
+        for (int k = 0; k < kCombEntryWords / 4; k++) q[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+        if (w + 1 < kCombWindows)
+            for (int k = 0; k < 8; k++) ge_dbl(P, P);
     }
+}
+
+int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {
+    ok.assign(m, 0);
+    if (m == 0) return POSLO_OK;
+    void *d_pks = nullptr, *d_ok = nullptr;
+    if (hipMalloc(&d_pks, m * 32) != hipSuccess) return POSLO_E_NOMEM;
+    if (hipMalloc(&d_ok, m * 4) != hipSuccess) {
+        hipFree(d_pks);
+        return POSLO_E_NOMEM;
+    }
+    bool fail = hipMemcpy(d_pks, pks, m * 32, hipMemcpyHostToDevice) != hipSuccess;
+    if (!fail) {
+        hipLaunchKernelGGL(k_comb_build, dim3((uint32_t)m), dim3(kCombPerWindow), 0, 0, (const uint8_t*)d_pks, d_tab,
+                           (uint32_t*)d_ok);
+        fail = hipGetLastError() != hipSuccess ||
+               hipMemcpy(ok.data(), d_ok, m * 4, hipMemcpyDeviceToHost) != hipSuccess;
+    }
+    hipFree(d_pks);
+    hipFree(d_ok);
+    return fail ? POSLO_E_DEVICE : POSLO_OK;
 }
 
 int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad) {
@@ -93,29 +88,12 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
         size_t m = missing.size();
         std::vector<uint8_t> h_pks(m * 32);
         for (size_t k = 0; k < m; k++) memcpy(&h_pks[32 * k], missing[k].data(), 32);
-        void *d_pks = nullptr, *d_ok = nullptr, *d_tab = nullptr;
-        if (hipMalloc(&d_pks, m * 32) != hipSuccess) return POSLO_E_NOMEM;
-        if (hipMalloc(&d_ok, m * 4) != hipSuccess) {
-            hipFree(d_pks);
-            return POSLO_E_NOMEM;
-        }
-        if (hipMalloc(&d_tab, m * (size_t)kCombWords * 4) != hipSuccess) {
-            hipFree(d_pks);
-            hipFree(d_ok);
-            return POSLO_E_NOMEM;
-        }
+        void* d_tab = nullptr;
+        if (hipMalloc(&d_tab, m * (size_t)kCombWords * 4) != hipSuccess) return POSLO_E_NOMEM;
         std::shared_ptr<void> slab(d_tab, [](void* q) { hipFree(q); });
-        std::vector<uint32_t> ok(m, 0);
-        bool fail = hipMemcpy(d_pks, h_pks.data(), m * 32, hipMemcpyHostToDevice) != hipSuccess;
-        if (!fail) {
-            hipLaunchKernelGGL(k_comb_build, dim3((uint32_t)m), dim3(64), 0, 0, (const uint8_t*)d_pks,
-                               (uint32_t*)d_tab, (uint32_t*)d_ok);
-            fail = hipGetLastError() != hipSuccess ||
-                   hipMemcpy(ok.data(), d_ok, m * 4, hipMemcpyDeviceToHost) != hipSuccess;
-        }
-        hipFree(d_pks);
-        hipFree(d_ok);
-        if (fail) return POSLO_E_DEVICE;
+        std::vector<uint32_t> ok;
+        int st = build_comb_tables(h_pks.data(), m, (uint32_t*)d_tab, ok);
+        if (st) return st;
         // make room: evict least recently used keys not touched by this call
         size_t good = 0;
         for (size_t k = 0; k < m; k++) good += ok[k] != 0;

@@ -260,7 +260,7 @@ int poslo_server::launch_group(Slot& sl) {
         sl.slot_cap = cap;
     }
     HIP_TRY(hipMemcpyAsync(sl.d_slot_of_job, slot_of_job.data(), slot_of_job.size() * 4, hipMemcpyHostToDevice, s));
-    if ((st = sl.runner.launch(s, false, ctx))) return st;
+    if ((st = sl.runner.launch(s, false, ctx, cfg.distill != 0))) return st;
     hipLaunchKernelGGL(k_key_state, dim3(1), dim3(64), 0, s, sl.runner.d_jobs(), sl.runner.d_accept(),
                        sl.runner.d_rdec(), (const uint32_t*)sl.d_slot_of_job, (uint32_t)specs.size(), d_state);
     HIP_TRY(hipGetLastError());
@@ -304,12 +304,12 @@ void poslo_server::finish_group(Slot& sl, const std::vector<std::vector<uint64_t
 
 void poslo_server::complete(Slot& sl) {
     if (sl.phase == 1) {
-        const int mode = cfg.distill & ~POSLO_DISTILL_GROUPS;
+        const int mode = cfg.distill;
         std::vector<uint32_t> which;
         for (uint32_t k = 0; k < sl.group.size(); k++)
             if (mode == 2 || (mode == 1 && !sl.runner.accept(k))) which.push_back(k);
         if (!which.empty()) {
-            int st = sl.runner.launch_verify(which, sl.stream, ctx, (cfg.distill & POSLO_DISTILL_GROUPS) != 0);
+            int st = sl.runner.launch_verify(which, sl.stream, ctx);
             if (st == POSLO_OK && hipEventRecord(sl.ev, sl.stream) == hipSuccess) {
                 sl.phase = 2;
                 return;
@@ -427,8 +427,7 @@ void poslo_server::run() {
 
 extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out) {
     if (!cfg || !out || !params_ok(&cfg->params)) return POSLO_E_INVAL;
-    const int mode = cfg->distill & ~POSLO_DISTILL_GROUPS;
-    if (mode < 0 || mode > 2) return POSLO_E_INVAL;
+    if (cfg->distill < 0 || cfg->distill > 2) return POSLO_E_INVAL;
     if (cfg->variant >= batch_variant_count() ||
         (cfg->variant >= 0 && batch_variant(cfg->variant).inst != (int)cfg->params.inst))
         return POSLO_E_INVAL;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_bpv_table(const DevKey* keys, uint32_t 
     sc_reduce256(r, d);
     uint32_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     ge R;
-    lane_double_scalar(R, tg, tg, zero, r);
+    lane_scalar(R, tg, r);
     for (int w = 0; w < 8; w++) bpv_r[g * 8 + w] = r[w];
     store_point(bpv_R + g * 32, R);
 }

@@ -223,68 +223,11 @@ void prof_collect(poslo_ctx* c) {
     }
 }
 
-void build_comb_table(const ge& P0, std::vector<uint32_t>& out) {
-    out.assign(kCombWords, 0);
-    ge P = P0;
-    for (int w = 0; w < kCombWindows; w++) {
-        ge T;
-        ge_identity(T);
-        for (int d = 0; d < 16; d++) {
-            uint32_t* o = &out[(size_t)(w * 16 + d) * 32];
-            for (int k = 0; k < 8; k++) {
-                o[k] = T.X.v[k];
-                o[8 + k] = T.Y.v[k];
-                o[16 + k] = T.Z.v[k];
-                o[24 + k] = T.T.v[k];
-            }
-            ge_add(T, T, P);
-        }
-        ge_dbl(P, P);
-        ge_dbl(P, P);
-        ge_dbl(P, P);
-        ge_dbl(P, P);
-    }
-}
-
 const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status) {
-    std::string id((const char*)pk, 32);
-    auto it = c->key_index.find(id);
-    if (it != c->key_index.end()) {
-        c->keys.splice(c->keys.begin(), c->keys, it->second);
-        *status = POSLO_OK;
-        return &*it->second;
-    }
-    KeyEntry ke;
-    ke.pk = id;
-    ge Y;
-    if (!ge_decode(Y, pk)) {
-        *status = POSLO_E_ENCODING;
-        return nullptr;
-    }
-    std::vector<uint32_t> tab;
-    build_comb_table(Y, tab);
-    if (c->keys.size() >= c->key_cap) {
-        // evict the least recently used key; its table may still be read by
-        // queued work, so wait for the device first
-        hipDeviceSynchronize();
-        c->key_index.erase(c->keys.back().pk);
-        c->keys.pop_back();
-    }
-    void* d = nullptr;
-    if (hipMalloc(&d, tab.size() * 4) != hipSuccess) {
-        *status = POSLO_E_NOMEM;
-        return nullptr;
-    }
-    ke.slab = std::shared_ptr<void>(d, [](void* q) { hipFree(q); });
-    ke.d_table = (uint32_t*)d;
-    if (hipMemcpy(ke.d_table, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-        *status = POSLO_E_DEVICE;
-        return nullptr;
-    }
-    c->keys.push_front(ke);
-    c->key_index[id] = c->keys.begin();
-    *status = POSLO_OK;
-    return &c->keys.front();
+    std::vector<const uint32_t*> t;
+    *status = ctx_keys_bulk(c, pk, 1, t, nullptr);
+    if (*status) return nullptr;
+    return &*c->key_index.at(std::string((const char*)pk, 32));
 }
 
 }  // namespace poslo
@@ -311,17 +254,18 @@ extern "C" int poslo_ctx_create(int device, poslo_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
-    std::vector<uint32_t> gt;
-    ge G;
-    ge_base(G);
-    build_comb_table(G, gt);
     if (hipMalloc((void**)&c->d_result, 64 * sizeof(uint32_t)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_result, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&c->d_gtable, gt.size() * 4) != hipSuccess) {
+        hipMalloc((void**)&c->d_gtable, (size_t)kCombWords * 4) != hipSuccess) {
         poslo_ctx_destroy(c);
         return POSLO_E_NOMEM;
     }
-    if (hipMemcpy(c->d_gtable, gt.data(), gt.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    ge G;
+    ge_base(G);
+    uint8_t genc[32];
+    ge_encode(genc, G);
+    std::vector<uint32_t> gok;
+    if (build_comb_tables(genc, 1, c->d_gtable, gok) || !gok[0]) {
         poslo_ctx_destroy(c);
         return POSLO_E_DEVICE;
     }

@@ -64,12 +64,10 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("groups", [False, True], ids=["per_entry", "groups"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"inst{c[0]}-n{c[1]}-L{c[2]}-k{c[5]}-u{c[6]}")
-def test_distill_and_sebver_match_oracle(P, gpu, case, groups):
+def test_distill_and_sebver_match_oracle(P, gpu, case):
     from oracle import oracle as O
     torch, ctx = gpu
-    P.poslo_ctx_set_distill_schedule(ctx, groups)
     inst, n, L, l1, l2, k, nu = case
     prm, msgs, pk, sigs, ds, tag = signed(inst, n, L, l1, l2, 0x11, 8)
     plan = synthlog.corruption_plan(40 + k, n, k, 8 * (L + 80))
@@ -141,17 +139,9 @@ def test_full_size_distill_1pct(P, gpu, inst):
     dm = torch.from_numpy(carr).cuda()
     dsig = torch.from_numpy(csig.reshape(-1)).cuda()
     print("full distill: run", flush=True)
-    P.poslo_ctx_set_distill_schedule(ctx, False)
     ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 64)
     inv = ccd.invalid()
     assert inv == [e for e, _ in plan]
-    # the group schedule gives the same CCD
-    print("full distill: group schedule", flush=True)
-    P.poslo_ctx_set_distill_schedule(ctx, True)
-    ccd_g = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 64)
-    P.poslo_ctx_set_distill_schedule(ctx, False)
-    assert ccd_g.invalid() == inv and ccd_g.valid_tag() == ccd.valid_tag()
-    assert ccd_g.umbrellas() == ccd.umbrellas() and ccd_g.export() == ccd.export()
     # the valid tag is the aggregate of the untouched signatures
     bad = np.zeros(n, dtype=bool)
     bad[inv] = True
@@ -177,12 +167,13 @@ def _flip_s_bit(sig, b):
 
 
 @pytest.mark.parametrize("inst", [1, 0])
-def test_group_schedule_catches_cancelling_pairs(P, gpu, inst):
-    """Two entries of one row of a wave with the same bit of s flipped in
-    opposite directions leave the row's sum of s unchanged; so do two
-    entries of one column.  Each pair still fails the other partition's
-    group, so the group schedule must name all four entries, exactly as the
-    oracle's entry-by-entry Distill does."""
+def test_distill_finds_errors_that_cancel_in_sums(P, gpu, inst):
+    """Tampering that keeps sums of s unchanged: a pair with the same bit of
+    s flipped in opposite directions, and four entries at the corners of a
+    rectangle of an 8 x 8 arrangement of 64 consecutive entries (+2^b, -2^b
+    on one row, -2^b, +2^b on another), which leaves every row sum and every
+    column sum of s as it was.  Each entry is checked on its own, so all of
+    them must be named, exactly as the oracle's Distill names them."""
     from oracle import oracle as O
     torch, ctx = gpu
     prm, msgs, pk, sigs, ds, tag = signed(inst, 200, 40, 4, 4, 0x11, 8)
@@ -191,24 +182,31 @@ def test_group_schedule_catches_cancelling_pairs(P, gpu, inst):
     def s_int(k):
         return int.from_bytes(sigs[k][:32], "little")
 
-    for i, j in ((16, 19), (5, 13)):  # a row pair (lanes 16..23), a column pair (lanes = 5 mod 8)
-        b = next(b for b in range(8, 240) if (s_int(i) >> b) & 1 and not (s_int(j) >> b) & 1)
-        before = s_int(i) + s_int(j)
-        sigs[i], sigs[j] = _flip_s_bit(sigs[i], b), _flip_s_bit(sigs[j], b)
-        assert s_int(i) + s_int(j) == before  # the pair's sum of s is unchanged
+    def bit(k, b):
+        return (s_int(k) >> b) & 1
+
+    i, j = 16, 19
+    b = next(b for b in range(8, 240) if bit(i, b) and not bit(j, b))
+    before = s_int(i) + s_int(j)
+    sigs[i], sigs[j] = _flip_s_bit(sigs[i], b), _flip_s_bit(sigs[j], b)
+    assert s_int(i) + s_int(j) == before
+    plus, minus = (74, 102), (78, 98)  # rows 1 and 4, columns 2 and 6 of entries 64..127
+    b = next(b for b in range(8, 240) if all(not bit(k, b) for k in plus) and all(bit(k, b) for k in minus))
+    before = [s_int(k) for k in plus + minus]
+    for k in plus + minus:
+        sigs[k] = _flip_s_bit(sigs[k], b)
+    after = [s_int(k) for k in plus + minus]
+    assert after[0] - before[0] == after[1] - before[1] == before[2] - after[2] == before[3] - after[3] == 1 << b
     want = O.distill(prm, pk, msgs, sigs, 0, ds, 1)
-    assert [t for t, _ in want.invalid] == [5, 13, 16, 19]
+    expect = [16, 19, 74, 78, 98, 102]
+    assert [t for t, _ in want.invalid] == expect
     params = P.make_params(inst, 4, 4)
     dm, dsig = to_dev(torch, msgs, sigs)
-    for groups in (False, True):
-        P.poslo_ctx_set_distill_schedule(ctx, groups)
-        ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 1)
-        assert ccd.invalid() == [5, 13, 16, 19], f"groups={groups}"
-        assert ccd.valid_tag() == want.valid_tag
-    P.poslo_ctx_set_distill_schedule(ctx, False)
-    # the multi-signer path's group schedule too (the tag is the honest one)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 1)
+    assert ccd.invalid() == expect
+    assert ccd.valid_tag() == want.valid_tag
+    # the multi-signer path (the tag is the honest one, so AVer accepts)
     bj = P.BatchJobs([dict(pk=pk, ds=ds, tag=tag, t0=0, n=200, entry_base=0)])
     off = torch.arange(0, 201 * 40, 40, dtype=torch.int64, device="cuda")
-    for mode in (2, 2 | P.POSLO_DISTILL_GROUPS):
-        acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=mode)
-        assert acc == [True] and inv == [(0, 5), (0, 13), (0, 16), (0, 19)], f"mode {mode}"
+    acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=2)
+    assert acc == [True] and inv == [(0, t) for t in expect]

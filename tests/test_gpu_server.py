@@ -110,7 +110,7 @@ def test_server_under_load(P, gpu, inst):
                                      p_corrupt=0.1, seed=900 + inst)
     assert sum(q["flip"] is not None for q in log.requests) >= 5
     budget = 256 << 10
-    srv = P.Server(0, log.params, n_streams=4, max_group=16, distill=2 | P.POSLO_DISTILL_GROUPS, mem_bytes=budget)
+    srv = P.Server(0, log.params, n_streams=4, max_group=16, distill=2, mem_bytes=budget)
     srv.register_keys(list(range(64)), log.pks)
     L = log.L
     reqs = []

@@ -56,9 +56,12 @@ __device__ __forceinline__ void mdc2_block_perm(const PermTables<NT>& tb, uint32
 
 // MDC-2 over m || x.  FAST (16-byte aligned, length divisible by 16): each
 // 128-byte line of the message is loaded once, all eight blocks at a time,
-// so no line has to survive in the cache between block loads.
-template <int NT, bool FAST>
-__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const EntryView& v, const uint32_t x[4],
+// so no line has to survive in the cache between block loads.  LEAN loads
+// two blocks at a time instead (the line's other segments come from L2) and
+// derives x_t only for the final block: about half the live registers, so
+// twice the resident waves where LDS allows.  xf(x) writes x_t.
+template <int NT, bool FAST, bool LEAN, class XF>
+__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const EntryView& v, const XF& xf,
                                                  uint32_t dig[8]) {
     uint32_t h[4], hp[4];
     uint64_t b = 0;
@@ -66,15 +69,27 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
         const uint4* p = reinterpret_cast<const uint4*>(v.m);
         uint64_t lines = v.L / 128;
         for (uint64_t ln = 0; ln < lines; ln++) {
-            uint4 q[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) q[k] = p[8 * ln + k];
+            if constexpr (LEAN) {
 #pragma unroll 1
-            for (int k = 0; k < 8; k++, b++) {
-                uint32_t m[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
-                mdc2_block_perm(tb, h, hp, m, b == 0);
+                for (int k = 0; k < 8; k += 2) {
+                    const uint4 q0 = p[8 * ln + k], q1 = p[8 * ln + k + 1];
+                    const uint32_t m0[4] = {q0.x, q0.y, q0.z, q0.w};
+                    mdc2_block_perm(tb, h, hp, m0, b == 0);
+                    const uint32_t m1[4] = {q1.x, q1.y, q1.z, q1.w};
+                    mdc2_block_perm(tb, h, hp, m1, false);
+                    b += 2;
+                }
+            } else {
+                uint4 q[8];
 #pragma unroll
-                for (int r = 0; r < 7; r++) q[r] = q[r + 1];
+                for (int k = 0; k < 8; k++) q[k] = p[8 * ln + k];
+#pragma unroll 1
+                for (int k = 0; k < 8; k++, b++) {
+                    uint32_t m[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+                    mdc2_block_perm(tb, h, hp, m, b == 0);
+#pragma unroll
+                    for (int r = 0; r < 7; r++) q[r] = q[r + 1];
+                }
             }
         }
         for (; 16 * b < v.L; b++) {
@@ -82,8 +97,12 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
             uint32_t m[4] = {u.x, u.y, u.z, u.w};
             mdc2_block_perm(tb, h, hp, m, b == 0);
         }
+        uint32_t x[4];
+        xf(x);
         mdc2_block_perm(tb, h, hp, x, b == 0);  // the final block is x_t
     } else {
+        uint32_t x[4];
+        xf(x);
         uint64_t nb = (v.L + 16 + 15) / 16;
         for (; b < nb; b++) {
             uint32_t m[4];
@@ -104,8 +123,9 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
     }
 }
 
-template <int NT, int BLOCK, bool FAST>
-__global__ __launch_bounds__(BLOCK) void k_agg_ekeys_aes_perm(BatchArgs a, uint32_t* partials) {
+template <int NT, int BLOCK, bool FAST, bool LEAN, int WPE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_agg_ekeys_aes_perm(
+    BatchArgs a, uint32_t* partials) {
     // the kernel's only LDS allocation: tables first, then reduction scratch
     __shared__ uint32_t lds[NT * 256 * 64];
     perm_tables_fill<NT>(lds);
@@ -114,14 +134,16 @@ __global__ __launch_bounds__(BLOCK) void k_agg_ekeys_aes_perm(BatchArgs a, uint3
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint64_t pos = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; pos < a.n; pos += (uint64_t)gridDim.x * BLOCK) {
         if (skipped(a, pos)) continue;
-        uint64_t t = a.t0 + pos;
-        uint32_t j = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
+        const uint64_t t = a.t0 + pos;
+        const uint32_t j = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
         const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
-        uint32_t x[4] = {j, 0u, 0u, 0u};
-        penc_rk(tb, rk, x);
-        x[0] ^= j;
+        auto xf = [&](uint32_t x[4]) {
+            x[0] = j, x[1] = 0u, x[2] = 0u, x[3] = 0u;
+            penc_rk(tb, rk, x);
+            x[0] ^= j;
+        };
         uint32_t dig[8];
-        digest_mdc2_perm<NT, FAST>(tb, entry_view(a, pos), x, dig);
+        digest_mdc2_perm<NT, FAST, LEAN>(tb, entry_view(a, pos), xf, dig);
         acc288_add256(acc, dig);
     }
     __syncthreads();  // every lane is done with the tables
@@ -134,19 +156,22 @@ static const AggVariant kVariants[] = {
     {"nt1_c32_b256", 1, 32, 256, 0},   {"nt1_c32_b512", 1, 32, 512, 0},  {"nt1_c64_b512", 1, 64, 512, 0},
     {"nt2_c32_b512", 2, 32, 512, 0},   {"perm2_c64_b1024", 2, 64, 1024, 1}, {"perm1_c64_b1024", 1, 64, 1024, 1},
     {"perm1_c64_b512", 1, 64, 512, 1}, {"perm2_c64_b512", 2, 64, 512, 1},
+    {"perm2_lean_b1024", 2, 64, 1024, 1}, {"perm1_lean_b1024_w8", 1, 64, 1024, 1},
+    {"perm1_lean_b512_w8", 1, 64, 512, 1},
 };
 
 int agg_aes_variant_count() { return (int)(sizeof kVariants / sizeof kVariants[0]); }
 const AggVariant& agg_aes_variant(int v) { return kVariants[v]; }
-int agg_aes_default_variant() { return 10; }  // perm2_c64_b1024: fastest in the sweep on MI355X
+int agg_aes_default_variant() { return 15; }  // perm1_lean_b1024_w8: fastest in the sweep on MI355X
 size_t agg_aes_lds_bytes(int v) { return (size_t)kVariants[v].nt * 256 * kVariants[v].copies * 4; }
 
 #define LAUNCH(NT, C, B)                                                                              \
     hipLaunchKernelGGL((k_agg_ekeys_aes<NT, C, B, true>), dim3(grid), dim3(B), 0, s, a, partials); \
     break
 
-#define LAUNCHP(NT, B)                                                                              \
-    hipLaunchKernelGGL((k_agg_ekeys_aes_perm<NT, B, true>), dim3(grid), dim3(B), 0, s, a, partials); \
+#define LAUNCHP(NT, B, LEAN, WPE)                                                              \
+    hipLaunchKernelGGL((k_agg_ekeys_aes_perm<NT, B, true, LEAN, WPE>), dim3(grid), dim3(B), 0, s, a, \
+                       partials);                                                                   \
     break
 
 int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* partials, hipStream_t s) {
@@ -166,10 +191,13 @@ int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* 
         case 7: LAUNCH(1, 32, 512);
         case 8: LAUNCH(1, 64, 512);
         case 9: LAUNCH(2, 32, 512);
-        case 10: LAUNCHP(2, 1024);
-        case 11: LAUNCHP(1, 1024);
-        case 12: LAUNCHP(1, 512);
-        case 13: LAUNCHP(2, 512);
+        case 10: LAUNCHP(2, 1024, false, 4);
+        case 11: LAUNCHP(1, 1024, false, 4);
+        case 12: LAUNCHP(1, 512, false, 4);
+        case 13: LAUNCHP(2, 512, false, 4);
+        case 14: LAUNCHP(2, 1024, true, 4);
+        case 15: LAUNCHP(1, 1024, true, 8);
+        case 16: LAUNCHP(1, 512, true, 8);
         default: return POSLO_E_INVAL;
     }
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;

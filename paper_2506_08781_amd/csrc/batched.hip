@@ -153,7 +153,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         if (threadIdx.x == 0) misc[0] = atomicAdd(A.counter, 1u);
         if (SORT && threadIdx.x < 64) counts[threadIdx.x] = 0;
         __syncthreads();
-        const uint32_t item = misc[0];
+        // uniform across the workgroup: keeps the item's job record in scalar registers
+        const uint32_t item = __builtin_amdgcn_readfirstlane(misc[0]);
         if (item >= A.n_items) break;
         const BItem it = A.items[item];
         const BJob J = A.jobs[it.job];
@@ -191,13 +192,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             EntryView ev = entry_view(a, p);
             uint32_t x[4], dig[8];
             if constexpr (INST == INST_AES) {
-                uint64_t t = a.t0 + p;
-                uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
+                const uint64_t t = a.t0 + p;
+                const uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
                 const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
-                x[0] = jj, x[1] = 0, x[2] = 0, x[3] = 0;
-                penc_rk(tb, rk, x);
-                x[0] ^= jj;
-                digest_mdc2_any(tb, ev, a.end, x, dig, Mdc2BlockPerm{});
+                auto xf = [&](uint32_t y[4]) {
+                    y[0] = jj, y[1] = 0, y[2] = 0, y[3] = 0;
+                    penc_rk(tb, rk, y);
+                    y[0] ^= jj;
+                };
+                digest_mdc2_any_late(tb, ev, a.end, xf, x, dig, Mdc2BlockPerm{});
             } else {
                 one_time_seed_sha(a, p, x);
                 digest_sha_any(ev, a.end, x, dig);
@@ -302,6 +305,7 @@ static const HotVariant kHot[] = {
     {"aes_perm1_b512_c1024_sorted", 1, 1, 512, 1024, 1, 4},   {"sha_b256_c1024_sorted_w3", 0, 1, 256, 1024, 1, 3},
     {"sha_b256_c1024_sorted_w4", 0, 1, 256, 1024, 1, 4},      {"sha_b256_c256_sorted_w3", 0, 1, 256, 256, 1, 3},
     {"sha_b256_c1024_w3", 0, 1, 256, 1024, 0, 3},             {"sha_b512_c2048_sorted_w3", 0, 1, 512, 2048, 1, 3},
+    {"aes_perm1_b1024_c1024_sorted_w8", 1, 1, 1024, 1024, 1, 8},
 };
 constexpr int kNumHot = sizeof kHot / sizeof kHot[0];
 
@@ -332,6 +336,7 @@ static int launch_hot(int v, uint32_t grid, const BHot& A, hipStream_t s) {
         case 7: HOT(0, 1, 256, 256, true, 3);
         case 8: HOT(0, 1, 256, 1024, false, 3);
         case 9: HOT(0, 1, 512, 2048, true, 3);
+        case 10: HOT(1, 1, 1024, 1024, true, 8);
         default: return POSLO_E_INVAL;
     }
 #undef HOT

@@ -63,6 +63,38 @@ __device__ __forceinline__ void digest_mdc2_any(const T& tb, const EntryView& v,
     }
 }
 
+// The same with x_t derived only for the final blocks: xf(x) writes it into
+// x, which is returned; fewer values live across the message blocks
+template <class T, class XF, class AesBlock>
+__device__ __forceinline__ void digest_mdc2_any_late(const T& tb, const EntryView& v, const uint8_t* end, const XF& xf,
+                                                     uint32_t x[4], uint32_t dig[8], AesBlock blockfn) {
+    uint32_t h[4], hp[4];
+    uint64_t nfull = v.L / 16, b = 0;
+    for (; b < nfull; b++) {
+        uint32_t m[4];
+        load_msg_words<4>(v.m, 16 * b, end, m);
+        blockfn(tb, h, hp, m, b == 0);
+    }
+    xf(x);
+    uint64_t nb = (v.L + 16 + 15) / 16;
+    for (; b < nb; b++) {
+        uint32_t m[4];
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) word |= stream_byte_aes(v, x, 16 * b + 4 * w + k) << (8 * k);
+            m[w] = word;
+        }
+        blockfn(tb, h, hp, m, b == 0);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        dig[w] = h[w];
+        dig[4 + w] = hp[w];
+    }
+}
+
 // one MDC-2 block with the generic T-table reader
 struct Mdc2BlockGeneric {
     template <class T>

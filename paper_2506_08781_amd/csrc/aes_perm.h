@@ -48,12 +48,20 @@ struct PermTables {
     }
 };
 
+// Word index (t << 14) | (x << 6) | c.  Lane l of each wave loads te0[4l..4l+3]
+// once; then, per entry, the owning lane's word is read into a scalar
+// register and the wave writes the entry's 64 copies (64 consecutive words,
+// one store).  Needs a workgroup size that is a multiple of 64.
 template <int NT>
 __device__ __forceinline__ void perm_tables_fill(uint32_t* lds) {
-    // word index (t << 14) | (x << 6) | c
-    for (int k = threadIdx.x; k < NT * 256 * 64; k += blockDim.x) {
-        int x = (k >> 6) & 255, t = k >> 14;
-        lds[k] = rotl32(c_aes.te0[x], 16 * t);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const uint32_t v0 = c_aes.te0[4 * lane], v1 = c_aes.te0[4 * lane + 1], v2 = c_aes.te0[4 * lane + 2],
+                   v3 = c_aes.te0[4 * lane + 3];
+    for (uint32_t e = wave; e < NT * 256u; e += nwaves) {
+        const uint32_t x = e & 255u, q = x & 3u;
+        const uint32_t mine = q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
+        const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)(x >> 2));
+        lds[(e << 6) | lane] = rotl32(v, 16 * (e >> 8));
     }
 }
 

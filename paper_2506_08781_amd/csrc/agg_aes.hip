@@ -57,7 +57,7 @@ __device__ __forceinline__ void mdc2_block_perm(const PermTables<NT>& tb, uint32
 // MDC-2 over m || x.  FAST (16-byte aligned, length divisible by 16): each
 // 128-byte line of the message is loaded once, all eight blocks at a time,
 // so no line has to survive in the cache between block loads.  LEAN loads
-// two blocks at a time instead (the line's other segments come from L2) and
+// four blocks (64 bytes, one L2 sector) at a time instead and
 // derives x_t only for the final block: about half the live registers, so
 // twice the resident waves where LDS allows.  xf(x) writes x_t.
 template <int NT, bool FAST, bool LEAN, class XF>
@@ -71,13 +71,17 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
         for (uint64_t ln = 0; ln < lines; ln++) {
             if constexpr (LEAN) {
 #pragma unroll 1
-                for (int k = 0; k < 8; k += 2) {
-                    const uint4 q0 = p[8 * ln + k], q1 = p[8 * ln + k + 1];
-                    const uint32_t m0[4] = {q0.x, q0.y, q0.z, q0.w};
-                    mdc2_block_perm(tb, h, hp, m0, b == 0);
-                    const uint32_t m1[4] = {q1.x, q1.y, q1.z, q1.w};
-                    mdc2_block_perm(tb, h, hp, m1, false);
-                    b += 2;
+                for (int k = 0; k < 8; k += 4) {
+                    uint4 q[4];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) q[r] = p[8 * ln + k + r];
+#pragma unroll 1
+                    for (int r = 0; r < 4; r++, b++) {
+                        const uint32_t m[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+                        mdc2_block_perm(tb, h, hp, m, b == 0);
+#pragma unroll
+                        for (int u = 0; u < 3; u++) q[u] = q[u + 1];
+                    }
                 }
             } else {
                 uint4 q[8];

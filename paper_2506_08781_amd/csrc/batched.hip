@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "aes_perm.h"
+#include "aes_quad.h"
 #include "batch_run.h"
 #include "device_verify.h"
 
@@ -63,10 +64,9 @@ struct BSeeds {
     uint32_t* rdec;  // 17 words per job: ok, x[8], y[8]
 };
 
+template <int INST>
 __global__ __launch_bounds__(256) void k_batch_seeds(BSeeds S) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
+    __shared__ uint32_t lds[INST == INST_AES ? 4 * 256 : 1];
     if (blockIdx.x >= S.row_blocks) {
         uint32_t j = (blockIdx.x - S.row_blocks) * blockDim.x + threadIdx.x;
         if (j >= S.njobs) return;
@@ -87,33 +87,33 @@ __global__ __launch_bounds__(256) void k_batch_seeds(BSeeds S) {
         }
         return;
     }
-    LdsTables<4, 1> tb{lds};
-    uint64_t row = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row == 0) S.counter[0] = 0;
-    if (row >= S.n_rows) return;
+    // AES: four lanes per row (aes_quad.h); SHA-256: one lane per row
+    if constexpr (INST == INST_AES) lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    const LdsTables<4, 1> tb{lds};
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t row = INST == INST_AES ? g >> 2 : g;
+    const uint32_t c = (uint32_t)g & 3u;
+    if (g == 0) S.counter[0] = 0;
+    if (row >= S.n_rows) return;  // whole quads leave together
     uint32_t j = S.job_of_row[row];
     const BJob& J = S.jobs[j];
     const DsArg& D = S.ds[j];
     uint64_t i = (J.t0 >> S.log2_n2) + (row - J.epoch_base);
     int k = ds_cover(D, i);
     if (k < 0) k = 0;  // coverage validated on the host
+    uint32_t* e = S.tab + row * kEpochWords;
+    if constexpr (INST == INST_AES) {
+        uint32_t xc = D.v[k][c];
+        for (int bt = (int)D.depth[k] - 1; bt >= 0; bt--) xc = quad_prf_node(tb, xc, (uint32_t)((i >> bt) & 1u), c);
+        quad_epoch_row(tb, xc, c, e);
+        return;
+    }
     uint32_t x[4] = {D.v[k][0], D.v[k][1], D.v[k][2], D.v[k][3]};
     for (int bt = (int)D.depth[k] - 1; bt >= 0; bt--) {
-        uint32_t bit = (uint32_t)((i >> bt) & 1u), nx[4];
-        if (S.inst == INST_AES)
-            prf_node_aes(tb, x, bit, nx);
-        else
-            prf_node_sha(x, bit, nx);
+        uint32_t nx[4];
+        prf_node_sha(x, (uint32_t)((i >> bt) & 1u), nx);
         x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
-    }
-    uint32_t* e = S.tab + row * kEpochWords;
-    if (S.inst == INST_AES) {
-        uint32_t st[4] = {x[0], x[1], x[2], x[3]};
-        aes128_encrypt_rk(tb, c_iv.a, st);
-        uint32_t h1[4] = {st[0] ^ x[0], st[1] ^ x[1], st[2] ^ x[2], st[3] ^ x[3]};
-        uint32_t rk[44];
-        aes128_expand(tb, h1, rk);
-        for (int w = 0; w < 44; w++) e[w] = rk[w];
     }
     for (int w = 0; w < 4; w++) e[44 + w] = x[w];
 }
@@ -507,7 +507,9 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     S.ds = (const DsArg*)d_ds_;
     S.job_of_row = (const uint32_t*)d_rows_;
     S.n_rows = rows;
-    S.row_blocks = (uint32_t)std::max<uint64_t>(1, (rows + 255) / 256);
+    // AES rows take four lanes each
+    const uint64_t row_lanes = rows * (prm_.inst == POSLO_INST_AES ? 4 : 1);
+    S.row_blocks = (uint32_t)std::max<uint64_t>(1, (row_lanes + 255) / 256);
     S.njobs = njobs;
     S.log2_n2 = prm_.log2_n2;
     S.inst = prm_.inst;
@@ -530,7 +532,10 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     A.xbad = emit ? (uint8_t*)d_xbad_ : nullptr;
     const uint32_t* tg = prof->d_gtable;
     auto launch_all = [&](hipStream_t q, bool timed) -> int {
-        hipLaunchKernelGGL(k_batch_seeds, dim3(seed_grid), dim3(256), 0, q, S);
+        if (prm_.inst == POSLO_INST_AES)
+            hipLaunchKernelGGL(k_batch_seeds<INST_AES>, dim3(seed_grid), dim3(256), 0, q, S);
+        else
+            hipLaunchKernelGGL(k_batch_seeds<INST_SHA256>, dim3(seed_grid), dim3(256), 0, q, S);
         if (timed) prof_begin(prof, POSLO_KT_BATCH_HOT, q);
         int r = launch_hot(tune_.variant, grid, A, q);
         if (timed) prof_end(prof, POSLO_KT_BATCH_HOT, q);

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <vector>
 
+#include "aes_quad.h"
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
@@ -30,40 +31,39 @@ namespace poslo {
 // A1: per-epoch seeds x_0[i] = SR(ds, i), plus the hoisted MMO state
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint32_t inst, uint64_t epoch_first,
-                                                   uint32_t n_epochs, uint32_t* tab) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
+// AES: four lanes per epoch (aes_quad.h), so each link of the walk's chain
+// of dependent PRF calls costs about a third of a one-lane encryption;
+// SHA-256: one lane per epoch.
+template <int INST>
+__global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_first, uint32_t n_epochs, uint32_t* tab) {
+    __shared__ uint32_t lds[INST == INST_AES ? 4 * 256 : 1];
+    if constexpr (INST == INST_AES) lds_tables_fill<4, 1>(lds);
     __syncthreads();
-    uint32_t ep = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ep >= n_epochs) return;
-    LdsTables<4, 1> tb{lds};
+    const LdsTables<4, 1> tb{lds};
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ep = INST == INST_AES ? g >> 2 : g, c = g & 3u;
+    if (ep >= n_epochs) return;  // whole quads leave together
     uint64_t i = epoch_first + ep;
     int k = ds_cover(ds, i);
     if (k < 0) k = 0;  // coverage is validated on the host before launch
-    uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
-    // SC: walk the bits of i below the node's depth, most significant first
-    for (int j = (int)ds.depth[k] - 1; j >= 0; j--) {
-        uint32_t b = (uint32_t)((i >> j) & 1u), nx[4];
-        if (inst == INST_AES)
-            prf_node_aes(tb, x, b, nx);
-        else
-            prf_node_sha(x, b, nx);
-        x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
-    }
     uint32_t* e = tab + (uint64_t)ep * kEpochWords;
-    if (inst == INST_AES) {
-        uint32_t s[4] = {x[0], x[1], x[2], x[3]};
-        aes128_encrypt_rk(tb, c_iv.a, s);
-        uint32_t h1[4] = {s[0] ^ x[0], s[1] ^ x[1], s[2] ^ x[2], s[3] ^ x[3]};
-        uint32_t rk[44];
-        aes128_expand(tb, h1, rk);
-        for (int w = 0; w < 44; w++) e[w] = rk[w];
+    if constexpr (INST == INST_AES) {
+        uint32_t xc = ds.v[k][c];
+        // SC: walk the bits of i below the node's depth, most significant first
+        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) xc = quad_prf_node(tb, xc, (uint32_t)((i >> j) & 1u), c);
+        quad_epoch_row(tb, xc, c, e);
+    } else {
+        uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
+        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) {
+            uint32_t nx[4];
+            prf_node_sha(x, (uint32_t)((i >> j) & 1u), nx);
+            x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
+        }
+        e[44] = x[0];
+        e[45] = x[1];
+        e[46] = x[2];
+        e[47] = x[3];
     }
-    e[44] = x[0];
-    e[45] = x[1];
-    e[46] = x[2];
-    e[47] = x[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -386,8 +386,12 @@ bool fast_layout(const poslo_msgs* m, uint64_t align) {
 
 int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s) {
     if (n_epochs == 0) return POSLO_OK;
-    hipLaunchKernelGGL(k_seed_table, dim3((n_epochs + 63) / 64), dim3(64), 0, s, dsa, inst, a.epoch_first,
-                       n_epochs, const_cast<uint32_t*>(a.tab));
+    if (inst == INST_AES)
+        hipLaunchKernelGGL(k_seed_table<INST_AES>, dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa, a.epoch_first,
+                           n_epochs, const_cast<uint32_t*>(a.tab));
+    else
+        hipLaunchKernelGGL(k_seed_table<INST_SHA256>, dim3((n_epochs + 63) / 64), dim3(64), 0, s, dsa,
+                           a.epoch_first, n_epochs, const_cast<uint32_t*>(a.tab));
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 

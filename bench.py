@@ -106,7 +106,7 @@ TRAFFIC = {
                       "sc25519.h"],
             "sha256": "b124bc6464674c9d", "profile": "profiles/pmc_aver_2p20x256.md"},
     "sha": {"fetch_kib": 133163.7, "write_kib": 1088.0, "fetch_scale": 2.0, "write_scale": 1.0,
-            "files": ["verifier.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h"],
+            "files": ["agg_sha.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h"],
             "sha256": "14f2f4bad312e1c7", "profile": "profiles/pmc_aver_2p20x256.md"},
 }
 

@@ -34,6 +34,10 @@ int agg_aes_default_variant();
 // launch variant v (fast layout) or the generic-layout kernel
 int launch_agg_aes(int v, bool fast, uint32_t grid, const void* batch_args, uint32_t* partials, hipStream_t s);
 size_t agg_aes_lds_bytes(int v);
+// the POSLO hot kernel (agg_sha.hip): layout 2 = 16-byte aligned fixed
+// length, 1 = 4-byte aligned fixed length, 0 = any
+constexpr int kAggShaBlock = 256;
+int launch_agg_sha(int layout, uint32_t grid, const void* batch_args, uint32_t* partials, hipStream_t s);
 
 struct KeyEntry {
     std::string pk;

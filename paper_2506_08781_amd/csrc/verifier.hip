@@ -1,6 +1,6 @@
-// POSLO-F aggregate verification on gfx950: the per-epoch seed table, the
-// SHA-256 instantiation's fused kernel, per-entry digests, the final fold
-// with the curve check, and the context and AVer entry points.
+// POSLO-F aggregate verification on gfx950: the per-epoch seed table,
+// per-entry digests, the final fold with the curve check, and the context
+// and AVer entry points.
 //
 // Paper: section "POSLO Parallel Batch Verification" (figure "Parallel
 // POSLO signature verification algorithm"): per entry SR, PRF_0, H mod q, a
@@ -10,7 +10,7 @@
 // table; digests are summed lazily as raw 256-bit integers in a 288-bit
 // accumulator and reduced mod q once (exact, since (sum H) mod q =
 // (sum (H mod q)) mod q); the final fold and the curve check run on the GPU
-// with per-key fixed-base tables: 128 table lookups and a 7-level tree of
+// with per-key fixed-base tables: 64 table lookups and a 6-level tree of
 // point additions instead of a 253-step double-and-add chain.
 #include <string.h>
 
@@ -67,23 +67,10 @@ __global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_firs
 }
 
 // ---------------------------------------------------------------------------
-// POSLO (SHA-256): fused per-entry PRF + digest + lazy sum
+// per-entry outputs (the hot kernels are in agg_aes.hip and agg_sha.hip)
 // ---------------------------------------------------------------------------
 
 constexpr int kBlock = 256;
-
-template <bool FAST, bool VEC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_agg_ekeys_sha(BatchArgs a, uint32_t* partials) {
-    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint64_t pos = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pos < a.n; pos += (uint64_t)gridDim.x * kBlock) {
-        if (skipped(a, pos)) continue;
-        uint32_t xw[4], dig[8];
-        one_time_seed_sha(a, pos, xw);
-        digest_sha<FAST, VEC>(entry_view(a, pos), xw, dig);
-        acc288_add256(acc, dig);
-    }
-    block_reduce288_store<kBlock>(acc, partials + (uint64_t)blockIdx.x * 9);
-}
 
 // per-entry outputs: e_t mod q (eight LE words) and x_t bytes (four LE words)
 template <bool FAST>
@@ -427,19 +414,14 @@ static int launch_agg(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m
         prof_end(c, POSLO_KT_AGG, s);
         *n_part = grid;
     } else {
-        uint64_t want = (m->n + kBlock - 1) / kBlock;
+        uint64_t want = (m->n + kAggShaBlock - 1) / kAggShaBlock;
         // four resident workgroups per CU measured best for the SHA-256 kernel
         uint64_t cap = (uint64_t)c->num_cu * (c->wg_per_cu > 0 ? c->wg_per_cu : 4);
         uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
         if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)grid * 9))) return st;
         prof_begin(c, POSLO_KT_AGG, s);
-        if (fast_layout(m, 16))
-            hipLaunchKernelGGL((k_agg_ekeys_sha<true, true>), dim3(grid), dim3(kBlock), 0, s, a, c->d_part);
-        else if (fast_layout(m, 4))
-            hipLaunchKernelGGL((k_agg_ekeys_sha<true, false>), dim3(grid), dim3(kBlock), 0, s, a, c->d_part);
-        else
-            hipLaunchKernelGGL((k_agg_ekeys_sha<false, false>), dim3(grid), dim3(kBlock), 0, s, a, c->d_part);
-        HIP_TRY(hipGetLastError());
+        if ((st = launch_agg_sha(fast_layout(m, 16) ? 2 : fast_layout(m, 4) ? 1 : 0, grid, &a, c->d_part, s)))
+            return st;
         prof_end(c, POSLO_KT_AGG, s);
         *n_part = grid;
     }

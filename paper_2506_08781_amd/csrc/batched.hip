@@ -267,9 +267,11 @@ struct BVerify {
     uint32_t* count;  // number appended
 };
 
-// PRE: e_t and the x checks come from the hashing kernel (launch with emit)
+// PRE: e_t and the x checks come from the hashing kernel (launch with
+// emit); each thread then checks entries i and i + 128 of its tile with one
+// shared inversion
 template <bool PRE>
-__global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
+__global__ __launch_bounds__(PRE ? 128 : 256) void k_batch_verify(BVerify V) {
     __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
     if constexpr (!PRE) {
         lds_tables_fill<4, 1>(lds);
@@ -278,21 +280,35 @@ __global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
     LdsTables<4, 1> tb{lds};
     const BItem it = V.tiles[blockIdx.x];
     const BJob& J = V.jobs[it.job];
-    bool bad = false;
-    uint64_t slot = 0;
-    if (threadIdx.x < it.count) {
-        uint64_t p = it.first + threadIdx.x;
-        uint32_t e[8], s[8];
-        if constexpr (PRE) {
-            for (int k = 0; k < 8; k++) e[k] = V.ekeys[(J.ebase + p) * 8 + k];
-            bad = V.xbad[J.ebase + p] || !verify_sig(J.sigs + p * 80, e, J.ty, V.tg, s);
-        } else {
+    if constexpr (PRE) {
+        uint64_t p[2];
+        bool act[2], go[2], ok[2];
+        const uint8_t* sg[2];
+        const uint32_t* e[2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            act[k] = threadIdx.x + 128u * k < it.count;
+            p[k] = it.first + threadIdx.x + 128u * k;
+            go[k] = act[k] && !V.xbad[J.ebase + p[k]];
+            // skipped entries point at the tile's first entry (in bounds)
+            sg[k] = J.sigs + (go[k] ? p[k] : it.first) * 80;
+            e[k] = V.ekeys + (J.ebase + (go[k] ? p[k] : it.first)) * 8;
+        }
+        verify_sig2(sg, e, go, J.ty, V.tg, ok);
+#pragma unroll
+        for (int k = 0; k < 2; k++) wave_append(act[k] && !ok[k], J.vbase + p[k], V.idx, V.count);
+    } else {
+        bool bad = false;
+        uint64_t slot = 0;
+        if (threadIdx.x < it.count) {
+            uint64_t p = it.first + threadIdx.x;
+            uint32_t e[8], s[8];
             BatchArgs a = job_args(J, V.log2_n2, V.tab);
             bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
+            slot = J.vbase + p;
         }
-        slot = J.vbase + p;
+        wave_append(bad, slot, V.idx, V.count);
     }
-    wave_append(bad, slot, V.idx, V.count);
 }
 
 __global__ void k_zero_u32(uint32_t* p) { p[0] = 0; }
@@ -626,7 +642,7 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.count = cnt;
     prof_begin(prof, POSLO_KT_VERIFY, s);
     if (emitted_)
-        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(128), 0, s, V);
     else
         hipLaunchKernelGGL(k_batch_verify<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
     prof_end(prof, POSLO_KT_VERIFY, s);

@@ -175,6 +175,59 @@ __device__ __forceinline__ bool verify_sig(const uint8_t* sg, const uint32_t e[8
     return ge_encodes_to(P, r);
 }
 
+// encode(P) == bytes given 1/Z (eight little-endian words)
+__device__ __forceinline__ bool encodes_to_zinv(const ge& P, const fe& zi, const uint32_t want[8]) {
+    fe x, y;
+    fe_mul(x, P.X, zi);
+    fe_mul(y, P.Y, zi);
+    uint8_t enc[32];
+    fe_to_bytes(enc, y);
+    enc[31] |= (uint8_t)(fe_isodd(x) << 7);
+    uint32_t diff = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) diff |= load_le32(enc + 4 * k) ^ want[k];
+    return diff == 0;
+}
+
+__device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, bool go, const uint32_t* ty,
+                                          const uint32_t* tg, ge& P) {
+    uint32_t ek[8], s[8];
+    for (int w = 0; w < 8; w++) {
+        s[w] = go ? load_le32(sg + 4 * w) : 0u;
+        ek[w] = go ? e[w] : 0u;
+    }
+    const bool c = go && sc_is_canonical(s);
+    if (!c)
+        for (int w = 0; w < 8; w++) s[w] = ek[w] = 0;  // the identity: Z stays nonzero
+    lane_double_scalar(P, ty, tg, ek, s);
+    return c;
+}
+
+__device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge& P, const fe& zi) {
+    uint32_t r[8];
+    for (int w = 0; w < 8; w++) r[w] = c ? load_le32(sg + 32 + 4 * w) : 0u;
+    return c && encodes_to_zinv(P, zi, r);
+}
+
+// The curve part of two entries' checks (as verify_sig; e[k] points to
+// e_t's eight words in memory) with one shared inversion (Montgomery's
+// trick: 1/Z0 = Z1 / (Z0 Z1), 1/Z1 = Z0 / (Z0 Z1)), which saves about 260
+// multiplications per pair.  go[k] = false skips entry k (reported false);
+// its pointers must still be readable.
+__device__ __forceinline__ void verify_sig2(const uint8_t* const sg[2], const uint32_t* const e[2], const bool go[2],
+                                            const uint32_t* ty, const uint32_t* tg, bool ok[2]) {
+    ge P0, P1;
+    const bool c0 = sig_point(sg[0], e[0], go[0], ty, tg, P0);
+    const bool c1 = sig_point(sg[1], e[1], go[1], ty, tg, P1);
+    fe zz, inv, zi;
+    fe_mul(zz, P0.Z, P1.Z);
+    fe_inv(inv, zz);
+    fe_mul(zi, inv, P1.Z);
+    ok[0] = sig_encodes(sg[0], c0, P0, zi);
+    fe_mul(zi, inv, P0.Z);
+    ok[1] = sig_encodes(sg[1], c1, P1, zi);
+}
+
 // Individual verification of the entry at batch position pos with signature
 // bytes sg (80): x_t equals the re-derived one-time seed, s_t < q, and
 // encode(e_t*Y + s_t*G) equals the R_t bytes.  On success e (mod q) and s are

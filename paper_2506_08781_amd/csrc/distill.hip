@@ -107,26 +107,45 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 }
 
 // the curve part of every entry's check, with e_t and the x check from
-// k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials
-__global__ __launch_bounds__(kTile) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys, const uint8_t* xbad) {
+// k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials.
+// Each thread checks entries i and i + kTile/2 of its tile with one shared
+// inversion.
+constexpr int kVerifyBlock = kTile / 2;
+__global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys,
+                                                               const uint8_t* xbad) {
     uint64_t start, end;
-    bool any = tile_range(v.g, blockIdx.x, start, end);
-    uint64_t pos = start + threadIdx.x;
+    const bool any = tile_range(v.g, blockIdx.x, start, end);
     uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (any && pos < end) {
-        uint32_t e[8], s[8];
-        for (int k = 0; k < 8; k++) e[k] = ekeys[pos * 8 + k];
-        const bool ok = !xbad[pos] && verify_sig(v.sigs + 80 * pos, e, v.ty, v.tg, s);
-        v.flags[pos] = ok ? 0 : 1;
-        if (ok) {
-            acc288_add256(ae, e);
-            acc288_add256(as, s);
+    uint64_t pos[2];
+    bool act[2], go[2], ok[2];
+    const uint8_t* sg[2];
+    const uint32_t* e[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        pos[k] = start + threadIdx.x + k * kVerifyBlock;
+        act[k] = any && pos[k] < end;
+        go[k] = act[k] && !xbad[pos[k]];
+        // skipped entries point at entry 0 (read by nothing that matters)
+        sg[k] = v.sigs + (go[k] ? 80 * pos[k] : 0);
+        e[k] = ekeys + (go[k] ? pos[k] * 8 : 0);
+    }
+    verify_sig2(sg, e, go, v.ty, v.tg, ok);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (!act[k]) continue;
+        v.flags[pos[k]] = ok[k] ? 0 : 1;
+        if (ok[k]) {
+            uint32_t w8[8];
+            for (int w = 0; w < 8; w++) w8[w] = e[k][w];
+            acc288_add256(ae, w8);
+            for (int w = 0; w < 8; w++) w8[w] = load_le32(sg[k] + 4 * w);
+            acc288_add256(as, w8);
         }
     }
     uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
-    block_reduce288_store<kTile>(ae, out);
+    block_reduce288_store<kVerifyBlock>(ae, out);
     __syncthreads();
-    block_reduce288_store<kTile>(as, out + 9);
+    block_reduce288_store<kVerifyBlock>(as, out + 9);
 }
 
 // list mode (SeBVer I): flags[i] = 1 when list item i is invalid
@@ -460,7 +479,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         else
             hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a, sigs,
                                (uint32_t*)ek, (uint8_t*)xb);
-        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, v, (const uint32_t*)ek,
+        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v, (const uint32_t*)ek,
                            (const uint8_t*)xb);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);

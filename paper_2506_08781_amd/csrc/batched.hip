@@ -257,7 +257,7 @@ __global__ __launch_bounds__(64) void k_batch_final(const BJob* jobs, const uint
 struct BVerify {
     const BJob* jobs;
     const BItem* tiles;  // up to 256 entries each
-    const uint32_t* tg;
+    const uint32_t* tg;  // G's wide table
     uint32_t inst;
     uint32_t log2_n2;
     const uint32_t* tab;
@@ -632,7 +632,8 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     BVerify V;
     V.jobs = (const BJob*)d_jobs_;
     V.tiles = (const BItem*)d_vtiles_;
-    V.tg = prof->d_gtable;
+    V.tg = ctx_gtable_wide(prof);
+    if (!V.tg) return POSLO_E_NOMEM;
     V.inst = prm_.inst;
     V.log2_n2 = prm_.log2_n2;
     V.tab = (const uint32_t*)d_tab_;

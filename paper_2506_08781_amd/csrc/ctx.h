@@ -7,6 +7,7 @@
 
 #include <list>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -68,6 +69,8 @@ struct poslo_ctx {
     uint32_t* h_result = nullptr;  // pinned
     // comb tables: G (static) and per-key Y, LRU-bounded
     uint32_t* d_gtable = nullptr;
+    uint32_t* d_gtable_wide = nullptr;  // built on first use (ctx_gtable_wide)
+    std::mutex wide_mu;
     size_t key_cap = 4096;
     std::list<poslo::KeyEntry> keys;  // front = most recent
     std::unordered_map<std::string, std::list<poslo::KeyEntry>::iterator> key_index;
@@ -93,6 +96,9 @@ const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
 // nullptr and are counted in *n_bad (the call then returns E_ENCODING).
 // Keys of one call are never evicted by that call.
 int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad);
+// G's wide table for the per-entry checks (comb.h), built on first use;
+// nullptr if it cannot be allocated
+const uint32_t* ctx_gtable_wide(poslo_ctx* c);
 // per-context state of the multi-signer path, released with the context
 void batch_release(poslo_ctx* c);
 // comb tables (comb.h layout) of the m encoded points pks (host, 32 bytes

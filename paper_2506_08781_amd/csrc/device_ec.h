@@ -78,10 +78,18 @@ PD int comb_digit(const uint32_t k[8], int w, uint32_t& carry) {
     return v > 128 ? v - 256 : v;
 }
 
+// signed radix-65536 digit of window w (the wide generator table)
+PD int wide_digit(const uint32_t k[8], int w, uint32_t& carry) {
+    const int v = (int)((k[w >> 1] >> (16 * (w & 1))) & 0xffffu) + (int)carry;
+    carry = v > 32768 ? 1u : 0u;
+    return v > 32768 ? v - 65536 : v;
+}
+
 // t[w][|d| - 1] with the sign of d applied; the identity for d = 0
+template <int PER = kCombPerWindow>
 PD void comb_lookup(gn& q, const uint32_t* table, int w, int d) {
     const uint32_t m = (uint32_t)(d < 0 ? -d : d);
-    const uint32_t* p = table + ((uint64_t)w * kCombPerWindow + (m ? m - 1 : 0)) * kCombEntryWords;
+    const uint32_t* p = table + ((uint64_t)w * PER + (m ? m - 1 : 0)) * kCombEntryWords;
     fe a, b, t;
 #pragma unroll
     for (int k = 0; k < 8; k++) {
@@ -144,6 +152,23 @@ __device__ __forceinline__ void lane_double_scalar(ge& P, const uint32_t* ty, co
         comb_lookup(q, ty, w, comb_digit(e, w, ce));
         ge_madd(P, P, q);
         comb_lookup(q, tg, w, comb_digit(s, w, cs));
+        ge_madd(P, P, q);
+    }
+}
+
+// e*Y + s*G by one lane with G's wide table: 32 + 16 lookups and mixed
+// additions; e, s < 2^253
+__device__ __forceinline__ void lane_double_scalar_wide(ge& P, const uint32_t* ty, const uint32_t* tg_wide,
+                                                        const uint32_t e[8], const uint32_t s[8]) {
+    ge_identity(P);
+    uint32_t ce = 0, cs = 0;
+    for (int w = 0; w < kWideWindows; w++) {
+        gn q;
+        comb_lookup(q, ty, 2 * w, comb_digit(e, 2 * w, ce));
+        ge_madd(P, P, q);
+        comb_lookup(q, ty, 2 * w + 1, comb_digit(e, 2 * w + 1, ce));
+        ge_madd(P, P, q);
+        comb_lookup<kWidePerWindow>(q, tg_wide, w, wide_digit(s, w, cs));
         ge_madd(P, P, q);
     }
 }

@@ -163,13 +163,13 @@ __device__ __forceinline__ void digest_sha_any(const EntryView& v, const uint8_t
 
 // The curve part of an entry's check, given e_t (mod q): s_t < q and
 // encode(e_t*Y + s_t*G) equals the R_t bytes of the signature sg (80 bytes:
-// s_t, R_t, x_t).  s is returned.
+// s_t, R_t, x_t).  s is returned.  ty: Y's table; tg_wide: G's wide table.
 __device__ __forceinline__ bool verify_sig(const uint8_t* sg, const uint32_t e[8], const uint32_t* ty,
-                                           const uint32_t* tg, uint32_t s[8]) {
+                                           const uint32_t* tg_wide, uint32_t s[8]) {
     for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
     if (!sc_is_canonical(s)) return false;
     ge P;
-    lane_double_scalar(P, ty, tg, e, s);
+    lane_double_scalar_wide(P, ty, tg_wide, e, s);
     uint32_t r[8];
     for (int k = 0; k < 8; k++) r[k] = load_le32(sg + 32 + 4 * k);
     return ge_encodes_to(P, r);
@@ -190,7 +190,7 @@ __device__ __forceinline__ bool encodes_to_zinv(const ge& P, const fe& zi, const
 }
 
 __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, bool go, const uint32_t* ty,
-                                          const uint32_t* tg, ge& P) {
+                                          const uint32_t* tg_wide, ge& P) {
     uint32_t ek[8], s[8];
     for (int w = 0; w < 8; w++) {
         s[w] = go ? load_le32(sg + 4 * w) : 0u;
@@ -199,7 +199,7 @@ __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, 
     const bool c = go && sc_is_canonical(s);
     if (!c)
         for (int w = 0; w < 8; w++) s[w] = ek[w] = 0;  // the identity: Z stays nonzero
-    lane_double_scalar(P, ty, tg, ek, s);
+    lane_double_scalar_wide(P, ty, tg_wide, ek, s);
     return c;
 }
 
@@ -215,10 +215,10 @@ __device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge&
 // multiplications per pair.  go[k] = false skips entry k (reported false);
 // its pointers must still be readable.
 __device__ __forceinline__ void verify_sig2(const uint8_t* const sg[2], const uint32_t* const e[2], const bool go[2],
-                                            const uint32_t* ty, const uint32_t* tg, bool ok[2]) {
+                                            const uint32_t* ty, const uint32_t* tg_wide, bool ok[2]) {
     ge P0, P1;
-    const bool c0 = sig_point(sg[0], e[0], go[0], ty, tg, P0);
-    const bool c1 = sig_point(sg[1], e[1], go[1], ty, tg, P1);
+    const bool c0 = sig_point(sg[0], e[0], go[0], ty, tg_wide, P0);
+    const bool c1 = sig_point(sg[1], e[1], go[1], ty, tg_wide, P1);
     fe zz, inv, zi;
     fe_mul(zz, P0.Z, P1.Z);
     fe_inv(inv, zz);
@@ -234,7 +234,7 @@ __device__ __forceinline__ void verify_sig2(const uint8_t* const sg[2], const ui
 // returned.
 template <class T>
 __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
-                                           uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg,
+                                           uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg_wide,
                                            uint32_t e[8], uint32_t s[8]) {
     uint32_t x[4], xs[4];
     for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
@@ -251,7 +251,7 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
         digest_sha_any(ev, end, x, dig);
     }
     sc_reduce256(e, dig);
-    return verify_sig(sg, e, ty, tg, s);
+    return verify_sig(sg, e, ty, tg_wide, s);
 }
 
 // append `value` for every lane with `flag` set: one atomic per wave (ballot,

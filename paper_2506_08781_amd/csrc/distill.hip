@@ -55,7 +55,7 @@ struct VerifyArgs {
     const uint64_t* list;  // list mode: batch positions
     uint64_t list_n;
     const uint32_t* ty;
-    const uint32_t* tg;
+    const uint32_t* tg;    // G's wide table (the per-entry checks)
     uint8_t* flags;        // 1 = invalid, per batch position (tile mode) or list item
     uint32_t* tile_part;   // 18 words per tile: lazy sums of e_t and s_t over valid entries
 };
@@ -459,6 +459,8 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         prof_begin(c, POSLO_KT_SEED, s);
         if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return fail(st);
         prof_end(c, POSLO_KT_SEED, s);
+        const uint32_t* gw = ctx_gtable_wide(c);
+        if (!gw) return fail(POSLO_E_NOMEM);
         VerifyArgs v;
         v.a = a;
         v.g = TileGeom{n, span, tpu};
@@ -467,7 +469,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         v.list = nullptr;
         v.list_n = 0;
         v.ty = key->d_table;
-        v.tg = c->d_gtable;
+        v.tg = gw;
         v.flags = (uint8_t*)flags;
         v.tile_part = (uint32_t*)tiles;
         prof_begin(c, POSLO_KT_VERIFY, s);
@@ -795,6 +797,8 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
             if (ccd->invalid[k] < m->t0 || ccd->invalid[k] - m->t0 >= m->n) return POSLO_E_INVAL;
             pos[k] = ccd->invalid[k] - m->t0;
         }
+        const uint32_t* gw = ctx_gtable_wide(c);
+        if (!gw) return POSLO_E_NOMEM;
         void *dpos, *dsig, *dflags;
         if ((st = scratch(c, S_IDX, ni * 8, &dpos)) || (st = scratch(c, S_SIGS, ni * 80, &dsig)) ||
             (st = scratch(c, S_FLAGS, ni, &dflags)))
@@ -810,7 +814,7 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
         v.list = (const uint64_t*)dpos;
         v.list_n = ni;
         v.ty = key->d_table;
-        v.tg = c->d_gtable;
+        v.tg = gw;
         v.flags = (uint8_t*)dflags;
         v.tile_part = nullptr;
         hipLaunchKernelGGL(k_verify_list, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);

@@ -9,10 +9,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "comb.h"
 #include "ctx.h"
+#include "device_ec.h"
 #include "ge25519.h"
 
 namespace poslo {
@@ -42,6 +44,41 @@ __global__ __launch_bounds__(kCombPerWindow) void k_comb_build(const uint8_t* pk
         if (w + 1 < kCombWindows)
             for (int k = 0; k < 8; k++) ge_dbl(P, P);
     }
+}
+
+// G's wide table: thread (w, i) forms ((i + 1) * 65536^w mod q) * G with the
+// 8-bit table (exact, G has order q) and stores it in affine form
+__global__ __launch_bounds__(256) void k_wide_build(const uint32_t* tg, uint32_t* wide) {
+    const uint32_t g = blockIdx.x * 256 + threadIdx.x;  // < kWideWindows * kWidePerWindow
+    const uint32_t w = g / kWidePerWindow, i = g % kWidePerWindow;
+    uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0}, kr[8];
+    // (i + 1) * 2^(16 w): i + 1 <= 2^15 occupies bits 16w .. 16w + 15
+    const uint32_t v = i + 1, sh = 16 * w;
+    k[sh >> 5] = v << (sh & 31);
+    if ((sh & 31) && (sh >> 5) + 1 < 8) k[(sh >> 5) + 1] = v >> (32 - (sh & 31));
+    sc_reduce256(kr, k);
+    ge P;
+    lane_scalar(P, tg, kr);
+    uint32_t o[kCombEntryWords];
+    comb_entry_of(o, P);
+    uint4* q = reinterpret_cast<uint4*>(wide + (uint64_t)g * kCombEntryWords);
+#pragma unroll
+    for (int t = 0; t < kCombEntryWords / 4; t++) q[t] = make_uint4(o[4 * t], o[4 * t + 1], o[4 * t + 2], o[4 * t + 3]);
+}
+
+const uint32_t* ctx_gtable_wide(poslo_ctx* c) {
+    std::lock_guard<std::mutex> lk(c->wide_mu);
+    if (c->d_gtable_wide) return c->d_gtable_wide;
+    uint32_t* d = nullptr;
+    if (hipMalloc((void**)&d, kWideWords * 4) != hipSuccess) return nullptr;
+    const uint32_t blocks = (uint32_t)(kWideWindows * kWidePerWindow / 256);
+    hipLaunchKernelGGL(k_wide_build, dim3(blocks), dim3(256), 0, 0, (const uint32_t*)c->d_gtable, d);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+        hipFree(d);
+        return nullptr;
+    }
+    c->d_gtable_wide = d;
+    return d;
 }
 
 int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {

@@ -436,6 +436,11 @@ extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, posl
     int st = poslo_ctx_create(device, &ctx);
     if (st) return st;
     ctx->key_cap = SIZE_MAX / 4;  // registered keys are never evicted
+    // the per-entry checks' generator table, built now rather than by the worker
+    if (cfg->distill && !ctx_gtable_wide(ctx)) {
+        poslo_ctx_destroy(ctx);
+        return POSLO_E_NOMEM;
+    }
     poslo_server* S = new poslo_server();
     S->device = device;
     S->cfg = *cfg;

@@ -269,6 +269,7 @@ extern "C" void poslo_ctx_destroy(poslo_ctx* c) {
     if (c->d_result) hipFree(c->d_result);
     if (c->h_result) hipHostFree(c->h_result);
     if (c->d_gtable) hipFree(c->d_gtable);
+    if (c->d_gtable_wide) hipFree(c->d_gtable_wide);
     batch_release(c);
     c->key_index.clear();
     c->keys.clear();

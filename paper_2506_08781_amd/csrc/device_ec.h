@@ -173,6 +173,21 @@ __device__ __forceinline__ void lane_double_scalar_wide(ge& P, const uint32_t* t
     }
 }
 
+// e*Y + s*G by one lane with both wide tables: 16 + 16 lookups and mixed
+// additions; e, s < 2^253
+__device__ __forceinline__ void lane_double_scalar_wide2(ge& P, const uint32_t* ty_wide, const uint32_t* tg_wide,
+                                                         const uint32_t e[8], const uint32_t s[8]) {
+    ge_identity(P);
+    uint32_t ce = 0, cs = 0;
+    for (int w = 0; w < kWideWindows; w++) {
+        gn q;
+        comb_lookup<kWidePerWindow>(q, ty_wide, w, wide_digit(e, w, ce));
+        ge_madd(P, P, q);
+        comb_lookup<kWidePerWindow>(q, tg_wide, w, wide_digit(s, w, cs));
+        ge_madd(P, P, q);
+    }
+}
+
 // k*P by one lane: 32 lookups and mixed additions; k < 2^253
 __device__ __forceinline__ void lane_scalar(ge& P, const uint32_t* t, const uint32_t k[8]) {
     ge_identity(P);

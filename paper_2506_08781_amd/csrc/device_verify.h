@@ -189,6 +189,8 @@ __device__ __forceinline__ bool encodes_to_zinv(const ge& P, const fe& zi, const
     return diff == 0;
 }
 
+// WY: ty is Y's wide table (else its 8-bit table)
+template <bool WY>
 __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, bool go, const uint32_t* ty,
                                           const uint32_t* tg_wide, ge& P) {
     uint32_t ek[8], s[8];
@@ -199,7 +201,10 @@ __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, 
     const bool c = go && sc_is_canonical(s);
     if (!c)
         for (int w = 0; w < 8; w++) s[w] = ek[w] = 0;  // the identity: Z stays nonzero
-    lane_double_scalar_wide(P, ty, tg_wide, ek, s);
+    if constexpr (WY)
+        lane_double_scalar_wide2(P, ty, tg_wide, ek, s);
+    else
+        lane_double_scalar_wide(P, ty, tg_wide, ek, s);
     return c;
 }
 
@@ -214,11 +219,12 @@ __device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge&
 // trick: 1/Z0 = Z1 / (Z0 Z1), 1/Z1 = Z0 / (Z0 Z1)), which saves about 260
 // multiplications per pair.  go[k] = false skips entry k (reported false);
 // its pointers must still be readable.
+template <bool WY = false>
 __device__ __forceinline__ void verify_sig2(const uint8_t* const sg[2], const uint32_t* const e[2], const bool go[2],
                                             const uint32_t* ty, const uint32_t* tg_wide, bool ok[2]) {
     ge P0, P1;
-    const bool c0 = sig_point(sg[0], e[0], go[0], ty, tg_wide, P0);
-    const bool c1 = sig_point(sg[1], e[1], go[1], ty, tg_wide, P1);
+    const bool c0 = sig_point<WY>(sg[0], e[0], go[0], ty, tg_wide, P0);
+    const bool c1 = sig_point<WY>(sg[1], e[1], go[1], ty, tg_wide, P1);
     fe zz, inv, zi;
     fe_mul(zz, P0.Z, P1.Z);
     fe_inv(inv, zz);

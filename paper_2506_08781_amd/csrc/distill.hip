@@ -31,6 +31,7 @@
 namespace poslo {
 
 constexpr int kTile = 256;  // entries per verification tile (one workgroup)
+constexpr uint64_t kWideKeyMinEntries = 1u << 18;  // Distill batches that use Y's wide table
 
 // tiles never straddle an umbrella: umbrella l covers [l*span, min(n, (l+1)*span))
 struct TileGeom {
@@ -110,7 +111,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials.
 // Each thread checks entries i and i + kTile/2 of its tile with one shared
 // inversion.
+// WY: v.ty is Y's wide table.
 constexpr int kVerifyBlock = kTile / 2;
+template <bool WY>
 __global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys,
                                                                const uint8_t* xbad) {
     uint64_t start, end;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, con
         sg[k] = v.sigs + (go[k] ? 80 * pos[k] : 0);
         e[k] = ekeys + (go[k] ? pos[k] * 8 : 0);
     }
-    verify_sig2(sg, e, go, v.ty, v.tg, ok);
+    verify_sig2<WY>(sg, e, go, v.ty, v.tg, ok);
 #pragma unroll
     for (int k = 0; k < 2; k++) {
         if (!act[k]) continue;
@@ -461,6 +464,8 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         prof_end(c, POSLO_KT_SEED, s);
         const uint32_t* gw = ctx_gtable_wide(c);
         if (!gw) return fail(POSLO_E_NOMEM);
+        // large batches also use Y's wide table (built once per key, 1.5 ms)
+        const uint32_t* yw = n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : nullptr;
         VerifyArgs v;
         v.a = a;
         v.g = TileGeom{n, span, tpu};
@@ -468,7 +473,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         v.sigs = sigs;
         v.list = nullptr;
         v.list_n = 0;
-        v.ty = key->d_table;
+        v.ty = yw ? yw : key->d_table;
         v.tg = gw;
         v.flags = (uint8_t*)flags;
         v.tile_part = (uint32_t*)tiles;
@@ -481,8 +486,12 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         else
             hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a, sigs,
                                (uint32_t*)ek, (uint8_t*)xb);
-        hipLaunchKernelGGL(k_verify_tiles, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v, (const uint32_t*)ek,
-                           (const uint8_t*)xb);
+        if (yw)
+            hipLaunchKernelGGL(k_verify_tiles<true>, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v,
+                               (const uint32_t*)ek, (const uint8_t*)xb);
+        else
+            hipLaunchKernelGGL(k_verify_tiles<false>, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v,
+                               (const uint32_t*)ek, (const uint8_t*)xb);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);
         FoldArgs f;

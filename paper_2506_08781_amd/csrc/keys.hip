@@ -46,19 +46,21 @@ __global__ __launch_bounds__(kCombPerWindow) void k_comb_build(const uint8_t* pk
     }
 }
 
-// G's wide table: thread (w, i) forms ((i + 1) * 65536^w mod q) * G with the
-// 8-bit table (exact, G has order q) and stores it in affine form
-__global__ __launch_bounds__(256) void k_wide_build(const uint32_t* tg, uint32_t* wide) {
+// Wide table of a point P from its 8-bit table t8: thread (w, i) forms
+// (i + 1) * 65536^w * P by double-and-add over the 16 bits of i + 1 from
+// B_w = 65536^w * P, which is t8's entry for window 2w, digit 1 (exact for
+// any point), and stores it in affine form.
+__global__ __launch_bounds__(256) void k_wide_build(const uint32_t* t8, uint32_t* wide) {
     const uint32_t g = blockIdx.x * 256 + threadIdx.x;  // < kWideWindows * kWidePerWindow
-    const uint32_t w = g / kWidePerWindow, i = g % kWidePerWindow;
-    uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0}, kr[8];
-    // (i + 1) * 2^(16 w): i + 1 <= 2^15 occupies bits 16w .. 16w + 15
-    const uint32_t v = i + 1, sh = 16 * w;
-    k[sh >> 5] = v << (sh & 31);
-    if ((sh & 31) && (sh >> 5) + 1 < 8) k[(sh >> 5) + 1] = v >> (32 - (sh & 31));
-    sc_reduce256(kr, k);
+    const uint32_t w = g / kWidePerWindow, m = g % kWidePerWindow + 1;
+    gn B;
+    comb_lookup(B, t8, 2 * (int)w, 1);
     ge P;
-    lane_scalar(P, tg, kr);
+    ge_identity(P);
+    for (int bit = 15; bit >= 0; bit--) {
+        ge_dbl(P, P);
+        if ((m >> bit) & 1u) ge_madd(P, P, B);
+    }
     uint32_t o[kCombEntryWords];
     comb_entry_of(o, P);
     uint4* q = reinterpret_cast<uint4*>(wide + (uint64_t)g * kCombEntryWords);
@@ -66,18 +68,43 @@ __global__ __launch_bounds__(256) void k_wide_build(const uint32_t* tg, uint32_t
     for (int t = 0; t < kCombEntryWords / 4; t++) q[t] = make_uint4(o[4 * t], o[4 * t + 1], o[4 * t + 2], o[4 * t + 3]);
 }
 
-const uint32_t* ctx_gtable_wide(poslo_ctx* c) {
-    std::lock_guard<std::mutex> lk(c->wide_mu);
-    if (c->d_gtable_wide) return c->d_gtable_wide;
+static uint32_t* build_wide(const uint32_t* t8) {
     uint32_t* d = nullptr;
     if (hipMalloc((void**)&d, kWideWords * 4) != hipSuccess) return nullptr;
     const uint32_t blocks = (uint32_t)(kWideWindows * kWidePerWindow / 256);
-    hipLaunchKernelGGL(k_wide_build, dim3(blocks), dim3(256), 0, 0, (const uint32_t*)c->d_gtable, d);
+    hipLaunchKernelGGL(k_wide_build, dim3(blocks), dim3(256), 0, 0, t8, d);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
         hipFree(d);
         return nullptr;
     }
-    c->d_gtable_wide = d;
+    return d;
+}
+
+const uint32_t* ctx_gtable_wide(poslo_ctx* c) {
+    std::lock_guard<std::mutex> lk(c->wide_mu);
+    if (!c->d_gtable_wide) c->d_gtable_wide = build_wide(c->d_gtable);
+    return c->d_gtable_wide;
+}
+
+const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]) {
+    auto it = c->key_index.find(std::string((const char*)pk, 32));
+    if (it == c->key_index.end()) return nullptr;
+    KeyEntry& ke = *it->second;
+    if (ke.wide) return (const uint32_t*)ke.wide.get();
+    // keep at most kMaxWideKeys wide key tables: drop the least recently used
+    size_t have = 0;
+    for (const KeyEntry& k : c->keys) have += k.wide != nullptr;
+    if (have >= kMaxWideKeys) {
+        hipDeviceSynchronize();  // queued work may still read them
+        for (auto r = c->keys.rbegin(); r != c->keys.rend() && have >= kMaxWideKeys; ++r)
+            if (r->wide && &*r != &ke) {
+                r->wide.reset();
+                have--;
+            }
+    }
+    uint32_t* d = build_wide(ke.d_table);
+    if (!d) return nullptr;
+    ke.wide = std::shared_ptr<void>(d, [](void* q) { hipFree(q); });
     return d;
 }
 

@@ -210,3 +210,42 @@ def test_distill_finds_errors_that_cancel_in_sums(P, gpu, inst):
     off = torch.arange(0, 201 * 40, 40, dtype=torch.int64, device="cuda")
     acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=2)
     assert acc == [True] and inv == [(0, t) for t in expect]
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_table_digit_extremes(P, gpu, inst):
+    """Entries re-signed with scalars at the edges of the fixed-base tables'
+    signed digits (0, digits of 128 / 129 / 32768 / 32769, q - 1, 2^252,
+    ...): R_t = e_t*Y + s_t*G is computed by the oracle, so these entries
+    are valid; s_t = q and s_t = 2^256 - 1 are not.  Distill and the
+    multi-signer checks must agree with the oracle entry by entry."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = signed(inst, 64, 40, 4, 4, 0x11, 8)
+    sigs = list(sigs)
+    q = O.Q
+    rep8 = sum(0x80 << (8 * k) for k in range(31))
+    rep16 = sum(0x8000 << (16 * k) for k in range(15))
+    special = [0, 1, 2, 127, 128, 129, 255, 256, 32767, 32768, 32769, 65535, 65536, q - 1, q - 2, q - 32768,
+               q - 128, 2 ** 252, 2 ** 252 - 1, rep8, rep8 + 1, rep16, rep16 + 0x10001, (rep8 ^ (rep8 >> 1)) % q]
+    assert all(0 <= s < q for s in special)
+    Y = O.decode(pk)
+    for t, s in enumerate(special):
+        x = sigs[t][64:80]
+        e = O.digest_int(prm.inst, msgs[t], x) % q
+        R = O.point_add(O.scalar_mult(e, Y), O.scalar_mult(s, O.G))
+        sigs[t] = O.to32(s) + O.encode(R) + x
+    bad = {40: q, 41: 2 ** 256 - 1}
+    for t, s in bad.items():
+        sigs[t] = s.to_bytes(32, "little") + sigs[t][32:]
+    want = O.distill(prm, pk, msgs, sigs, 0, ds, 1)
+    assert [t for t, _ in want.invalid] == sorted(bad)
+    params = P.make_params(inst, 4, 4)
+    dm, dsig = to_dev(torch, msgs, sigs)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, 1)
+    assert ccd.invalid() == sorted(bad)
+    assert ccd.valid_tag() == want.valid_tag
+    bj = P.BatchJobs([dict(pk=pk, ds=ds, tag=tag, t0=0, n=64, entry_base=0)])
+    off = torch.arange(0, 65 * 40, 40, dtype=torch.int64, device="cuda")
+    acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=2)
+    assert acc == [True] and inv == [(0, t) for t in sorted(bad)]

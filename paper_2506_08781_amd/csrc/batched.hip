@@ -163,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             // counting sort of the item's slots by block count
             for (uint32_t s = threadIdx.x; s < it.count; s += BLOCK) {
                 uint64_t p = it.first + s;
-                uint64_t L = a.offsets ? a.offsets[p + 1] - a.offsets[p] : a.msg_len;
+                uint64_t L = a.offsets ? gload(a.offsets + p + 1) - gload(a.offsets + p) : a.msg_len;
                 uint64_t nb = INST == INST_AES ? (L + 31) / 16 : (L + 25 + 63) / 64;
                 uint32_t key = nb < 63 ? (uint32_t)nb : 63u;
                 keys[s] = (uint8_t)key;
@@ -187,7 +187,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             __syncthreads();
         }
         uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // an item holds at most CHUNK entries: with CHUNK <= BLOCK a lane has
+        // at most one, so nothing accumulates across the digest
         for (uint32_t s = threadIdx.x; s < it.count; s += BLOCK) {
+            if (CHUNK <= BLOCK && s >= BLOCK) break;
             uint64_t p = it.first + (SORT ? order[s] : s);
             EntryView ev = entry_view(a, p);
             uint32_t x[4], dig[8];
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 const uint8_t* sg = J.sigs + p * 80 + 64;
                 uint32_t d = 0;
 #pragma unroll
-                for (int w = 0; w < 4; w++) d |= x[w] ^ load_le32(sg + 4 * w);
+                for (int w = 0; w < 4; w++) d |= x[w] ^ gload_le32(sg + 4 * w);
                 uint32_t e[8];
                 sc_reduce256(e, dig);
                 uint32_t* eo = A.e_out + (J.ebase + p) * 8;

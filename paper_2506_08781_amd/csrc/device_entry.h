@@ -27,10 +27,34 @@ struct EntryView {
     uint64_t L;
 };
 
+// Loads through the global address space.  Pointers that kernels read out
+// of job tables in memory are generic to the compiler, and generic (flat)
+// loads also count against the LDS wait counter, which would tie every
+// message load to the T-table lookups in flight.  Every pointer given to
+// these is device memory.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<uintptr_t>(p));
+}
+
+// 16 bytes at a 16-byte-aligned address (a native vector type: HIP's uint4
+// cannot be copied out of the global address space directly)
+__device__ __forceinline__ uint4 gload(const uint4* p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(reinterpret_cast<uintptr_t>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// little-endian 32-bit word at any byte address of device memory
+__device__ __forceinline__ uint32_t gload_le32(const uint8_t* p) {
+    return (uint32_t)gload(p) | ((uint32_t)gload(p + 1) << 8) | ((uint32_t)gload(p + 2) << 16) |
+           ((uint32_t)gload(p + 3) << 24);
+}
+
 __device__ __forceinline__ EntryView entry_view(const BatchArgs& a, uint64_t pos) {
     EntryView v;
     if (a.offsets) {
-        uint64_t o0 = a.offsets[pos], o1 = a.offsets[pos + 1];
+        uint64_t o0 = gload(a.offsets + pos), o1 = gload(a.offsets + pos + 1);
         v.m = a.data + o0;
         v.L = o1 - o0;
     } else {
@@ -48,7 +72,7 @@ __device__ __forceinline__ bool skipped(const BatchArgs& a, uint64_t pos) {
 
 // byte pos of the stream m || x || zero padding (x as four little-endian words)
 __device__ __forceinline__ uint32_t stream_byte_aes(const EntryView& v, const uint32_t x[4], uint64_t pos) {
-    if (pos < v.L) return v.m[pos];
+    if (pos < v.L) return gload(v.m + pos);
     uint64_t o = pos - v.L;
     if (o < 16) return (x[o >> 2] >> (8 * (o & 3))) & 0xffu;
     return 0;
@@ -79,7 +103,7 @@ __device__ __forceinline__ void digest_mdc2(const T& tb, const EntryView& v, con
         uint32_t m[4];
         if (FAST) {
             if (16 * b < v.L) {
-                uint4 q = reinterpret_cast<const uint4*>(v.m)[b];
+                uint4 q = gload(reinterpret_cast<const uint4*>(v.m) + b);
                 m[0] = q.x, m[1] = q.y, m[2] = q.z, m[3] = q.w;
             } else {
                 m[0] = x[0], m[1] = x[1], m[2] = x[2], m[3] = x[3];
@@ -140,7 +164,7 @@ __device__ __forceinline__ uint32_t sha_stream_word(const EntryView& v, const ui
                                                     uint64_t total) {
     uint64_t L = v.L;
     if (FAST) {
-        if (o < L) return bswap32(*reinterpret_cast<const uint32_t*>(v.m + o));
+        if (o < L) return bswap32(gload(reinterpret_cast<const uint32_t*>(v.m + o)));
         if (o < L + 16) return xw[(o - L) >> 2];
         if (o == L + 16) return 0x80000000u;
         if (o == total - 8) return (uint32_t)((L + 16) >> 29);
@@ -152,7 +176,7 @@ __device__ __forceinline__ uint32_t sha_stream_word(const EntryView& v, const ui
         uint64_t p = o + k;
         uint32_t byte;
         if (p < L)
-            byte = v.m[p];
+            byte = gload(v.m + p);
         else if (p < L + 16)
             byte = (xw[(p - L) >> 2] >> (8 * (3 - ((p - L) & 3)))) & 0xffu;
         else if (p == L + 16)
@@ -182,7 +206,7 @@ __device__ __forceinline__ void digest_sha(const EntryView& v, const uint32_t xw
         for (; off + 128 <= v.L; off += 128) {
             uint4 q[8];
 #pragma unroll
-            for (int k = 0; k < 8; k++) q[k] = p[off / 16 + k];
+            for (int k = 0; k < 8; k++) q[k] = gload(p + off / 16 + k);
 #pragma unroll
             for (int half = 0; half < 2; half++) {
                 uint32_t W[16];

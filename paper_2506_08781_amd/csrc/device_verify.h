@@ -20,16 +20,16 @@ __device__ __forceinline__ void load_msg_words(const uint8_t* m, uint64_t o, con
     const uint32_t* base = reinterpret_cast<const uint32_t*>(a - sh);
     if (sh == 0) {
 #pragma unroll
-        for (int k = 0; k < NW; k++) w[k] = base[k];
+        for (int k = 0; k < NW; k++) w[k] = gload(base + k);
     } else if (reinterpret_cast<const uint8_t*>(base + NW + 1) <= end) {
         uint32_t d[NW + 1];
 #pragma unroll
-        for (int k = 0; k <= NW; k++) d[k] = base[k];
+        for (int k = 0; k <= NW; k++) d[k] = gload(base + k);
 #pragma unroll
         for (int k = 0; k < NW; k++) w[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
     } else {
 #pragma unroll
-        for (int k = 0; k < NW; k++) w[k] = load_le32(A + 4 * k);
+        for (int k = 0; k < NW; k++) w[k] = gload_le32(A + 4 * k);
     }
 }
 
@@ -166,12 +166,12 @@ __device__ __forceinline__ void digest_sha_any(const EntryView& v, const uint8_t
 // s_t, R_t, x_t).  s is returned.  ty: Y's table; tg_wide: G's wide table.
 __device__ __forceinline__ bool verify_sig(const uint8_t* sg, const uint32_t e[8], const uint32_t* ty,
                                            const uint32_t* tg_wide, uint32_t s[8]) {
-    for (int k = 0; k < 8; k++) s[k] = load_le32(sg + 4 * k);
+    for (int k = 0; k < 8; k++) s[k] = gload_le32(sg + 4 * k);
     if (!sc_is_canonical(s)) return false;
     ge P;
     lane_double_scalar_wide(P, ty, tg_wide, e, s);
     uint32_t r[8];
-    for (int k = 0; k < 8; k++) r[k] = load_le32(sg + 32 + 4 * k);
+    for (int k = 0; k < 8; k++) r[k] = gload_le32(sg + 32 + 4 * k);
     return ge_encodes_to(P, r);
 }
 
@@ -195,7 +195,7 @@ __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, 
                                           const uint32_t* tg_wide, ge& P) {
     uint32_t ek[8], s[8];
     for (int w = 0; w < 8; w++) {
-        s[w] = go ? load_le32(sg + 4 * w) : 0u;
+        s[w] = go ? gload_le32(sg + 4 * w) : 0u;
         ek[w] = go ? e[w] : 0u;
     }
     const bool c = go && sc_is_canonical(s);
@@ -210,7 +210,7 @@ __device__ __forceinline__ bool sig_point(const uint8_t* sg, const uint32_t* e, 
 
 __device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge& P, const fe& zi) {
     uint32_t r[8];
-    for (int w = 0; w < 8; w++) r[w] = c ? load_le32(sg + 32 + 4 * w) : 0u;
+    for (int w = 0; w < 8; w++) r[w] = c ? gload_le32(sg + 32 + 4 * w) : 0u;
     return c && encodes_to_zinv(P, zi, r);
 }
 
@@ -243,7 +243,7 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
                                            uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg_wide,
                                            uint32_t e[8], uint32_t s[8]) {
     uint32_t x[4], xs[4];
-    for (int k = 0; k < 4; k++) xs[k] = load_le32(sg + 64 + 4 * k);
+    for (int k = 0; k < 4; k++) xs[k] = gload_le32(sg + 64 + 4 * k);
     EntryView ev = entry_view(a, pos);
     uint32_t dig[8];
     if (inst == INST_AES) {

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         const uint8_t* sx = sigs + p * 80 + 64;
         uint32_t d = 0;
 #pragma unroll
-        for (int w = 0; w < 4; w++) d |= x[w] ^ load_le32(sx + 4 * w);
+        for (int w = 0; w < 4; w++) d |= x[w] ^ gload_le32(sx + 4 * w);
         uint32_t e[8];
         sc_reduce256(e, dig);
 #pragma unroll
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, con
             uint32_t w8[8];
             for (int w = 0; w < 8; w++) w8[w] = e[k][w];
             acc288_add256(ae, w8);
-            for (int w = 0; w < 8; w++) w8[w] = load_le32(sg[k] + 4 * w);
+            for (int w = 0; w < 8; w++) w8[w] = gload_le32(sg[k] + 4 * w);
             acc288_add256(as, w8);
         }
     }

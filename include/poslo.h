@@ -370,6 +370,9 @@ typedef struct poslo_server_cfg {
     int distill;          /* 0: accept bit only; 1: invalid entries of rejected requests;
                              2: invalid entries of every request */
     int variant;          /* hot-kernel variant (-1: the default of the instantiation) */
+    uint64_t max_group_entries; /* entries per launch group (0: 2^21); a group always takes at
+                                   least one request.  Smaller groups cut the time a request
+                                   waits for its group's slowest member; larger ones batch more */
 } poslo_server_cfg;
 
 typedef struct poslo_request {

@@ -64,7 +64,8 @@ class poslo_tuning(ctypes.Structure):
 
 class poslo_server_cfg(ctypes.Structure):
     _fields_ = [("params", poslo_params), ("n_streams", ctypes.c_uint32), ("max_group", ctypes.c_uint32),
-                ("mem_bytes", ctypes.c_uint64), ("distill", ctypes.c_int), ("variant", ctypes.c_int)]
+                ("mem_bytes", ctypes.c_uint64), ("distill", ctypes.c_int), ("variant", ctypes.c_int),
+                ("max_group_entries", ctypes.c_uint64)]
 
 
 class poslo_request(ctypes.Structure):
@@ -653,8 +654,8 @@ class Server:
     """Owns a poslo_server*."""
 
     def __init__(self, device: int, params: poslo_params, n_streams: int = 4, max_group: int = 256,
-                 mem_bytes: int = 0, distill: int = 1, variant: int = -1):
-        cfg = poslo_server_cfg(params, n_streams, max_group, mem_bytes, distill, variant)
+                 mem_bytes: int = 0, distill: int = 1, variant: int = -1, max_group_entries: int = 0):
+        cfg = poslo_server_cfg(params, n_streams, max_group, mem_bytes, distill, variant, max_group_entries)
         h = ctypes.c_void_p()
         _check(lib().poslo_server_create(device, ctypes.byref(cfg), ctypes.byref(h)), "poslo_server_create")
         self.handle = h

@@ -391,7 +391,15 @@ void poslo_server::run() {
                     break;
                 }
             if (free_slot && !admitted.empty()) {
-                size_t take = std::min<size_t>(admitted.size(), cfg.max_group);
+                // up to max_group requests and max_group_entries entries (at least one)
+                size_t take = 0;
+                uint64_t ent = 0;
+                while (take < admitted.size() && take < cfg.max_group) {
+                    const uint64_t n = admitted[take]->r.n;
+                    if (take > 0 && ent + n > cfg.max_group_entries) break;
+                    ent += n;
+                    take++;
+                }
                 to_launch.assign(admitted.begin(), admitted.begin() + take);
                 admitted.erase(admitted.begin(), admitted.begin() + take);
                 launching = 1;
@@ -446,6 +454,7 @@ extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, posl
     S->cfg = *cfg;
     if (!S->cfg.n_streams) S->cfg.n_streams = 4;
     if (!S->cfg.max_group) S->cfg.max_group = 256;
+    if (!S->cfg.max_group_entries) S->cfg.max_group_entries = 1ull << 21;
     if (!S->cfg.mem_bytes) S->cfg.mem_bytes = 8ull << 30;
     if (S->cfg.variant < 0) S->cfg.variant = -1;
     S->ctx = ctx;

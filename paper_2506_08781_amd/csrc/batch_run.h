@@ -58,6 +58,7 @@ struct JobSpec {
 struct HotVariant {
     const char* name;
     int inst, nt, block, chunk, sort, waves_per_simd;
+    int pair;  // chunk = 2 * block: a lane takes the k-th shortest and the k-th longest entry
 };
 int batch_variant_count();
 const HotVariant& batch_variant(int v);

@@ -134,8 +134,12 @@ struct BHot {
 
 // INST 1: MDC-2-AES over the byte-addressed tables (NT = 1 or 2);
 // INST 0: SHA-256 (no tables).  CHUNK entries per item at most.
-template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT>
+// PAIR (SORT, CHUNK == 2 * BLOCK): thread g takes the g-th shortest and the
+// g-th longest entry of the sorted item, so every lane and wave gets about
+// the same total length and waves do not idle at the item's closing barrier.
+template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT, bool PAIR = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_batch_hot(BHot A) {
+    static_assert(!PAIR || (SORT && CHUNK == 2 * BLOCK), "pairing needs sorted items of two entries per thread");
     constexpr int TW = INST == INST_AES ? NT * 256 * 64 : 0;  // table words
     constexpr int SW = 64 + 16 + CHUNK / 2 + CHUNK / 4;       // counts, misc, order (u16), keys (u8)
     __shared__ uint32_t lds[TW + SW + (BLOCK / 64) * 9];
@@ -191,7 +195,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         // at most one, so nothing accumulates across the digest
         for (uint32_t s = threadIdx.x; s < it.count; s += BLOCK) {
             if (CHUNK <= BLOCK && s >= BLOCK) break;
-            uint64_t p = it.first + (SORT ? order[s] : s);
+            // slots [BLOCK, count) map to count - 1 - (s - BLOCK): the longest first
+            const uint32_t slot = (PAIR && s >= BLOCK) ? it.count - 1 - (s - BLOCK) : s;
+            uint64_t p = it.first + (SORT ? order[slot] : slot);
             EntryView ev = entry_view(a, p);
             uint32_t x[4], dig[8];
             if constexpr (INST == INST_AES) {
@@ -325,6 +331,10 @@ static const HotVariant kHot[] = {
     {"sha_b256_c1024_sorted_w4", 0, 1, 256, 1024, 1, 4},      {"sha_b256_c256_sorted_w3", 0, 1, 256, 256, 1, 3},
     {"sha_b256_c1024_w3", 0, 1, 256, 1024, 0, 3},             {"sha_b512_c2048_sorted_w3", 0, 1, 512, 2048, 1, 3},
     {"aes_perm1_b1024_c1024_sorted_w8", 1, 1, 1024, 1024, 1, 8},
+    {"aes_perm1_b1024_c2048_paired_w8", 1, 1, 1024, 2048, 1, 8, 1},
+    {"aes_perm2_b1024_c2048_paired", 1, 2, 1024, 2048, 1, 4, 1},
+    {"sha_b256_c512_paired_w3", 0, 1, 256, 512, 1, 3, 1},
+    {"sha_b512_c1024_paired_w3", 0, 1, 512, 1024, 1, 3, 1},
 };
 constexpr int kNumHot = sizeof kHot / sizeof kHot[0];
 
@@ -344,6 +354,12 @@ static int launch_hot(int v, uint32_t grid, const BHot& A, hipStream_t s) {
     else                                                                                              \
         hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, S, W, false>), dim3(grid), dim3(B), 0, s, A); \
     break
+#define HOTP(I, NT, B, C, W)                                                                                 \
+    if (A.e_out)                                                                                             \
+        hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, true, W, true, true>), dim3(grid), dim3(B), 0, s, A);  \
+    else                                                                                                     \
+        hipLaunchKernelGGL((k_batch_hot<I, NT, B, C, true, W, false, true>), dim3(grid), dim3(B), 0, s, A); \
+    break
     switch (v) {
         case 0: HOT(1, 2, 1024, 1024, true, 4);
         case 1: HOT(1, 2, 1024, 2048, true, 4);
@@ -356,9 +372,14 @@ static int launch_hot(int v, uint32_t grid, const BHot& A, hipStream_t s) {
         case 8: HOT(0, 1, 256, 1024, false, 3);
         case 9: HOT(0, 1, 512, 2048, true, 3);
         case 10: HOT(1, 1, 1024, 1024, true, 8);
+        case 11: HOTP(1, 1, 1024, 2048, 8);
+        case 12: HOTP(1, 2, 1024, 2048, 4);
+        case 13: HOTP(0, 1, 256, 512, 3);
+        case 14: HOTP(0, 1, 512, 1024, 3);
         default: return POSLO_E_INVAL;
     }
 #undef HOT
+#undef HOTP
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 

@@ -277,36 +277,37 @@ struct BVerify {
 };
 
 // PRE: e_t and the x checks come from the hashing kernel (launch with
-// emit); each thread then checks entries i and i + 128 of its tile with one
-// shared inversion
+// emit); each thread then checks entries i + 64 k (k < 4) of its tile with
+// one shared inversion
+constexpr int kVerifyNE = 4;
 template <bool PRE>
-__global__ __launch_bounds__(PRE ? 128 : 256) void k_batch_verify(BVerify V) {
-    __shared__ uint32_t lds[PRE ? 1 : 4 * 256];
+__global__ __launch_bounds__(PRE ? 256 / kVerifyNE : 256) void k_batch_verify(BVerify V) {
+    constexpr int VB = 256 / kVerifyNE;
+    __shared__ uint32_t lds[PRE ? verify_batch_lds_words<kVerifyNE, VB>() : 4 * 256];
     if constexpr (!PRE) {
         lds_tables_fill<4, 1>(lds);
         __syncthreads();
     }
-    LdsTables<4, 1> tb{lds};
     const BItem it = V.tiles[blockIdx.x];
     const BJob& J = V.jobs[it.job];
     if constexpr (PRE) {
-        uint64_t p[2];
-        bool act[2], go[2], ok[2];
-        const uint8_t* sg[2];
-        const uint32_t* e[2];
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-            act[k] = threadIdx.x + 128u * k < it.count;
-            p[k] = it.first + threadIdx.x + 128u * k;
-            go[k] = act[k] && !V.xbad[J.ebase + p[k]];
+        auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
+            const uint32_t idx = threadIdx.x + (uint32_t)(VB * k);
+            const uint64_t p = it.first + (idx < it.count ? idx : 0);
+            go = idx < it.count && !gload(V.xbad + J.ebase + p);
             // skipped entries point at the tile's first entry (in bounds)
-            sg[k] = J.sigs + (go[k] ? p[k] : it.first) * 80;
-            e[k] = V.ekeys + (J.ebase + (go[k] ? p[k] : it.first)) * 8;
+            const uint64_t q = go ? p : it.first;
+            sg = J.sigs + q * 80;
+            e = V.ekeys + (J.ebase + q) * 8;
+        };
+        const uint32_t okmask = verify_sig_batch<false, kVerifyNE, VB>(ent, J.ty, V.tg, lds);
+#pragma unroll 1
+        for (int k = 0; k < kVerifyNE; k++) {
+            const uint32_t idx = threadIdx.x + (uint32_t)(VB * k);
+            wave_append(idx < it.count && !((okmask >> k) & 1u), J.vbase + it.first + idx, V.idx, V.count);
         }
-        verify_sig2(sg, e, go, J.ty, V.tg, ok);
-#pragma unroll
-        for (int k = 0; k < 2; k++) wave_append(act[k] && !ok[k], J.vbase + p[k], V.idx, V.count);
     } else {
+        LdsTables<4, 1> tb{lds};
         bool bad = false;
         uint64_t slot = 0;
         if (threadIdx.x < it.count) {
@@ -667,7 +668,7 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.count = cnt;
     prof_begin(prof, POSLO_KT_VERIFY, s);
     if (emitted_)
-        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(128), 0, s, V);
+        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(256 / kVerifyNE), 0, s, V);
     else
         hipLaunchKernelGGL(k_batch_verify<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
     prof_end(prof, POSLO_KT_VERIFY, s);

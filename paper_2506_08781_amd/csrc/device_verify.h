@@ -214,24 +214,91 @@ __device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge&
     return c && encodes_to_zinv(P, zi, r);
 }
 
-// The curve part of two entries' checks (as verify_sig; e[k] points to
-// e_t's eight words in memory) with one shared inversion (Montgomery's
-// trick: 1/Z0 = Z1 / (Z0 Z1), 1/Z1 = Z0 / (Z0 Z1)), which saves about 260
-// multiplications per pair.  go[k] = false skips entry k (reported false);
-// its pointers must still be readable.
-template <bool WY = false>
-__device__ __forceinline__ void verify_sig2(const uint8_t* const sg[2], const uint32_t* const e[2], const bool go[2],
-                                            const uint32_t* ty, const uint32_t* tg_wide, bool ok[2]) {
-    ge P0, P1;
-    const bool c0 = sig_point<WY>(sg[0], e[0], go[0], ty, tg_wide, P0);
-    const bool c1 = sig_point<WY>(sg[1], e[1], go[1], ty, tg_wide, P1);
-    fe zz, inv, zi;
-    fe_mul(zz, P0.Z, P1.Z);
-    fe_inv(inv, zz);
-    fe_mul(zi, inv, P1.Z);
-    ok[0] = sig_encodes(sg[0], c0, P0, zi);
-    fe_mul(zi, inv, P0.Z);
-    ok[1] = sig_encodes(sg[1], c1, P1, zi);
+// The curve part of NE entries' checks per thread with one inversion for all
+// of them (Montgomery's trick).  Entries 0 .. NE-2 wait in the workgroup's
+// LDS as (X, Y, Z), 24 words each at lds[(24 k + w) * BLOCK + thread]; the
+// last stays in registers.  With c_k = Z_0 ... Z_k and inv = 1 / c_{NE-1},
+// entry k takes 1/Z_k = inv * c_{k-1} and then inv *= Z_k, going down.
+// ent(k, sg, e, go) names entry k: signature, e_t in memory, and whether to
+// check it (go = false reports it invalid; its pointers must still be
+// readable).  Bit k of the result is set when entry k is valid.
+template <int NE, int BLOCK>
+constexpr int verify_batch_lds_words() {
+    return (NE - 1) * 24 * BLOCK;
+}
+
+template <bool WY, int NE, int BLOCK, class ENT>
+__device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, const uint32_t* ty, const uint32_t* tg_wide,
+                                                     uint32_t* lds) {
+    static_assert(NE >= 2 && NE <= 32, "entries per thread");
+    uint32_t* my = lds + threadIdx.x;
+    uint32_t okmask = 0;
+    fe c, c_prev;  // running product of the Z coordinates, and the one before the last entry
+    ge P;
+#pragma unroll 1
+    for (int k = 0; k < NE; k++) {
+        const uint8_t* sg;
+        const uint32_t* e;
+        bool go;
+        ent(k, sg, e, go);
+        if (sig_point<WY>(sg, e, go, ty, tg_wide, P)) okmask |= 1u << k;
+        if (k == 0) {
+            c = P.Z;
+        } else {
+            c_prev = c;
+            fe_mul(c, c, P.Z);
+        }
+        if (k < NE - 1) {
+            uint32_t* o = my + 24 * k * BLOCK;
+            for (int w = 0; w < 8; w++) {
+                o[w * BLOCK] = P.X.v[w];
+                o[(8 + w) * BLOCK] = P.Y.v[w];
+                o[(16 + w) * BLOCK] = P.Z.v[w];
+            }
+        }
+    }
+    fe inv, zi;
+    fe_inv(inv, c);  // 1 / (Z_0 ... Z_{NE-1})
+    {
+        // the last entry, from registers
+        fe_mul(zi, inv, c_prev);
+        fe_mul(inv, inv, P.Z);
+        const uint8_t* sg;
+        const uint32_t* e;
+        bool go;
+        ent(NE - 1, sg, e, go);
+        if (!sig_encodes(sg, (okmask >> (NE - 1)) & 1u, P, zi)) okmask &= ~(1u << (NE - 1));
+    }
+#pragma unroll 1
+    for (int k = NE - 2; k >= 0; k--) {
+        const uint32_t* o = my + 24 * k * BLOCK;
+        fe z;
+        for (int w = 0; w < 8; w++) {
+            P.X.v[w] = o[w * BLOCK];
+            P.Y.v[w] = o[(8 + w) * BLOCK];
+            z.v[w] = o[(16 + w) * BLOCK];
+        }
+        if (k > 0) {
+            // c_{k-1} = Z_0 ... Z_{k-1}, again from LDS
+            fe ck;
+            for (int w = 0; w < 8; w++) ck.v[w] = my[16 * BLOCK + w * BLOCK];
+            for (int j = 1; j < k; j++) {
+                fe zj;
+                for (int w = 0; w < 8; w++) zj.v[w] = my[(24 * j + 16 + w) * BLOCK];
+                fe_mul(ck, ck, zj);
+            }
+            fe_mul(zi, inv, ck);
+            fe_mul(inv, inv, z);
+        } else {
+            zi = inv;
+        }
+        const uint8_t* sg;
+        const uint32_t* e;
+        bool go;
+        ent(k, sg, e, go);
+        if (!sig_encodes(sg, (okmask >> k) & 1u, P, zi)) okmask &= ~(1u << k);
+    }
+    return okmask;
 }
 
 // Individual verification of the entry at batch position pos with signature

@@ -109,39 +109,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
 // the curve part of every entry's check, with e_t and the x check from
 // k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials.
-// Each thread checks entries i and i + kTile/2 of its tile with one shared
-// inversion.
-// WY: v.ty is Y's wide table.
-constexpr int kVerifyBlock = kTile / 2;
+// Each thread checks entries i + 64 k (k < 4) of its tile with one shared
+// inversion.  WY: v.ty is Y's wide table.
+constexpr int kVerifyNE = 4;
+constexpr int kVerifyBlock = kTile / kVerifyNE;
 template <bool WY>
 __global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys,
                                                                const uint8_t* xbad) {
+    __shared__ uint32_t pts[verify_batch_lds_words<kVerifyNE, kVerifyBlock>()];
     uint64_t start, end;
     const bool any = tile_range(v.g, blockIdx.x, start, end);
-    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t pos[2];
-    bool act[2], go[2], ok[2];
-    const uint8_t* sg[2];
-    const uint32_t* e[2];
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        pos[k] = start + threadIdx.x + k * kVerifyBlock;
-        act[k] = any && pos[k] < end;
-        go[k] = act[k] && !xbad[pos[k]];
+    auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
+        const uint64_t pos = start + threadIdx.x + (uint64_t)k * kVerifyBlock;
+        go = any && pos < end && !xbad[pos];
         // skipped entries point at entry 0 (read by nothing that matters)
-        sg[k] = v.sigs + (go[k] ? 80 * pos[k] : 0);
-        e[k] = ekeys + (go[k] ? pos[k] * 8 : 0);
-    }
-    verify_sig2<WY>(sg, e, go, v.ty, v.tg, ok);
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        if (!act[k]) continue;
-        v.flags[pos[k]] = ok[k] ? 0 : 1;
-        if (ok[k]) {
+        sg = v.sigs + (go ? 80 * pos : 0);
+        e = ekeys + (go ? pos * 8 : 0);
+    };
+    const uint32_t okmask = verify_sig_batch<WY, kVerifyNE, kVerifyBlock>(ent, v.ty, v.tg, pts);
+    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int k = 0; k < kVerifyNE; k++) {
+        const uint64_t pos = start + threadIdx.x + (uint64_t)k * kVerifyBlock;
+        if (!any || pos >= end) continue;
+        const bool ok = (okmask >> k) & 1u;
+        v.flags[pos] = ok ? 0 : 1;
+        if (ok) {
             uint32_t w8[8];
-            for (int w = 0; w < 8; w++) w8[w] = e[k][w];
+            for (int w = 0; w < 8; w++) w8[w] = gload(ekeys + pos * 8 + w);
             acc288_add256(ae, w8);
-            for (int w = 0; w < 8; w++) w8[w] = gload_le32(sg[k] + 4 * w);
+            for (int w = 0; w < 8; w++) w8[w] = gload_le32(v.sigs + 80 * pos + 4 * w);
             acc288_add256(as, w8);
         }
     }

@@ -70,25 +70,29 @@ __device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const Ve
 // Per entry, ahead of the curve checks: e_t mod q and whether x_t differs
 // from the signature's (AES with the byte-addressed bank-private LDS tables
 // of the AVer hot kernel, 1,024 threads per workgroup)
-template <int INST, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_distill_hash(
+// AES: one 64 KB table per workgroup and x_t derived only for the final
+// blocks, so two 1,024-thread workgroups fit per CU (eight waves per SIMD)
+template <int INST, int BLOCK, int WPE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_distill_hash(
     BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
-    constexpr int TW = INST == INST_AES ? 2 * 256 * 64 : 1;
+    constexpr int TW = INST == INST_AES ? 256 * 64 : 1;
     __shared__ uint32_t lds[TW];
-    if constexpr (INST == INST_AES) perm_tables_fill<2>(lds);
+    if constexpr (INST == INST_AES) perm_tables_fill<1>(lds);
     __syncthreads();
-    const PermTables<2> tb = perm_tables<2>(lds);
+    const PermTables<1> tb = perm_tables<1>(lds);
     for (uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; p < a.n; p += (uint64_t)gridDim.x * BLOCK) {
         EntryView ev = entry_view(a, p);
         uint32_t x[4], dig[8];
         if constexpr (INST == INST_AES) {
-            uint64_t t = a.t0 + p;
-            uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
+            const uint64_t t = a.t0 + p;
+            const uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
             const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
-            x[0] = jj, x[1] = 0, x[2] = 0, x[3] = 0;
-            penc_rk(tb, rk, x);
-            x[0] ^= jj;
-            digest_mdc2_any(tb, ev, a.end, x, dig, Mdc2BlockPerm{});
+            auto xf = [&](uint32_t y[4]) {
+                y[0] = jj, y[1] = 0, y[2] = 0, y[3] = 0;
+                penc_rk(tb, rk, y);
+                y[0] ^= jj;
+            };
+            digest_mdc2_any_late(tb, ev, a.end, xf, x, dig, Mdc2BlockPerm{});
         } else {
             one_time_seed_sha(a, p, x);
             digest_sha_any(ev, a.end, x, dig);
@@ -199,15 +203,23 @@ struct FoldArgs {
     uint32_t* umb_es;     // mode 0: per umbrella e mod q [8], s mod q [8]
     uint8_t* umb_tags;    // mode 0: 64 bytes per umbrella
     uint32_t* umb_bits;   // mode 1: accept per umbrella
+    uint32_t n_umb;       // mode 0 with valid_tag: block n_umb computes CCD^v
+    uint8_t* valid_tag;   // mode 0: CCD^v (64 bytes), or nullptr
 };
 
+// Block n_umb (mode 0, valid_tag set) folds every tile instead: CCD^v, the
+// aggregate of all valid entries, computed beside the umbrellas rather than
+// after them (each block's curve work is one wave's latency).
 __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
     __shared__ uint32_t tot_e[9], tot_s[9];
     __shared__ uint32_t sh[16];
     const uint32_t l = blockIdx.x;
+    const bool valid_block = f.valid_tag && l == f.n_umb;
     uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t k = threadIdx.x; k < f.tiles_per_umb; k += kTile) {
-        const uint32_t* tp = f.tile_part + ((uint64_t)l * f.tiles_per_umb + k) * 18;
+    const uint64_t first = valid_block ? 0 : (uint64_t)l * f.tiles_per_umb;
+    const uint64_t count = valid_block ? (uint64_t)f.n_umb * f.tiles_per_umb : f.tiles_per_umb;
+    for (uint64_t k = threadIdx.x; k < count; k += kTile) {
+        const uint32_t* tp = f.tile_part + (first + k) * 18;
         acc288_add(ae, tp);
         acc288_add(as, tp + 9);
     }
@@ -238,7 +250,10 @@ __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
         ge P;
         wave_double_scalar(P, f.ty, f.tg, e, s);
         if (threadIdx.x == 0) {
-            if (f.mode == 0) {
+            if (valid_block) {
+                for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
+                ge_encode(f.valid_tag + 32, P);
+            } else if (f.mode == 0) {
                 uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
                 for (int k = 0; k < 8; k++) {
                     store_le32(tag + 4 * k, s[k]);
@@ -478,11 +493,11 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         void *ek, *xb;
         if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
         if (prm->inst == POSLO_INST_AES)
-            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024>), dim3(c->num_cu), dim3(1024), 0, s, v.a, sigs,
+            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a, sigs,
                                (uint32_t*)ek, (uint8_t*)xb);
         else
-            hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a, sigs,
-                               (uint32_t*)ek, (uint8_t*)xb);
+            hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256, 4>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
+                               sigs, (uint32_t*)ek, (uint8_t*)xb);
         if (yw)
             hipLaunchKernelGGL(k_verify_tiles<true>, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v,
                                (const uint32_t*)ek, (const uint8_t*)xb);
@@ -501,8 +516,10 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         f.umb_es = (uint32_t*)umb_es;
         f.umb_tags = (uint8_t*)umb_tags;
         f.umb_bits = nullptr;
+        f.n_umb = (uint32_t)n_umb;
+        f.valid_tag = d_valid_tag;
         prof_begin(c, POSLO_KT_COMPACT, s);
-        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
+        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb + 1), dim3(kTile), 0, s, f);
         const uint32_t nblk = (uint32_t)((n + kCmpBlock - 1) / kCmpBlock);
         uint32_t* blk = (uint32_t*)((uint8_t*)misc + 256);  // per-block counts after the tag and count
         hipLaunchKernelGGL(k_flag_count, dim3(nblk), dim3(kCmpThreads), 0, s, (const uint8_t*)flags, n, blk);
@@ -511,9 +528,9 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     } else {
         prof_begin(c, POSLO_KT_COMPACT, s);
+        hipLaunchKernelGGL(k_valid_fold, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es, (uint32_t)n_umb,
+                           key->d_table, c->d_gtable, d_valid_tag);
     }
-    hipLaunchKernelGGL(k_valid_fold, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es, (uint32_t)n_umb,
-                       key->d_table, c->d_gtable, d_valid_tag);
     if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     prof_end(c, POSLO_KT_COMPACT, s);
     uint64_t count = 0;
@@ -785,6 +802,8 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
         f.umb_es = nullptr;
         f.umb_tags = nullptr;
         f.umb_bits = (uint32_t*)dbits;
+        f.n_umb = (uint32_t)n_umb;
+        f.valid_tag = nullptr;
         hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
         HIP_TRY(hipGetLastError());
         std::vector<uint32_t> hb(n_umb);

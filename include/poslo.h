@@ -157,10 +157,13 @@ int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32],
                const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                uint8_t e_out[32]);
 
-/* Kernel timing (opt-in): while enabled, the context records HIP events on
- * the launch stream around each kernel below and accumulates their elapsed
- * time.  poslo_ctx_kernel_time returns the accumulated milliseconds and the
- * number of timed launches of one kernel (and clears them if reset != 0). */
+/* Kernel timing (opt-in): for each kernel whose bit (1 << POSLO_KT_*) is set
+ * in the mask given to poslo_ctx_profile, the context records HIP events on
+ * the launch stream around its launches and accumulates their elapsed time
+ * (each event pair adds a few microseconds of stream gaps, so time only the
+ * kernels you need; 0 turns timing off, POSLO_PROFILE_ALL times them all).
+ * poslo_ctx_kernel_time returns the accumulated milliseconds and the number
+ * of timed launches of one kernel (and clears them if reset != 0). */
 enum {
     POSLO_KT_SEED = 0,   /* per-epoch seed table (SR / SC, hoisted PRF state) */
     POSLO_KT_AGG = 1,    /* fused PRF + digest + lazy aggregate (the hot loop) */
@@ -171,7 +174,8 @@ enum {
     POSLO_KT_BATCH_HOT = 6, /* multi-signer persistent hashing kernel (eager launches only) */
     POSLO_KT_BATCH = 7      /* multi-signer pipeline: seeds, hashing, per-job checks */
 };
-int poslo_ctx_profile(poslo_ctx* ctx, int enable);
+#define POSLO_PROFILE_ALL 0xff
+int poslo_ctx_profile(poslo_ctx* ctx, int kernels);
 int poslo_ctx_kernel_time(poslo_ctx* ctx, int kernel, int reset, double* total_ms, uint64_t* launches);
 
 /* Kernel tuning.  The POSLO+ hot kernel exists in several variants (number

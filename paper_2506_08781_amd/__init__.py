@@ -313,6 +313,7 @@ def poslo_ctx_create(device: int = 0) -> Ctx:
 
 (POSLO_KT_SEED, POSLO_KT_AGG, POSLO_KT_FINAL, POSLO_KT_EKEYS, POSLO_KT_VERIFY, POSLO_KT_COMPACT,
  POSLO_KT_BATCH_HOT, POSLO_KT_BATCH) = range(8)
+POSLO_PROFILE_ALL = 0xFF
 
 
 def poslo_agg_variant_count() -> int:
@@ -330,8 +331,18 @@ def poslo_ctx_set_tuning(ctx: Ctx, agg_variant: int = -1, wg_per_cu: int = 0) ->
     _check(lib().poslo_ctx_set_tuning(ctx.handle, agg_variant, wg_per_cu), "poslo_ctx_set_tuning")
 
 
-def poslo_ctx_profile(ctx: Ctx, enable: bool) -> None:
-    _check(lib().poslo_ctx_profile(ctx.handle, 1 if enable else 0), "poslo_ctx_profile")
+def poslo_ctx_profile(ctx: Ctx, kernels) -> None:
+    """Time the kernels whose POSLO_KT_* ids are given (an iterable of ids;
+    True: all of them; False or empty: none)."""
+    if kernels is True:
+        mask = POSLO_PROFILE_ALL
+    elif kernels is False or kernels is None:
+        mask = 0
+    else:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+    _check(lib().poslo_ctx_profile(ctx.handle, mask), "poslo_ctx_profile")
 
 
 def poslo_ctx_kernel_time(ctx: Ctx, kernel: int, reset: bool = False) -> tuple[float, int]:

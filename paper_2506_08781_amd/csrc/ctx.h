@@ -58,7 +58,7 @@ struct poslo_ctx {
     int agg_variant = -1;
     int wg_per_cu = 0;
     // per-kernel timing with HIP events on the launch stream (opt-in)
-    bool profile = false;
+    uint32_t profile_mask = 0;  // bit k: time kernel POSLO_KT_k
     hipEvent_t ev[poslo::kKtCount][2] = {};
     bool ev_pending[poslo::kKtCount] = {};
     double kt_ms[poslo::kKtCount] = {};

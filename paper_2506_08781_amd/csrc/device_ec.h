@@ -199,6 +199,131 @@ __device__ __forceinline__ void lane_scalar(ge& P, const uint32_t* t, const uint
     }
 }
 
+// word v of quad lane (c + D) & 3, for the lane c of this lane's quad
+template <int D>
+__device__ __forceinline__ uint32_t ec_quad_rot(uint32_t v) {
+    constexpr int ctrl = D == 1 ? 0x39 : D == 2 ? 0x4e : 0x93;  // quad_perm [c + D mod 4]
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ void lds_load_fe(fe& a, const uint32_t* p) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) a.v[k] = p[k];
+}
+
+__device__ __forceinline__ void lds_store_fe(uint32_t* p, const fe& a) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) p[k] = a.v[k];
+}
+
+constexpr int kQuadBlock = 256;               // threads of block_double_scalar_is
+constexpr int kQuadLdsWords = 64 * 4 * 8;     // its LDS: 64 points of 4 coordinates
+
+// e*Y + s*G == (rx, ry) (affine) by a whole 256-thread block, for a single
+// check where latency decides.  The quad of lanes 4k..4k+3 owns point k of
+// 64 (k < 32: window k of e on Y's comb table; k >= 32: window k - 32 of s on
+// G's), lane c holding coordinate c in the order X, Y, Z, T.  A six-level
+// tree of complete additions follows, each addition split over its quad:
+// the four products A, B, C, D of the addition law go one per lane (with
+// the factor 2d taken by a second product on lane C), then the four output
+// products X3 = EF, Y3 = GH, Z3 = FG, T3 = EH go one per lane, so a level
+// costs three multiplications of latency instead of nine.  e, s < 2^253.
+// lds holds kQuadLdsWords words; every thread of the block must call it;
+// the verdict is valid in thread 0.
+__device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
+                                                       const uint32_t e[8], const uint32_t s[8], const fe& rx,
+                                                       const fe& ry) {
+    const int k = (int)(threadIdx.x >> 2), c = (int)(threadIdx.x & 3);
+    const uint32_t* sc = k < 32 ? e : s;
+    const int w = k & 31;
+    uint32_t carry = 0;
+    int d = 0;
+    for (int i = 0; i < kCombWindows; i++) {
+        const int di = comb_digit(sc, i, carry);
+        if (i == w) d = di;
+    }
+    gn q;
+    comb_lookup(q, k < 32 ? ty : tg, w, d);
+    // the affine point (x, y) as (4x : 4y : 4 : 4xy) from y + x and y - x
+    fe a, b, m, v;
+    fe_sub(a, q.yp, q.ym);
+    fe_add(b, q.yp, q.ym);
+    fe_mul(m, a, b);
+    if (c == 0)
+        fe_add(v, a, a);
+    else if (c == 1)
+        fe_add(v, b, b);
+    else if (c == 2)
+        fe_set(v, 4);
+    else
+        v = m;
+    lds_store_fe(lds + (k * 4 + c) * 8, v);
+    for (int o = 32; o >= 1; o >>= 1) {
+        __syncthreads();
+        if (k < o) {
+            const uint32_t* p1 = lds + k * 32;
+            const uint32_t* p2 = lds + (k + o) * 32;
+            // lanes 0 and 1: (Y1 -+ X1)(Y2 -+ X2); lane 2: 2d T1 T2; lane 3: 2 Z1 Z2
+            const int co = c < 2 ? 0 : c == 2 ? 3 : 2;
+            fe u1, u2, y1, y2;
+            lds_load_fe(u1, p1 + co * 8);
+            lds_load_fe(u2, p2 + co * 8);
+            if (c < 2) {
+                lds_load_fe(y1, p1 + 8);
+                lds_load_fe(y2, p2 + 8);
+                if (c == 0) {
+                    fe_sub(u1, y1, u1);
+                    fe_sub(u2, y2, u2);
+                } else {
+                    fe_add(u1, y1, u1);
+                    fe_add(u2, y2, u2);
+                }
+            }
+            fe_mul(m, u1, u2);
+            if (c == 2) {
+                const fe d2 = POSLO_FE_D2;
+                fe_mul(m, m, d2);
+            } else if (c == 3) {
+                fe_add(m, m, m);
+            }
+            // every lane of the quad gets A, B, C, D
+            fe A, B, C, D;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t r0 = m.v[j], r1 = ec_quad_rot<1>(r0), r2 = ec_quad_rot<2>(r0),
+                               r3 = ec_quad_rot<3>(r0);
+                // the word of lane L sits (L - c) & 3 lanes to the right
+                A.v[j] = c == 0 ? r0 : c == 1 ? r3 : c == 2 ? r2 : r1;
+                B.v[j] = c == 1 ? r0 : c == 2 ? r3 : c == 3 ? r2 : r1;
+                C.v[j] = c == 2 ? r0 : c == 3 ? r3 : c == 0 ? r2 : r1;
+                D.v[j] = c == 3 ? r0 : c == 0 ? r3 : c == 1 ? r2 : r1;
+            }
+            fe E, F, G, H;
+            fe_sub(E, B, A);
+            fe_sub(F, D, C);
+            fe_add(G, D, C);
+            fe_add(H, B, A);
+            // lane 0: X3 = EF, lane 1: Y3 = GH, lane 2: Z3 = FG, lane 3: T3 = EH
+            const fe& l = c == 0 ? E : c == 1 ? G : c == 2 ? F : E;
+            const fe& r = c == 0 ? F : c == 1 ? H : c == 2 ? G : H;
+            fe_mul(v, l, r);
+            lds_store_fe(lds + (k * 4 + c) * 8, v);
+        }
+    }
+    __syncthreads();
+    // the sum sits in slot 0: X == x_R Z on lane 0 and Y == y_R Z on lane 1
+    bool ok = true;
+    if (k == 0 && c < 2) {
+        fe Z, V;
+        lds_load_fe(Z, lds + 2 * 8);
+        lds_load_fe(V, lds + c * 8);
+        fe_mul(m, c == 0 ? rx : ry, Z);
+        ok = fe_equal(m, V);
+    }
+    const uint64_t bad = __ballot(!ok);
+    return (bad & 3u) == 0;
+}
+
 // encode(P) == bytes (32 bytes as eight little-endian words)
 __device__ __forceinline__ bool ge_encodes_to(const ge& P, const uint32_t want[8]) {
     uint8_t enc[32];

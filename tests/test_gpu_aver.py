@@ -199,3 +199,34 @@ def test_every_tuning_variant_agrees(P, gpu):
                 assert acc and int.from_bytes(e, "little") == want, P.poslo_agg_variant_name(v)
     finally:
         P.poslo_ctx_set_tuning(ctx, -1, 0)
+
+
+def test_kernel_timing_mask(P, gpu):
+    """Only the kernels named in the profile mask are timed."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = oracle_case(1, 777, 48, 4, 6, 0, 1)
+    params = P.make_params(1, 4, 6)
+    d, _ = upload(torch, msgs, True)
+    for k in range(8):
+        P.poslo_ctx_kernel_time(ctx, k, reset=True)
+    P.poslo_ctx_profile(ctx, [P.POSLO_KT_AGG])
+    try:
+        for _ in range(3):
+            acc, _ = P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)
+            assert acc
+    finally:
+        P.poslo_ctx_profile(ctx, False)
+    ms, n = P.poslo_ctx_kernel_time(ctx, P.POSLO_KT_AGG, reset=True)
+    assert n == 3 and ms > 0
+    for k in (P.POSLO_KT_SEED, P.POSLO_KT_FINAL):
+        assert P.poslo_ctx_kernel_time(ctx, k, reset=True) == (0.0, 0)
+    P.poslo_ctx_profile(ctx, True)
+    try:
+        P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)
+    finally:
+        P.poslo_ctx_profile(ctx, False)
+    for k in (P.POSLO_KT_SEED, P.POSLO_KT_AGG, P.POSLO_KT_FINAL):
+        assert P.poslo_ctx_kernel_time(ctx, k, reset=True)[1] == 1
+    with pytest.raises(P.PosloError):
+        P.poslo_ctx_profile(ctx, [9])

@@ -235,43 +235,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     }
 }
 
-// ---- per-job checks: one 256-thread block per job ----------------------------
+// ---- per-job checks: one wave per job ----------------------------------------
+// (many jobs at once: independent one-wave checks keep more of them resident
+// than the quad-split block check, whose registers allow four blocks per CU)
 
-__global__ __launch_bounds__(kQuadBlock) void k_batch_final(const BJob* jobs, const uint32_t* partials,
-                                                            const uint32_t* tg, const uint32_t* rdec,
-                                                            uint32_t* result) {
-    __shared__ uint32_t total[9];
-    __shared__ uint32_t sh_es[16];
-    __shared__ uint32_t pts[kQuadLdsWords];
+__global__ __launch_bounds__(64) void k_batch_final(const BJob* jobs, const uint32_t* partials, const uint32_t* tg,
+                                                    const uint32_t* rdec, uint32_t* result) {
     const BJob& J = jobs[blockIdx.x];
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint64_t k = J.item_base + threadIdx.x; k < J.item_end; k += kQuadBlock) acc288_add(acc, partials + k * 9);
-    block_reduce288_store<kQuadBlock>(acc, total);
-    __syncthreads();
-    // e mod q on the first wave and s mod q on the second, side by side
-    if (threadIdx.x == 0) {
-        uint32_t e[8];
-        sc_reduce288(e, total);
-        for (int k = 0; k < 8; k++) sh_es[k] = e[k];
-    } else if (threadIdx.x == 64) {
-        uint32_t sr[8];
-        sc_reduce256(sr, J.tag);
-        for (int k = 0; k < 8; k++) sh_es[8 + k] = sr[k];
-    }
-    __syncthreads();
+    for (uint64_t k = J.item_base + threadIdx.x; k < J.item_end; k += 64) acc288_add(acc, partials + k * 9);
+    wave_reduce288(acc);  // every lane holds the sum
     uint32_t e[8], s[8];
-    for (int k = 0; k < 8; k++) {
-        e[k] = sh_es[k];
-        s[k] = sh_es[8 + k];
+    sc_reduce288(e, acc);
+    for (int k = 0; k < 8; k++) s[k] = J.tag[k];
+    ge P;
+    wave_double_scalar(P, J.ty, tg, e, s);
+    if (threadIdx.x == 0) {
+        const uint32_t* r = rdec + (uint64_t)blockIdx.x * 17;
+        fe rx, ry, t0, t1;
+        for (int k = 0; k < 8; k++) {
+            rx.v[k] = r[1 + k];
+            ry.v[k] = r[9 + k];
+        }
+        fe_mul(t0, rx, P.Z);
+        fe_mul(t1, ry, P.Z);
+        result[blockIdx.x] = (r[0] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
     }
-    const uint32_t* r = rdec + (uint64_t)blockIdx.x * 17;
-    fe rx, ry;
-    for (int k = 0; k < 8; k++) {
-        rx.v[k] = r[1 + k];
-        ry.v[k] = r[9 + k];
-    }
-    const bool eq = block_double_scalar_is(pts, J.ty, tg, e, s, rx, ry);
-    if (threadIdx.x == 0) result[blockIdx.x] = (r[0] && eq) ? 1u : 0u;
 }
 
 // ---- individual verification of the entries of chosen jobs ----------------
@@ -595,7 +584,7 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
         if (timed) prof_end(prof, POSLO_KT_BATCH_HOT, q);
         if (r) return r;
         if (njobs)
-            hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(kQuadBlock), 0, q, (const BJob*)d_jobs_,
+            hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs_,
                                (const uint32_t*)d_part_, tg, (const uint32_t*)d_rdec_, (uint32_t*)d_res_);
         return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
     };

@@ -230,3 +230,43 @@ def test_kernel_timing_mask(P, gpu):
         assert P.poslo_ctx_kernel_time(ctx, k, reset=True)[1] == 1
     with pytest.raises(P.PosloError):
         P.poslo_ctx_profile(ctx, [9])
+
+
+def test_aggregate_check_scalar_extremes(P, gpu):
+    """Tags whose s sits at the edges of the signed comb digits (0, digits of
+    128 / 129, q - 1, 2^252, ...), with R = e*Y + s*G computed by the oracle
+    for the batch's own e: the single-batch check (the block-wide quad tree)
+    and the per-job check of the multi-signer path must accept exactly where
+    the oracle does, and reject R + G and s >= q."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, pk, sigs, ds, tag = oracle_case(1, 777, 48, 4, 6, 0, 1)
+    params = P.make_params(1, 4, 6)
+    d, _ = upload(torch, msgs, True)
+    q = O.Q
+    e = O.ekeys_sum(prm, msgs, 0, ds) % q
+    Y = O.decode(pk)
+    eY = O.scalar_mult(e, Y)
+    rep8 = sum(0x80 << (8 * k) for k in range(31))
+    special = [0, 1, 127, 128, 129, 255, 256, q - 1, q - 2, q - 128, 2 ** 252, 2 ** 252 - 1, rep8, rep8 + 1,
+               (rep8 ^ (rep8 >> 1)) % q]
+    tags, want = [], []
+    for s in special:
+        R = O.point_add(eY, O.scalar_mult(s, O.G))
+        tags.append(O.to32(s) + O.encode(R))
+        tags.append(O.to32(s) + O.encode(O.point_add(R, O.G)))
+    # s = q: R equals e*Y + s*G on the curve, but s is not canonical
+    tags.append(O.to32(q) + O.encode(eY))
+    want = [O.aggregate_check(pk, e, t) for t in tags]
+    assert want == [True, False] * len(special) + [False]
+    got = [P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, t)[0] for t in tags]
+    assert got == want
+    n = len(msgs)
+    bj = P.BatchJobs([dict(pk=pk, ds=ds, tag=t, t0=0, n=n, entry_base=k * n) for k, t in enumerate(tags)])
+    base = np.frombuffer(b"".join(msgs), dtype=np.uint8)
+    flat = torch.from_numpy(np.tile(base, len(tags))).cuda()
+    L = len(msgs[0])
+    # job k reads its own copy of the messages, entries k * n .. k * n + n - 1
+    off = torch.arange(0, len(tags) * n * L + 1, L, dtype=torch.int64, device="cuda")
+    acc, _ = P.poslo_verify_batch(ctx, params, bj, flat, off)
+    assert acc == want

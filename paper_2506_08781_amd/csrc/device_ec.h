@@ -224,10 +224,14 @@ constexpr int kQuadLdsWords = 64 * 4 * 8;     // its LDS: 64 points of 4 coordin
 // 64 (k < 32: window k of e on Y's comb table; k >= 32: window k - 32 of s on
 // G's), lane c holding coordinate c in the order X, Y, Z, T.  A six-level
 // tree of complete additions follows, each addition split over its quad:
-// the four products A, B, C, D of the addition law go one per lane (with
-// the factor 2d taken by a second product on lane C), then the four output
-// products X3 = EF, Y3 = GH, Z3 = FG, T3 = EH go one per lane, so a level
-// costs three multiplications of latency instead of nine.  e, s < 2^253.
+// the four products A, B, C, D of the addition law go one per lane, then the
+// four output products X3 = EF, Y3 = GH, Z3 = FG, T3 = EH go one per lane,
+// so a level costs two multiplications of latency instead of nine.  The
+// factor 2d = -2 * 121665 / 121666 of C is kept out of the chain by scaling
+// A, B, C and D by 121666 (small-constant products): A and B by 121666, C by
+// 2 * 121665 with its sign moved into F and G, D by 2 * 121666.  E, F, G and
+// H then all carry the factor 121666, so the result is the same point with
+// every coordinate scaled by 121666^2.  e, s < 2^253.
 // lds holds kQuadLdsWords words; every thread of the block must call it;
 // the verdict is valid in thread 0.
 __device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
@@ -263,7 +267,8 @@ __device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint
         if (k < o) {
             const uint32_t* p1 = lds + k * 32;
             const uint32_t* p2 = lds + (k + o) * 32;
-            // lanes 0 and 1: (Y1 -+ X1)(Y2 -+ X2); lane 2: 2d T1 T2; lane 3: 2 Z1 Z2
+            // lanes 0 and 1: 121666 (Y1 -+ X1)(Y2 -+ X2); lane 2: 243330 T1 T2
+            // (= -121666 * 2d T1 T2); lane 3: 243332 Z1 Z2 (= 121666 * 2 Z1 Z2)
             const int co = c < 2 ? 0 : c == 2 ? 3 : 2;
             fe u1, u2, y1, y2;
             lds_load_fe(u1, p1 + co * 8);
@@ -280,12 +285,7 @@ __device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint
                 }
             }
             fe_mul(m, u1, u2);
-            if (c == 2) {
-                const fe d2 = POSLO_FE_D2;
-                fe_mul(m, m, d2);
-            } else if (c == 3) {
-                fe_add(m, m, m);
-            }
+            fe_mul_small(m, m, c < 2 ? 121666u : c == 2 ? 243330u : 243332u);
             // every lane of the quad gets A, B, C, D
             fe A, B, C, D;
 #pragma unroll
@@ -298,10 +298,11 @@ __device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint
                 C.v[j] = c == 2 ? r0 : c == 3 ? r3 : c == 0 ? r2 : r1;
                 D.v[j] = c == 3 ? r0 : c == 0 ? r3 : c == 1 ? r2 : r1;
             }
+            // C holds minus the scaled 2d T1 T2: F = D + C, G = D - C
             fe E, F, G, H;
             fe_sub(E, B, A);
-            fe_sub(F, D, C);
-            fe_add(G, D, C);
+            fe_add(F, D, C);
+            fe_sub(G, D, C);
             fe_add(H, B, A);
             // lane 0: X3 = EF, lane 1: Y3 = GH, lane 2: Z3 = FG, lane 3: T3 = EH
             const fe& l = c == 0 ? E : c == 1 ? G : c == 2 ? F : E;

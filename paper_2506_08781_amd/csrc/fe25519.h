@@ -67,6 +67,27 @@ PD void fe_sub(fe& r, const fe& a, const fe& b) {
     r.v[0] -= (uint32_t)(-c) * 38u;
 }
 
+// a * k for a small constant k < 2^26 (2^256 = 38 mod p)
+PD void fe_mul_small(fe& r, const fe& a, uint32_t k) {
+    uint32_t t[8];
+    uint64_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        c += (uint64_t)a.v[i] * k;
+        t[i] = (uint32_t)c;
+        c >>= 32;
+    }
+    c *= 38;  // c < 2^26, so 38c < 2^32
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        c += t[i];
+        r.v[i] = (uint32_t)c;
+        c >>= 32;
+    }
+    // a second wrap leaves r < 2^32 - 38, so adding 38 cannot carry
+    r.v[0] += (uint32_t)c * 38u;
+}
+
 // t_lo + 38 * t_hi for the 512-bit product t (2^256 = 38 mod p)
 PD void fe_fold512(fe& r, const uint32_t t[16]) {
     uint32_t u[8];

@@ -575,7 +575,11 @@ def main():
     # other sections, it measured slower (burst 1.10 vs 1.74 G entries/s),
     # while running it first slowed the invalid-set pass after it
     if child is not None:
-        out["serving"] = finish_serving_child(child)
+        try:
+            out["serving"] = finish_serving_child(child)
+        except Exception as exc:  # the other sections' results still print
+            child.kill()
+            out["serving"] = {"error": f"{type(exc).__name__}: {exc}"}
     print(json.dumps(out), flush=True)
 
 

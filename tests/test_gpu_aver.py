@@ -270,3 +270,35 @@ def test_aggregate_check_scalar_extremes(P, gpu):
     off = torch.arange(0, len(tags) * n * L + 1, L, dtype=torch.int64, device="cuda")
     acc, _ = P.poslo_verify_batch(ctx, params, bj, flat, off)
     assert acc == want
+
+
+def test_aggregate_check_doubling_and_cancelling(P, gpu):
+    """With Y = G, s = e makes every first-level addition of the check's tree
+    a doubling (window w of e on Y's table meets window w of s on G's), and
+    s = q - e makes every one cancel to the identity; the complete addition
+    law (and its quad-split, scaled form) must handle both.  R comes from the
+    oracle; R + G must be rejected."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm, msgs, _, _, ds, _ = oracle_case(1, 777, 48, 4, 6, 0, 1)
+    params = P.make_params(1, 4, 6)
+    d, _ = upload(torch, msgs, True)
+    q = O.Q
+    e = O.ekeys_sum(prm, msgs, 0, ds) % q
+    pk = O.encode(O.G)
+    tags = []
+    for s in (e, (q - e) % q, 0):
+        R = O.scalar_mult((e + s) % q, O.G)
+        tags.append(O.to32(s) + O.encode(R))
+        tags.append(O.to32(s) + O.encode(O.point_add(R, O.G)))
+    want = [O.aggregate_check(pk, e, t) for t in tags]
+    assert want == [True, False] * 3
+    assert tags[2][32:] == (1).to_bytes(32, "little")  # s = q - e: R is the identity
+    got = [P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, t)[0] for t in tags]
+    assert got == want
+    n, L = len(msgs), len(msgs[0])
+    bj = P.BatchJobs([dict(pk=pk, ds=ds, tag=t, t0=0, n=n, entry_base=k * n) for k, t in enumerate(tags)])
+    flat = torch.from_numpy(np.tile(np.frombuffer(b"".join(msgs), dtype=np.uint8), len(tags))).cuda()
+    off = torch.arange(0, len(tags) * n * L + 1, L, dtype=torch.int64, device="cuda")
+    acc, _ = P.poslo_verify_batch(ctx, params, bj, flat, off)
+    assert acc == want

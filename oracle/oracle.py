@@ -623,3 +623,19 @@ def sign_batch(prm: Params, seed: bytes, msgs: list[bytes]):
     signer, pk = kg(prm, seed)
     sigs = [sig(signer, m) for m in msgs]
     return pk, sigs, ds_encode(signer.ds), agg(sigs), signer
+
+
+def signer_at(prm: Params, seed: bytes, t: int) -> Signer:
+    """The signer's state St after entries 0 .. t-1 have been signed, reached
+    through POSLO-F.Sig's state transitions alone: Sig changes (ds, x_0)
+    only at the first entry of an epoch (the SSO call) and otherwise only
+    advances the counter, so St after t entries is SSO applied for epochs
+    0 .. ceil(t / n2) - 1 with the counter at t.  Signing from this state
+    gives the same signatures as signing every earlier entry first."""
+    if not 0 <= t <= prm.n1 * prm.n2:
+        raise ValueError("state index out of range")
+    signer, _ = kg(prm, seed)
+    for i in range(-(-t // prm.n2)):
+        signer.ds, signer.x0 = SSO(prm.inst, signer.ds, signer.root, prm.log2_n1, i)
+    signer.t = t
+    return signer

@@ -1,0 +1,203 @@
+"""Oracle results over full-size batches, computed on the host cores.
+
+Test infrastructure.  Everything here comes from ``oracle`` and ``synthlog``
+alone: the messages are synthlog's, the keys, signatures, ds and tags are the
+oracle signer's, and every expected value is an oracle function applied to
+them.  Nothing is read back from the GPU library.
+
+The batch is cut into umbrella-sized chunks (umbrella l covers batch
+positions [l*U, min(N, (l+1)*U)), U = ceil(N / n_u)), and a process pool runs
+the oracle on the chunks side by side.  Each chunk starts from the signer
+state after the entries before it (``oracle.signer_at``), so the chunks'
+signatures are the sequential signer's.  The per-batch results combine by
+the plain sums that define them: e = (sum of the raw digests) mod q, and
+Agg is a sum over its records, so the aggregate of a batch is Agg over the
+aggregates of its parts.  ``test_oracle_fullsize.py`` checks the pooled
+results against the sequential oracle (sign_batch, aver, distill) on a small
+batch.
+
+Per chunk the workers produce:
+  * the honest signatures, per-entry raw digests H(m_t || x_t) reduced mod q
+    and one-time seeds x_t (x_t re-derived from the final ds by SR, as AVer
+    does);
+  * after the corruption plan is applied (one flipped bit of m_t || sigma_t
+    per planned entry): the individual verdict of every planned entry, the
+    individual verdict of two unplanned entries (a sample: unplanned entries
+    carry the honest signature, which the oracle's pins show valid), the
+    umbrella's Agg over its valid entries, and the raw digest sum of the
+    corrupted messages.
+"""
+
+from __future__ import annotations
+
+import functools
+import multiprocessing as mp
+import os
+import random
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import synthlog
+
+# the box gives one GPU process a share of 16 host cores
+MAX_WORKERS = 16
+
+
+def workers() -> int:
+    return max(1, min(MAX_WORKERS, os.cpu_count() or 1))
+
+
+@dataclass
+class FullCase:
+    inst: int
+    log2_n1: int
+    log2_n2: int
+    n: int
+    L: int
+    key_first: int
+    msg_seed: int
+    n_u: int
+    pk: bytes
+    ds: bytes
+    tag: bytes                      # Agg over all honest signatures
+    msgs: np.ndarray                # (n, L) honest messages
+    sigs: np.ndarray                # (n, 80) honest signatures
+    e_t: np.ndarray                 # (n, 32) H(m_t || x_t) mod q, little-endian
+    x_t: np.ndarray                 # (n, 16)
+    e: int                          # sum of e_t mod q (AVer's aggregate key)
+    plan: list = field(default_factory=list)   # (entry, bit) flips
+    cmsgs: np.ndarray | None = None            # corrupted copies
+    csigs: np.ndarray | None = None
+    invalid: list = field(default_factory=list)  # entries the oracle finds invalid
+    span: int = 0
+    umbrellas: list = field(default_factory=list)  # Agg over each umbrella's valid entries
+    valid_tag: bytes = b""                         # Agg over all valid entries
+    e_corrupt: int = 0                             # AVer's aggregate key of the corrupted batch
+    aver_corrupt: bool = True                      # AVer of the corrupted batch under the honest tag
+    aver_honest: bool = True                       # AVer of the honest batch
+
+
+_W = {}
+
+
+def _bpv_part(args):
+    from oracle import oracle as O
+    inst, log2_n1, log2_n2, seed, ks = args
+    prm = O.Params(inst, log2_n1, log2_n2)
+    signer, _ = O.kg(prm, seed)
+    return {k: signer.bpv_pair(k) for k in ks}
+
+
+def _chunk(args):
+    from oracle import oracle as O
+    (inst, log2_n1, log2_n2, seed, ds, msg_seed, L, a, b, plan, gamma) = args
+    prm = O.Params(inst, log2_n1, log2_n2)
+    msgs = [bytes(r) for r in synthlog.messages_fixed(msg_seed, b - a, L, t0=a)]
+    signer = O.signer_at(prm, seed, a)
+    signer._gamma = gamma
+    pk = O.encode(O.scalar_mult(signer.y, O.G))
+    sigs = [O.sig(signer, m) for m in msgs]
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), a, b - a)
+    e_t, x_t, raw = [], [], 0
+    for p, m in enumerate(msgs):
+        t = a + p
+        x = O.one_time_seed(inst, seeds[t >> log2_n2], t & (prm.n2 - 1))
+        d = O.digest_int(inst, m, x)
+        raw += d
+        e_t.append(O.to32(d % O.Q))
+        x_t.append(x)
+    # the corruption plan, then the verdicts the oracle gives on the result
+    cm, cs = list(msgs), list(sigs)
+    flipped = {}
+    for e, bit in plan:
+        p = e - a
+        blob = bytearray(msgs[p] + sigs[p])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        cm[p], cs[p] = bytes(blob[:L]), bytes(blob[L:])
+        flipped[p] = True
+    bad = []
+    for p in sorted(flipped):
+        t = a + p
+        if not O.entry_valid(prm, pk, cm[p], t, cs[p], seeds[t >> log2_n2]):
+            bad.append(t)
+    rng = random.Random(a)
+    unplanned = [p for p in range(b - a) if p not in flipped]
+    sample_bad = []
+    for p in rng.sample(unplanned, min(2, len(unplanned))):
+        t = a + p
+        if not O.entry_valid(prm, pk, cm[p], t, cs[p], seeds[t >> log2_n2]):
+            sample_bad.append(t)
+    bad_set = set(bad)
+    valid_tag = O.agg([cs[p] for p in range(b - a) if a + p not in bad_set])
+    raw_c = 0
+    for p in flipped:
+        t = a + p
+        x = O.one_time_seed(inst, seeds[t >> log2_n2], t & (prm.n2 - 1))
+        raw_c += O.digest_int(inst, cm[p], x) - O.digest_int(inst, msgs[p], x)
+    return dict(a=a, b=b, sigs=b"".join(sigs), e_t=b"".join(e_t), x_t=b"".join(x_t), raw=raw,
+                raw_c=raw + raw_c, bad=bad, sample_bad=sample_bad, valid_tag=valid_tag,
+                bad_sigs=[sigs[t - a] for t in bad], cm={a + p: cm[p] for p in flipped},
+                cs={a + p: cs[p] for p in flipped})
+
+
+def _pool(n):
+    return mp.get_context("spawn").Pool(n)
+
+
+@functools.lru_cache(maxsize=None)
+def full_case(inst: int, n: int, L: int, log2_n1: int, log2_n2: int, key_first: int, msg_seed: int,
+              n_u: int, flip_seed: int, k_flips: int, nproc: int | None = None) -> FullCase:
+    """Oracle-signed batch of n entries of L-byte messages (synthlog seed
+    msg_seed, key seed bytes key_first..key_first+31) with its oracle
+    results, and the same batch with k_flips entries corrupted
+    (synthlog.corruption_plan with flip_seed over the 8 (L + 80) bits of
+    m_t || sigma_t), distilled into n_u umbrellas."""
+    from oracle import oracle as O
+    prm = O.Params(inst, log2_n1, log2_n2)
+    seed = synthlog.key_seed_bytes(key_first)
+    signer = O.signer_at(prm, seed, n)
+    ds = O.ds_encode(signer.ds)
+    pk = O.encode(O.scalar_mult(signer.y, O.G))
+    span = max(1, -(-n // n_u))
+    plan = synthlog.corruption_plan(flip_seed, n, k_flips, 8 * (L + 80)) if k_flips else []
+    nproc = nproc or workers()
+    with _pool(nproc) as pool:
+        ks = list(range(prm.v))
+        parts = pool.map(_bpv_part, [(inst, log2_n1, log2_n2, seed, ks[i::nproc]) for i in range(nproc)])
+        gamma = {}
+        for p in parts:
+            gamma.update(p)
+        jobs = []
+        for a in range(0, n, span):
+            b = min(n, a + span)
+            jobs.append((inst, log2_n1, log2_n2, seed, ds, msg_seed, L, a, b,
+                         [(e, bit) for e, bit in plan if a <= e < b], gamma))
+        res = pool.map(_chunk, jobs, chunksize=1)
+    msgs = synthlog.messages_fixed(msg_seed, n, L)
+    sigs = np.frombuffer(b"".join(r["sigs"] for r in res), dtype=np.uint8).reshape(n, 80)
+    e_t = np.frombuffer(b"".join(r["e_t"] for r in res), dtype=np.uint8).reshape(n, 32)
+    x_t = np.frombuffer(b"".join(r["x_t"] for r in res), dtype=np.uint8).reshape(n, 16)
+    raw = sum(r["raw"] for r in res)
+    raw_c = sum(r["raw_c"] for r in res)
+    invalid = sorted(t for r in res for t in r["bad"])
+    sample_bad = [t for r in res for t in r["sample_bad"]]
+    if sample_bad:
+        raise AssertionError(f"honest entries the oracle rejects: {sample_bad[:8]}")
+    umbrellas = [r["valid_tag"] for r in res]
+    # Agg over a batch is Agg over the aggregates of its parts
+    valid_tag = O.agg(umbrellas)
+    tag = O.agg(umbrellas + [s for r in res for s in r["bad_sigs"]])
+    cmsgs, csigs = msgs.copy(), sigs.copy()
+    for r in res:
+        for t, m in r["cm"].items():
+            cmsgs[t] = np.frombuffer(m, dtype=np.uint8)
+        for t, s in r["cs"].items():
+            csigs[t] = np.frombuffer(s, dtype=np.uint8)
+    e = raw % O.Q
+    e_c = raw_c % O.Q
+    return FullCase(inst=inst, log2_n1=log2_n1, log2_n2=log2_n2, n=n, L=L, key_first=key_first,
+                    msg_seed=msg_seed, n_u=n_u, pk=pk, ds=ds, tag=tag, msgs=msgs, sigs=sigs, e_t=e_t,
+                    x_t=x_t, e=e, plan=plan, cmsgs=cmsgs, csigs=csigs, invalid=invalid, span=span,
+                    umbrellas=umbrellas, valid_tag=valid_tag, e_corrupt=e_c,
+                    aver_corrupt=O.aggregate_check(pk, e_c, tag), aver_honest=O.aggregate_check(pk, e, tag))

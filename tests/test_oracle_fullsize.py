@@ -1,0 +1,49 @@
+"""The pooled full-size oracle results (tests/oracle_fullsize.py) equal the
+sequential oracle on a small batch: the chunked signer continues the
+sequential signer exactly, and the combined sums (e, Agg, umbrellas, the
+invalid set) equal sign_batch, aver and distill run in order."""
+
+import numpy as np
+
+import synthlog
+
+
+def _corrupt(msgs, sigs, plan):
+    msgs, sigs = list(msgs), list(sigs)
+    for e, bit in plan:
+        blob = bytearray(msgs[e] + sigs[e])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        L = len(msgs[e])
+        msgs[e], sigs[e] = bytes(blob[:L]), bytes(blob[L:])
+    return msgs, sigs
+
+
+def test_pooled_case_equals_sequential_oracle(O):
+    import oracle_fullsize as F
+    inst, n, L, l1, l2, key_first, msg_seed, n_u, flip_seed, k = 1, 150, 40, 4, 4, 9, 11, 4, 12, 6
+    case = F.full_case(inst, n, L, l1, l2, key_first, msg_seed, n_u, flip_seed, k, nproc=3)
+    prm = O.Params(inst, l1, l2)
+    msgs = [bytes(r) for r in synthlog.messages_fixed(msg_seed, n, L)]
+    pk, sigs, ds, tag, _ = O.sign_batch(prm, synthlog.key_seed_bytes(key_first), msgs)
+    assert case.pk == pk and case.ds == ds and case.tag == tag
+    assert [bytes(r) for r in case.msgs] == msgs
+    assert [bytes(r) for r in case.sigs] == sigs
+    assert case.e == O.ekeys_sum(prm, msgs, 0, ds)
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), 0, n)
+    for t in range(n):
+        x = O.one_time_seed(inst, seeds[t >> l2], t & (prm.n2 - 1))
+        assert bytes(case.x_t[t]) == x
+        assert int.from_bytes(bytes(case.e_t[t]), "little") == O.digest_int(inst, msgs[t], x) % O.Q
+    assert case.aver_honest
+    plan = synthlog.corruption_plan(flip_seed, n, k, 8 * (L + 80))
+    assert case.plan == plan
+    cm, cs = _corrupt(msgs, sigs, plan)
+    assert [bytes(r) for r in case.cmsgs] == cm and [bytes(r) for r in case.csigs] == cs
+    ccd = O.distill(prm, pk, cm, cs, 0, ds, n_u)
+    assert case.invalid == [t for t, _ in ccd.invalid] == sorted(e for e, _ in plan)
+    assert case.span == ccd.span
+    assert case.umbrellas == [u for u, _ in ccd.umbrellas]
+    assert case.valid_tag == ccd.valid_tag
+    assert case.e_corrupt == O.ekeys_sum(prm, cm, 0, ds)
+    assert case.aver_corrupt == O.aver(prm, pk, cm, 0, ds, tag)
+    assert isinstance(case.msgs, np.ndarray)

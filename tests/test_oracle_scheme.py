@@ -172,3 +172,17 @@ def test_seed_retrieval_failure_and_exhaustion(O):
         O.sig(signer, bytes(8))
     with pytest.raises(RuntimeError):
         O.sig(signer, bytes(8))  # t = n1 * n2 = 8
+
+
+@pytest.mark.parametrize("inst", [0, 1])
+def test_signer_at_continues_the_sequential_signer(O, inst):
+    # the state after t entries, reached by SSO calls alone, signs the rest
+    # of the batch exactly as the signer that signed entries 0 .. t-1
+    prm, msgs, pk, sigs, ds, tag, signer = _batch(O, inst, 19, 12, log2_n1=3, log2_n2=2)
+    seed = synthlog.key_seed_bytes(0)
+    for t in (0, 1, 3, 4, 5, 8, 16, 19):
+        st = O.signer_at(prm, seed, t)
+        assert [O.sig(st, m) for m in msgs[t:]] == sigs[t:], t
+        assert O.ds_encode(st.ds) == ds
+    with pytest.raises(ValueError):
+        O.signer_at(prm, seed, prm.n1 * prm.n2 + 1)

@@ -639,3 +639,203 @@ def signer_at(prm: Params, seed: bytes, t: int) -> Signer:
         signer.ds, signer.x0 = SSO(prm.inst, signer.ds, signer.root, prm.log2_n1, i)
     signer.t = t
     return signer
+
+
+# ---------------------------------------------------------------------------
+# POSLO-C: coarse-grained, one aggregate signature per epoch (figure
+# "Coarse-grained signer-optimal POSLO": Kg, Agg, Sig, AVer, Distill,
+# SeBVer).  Readings beyond R1-R9:
+#   C1  r_i^j = PRF_0(r || LE32(i) || LE32(j)) read as a little-endian
+#       128-bit integer (below q, so its "mod q" leaves it unchanged); r is
+#       the first 16 bytes of derive(seed, "r", 0).
+#   C2  Sig's one-time seed is x_i^j = PRF_0(x_0[i] || LE32(j)) with
+#       (ds_i, x_0[i]) = SSO(ds_{i-1}, x_D[0], i) (the figure writes x_D[i]
+#       in both places; AVer re-derives x_0[i] by SR, so the two must agree).
+#   C3  byte formats: pk = enc(Y) || enc(R~_0) || ... || enc(R~_{n1-1});
+#       an epoch signature is LE32B(s~_i) with ds_i after epoch i; a
+#       verifier's aggregate tag over a set of epochs is LE32B(s~) || enc(R~).
+#   C4  the umbrella span is U = ceil(k / n_u) epochs of a k-epoch batch
+#       (Distill's "i = 0 mod floor(n1/n^u)" for 0-based epochs, with the
+#       batch's k in place of n1, as R8 reads it for entries).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class CSigner:
+    params: Params
+    seed: bytes
+    y: int
+    root: bytes          # x_D[0]
+    r: bytes             # seed of the per-entry commitments r_i^j
+    i: int = 0           # next epoch (state St = (i, ds))
+    ds: list = field(default_factory=list)
+
+
+def posloc_r(inst: int, r: bytes, i: int, j: int) -> int:
+    """r_i^j = PRF_0(r || i || j) mod q (reading C1)."""
+    return le256(prf(inst, 0, r + le32(i) + le32(j))) % Q
+
+
+def posloc_kg(params: Params, seed: bytes):
+    """POSLO-C.Kg: y and Y = y*G as in POSLO-F.Kg, the root x_D[0], the
+    commitment seed r, and per epoch i the aggregate commitment
+    R~_i = (sum over j of r_i^j mod q) * G.  Returns (signer, pk bytes)."""
+    signer_f, pk_y = kg(params, seed)
+    r = derive(params.inst, seed, b"r", 0)[:16]
+    out = bytearray(pk_y)
+    for i in range(params.n1):
+        ri = 0
+        for j in range(params.n2):
+            ri = (ri + posloc_r(params.inst, r, i, j)) % Q
+        out += encode(scalar_mult(ri, G))
+    return CSigner(params=params, seed=seed, y=signer_f.y, root=signer_f.root, r=r), bytes(out)
+
+
+def posloc_pk_parts(params: Params, pk: bytes):
+    """(Y bytes, [R~_i bytes]) of a POSLO-C public key."""
+    if len(pk) != 32 * (1 + params.n1):
+        raise ValueError("POSLO-C public key holds Y and one commitment per epoch")
+    return pk[:32], [pk[32 * (1 + i):32 * (2 + i)] for i in range(params.n1)]
+
+
+def posloc_sig(signer: CSigner, msgs: list[bytes]) -> tuple[bytes, bytes]:
+    """POSLO-C.Sig of epoch i = St.i over its n2 messages: s~_i = sum over j
+    of (r_i^j - e_i^j * y) mod q; returns (LE32B(s~_i), ds_i)."""
+    prm = signer.params
+    i = signer.i
+    if i >= prm.n1:
+        raise RuntimeError("signer exhausted: every epoch is signed")
+    if len(msgs) != prm.n2:
+        raise ValueError("an epoch signature covers exactly n2 messages")
+    signer.ds, x0 = SSO(prm.inst, signer.ds, signer.root, prm.log2_n1, i)
+    s = 0
+    for j, m in enumerate(msgs):
+        x = one_time_seed(prm.inst, x0, j)
+        e = digest_int(prm.inst, m, x) % Q
+        s = (s + posloc_r(prm.inst, signer.r, i, j) - e * signer.y) % Q
+    signer.i = i + 1
+    return to32(s), ds_encode(signer.ds)
+
+
+def posloc_epoch_e(prm: Params, msgs: list[bytes], i: int, ds: list[Node]) -> int:
+    """AVer's inner loops for one epoch: sum over j of H(m_i^j || x_i^j) mod q
+    with x_0[i] = SR(ds, i)."""
+    x0 = SR(prm.inst, ds, i)
+    if x0 is None:
+        raise LookupError(f"SR returned bottom for epoch {i}")
+    e = 0
+    for j, m in enumerate(msgs):
+        e = (e + digest_int(prm.inst, m, one_time_seed(prm.inst, x0, j))) % Q
+    return e
+
+
+def posloc_aver(prm: Params, pk: bytes, epochs: list, ds_bytes: bytes, s_tag: bytes,
+                R_tag: bytes | None = None) -> bool:
+    """POSLO-C.AVer over the epochs [(i, [n2 messages]), ...] against the
+    aggregate s~ (32 bytes).  R~ is the Agg of the epochs' R~_i in pk unless
+    the signature carries one (R_tag).  accept iff every epoch is whole,
+    s~ < q and R~ = e~*Y + s~*G with e~ the sum of the epochs' hashes."""
+    Yb, Rs = posloc_pk_parts(prm, pk)
+    for i, msgs in epochs:
+        if len(msgs) != prm.n2 or not 0 <= i < prm.n1:
+            raise ValueError("AVer takes whole epochs")
+    if R_tag is None:
+        R = IDENTITY
+        for i, _ in epochs:
+            Ri = decode(Rs[i])
+            if Ri is None:
+                raise ValueError("undecodable epoch commitment in pk")
+            R = point_add(R, Ri)
+        R_tag = encode(R)
+    ds = ds_decode(ds_bytes)
+    e = 0
+    for i, msgs in epochs:
+        e = (e + posloc_epoch_e(prm, msgs, i, ds)) % Q
+    return aggregate_check(Yb, e, bytes(s_tag) + bytes(R_tag))
+
+
+def posloc_agg_s(s_list: list[bytes]) -> bytes:
+    """POSLO-C.Agg of the additive parts: sum mod q."""
+    s = 0
+    for b in s_list:
+        s = (s + le256(b)) % Q
+    return to32(s)
+
+
+@dataclass
+class CCDC:
+    valid_tag: bytes                                  # CCD^v: LE32B(s~) || enc(R~)
+    umbrellas: list = field(default_factory=list)     # CCD^u: (tag, l)
+    invalid: list = field(default_factory=list)       # CCD^i: (i, LE32B(s~_i) || enc(R~_i))
+    ds: bytes = b""
+    i0: int = 0
+    k: int = 0
+    span: int = 0
+
+
+def posloc_distill(prm: Params, pk: bytes, msgs: list[bytes], s_epochs: list[bytes], i0: int,
+                   ds_bytes: bytes, n_u: int) -> CCDC:
+    """POSLO-C.Distill over k consecutive epochs i0 .. i0+k-1 (msgs holds
+    their k*n2 messages in order, s_epochs their signatures s~_i): each
+    epoch is checked by AVer against (s~_i, R~_i from pk); valid epochs go
+    into CCD^v and the current umbrella, invalid ones into CCD^i with
+    (s~_i, R~_i)."""
+    if len(msgs) != len(s_epochs) * prm.n2:
+        raise ValueError("n2 messages per epoch signature")
+    if n_u < 1:
+        raise ValueError("at least one umbrella")
+    k = len(s_epochs)
+    _, Rs = posloc_pk_parts(prm, pk)
+    span = max(1, -(-k // n_u))
+    sv, Rv, su, Ru = 0, IDENTITY, 0, IDENTITY
+    ccd = CCDC(valid_tag=b"", ds=bytes(ds_bytes), i0=i0, k=k, span=span)
+    for p in range(k):
+        i = i0 + p
+        em = msgs[p * prm.n2:(p + 1) * prm.n2]
+        if posloc_aver(prm, pk, [(i, em)], ds_bytes, s_epochs[p]):
+            s, R = le256(s_epochs[p]), decode(Rs[i])
+            sv, Rv = (sv + s) % Q, point_add(Rv, R)
+            su, Ru = (su + s) % Q, point_add(Ru, R)
+        else:
+            ccd.invalid.append((i, bytes(s_epochs[p]) + Rs[i]))
+        if (p + 1) % span == 0 or p == k - 1:
+            ccd.umbrellas.append((to32(su) + encode(Ru), p // span))
+            su, Ru = 0, IDENTITY
+    ccd.valid_tag = to32(sv) + encode(Rv)
+    return ccd
+
+
+def posloc_sebver(prm: Params, pk: bytes, msgs: list[bytes], ccd: CCDC, mode: str) -> list[bool]:
+    """POSLO-C.SeBVer.  V: AVer of every epoch not in CCD^i against CCD^v.
+    U: per umbrella, AVer of its epochs minus CCD^i against its tag.
+    I: AVer of each CCD^i epoch against its own (s~_i, R~_i)."""
+    bad = {i for i, _ in ccd.invalid}
+
+    def ep(p):
+        return (ccd.i0 + p, msgs[p * prm.n2:(p + 1) * prm.n2])
+
+    if mode == "V":
+        eps = [ep(p) for p in range(ccd.k) if ccd.i0 + p not in bad]
+        return [posloc_aver(prm, pk, eps, ccd.ds, ccd.valid_tag[:32], ccd.valid_tag[32:])]
+    if mode == "U":
+        out = []
+        for tag, l in ccd.umbrellas:
+            a, b = l * ccd.span, min(ccd.k, (l + 1) * ccd.span)
+            eps = [ep(p) for p in range(a, b) if ccd.i0 + p not in bad]
+            out.append(posloc_aver(prm, pk, eps, ccd.ds, tag[:32], tag[32:]))
+        return out
+    if mode == "I":
+        return [posloc_aver(prm, pk, [ep(i - ccd.i0)], ccd.ds, sg[:32], sg[32:]) for i, sg in ccd.invalid]
+    raise ValueError("mode must be V, U or I")
+
+
+def posloc_sign_batch(prm: Params, seed: bytes, msgs: list[bytes]):
+    """POSLO-C key generation and signing of len(msgs) / n2 whole epochs in
+    order: (pk, [s~_i], ds after the last epoch, signer)."""
+    if len(msgs) % prm.n2:
+        raise ValueError("whole epochs only")
+    signer, pk = posloc_kg(prm, seed)
+    s_list, ds = [], ds_encode([])
+    for p in range(len(msgs) // prm.n2):
+        s, ds = posloc_sig(signer, msgs[p * prm.n2:(p + 1) * prm.n2])
+        s_list.append(s)
+    return pk, s_list, ds, signer

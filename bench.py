@@ -10,6 +10,10 @@ n2 = 256, n1 = 4096, POSLO+ instantiation (MMO-AES-128 PRF, MDC-2-AES-128
 hash), one aggregate tag over honest signatures.
 
 The same run also measures, each on its own synthetic log:
+ - small: the 1,024 x 32-byte configuration (latency-bound): microseconds
+   per AVer call, the kernels' durations and the launch overhead;
+ - sha (or aes with --inst sha): the headline configuration under the other
+   instantiation, with its own roofline;
  - distill: Distill of 2^20 x 256-byte entries with 1% of entries carrying
    one flipped bit of m_t || sigma_t (exact invalid set, CCD);
  - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
@@ -167,7 +171,26 @@ def cpu_baseline(cfg, inst, log, target_s: float):
     ok = O.aver(prm, log.pk, sample, 0, log.ds, tag)
     dt = time.perf_counter() - t
     return {"value": ns / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle AVer over the first {ns} entries of the same batch ({dt:.1f} s, accept={ok})"}
+            "sample": f"oracle AVer over the first {ns} entries of the same batch ({dt:.1f} s, accept={ok})",
+            "host": host_info()}
+
+
+def host_info():
+    """CPU model and core counts of the machine the oracle ran on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
 
 def bench_plain(P, torch, ctx, cfg, inst, steps, warmup, calib_copy):
@@ -211,6 +234,66 @@ def bench_plain(P, torch, ctx, cfg, inst, steps, warmup, calib_copy):
     P.poslo_ctx_profile(ctx, False)
     kt = {"seed": kernel_ms(P, ctx, P.POSLO_KT_SEED), "agg": agg, "final": kernel_ms(P, ctx, P.POSLO_KT_FINAL)}
     return log, total, lat, kt
+
+
+def bench_small(P, torch, ctx, inst, calls):
+    """The 1,024 x 32-byte configuration: latency-bound, so the figures are
+    microseconds per AVer call (host call to verdict), the kernels' own
+    durations, and the launch overhead (call latency minus kernel time)."""
+    from paper_2506_08781_amd import workloads
+    cfg = CONFIGS["c1"]
+    log = workloads.single_signer_fixed(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
+    msgs = P.make_msgs(log.data)
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        assert P.poslo_aver(ctx, log.params, log.pk, msgs, log.ds, log.tag, stream)[0]
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        s = time.perf_counter()
+        ok, _ = P.poslo_aver(ctx, log.params, log.pk, msgs, log.ds, log.tag, stream)
+        lat.append(time.perf_counter() - s)
+        assert ok
+    total = time.perf_counter() - t0
+    # untimed: each kernel's duration, one kernel timed per pass
+    kt = {}
+    for name, k in (("seed", P.POSLO_KT_SEED), ("agg", P.POSLO_KT_AGG), ("final", P.POSLO_KT_FINAL)):
+        P.poslo_ctx_profile(ctx, [k])
+        reset_times(P, ctx)
+        for _ in range(50):
+            P.poslo_aver(ctx, log.params, log.pk, msgs, log.ds, log.tag, stream)
+        torch.cuda.synchronize()
+        kt[name] = kernel_ms(P, ctx, k)
+    P.poslo_ctx_profile(ctx, False)
+    lat_us = {k: 1e3 * v for k, v in lat_summary(lat).items() if k != "samples"}
+    kernels_us = 1e3 * sum(kt.values())
+    return {"workload": cfg["name"] + (", POSLO+" if inst else ", POSLO"), "calls": calls,
+            "entries_per_s": cfg["n"] * calls / total, "latency_us": lat_us,
+            "kernel_us": {k: 1e3 * v for k, v in kt.items()},
+            "launch_overhead_us": lat_us["p50"] - kernels_us}
+
+
+def bench_plain_other(P, torch, ctx, inst, steps, warmup):
+    """The headline configuration under the other instantiation, with its own
+    roofline (the same measurement as the headline)."""
+    cfg = CONFIGS["c2"]
+    log, total, lat, kt = bench_plain(P, torch, ctx, cfg, inst, steps, warmup, False)
+    del log
+    n = cfg["n"]
+    ope = ops_per_entry(inst, cfg["L"])
+    achieved = n * ope / (kt["agg"] / 1e3) / 1e12
+    name = "aes" if inst else "sha"
+    value = n / (total / steps)
+    return {"workload": cfg["name"] + (", POSLO+ (MMO/MDC-2 over AES-128)" if inst else ", POSLO (SHA-256)"),
+            "entries_per_s": value, "ms_per_step": 1e3 * total / steps, "latency_ms": lat_summary(lat),
+            "hashes_per_s": value * hash_calls_per_entry(inst, cfg["L"]),
+            "hash_unit": "AES-128 blocks/s" if inst else "SHA-256 compressions/s", "kernel_ms": kt,
+            "roofline": {"bound": "alu", "kernel": "k_agg_ekeys_" + name, "achieved": achieved,
+                         "peak": INT32_PEAK_TOPS, "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS,
+                         "ops_per_entry": ope, "traffic": traffic_bytes(name),
+                         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                         "algorithmic_bytes": n * cfg["L"], "hbm_GBs": n * cfg["L"] / (kt["agg"] / 1e3) / 1e9}}
 
 
 def bench_distill(P, torch, ctx, inst, steps):
@@ -488,8 +571,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--inst", default="aes", choices=["aes", "sha"])
-    ap.add_argument("--sections", default="plain,distill,batched,serving",
-                    help="comma list of plain, distill, batched, serving (plain always runs)")
+    ap.add_argument("--sections", default="plain,small,other,distill,batched,serving",
+                    help="comma list of plain, small (the 1,024 x 32-byte configuration), other (the headline "
+                         "configuration under the other instantiation), distill, batched, serving (plain always "
+                         "runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
@@ -563,6 +648,11 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, inst, log, args.cpu_seconds)
     del log
     torch.cuda.empty_cache()
+    if "small" in sections:
+        out["small"] = bench_small(P, torch, ctx, inst, 400)
+    if "other" in sections:
+        out["sha" if inst else "aes"] = bench_plain_other(P, torch, ctx, 1 - inst, args.steps, args.warmup)
+        torch.cuda.empty_cache()
     if "distill" in sections:
         out["distill"] = bench_distill(P, torch, ctx, inst, max(2, args.steps // 4))
         torch.cuda.empty_cache()

@@ -191,7 +191,8 @@ int poslo_ctx_set_tuning(poslo_ctx* ctx, int agg_variant, int wg_per_cu);
 /* Per-entry digests e_t mod q (32 bytes LE each) of a batch into e_dev
  * (device, 32*n bytes) and the one-time seeds x_t (16 bytes each) into
  * x_dev (device, 16*n bytes, may be NULL): the per-entry stage of AVer,
- * exposed for distillation tooling and sampled checks.  Asynchronous on
+ * computed by poslo_aver's hot kernel (its default variant and launch
+ * shape) in a form that also stores each entry's values.  Asynchronous on
  * stream, except for the seed-coverage check. */
 int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* msgs, const uint8_t* ds,
                 size_t ds_len, uint8_t* e_dev, uint8_t* x_dev, void* stream);

@@ -13,6 +13,7 @@
 #include "ctx.h"
 #include "aes_perm.h"
 #include "device_entry.h"
+#include "device_verify.h"
 
 namespace poslo {
 
@@ -61,11 +62,11 @@ __device__ __forceinline__ void mdc2_block_perm(const PermTables<NT>& tb, uint32
 // derives x_t only for the final block: about half the live registers, so
 // twice the resident waves where LDS allows.  xf(x) writes x_t.
 template <int NT, bool FAST, bool LEAN, class XF>
-__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const EntryView& v, const XF& xf,
-                                                 uint32_t dig[8]) {
+__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const EntryView& v, const uint8_t* end,
+                                                 const XF& xf, uint32_t dig[8]) {
     uint32_t h[4], hp[4];
     uint64_t b = 0;
-    if (FAST) {
+    if constexpr (FAST) {
         const uint4* p = reinterpret_cast<const uint4*>(v.m);
         uint64_t lines = v.L / 128;
         for (uint64_t ln = 0; ln < lines; ln++) {
@@ -105,20 +106,11 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
         xf(x);
         mdc2_block_perm(tb, h, hp, x, b == 0);  // the final block is x_t
     } else {
+        // any length and alignment: word loads funnel-shifted to the
+        // message's alignment, bounded by the end of the data buffer
         uint32_t x[4];
-        xf(x);
-        uint64_t nb = (v.L + 16 + 15) / 16;
-        for (; b < nb; b++) {
-            uint32_t m[4];
-#pragma unroll
-            for (int w = 0; w < 4; w++) {
-                uint32_t word = 0;
-#pragma unroll
-                for (int k = 0; k < 4; k++) word |= stream_byte_aes(v, x, 16 * b + 4 * w + k) << (8 * k);
-                m[w] = word;
-            }
-            mdc2_block_perm(tb, h, hp, m, b == 0);
-        }
+        digest_mdc2_any_late(tb, v, end, xf, x, dig, Mdc2BlockPerm{});
+        return;
     }
 #pragma unroll
     for (int w = 0; w < 4; w++) {
@@ -127,9 +119,11 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
     }
 }
 
-template <int NT, int BLOCK, bool FAST, bool LEAN, int WPE>
+// EMIT: also store every entry's e_t = H(m_t || x_t) mod q (eight LE words)
+// and x_t (four LE words, when x_out is set); the hashing is the same code.
+template <int NT, int BLOCK, bool FAST, bool LEAN, int WPE, bool EMIT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_agg_ekeys_aes_perm(
-    BatchArgs a, uint32_t* partials) {
+    BatchArgs a, uint32_t* partials, uint32_t* e_out, uint32_t* x_out) {
     // the kernel's only LDS allocation: tables first, then reduction scratch
     __shared__ uint32_t lds[NT * 256 * 64];
     perm_tables_fill<NT>(lds);
@@ -141,14 +135,27 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         const uint64_t t = a.t0 + pos;
         const uint32_t j = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
         const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
+        uint32_t xo[4];
         auto xf = [&](uint32_t x[4]) {
             x[0] = j, x[1] = 0u, x[2] = 0u, x[3] = 0u;
             penc_rk(tb, rk, x);
             x[0] ^= j;
+            if constexpr (EMIT)
+#pragma unroll
+                for (int w = 0; w < 4; w++) xo[w] = x[w];
         };
         uint32_t dig[8];
-        digest_mdc2_perm<NT, FAST, LEAN>(tb, entry_view(a, pos), xf, dig);
+        digest_mdc2_perm<NT, FAST, LEAN>(tb, entry_view(a, pos), a.end, xf, dig);
         acc288_add256(acc, dig);
+        if constexpr (EMIT) {
+            uint32_t e[8];
+            sc_reduce256(e, dig);
+#pragma unroll
+            for (int w = 0; w < 8; w++) e_out[pos * 8 + w] = e[w];
+            if (x_out)
+#pragma unroll
+                for (int w = 0; w < 4; w++) x_out[pos * 4 + w] = xo[w];
+        }
     }
     __syncthreads();  // every lane is done with the tables
     block_reduce288_scratch<BLOCK>(acc, partials + (uint64_t)blockIdx.x * 9, lds);
@@ -173,15 +180,19 @@ size_t agg_aes_lds_bytes(int v) { return (size_t)kVariants[v].nt * 256 * kVarian
     hipLaunchKernelGGL((k_agg_ekeys_aes<NT, C, B, true>), dim3(grid), dim3(B), 0, s, a, partials); \
     break
 
-#define LAUNCHP(NT, B, LEAN, WPE)                                                              \
-    hipLaunchKernelGGL((k_agg_ekeys_aes_perm<NT, B, true, LEAN, WPE>), dim3(grid), dim3(B), 0, s, a, \
-                       partials);                                                                   \
+#define LAUNCHP(NT, B, LEAN, WPE)                                                                      \
+    hipLaunchKernelGGL((k_agg_ekeys_aes_perm<NT, B, true, LEAN, WPE>), dim3(grid), dim3(B), 0, s, a, partials, \
+                       nullptr, nullptr);                                                                   \
     break
+
+int agg_aes_any_block() { return 1024; }
 
 int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* partials, hipStream_t s) {
     const BatchArgs& a = *static_cast<const BatchArgs*>(args);
     if (!fast) {
-        hipLaunchKernelGGL((k_agg_ekeys_aes<4, 1, 256, false>), dim3(grid), dim3(256), 0, s, a, partials);
+        // any layout: the default variant's tables and shape with word loads
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, false, true, 8>), dim3(grid), dim3(1024), 0, s, a,
+                           partials, nullptr, nullptr);
         return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
     }
     switch (v) {
@@ -204,6 +215,20 @@ int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* 
         case 16: LAUNCHP(1, 512, true, 8);
         default: return POSLO_E_INVAL;
     }
+    return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
+}
+
+// The default variant (or the any-layout form) with every entry's e_t and
+// x_t stored: the per-entry outputs of the kernel that AVer runs.
+int launch_agg_aes_emit(bool fast, uint32_t grid, const void* args, uint32_t* partials, uint32_t* e_out,
+                        uint32_t* x_out, hipStream_t s) {
+    const BatchArgs& a = *static_cast<const BatchArgs*>(args);
+    if (fast)
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, true, true, 8, true>), dim3(grid), dim3(1024), 0, s, a,
+                           partials, e_out, x_out);
+    else
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, false, true, 8, true>), dim3(grid), dim3(1024), 0, s, a,
+                           partials, e_out, x_out);
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 

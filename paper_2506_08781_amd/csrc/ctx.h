@@ -34,11 +34,19 @@ const AggVariant& agg_aes_variant(int v);
 int agg_aes_default_variant();
 // launch variant v (fast layout) or the generic-layout kernel
 int launch_agg_aes(int v, bool fast, uint32_t grid, const void* batch_args, uint32_t* partials, hipStream_t s);
+// the default variant (fast layout) or the any-layout form, also storing
+// every entry's e_t mod q (8 words) and x_t (4 words, x_out may be null)
+int launch_agg_aes_emit(bool fast, uint32_t grid, const void* batch_args, uint32_t* partials, uint32_t* e_out,
+                        uint32_t* x_out, hipStream_t s);
+// threads per workgroup of the any-layout form (and of the emit launches)
+int agg_aes_any_block();
 size_t agg_aes_lds_bytes(int v);
 // the POSLO hot kernel (agg_sha.hip): layout 2 = 16-byte aligned fixed
 // length, 1 = 4-byte aligned fixed length, 0 = any
 constexpr int kAggShaBlock = 256;
 int launch_agg_sha(int layout, uint32_t grid, const void* batch_args, uint32_t* partials, hipStream_t s);
+int launch_agg_sha_emit(int layout, uint32_t grid, const void* batch_args, uint32_t* partials, uint32_t* e_out,
+                        uint32_t* x_out, hipStream_t s);
 
 struct KeyEntry {
     std::string pk;

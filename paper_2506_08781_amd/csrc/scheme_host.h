@@ -165,22 +165,32 @@ inline int sr_node(const DsNode* ds, int count, uint64_t ip) {
     return k;
 }
 
-// strict parse of the ds wire format
-inline bool ds_parse(const uint8_t* buf, size_t len, std::vector<DsNode>& out) {
-    out.clear();
+// strict parse of the ds wire format into a fixed array of 32 nodes (no
+// allocation); *count gets the number of nodes
+inline bool ds_parse(const uint8_t* buf, size_t len, DsNode out[32], int* count) {
+    *count = 0;
     if (!buf || len < 1) return false;
     uint32_t cnt = buf[0];
     if (cnt > 32 || len != 1 + 24 * (size_t)cnt) return false;
     for (uint32_t k = 0; k < cnt; k++) {
         const uint8_t* p = buf + 1 + 24 * k;
-        DsNode n;
+        DsNode& n = out[k];
         n.depth = p[0];
         if (p[1] | p[2] | p[3]) return false;
         n.index = load_le32(p + 4);
         if (n.depth > 32 || (n.depth > 0 && n.depth < 32 && (n.index >> (32 - n.depth)))) return false;
         memcpy(n.v, p + 8, 16);
-        out.push_back(n);
     }
+    *count = (int)cnt;
+    return true;
+}
+
+inline bool ds_parse(const uint8_t* buf, size_t len, std::vector<DsNode>& out) {
+    DsNode nodes[32];
+    int cnt = 0;
+    out.clear();
+    if (!ds_parse(buf, len, nodes, &cnt)) return false;
+    out.assign(nodes, nodes + cnt);
     return true;
 }
 

@@ -66,39 +66,7 @@ __global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_firs
     }
 }
 
-// ---------------------------------------------------------------------------
-// per-entry outputs (the hot kernels are in agg_aes.hip and agg_sha.hip)
-// ---------------------------------------------------------------------------
-
 constexpr int kBlock = 256;
-
-// per-entry outputs: e_t mod q (eight LE words) and x_t bytes (four LE words)
-template <bool FAST>
-__global__ __launch_bounds__(kBlock) void k_ekeys(BatchArgs a, uint32_t inst, uint32_t* e_out, uint32_t* x_out) {
-    __shared__ uint32_t lds[4 * 256];
-    lds_tables_fill<4, 1>(lds);
-    __syncthreads();
-    LdsTables<4, 1> tb{lds};
-    for (uint64_t pos = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pos < a.n; pos += (uint64_t)gridDim.x * kBlock) {
-        uint32_t x[4], dig[8], e[8];
-        EntryView v = entry_view(a, pos);
-        if (inst == INST_AES) {
-            one_time_seed_aes(tb, a, pos, x);
-            digest_mdc2<FAST>(tb, v, x, dig);
-        } else {
-            one_time_seed_sha(a, pos, x);
-            digest_sha<FAST>(v, x, dig);
-#pragma unroll
-            for (int w = 0; w < 4; w++) x[w] = bswap32(x[w]);
-        }
-        sc_reduce256(e, dig);
-#pragma unroll
-        for (int w = 0; w < 8; w++) e_out[pos * 8 + w] = e[w];
-        if (x_out)
-#pragma unroll
-            for (int w = 0; w < 4; w++) x_out[pos * 4 + w] = x[w];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // A4 tail + A5: fold the partials, reduce mod q once, aggregate check
@@ -324,7 +292,7 @@ bool params_ok(const poslo_params* p) {
 }
 
 // host-side checks shared by the verifier entry points; fills the kernel
-// argument block and the by-value ds
+// argument block and the by-value ds, sizes the epoch table
 int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds, size_t ds_len,
                   BatchArgs& a, DsArg& dsa, uint32_t& n_epochs) {
     if (!c || !params_ok(prm) || !m) return POSLO_E_INVAL;
@@ -332,11 +300,12 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     uint64_t nmax = 1ull << (prm->log2_n1 + prm->log2_n2);
     if (m->t0 > nmax || m->n > nmax - m->t0) return POSLO_E_INVAL;
     if (m->n >= (1ull << 32)) return POSLO_E_INVAL;  // keeps the lazy sum below 2^288
-    std::vector<hostside::DsNode> nodes;
-    if (!hostside::ds_parse(ds, ds_len, nodes)) return POSLO_E_INVAL;
+    hostside::DsNode nodes[32];
+    int count = 0;
+    if (!hostside::ds_parse(ds, ds_len, nodes, &count)) return POSLO_E_INVAL;
     memset(&dsa, 0, sizeof dsa);
-    dsa.count = (uint32_t)nodes.size();
-    for (size_t k = 0; k < nodes.size(); k++) {
+    dsa.count = (uint32_t)count;
+    for (int k = 0; k < count; k++) {
         dsa.depth[k] = nodes[k].depth;
         dsa.index[k] = nodes[k].index;
         for (int w = 0; w < 4; w++) dsa.v[k][w] = load_le32(nodes[k].v + 4 * w);
@@ -362,11 +331,11 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     uint64_t ne = e_last - a.epoch_first + 1;
     // SR must succeed for every epoch of the batch (bottom is an error)
     for (uint64_t i = a.epoch_first; i <= e_last; i++)
-        if (hostside::sr_node(nodes.data(), (int)nodes.size(), i) < 0) return POSLO_E_SEED;
-    n_epochs = (uint32_t)ne;
+        if (hostside::sr_node(nodes, count, i) < 0) return POSLO_E_SEED;
     int st = ctx_ensure(&c->d_tab, &c->tab_words, (size_t)ne * kEpochWords);
     if (st) return st;
     a.tab = c->d_tab;
+    n_epochs = (uint32_t)ne;
     return POSLO_OK;
 }
 
@@ -398,38 +367,61 @@ static uint32_t variant_wg_per_cu(const poslo_ctx* c, int v) {
     return std::max<uint32_t>(1, std::min(by_lds, by_waves));
 }
 
-// launch the fused per-entry kernel; returns the number of partials written
-static int launch_agg(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const BatchArgs& a,
-                      hipStream_t s, uint32_t* n_part) {
-    *n_part = 0;
-    if (m->n == 0) return POSLO_OK;
-    int st;
+namespace poslo {
+
+// Launch shape of the fused per-entry kernel for a batch: the AES variant
+// (the any-layout form for offsets or unaligned messages), workgroups
+// resident per CU and the grid (at most that many per CU, fewer for small
+// batches).
+struct AggShape {
+    bool fast;
+    int variant;  // AES variant; -1 with fast = false: the any-layout form
+    int sha_layout;
+    uint32_t grid;
+};
+
+AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m) {
+    AggShape g{};
     if (prm->inst == POSLO_INST_AES) {
-        bool fast = fast_layout(m, 16);
-        int v = fast ? (c->agg_variant >= 0 ? c->agg_variant : agg_aes_default_variant()) : 0;
-        uint32_t block = fast ? (uint32_t)agg_aes_variant(v).block : 256;
+        g.fast = fast_layout(m, 16);
+        g.variant = g.fast ? (c->agg_variant >= 0 ? c->agg_variant : agg_aes_default_variant()) : -1;
+        // the any-layout form shares the default variant's shape
+        const int vs = g.fast ? g.variant : agg_aes_default_variant();
+        uint32_t block = g.fast ? (uint32_t)agg_aes_variant(vs).block : (uint32_t)agg_aes_any_block();
         uint64_t want = (m->n + block - 1) / block;
-        uint64_t cap = (uint64_t)c->num_cu * (fast ? variant_wg_per_cu(c, v) : 8);
-        uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
-        if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)grid * 9))) return st;
-        prof_begin(c, POSLO_KT_AGG, s);
-        if ((st = launch_agg_aes(v, fast, grid, &a, c->d_part, s))) return st;
-        prof_end(c, POSLO_KT_AGG, s);
-        *n_part = grid;
+        uint64_t cap = (uint64_t)c->num_cu * variant_wg_per_cu(c, vs);
+        g.grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
     } else {
+        g.sha_layout = fast_layout(m, 16) ? 2 : fast_layout(m, 4) ? 1 : 0;
         uint64_t want = (m->n + kAggShaBlock - 1) / kAggShaBlock;
         // four resident workgroups per CU measured best for the SHA-256 kernel
         uint64_t cap = (uint64_t)c->num_cu * (c->wg_per_cu > 0 ? c->wg_per_cu : 4);
-        uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
-        if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)grid * 9))) return st;
-        prof_begin(c, POSLO_KT_AGG, s);
-        if ((st = launch_agg_sha(fast_layout(m, 16) ? 2 : fast_layout(m, 4) ? 1 : 0, grid, &a, c->d_part, s)))
-            return st;
-        prof_end(c, POSLO_KT_AGG, s);
-        *n_part = grid;
+        g.grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
     }
+    return g;
+}
+
+// launch the fused per-entry kernel (g.grid partials of 9 words into
+// partials); with e_out set, the emit form that also stores every entry's
+// e_t mod q and x_t
+int launch_agg(poslo_ctx* c, const poslo_params* prm, const AggShape& g, const BatchArgs& a, uint32_t* partials,
+               uint32_t* e_out, uint32_t* x_out, hipStream_t s) {
+    int st;
+    prof_begin(c, POSLO_KT_AGG, s);
+    if (prm->inst == POSLO_INST_AES) {
+        if (e_out && g.fast && g.variant != agg_aes_default_variant()) return POSLO_E_INVAL;
+        st = e_out ? launch_agg_aes_emit(g.fast, g.grid, &a, partials, e_out, x_out, s)
+                   : launch_agg_aes(g.variant, g.fast, g.grid, &a, partials, s);
+    } else {
+        st = e_out ? launch_agg_sha_emit(g.sha_layout, g.grid, &a, partials, e_out, x_out, s)
+                   : launch_agg_sha(g.sha_layout, g.grid, &a, partials, s);
+    }
+    if (st) return st;
+    prof_end(c, POSLO_KT_AGG, s);
     return POSLO_OK;
 }
+
+}  // namespace poslo
 
 // host-side tag checks: s < q and R decodes (done while the GPU hashes)
 static void tag_checks(const uint8_t tag[64], FinalArgs& f) {
@@ -471,7 +463,12 @@ int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
     if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
     prof_end(c, POSLO_KT_SEED, s);
     uint32_t n_part = 0;
-    if ((st = launch_agg(c, prm, m, a, s, &n_part))) return st;
+    if (m->n > 0) {
+        const AggShape g = agg_shape(c, prm, m);
+        if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)g.grid * 9))) return st;
+        if ((st = launch_agg(c, prm, g, a, c->d_part, nullptr, nullptr, s))) return st;
+        n_part = g.grid;
+    }
     FinalArgs f;
     f.partials = c->d_part;
     f.n_part = n_part;
@@ -512,17 +509,12 @@ extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_ms
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
-    uint64_t want = (m->n + kBlock - 1) / kBlock;
-    uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->num_cu * 8));
-    bool fast = fast_layout(m, prm->inst == POSLO_INST_AES ? 16 : 4);
-    prof_begin(c, POSLO_KT_EKEYS, s);
-    if (fast)
-        hipLaunchKernelGGL(k_ekeys<true>, dim3(grid), dim3(kBlock), 0, s, a, prm->inst, (uint32_t*)e_dev,
-                           (uint32_t*)x_dev);
-    else
-        hipLaunchKernelGGL(k_ekeys<false>, dim3(grid), dim3(kBlock), 0, s, a, prm->inst, (uint32_t*)e_dev,
-                           (uint32_t*)x_dev);
-    HIP_TRY(hipGetLastError());
-    prof_end(c, POSLO_KT_EKEYS, s);
-    return POSLO_OK;
+    // the AVer hot kernel's default shape, in its emit form
+    const int saved = c->agg_variant;
+    c->agg_variant = -1;
+    const AggShape g = agg_shape(c, prm, m);
+    c->agg_variant = saved;
+    if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)g.grid * 9))) return st;
+    return launch_agg(c, prm, g, a, c->d_part, (uint32_t*)e_dev, (uint32_t*)x_dev, s);
 }
+

@@ -2,14 +2,11 @@
 the oracle, through the C ABI.
 
 Inputs are seeded synthetic messages; keys, signatures, ds and tags for the
-small cases come from the oracle's own signer.  At the full 2^20 x 256-byte
-size the oracle checks sampled entries one by one, and the accept bit is
-checked on an honest batch (signed by the library's host signer, whose
-output equals the oracle's byte for byte in the CPU tests) and on a batch
-with one flipped message bit."""
+small cases come from the oracle's own signer.  The full 2^20 x 256-byte
+configuration is compared with the oracle over the whole batch in
+test_gpu_fullsize.py."""
 
 import functools
-import random
 
 import numpy as np
 import pytest
@@ -139,47 +136,6 @@ def test_empty_batch_and_errors(P, gpu):
     # a malformed ds is an invalid argument
     with pytest.raises(P.PosloError):
         P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds + b"\0", tag)
-
-
-@pytest.mark.parametrize("inst", [1, 0])
-def test_full_size_2p20_x_256(P, gpu, inst):
-    """2^20 entries of 256-byte messages, n2 = 256, n1 = 4096: the large
-    plain configuration, in the launch configuration the benchmark times."""
-    from oracle import oracle as O
-    torch, ctx = gpu
-    n, L, l1, l2 = 1 << 20, 256, 12, 8
-    print(f"full size inst {inst}: generate", flush=True)
-    arr = synthlog.messages_fixed(2, n, L)
-    params = P.make_params(inst, l1, l2)
-    sk, pk = P.poslo_kg(params, synthlog.key_seed_bytes(0x20))
-    sigs = P.poslo_sig_batch(sk, arr)
-    ds = P.poslo_ds_export(sk)
-    tag = P.poslo_agg(sigs)
-    d = torch.from_numpy(arr).cuda()
-    print("full size: aver", flush=True)
-    acc, e = P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)
-    assert acc
-    eg, xg = P.poslo_ekeys(ctx, params, P.make_msgs(d), ds)
-    # property: the lazy aggregate equals the sum of per-entry residues
-    ev = eg.cpu().numpy()
-    total = 0
-    for w in range(4):
-        limb = ev[:, 8 * w:8 * w + 8].copy().view("<u8")[:, 0]
-        total += int(limb.astype(object).sum()) << (64 * w)
-    assert total % O.Q == int.from_bytes(e, "little")
-    # sampled entries against the oracle, one by one
-    prm = O.Params(inst, l1, l2)
-    rng = random.Random(99)
-    sample = sorted({0, 255, 256, n - 1} | {rng.randrange(n) for _ in range(252)})
-    xv = xg.cpu().numpy()
-    dsn = O.ds_decode(ds)
-    for t in sample:
-        x = O.one_time_seed(inst, O.SR(inst, dsn, t >> l2), t & 255)
-        assert bytes(xv[t]) == x == bytes(sigs[t][64:80])
-        assert int.from_bytes(bytes(ev[t]), "little") == O.digest_int(inst, bytes(arr[t]), x) % O.Q
-    # one flipped message bit makes the aggregate reject
-    d[n // 3, 17] ^= 4
-    assert not P.poslo_aver(ctx, params, pk, P.make_msgs(d), ds, tag)[0]
 
 
 def test_every_tuning_variant_agrees(P, gpu):

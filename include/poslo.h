@@ -157,6 +157,27 @@ int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32],
                const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                uint8_t e_out[32]);
 
+/* AVer that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as poslo_aver.
+ * Its scratch (per-epoch seed rows, per-workgroup partial sums, result
+ * words) is a fixed device array of POSLO_AVER_FIXED_SCRATCH_BYTES that each
+ * GPU the library runs on holds until the process ends; the launch shape is
+ * poslo_aver's default with the grid capped at 4096 workgroups.  Limits and
+ * extra errors: E_INVAL when the batch spans more than
+ * POSLO_AVER_FIXED_MAX_EPOCHS epochs, or when pk's table is not resident in
+ * the context (load it first with poslo_ctx_keys_load; keys are evicted
+ * only by later loads beyond the context's key capacity).  Every call on
+ * one GPU uses the same array: calls that overlap in time on one GPU (any
+ * context, any stream, any host thread) race and give wrong results; calls
+ * that follow each other are independent (nothing in the array needs to
+ * start at zero). */
+#define POSLO_AVER_FIXED_MAX_EPOCHS 16384
+#define POSLO_AVER_FIXED_SCRATCH_BYTES 3293440
+int poslo_aver_fixed(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
+                     const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
+                     uint8_t e_out[32]);
+
 /* Kernel timing (opt-in): for each kernel whose bit (1 << POSLO_KT_*) is set
  * in the mask given to poslo_ctx_profile, the context records HIP events on
  * the launch stream around its launches and accumulates their elapsed time

@@ -28,6 +28,8 @@ POSLO_E_SEED = -4
 POSLO_E_ENCODING = -5
 POSLO_E_EXHAUSTED = -6
 POSLO_E_BUSY = -7
+# limit of the allocation-free AVer entry point (include/poslo.h)
+POSLO_AVER_FIXED_MAX_EPOCHS = 16384
 
 
 class PosloError(RuntimeError):
@@ -134,6 +136,8 @@ def lib():
             "poslo_ctx_create": ([_I, P(_VP)], _I),
             "poslo_ctx_destroy": ([_VP], None),
             "poslo_aver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _U8P, _SZ, _U8P, _VP, P(_I), _VP], _I),
+            "poslo_aver_fixed": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _U8P, _SZ, _U8P, _VP, P(_I), _VP],
+                                 _I),
             "poslo_ekeys": ([_VP, P(poslo_params), P(poslo_msgs), _U8P, _SZ, _VP, _VP, _VP], _I),
             "poslo_ctx_profile": ([_VP, _I], _I),
             "poslo_ctx_kernel_time": ([_VP, _I, _I, P(ctypes.c_double), P(_U64)], _I),
@@ -387,6 +391,18 @@ def poslo_aver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ds: 
     st = lib().poslo_aver(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs), bytes(ds), len(ds),
                           bytes(tag), _stream_ptr(stream), ctypes.byref(acc), e)
     _check(st, "poslo_aver")
+    return bool(acc.value), e.raw
+
+
+def poslo_aver_fixed(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ds: bytes, tag: bytes,
+                     stream=None) -> tuple[bool, bytes]:
+    """poslo_aver without device allocation (fixed per-device scratch; pk
+    must be resident, see poslo_ctx_keys_load).  Returns (accept, e mod q)."""
+    acc = ctypes.c_int()
+    e = ctypes.create_string_buffer(32)
+    st = lib().poslo_aver_fixed(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs), bytes(ds),
+                                len(ds), bytes(tag), _stream_ptr(stream), ctypes.byref(acc), e)
+    _check(st, "poslo_aver_fixed")
     return bool(acc.value), e.raw
 
 

@@ -78,6 +78,10 @@ struct poslo_ctx {
     size_t part_words = 0;
     uint32_t* d_result = nullptr;
     uint32_t* h_result = nullptr;  // pinned
+    // this device's copy of the fixed scratch array of the allocation-free
+    // AVer entry point (its device address; shared by every context on the
+    // device, kept until the process ends)
+    uint32_t* d_fixed = nullptr;
     // comb tables: G (static) and per-key Y, LRU-bounded
     uint32_t* d_gtable = nullptr;
     uint32_t* d_gtable_wide = nullptr;  // built on first use (ctx_gtable_wide)
@@ -125,9 +129,10 @@ struct DsArg;
 bool params_ok(const poslo_params* p);
 // host-side checks of a batch (parameters, ds parse, SR coverage of every
 // epoch); fills the kernel argument block and the by-value ds, sizes the
-// epoch table
+// epoch table (the context's, or fixed_tab of fixed_epochs rows when set)
 int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds, size_t ds_len,
-                  BatchArgs& a, DsArg& dsa, uint32_t& n_epochs);
+                  BatchArgs& a, DsArg& dsa, uint32_t& n_epochs, uint32_t* fixed_tab = nullptr,
+                  uint64_t fixed_epochs = 0);
 bool fast_layout(const poslo_msgs* m, uint64_t align);
 int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s);
 

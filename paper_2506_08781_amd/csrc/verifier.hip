@@ -189,6 +189,45 @@ const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status) {
 
 }  // namespace poslo
 
+namespace poslo {
+
+// ---------------------------------------------------------------------------
+// fixed scratch of the allocation-free AVer entry point: per-epoch rows,
+// per-workgroup partials and the result words, in one device array that
+// every GPU the library runs on holds until the process ends
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kFixedMaxEpochs = POSLO_AVER_FIXED_MAX_EPOCHS;
+constexpr uint32_t kFixedMaxGrid = 4096;
+constexpr size_t kFixedTabWords = (size_t)kFixedMaxEpochs * kEpochWords;
+constexpr size_t kFixedPartWords = (size_t)kFixedMaxGrid * 9;
+constexpr size_t kFixedWords = kFixedTabWords + kFixedPartWords + 64;
+static_assert(kFixedWords * 4 == (size_t)POSLO_AVER_FIXED_SCRATCH_BYTES, "scratch size in the header");
+
+static __device__ __align__(256) uint32_t scratch[kFixedWords];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_fixed_mu;
+static uint32_t* g_fixed[kMaxDevices];  // device address of `scratch` on each device
+
+// the device address of this device's `scratch`, looked up once per device
+// (the array's name is not a device address in host code); the device must
+// be current
+static int fixed_scratch_init(int device, uint32_t** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return POSLO_E_DEVICE;
+    std::lock_guard<std::mutex> g(g_fixed_mu);
+    if (!g_fixed[device]) {
+        uint32_t* p = nullptr;
+        if (hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return POSLO_E_DEVICE;
+        g_fixed[device] = p;
+    }
+    *out = g_fixed[device];
+    return POSLO_OK;
+}
+
+}  // namespace poslo
+
 // ===========================================================================
 // entry points
 // ===========================================================================
@@ -222,7 +261,7 @@ extern "C" int poslo_ctx_create(int device, poslo_ctx** out) {
     uint8_t genc[32];
     ge_encode(genc, G);
     std::vector<uint32_t> gok;
-    if (build_comb_tables(genc, 1, c->d_gtable, gok) || !gok[0]) {
+    if (build_comb_tables(genc, 1, c->d_gtable, gok) || !gok[0] || fixed_scratch_init(device, &c->d_fixed)) {
         poslo_ctx_destroy(c);
         return POSLO_E_DEVICE;
     }
@@ -292,9 +331,11 @@ bool params_ok(const poslo_params* p) {
 }
 
 // host-side checks shared by the verifier entry points; fills the kernel
-// argument block and the by-value ds, sizes the epoch table
+// argument block and the by-value ds.  The epoch table goes to the
+// context's buffer (grown as needed), or to fixed_tab when it is set (no
+// allocation; E_INVAL beyond fixed_epochs epochs).
 int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds, size_t ds_len,
-                  BatchArgs& a, DsArg& dsa, uint32_t& n_epochs) {
+                  BatchArgs& a, DsArg& dsa, uint32_t& n_epochs, uint32_t* fixed_tab, uint64_t fixed_epochs) {
     if (!c || !params_ok(prm) || !m) return POSLO_E_INVAL;
     if (m->n > 0 && !m->data) return POSLO_E_INVAL;
     uint64_t nmax = 1ull << (prm->log2_n1 + prm->log2_n2);
@@ -332,9 +373,14 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     // SR must succeed for every epoch of the batch (bottom is an error)
     for (uint64_t i = a.epoch_first; i <= e_last; i++)
         if (hostside::sr_node(nodes, count, i) < 0) return POSLO_E_SEED;
-    int st = ctx_ensure(&c->d_tab, &c->tab_words, (size_t)ne * kEpochWords);
-    if (st) return st;
-    a.tab = c->d_tab;
+    if (fixed_tab) {
+        if (ne > fixed_epochs) return POSLO_E_INVAL;
+        a.tab = fixed_tab;
+    } else {
+        int st = ctx_ensure(&c->d_tab, &c->tab_words, (size_t)ne * kEpochWords);
+        if (st) return st;
+        a.tab = c->d_tab;
+    }
     n_epochs = (uint32_t)ne;
     return POSLO_OK;
 }
@@ -518,3 +564,58 @@ extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_ms
     return launch_agg(c, prm, g, a, c->d_part, (uint32_t*)e_dev, (uint32_t*)x_dev, s);
 }
 
+// AVer with no device allocation: the epoch rows, partials and result words
+// live in this device's fixed scratch array, the key's table must already be
+// resident, and the launch shape is the default one (grid capped at the
+// array's partial slots).
+extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
+                                const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
+                                uint8_t e_out[32]) {
+    if (!c || !pk || !tag || !accept) return POSLO_E_INVAL;
+    *accept = 0;
+    if (!c->d_fixed) return POSLO_E_DEVICE;
+    uint32_t* fx_tab = c->d_fixed;
+    uint32_t* fx_part = c->d_fixed + kFixedTabWords;
+    uint32_t* fx_result = fx_part + kFixedPartWords;
+    BatchArgs a;
+    DsArg dsa;
+    uint32_t n_epochs;
+    int st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs, fx_tab, kFixedMaxEpochs);
+    if (st) return st;
+    // the key's comb table must be resident (poslo_ctx_keys_load): a lookup
+    // that neither builds nor reorders anything
+    const KeyEntry* key = nullptr;
+    for (const KeyEntry& k : c->keys)
+        if (memcmp(k.pk.data(), pk, 32) == 0) {
+            key = &k;
+            break;
+        }
+    if (!key) return POSLO_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(c->device));
+    if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
+    uint32_t n_part = 0;
+    if (m->n > 0) {
+        AggShape g = agg_shape(c, prm, m);
+        g.grid = std::min(g.grid, kFixedMaxGrid);
+        st = prm->inst == POSLO_INST_AES ? launch_agg_aes(g.variant, g.fast, g.grid, &a, fx_part, s)
+                                          : launch_agg_sha(g.sha_layout, g.grid, &a, fx_part, s);
+        if (st) return st;
+        n_part = g.grid;
+    }
+    FinalArgs f;
+    f.partials = fx_part;
+    f.n_part = n_part;
+    f.ty = key->d_table;
+    f.tg = c->d_gtable;
+    f.result = fx_result;
+    tag_checks(tag, f);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->h_result, fx_result, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *accept = c->h_result[8] ? 1 : 0;
+    if (e_out)
+        for (int w = 0; w < 8; w++) store_le32(e_out + 4 * w, c->h_result[w]);
+    return POSLO_OK;
+}

@@ -683,11 +683,32 @@ def posloc_kg(params: Params, seed: bytes):
     r = derive(params.inst, seed, b"r", 0)[:16]
     out = bytearray(pk_y)
     for i in range(params.n1):
-        ri = 0
-        for j in range(params.n2):
-            ri = (ri + posloc_r(params.inst, r, i, j)) % Q
-        out += encode(scalar_mult(ri, G))
+        out += posloc_commitment(params, r, i)
     return CSigner(params=params, seed=seed, y=signer_f.y, root=signer_f.root, r=r), bytes(out)
+
+
+def posloc_commitment(params: Params, r: bytes, i: int) -> bytes:
+    """enc(R~_i) with R~_i = (sum over j of r_i^j mod q) * G (Kg's loop body)."""
+    ri = 0
+    for j in range(params.n2):
+        ri = (ri + posloc_r(params.inst, r, i, j)) % Q
+    return encode(scalar_mult(ri, G))
+
+
+def posloc_signer_at(params: Params, seed: bytes, i: int) -> CSigner:
+    """The POSLO-C signer's state after epochs 0 .. i-1 are signed, through
+    Sig's state transitions alone (SSO for each of those epochs, the epoch
+    counter at i); signing from it continues the sequence exactly.  The
+    public key is not built (its commitments do not enter Sig)."""
+    if not 0 <= i <= params.n1:
+        raise ValueError("epoch index out of range")
+    signer_f, _ = kg(params, seed)
+    cs = CSigner(params=params, seed=seed, y=signer_f.y, root=signer_f.root,
+                 r=derive(params.inst, seed, b"r", 0)[:16])
+    for e in range(i):
+        cs.ds, _ = SSO(params.inst, cs.ds, cs.root, params.log2_n1, e)
+    cs.i = i
+    return cs
 
 
 def posloc_pk_parts(params: Params, pk: bytes):

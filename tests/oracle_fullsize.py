@@ -78,8 +78,6 @@ class FullCase:
     aver_honest: bool = True                       # AVer of the honest batch
 
 
-_W = {}
-
 
 def _bpv_part(args):
     from oracle import oracle as O
@@ -201,3 +199,130 @@ def full_case(inst: int, n: int, L: int, log2_n1: int, log2_n2: int, key_first: 
                     x_t=x_t, e=e, plan=plan, cmsgs=cmsgs, csigs=csigs, invalid=invalid, span=span,
                     umbrellas=umbrellas, valid_tag=valid_tag, e_corrupt=e_c,
                     aver_corrupt=O.aggregate_check(pk, e_c, tag), aver_honest=O.aggregate_check(pk, e, tag))
+
+
+# ---------------------------------------------------------------------------
+# POSLO-C: one signature per epoch
+# ---------------------------------------------------------------------------
+
+@dataclass
+class FullCaseC:
+    inst: int
+    log2_n1: int
+    log2_n2: int
+    n: int
+    L: int
+    n_u: int
+    pk: bytes
+    ds: bytes
+    msgs: np.ndarray                # (n, L) honest messages
+    s_epochs: bytes                 # 32 bytes per epoch, honest
+    s_total: bytes                  # Agg of every epoch's signature
+    e: int                          # e~ of the honest batch
+    aver_honest: bool
+    plan: list = field(default_factory=list)      # (epoch, bit) over m_i || s~_i
+    cmsgs: np.ndarray | None = None
+    cs_epochs: bytes = b""
+    invalid: list = field(default_factory=list)   # epochs the oracle finds invalid
+    span: int = 0
+    umbrellas: list = field(default_factory=list)
+    valid_tag: bytes = b""
+    e_corrupt: int = 0
+    aver_corrupt: bool = True
+
+
+def _c_commitments(args):
+    from oracle import oracle as O
+    inst, log2_n1, log2_n2, r, epochs = args
+    prm = O.Params(inst, log2_n1, log2_n2)
+    return [O.posloc_commitment(prm, r, i) for i in epochs]
+
+
+def _c_chunk(args):
+    from oracle import oracle as O
+    (inst, log2_n1, log2_n2, seed, pk, ds, msg_seed, L, a, b, plan) = args
+    prm = O.Params(inst, log2_n1, log2_n2)
+    n2 = prm.n2
+    msgs = [bytes(r) for r in synthlog.messages_fixed(msg_seed, (b - a) * n2, L, t0=a * n2)]
+    signer = O.posloc_signer_at(prm, seed, a)
+    s_list = [O.posloc_sig(signer, msgs[p * n2:(p + 1) * n2])[0] for p in range(b - a)]
+    dsn = O.ds_decode(ds)
+    raw = 0
+    for p in range(b - a):
+        x0 = O.SR(inst, dsn, a + p)
+        for j in range(n2):
+            raw += O.digest_int(inst, msgs[p * n2 + j], O.one_time_seed(inst, x0, j))
+    cm, cs = list(msgs), list(s_list)
+    raw_c = raw
+    flipped_m = {}
+    for i, bit in plan:
+        p = i - a
+        blob = bytearray(b"".join(msgs[p * n2:(p + 1) * n2]) + s_list[p])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        x0 = O.SR(inst, dsn, i)
+        for j in range(n2):
+            m_new = bytes(blob[j * L:(j + 1) * L])
+            if m_new != msgs[p * n2 + j]:
+                x = O.one_time_seed(inst, x0, j)
+                raw_c += O.digest_int(inst, m_new, x) - O.digest_int(inst, msgs[p * n2 + j], x)
+                cm[p * n2 + j] = m_new
+                flipped_m[a * n2 + p * n2 + j] = m_new
+        cs[p] = bytes(blob[n2 * L:])
+    ccd = O.posloc_distill(prm, pk, cm, cs, a, ds, 1)
+    return dict(a=a, b=b, s=b"".join(s_list), cs=b"".join(cs), raw=raw, raw_c=raw_c,
+                bad=[i for i, _ in ccd.invalid], umb=ccd.umbrellas[0][0], cm=flipped_m)
+
+
+@functools.lru_cache(maxsize=None)
+def full_case_c(inst: int, n: int, L: int, log2_n1: int, log2_n2: int, key_first: int, msg_seed: int,
+                n_u: int, flip_seed: int, k_flips: int, nproc: int | None = None) -> FullCaseC:
+    """Oracle-signed POSLO-C batch of n entries (whole epochs) with its
+    oracle results, and the same batch with k_flips epochs corrupted by one
+    flipped bit uniform over the epoch's message bytes and its signature
+    (synthlog.corruption_plan over epochs), distilled into n_u umbrellas of
+    epochs."""
+    from oracle import oracle as O
+    prm = O.Params(inst, log2_n1, log2_n2)
+    seed = synthlog.key_seed_bytes(key_first)
+    k = n // prm.n2
+    if k * prm.n2 != n:
+        raise ValueError("whole epochs only")
+    st0 = O.posloc_signer_at(prm, seed, 0)
+    Yb = O.encode(O.scalar_mult(st0.y, O.G))
+    ds = O.ds_encode(O.posloc_signer_at(prm, seed, k).ds)
+    span = max(1, -(-k // n_u))
+    plan = synthlog.corruption_plan(flip_seed, k, k_flips, 8 * (prm.n2 * L + 32)) if k_flips else []
+    nproc = nproc or workers()
+    with _pool(nproc) as pool:
+        eps = list(range(prm.n1))
+        parts = pool.map(_c_commitments, [(inst, log2_n1, log2_n2, st0.r, eps[i::nproc]) for i in range(nproc)])
+        com = [None] * prm.n1
+        for i in range(nproc):
+            for e, c in zip(eps[i::nproc], parts[i]):
+                com[e] = c
+        pk = Yb + b"".join(com)
+        jobs = [(inst, log2_n1, log2_n2, seed, pk, ds, msg_seed, L, a, min(k, a + span),
+                 [(e, bit) for e, bit in plan if a <= e < min(k, a + span)]) for a in range(0, k, span)]
+        res = pool.map(_c_chunk, jobs, chunksize=1)
+    msgs = synthlog.messages_fixed(msg_seed, n, L)
+    s_epochs = b"".join(r["s"] for r in res)
+    cs_epochs = b"".join(r["cs"] for r in res)
+    cmsgs = msgs.copy()
+    for r in res:
+        for t, m in r["cm"].items():
+            cmsgs[t] = np.frombuffer(m, dtype=np.uint8)
+    e = sum(r["raw"] for r in res) % O.Q
+    e_c = sum(r["raw_c"] for r in res) % O.Q
+    s_total = O.posloc_agg_s([s_epochs[32 * i:32 * i + 32] for i in range(k)])
+    R = O.IDENTITY
+    for i in range(k):
+        R = O.point_add(R, O.decode(com[i]))
+    R_tag = O.encode(R)
+    umbrellas = [r["umb"] for r in res]
+    return FullCaseC(inst=inst, log2_n1=log2_n1, log2_n2=log2_n2, n=n, L=L, n_u=n_u, pk=pk, ds=ds, msgs=msgs,
+                     s_epochs=s_epochs, s_total=s_total, e=e,
+                     aver_honest=O.aggregate_check(Yb, e, s_total + R_tag), plan=plan, cmsgs=cmsgs,
+                     cs_epochs=cs_epochs, invalid=sorted(i for r in res for i in r["bad"]), span=span,
+                     umbrellas=umbrellas, valid_tag=O.agg(umbrellas), e_corrupt=e_c,
+                     aver_corrupt=O.aggregate_check(
+                         Yb, e_c, O.posloc_agg_s([cs_epochs[32 * i:32 * i + 32] for i in range(k)]) + R_tag))

@@ -47,3 +47,35 @@ def test_pooled_case_equals_sequential_oracle(O):
     assert case.e_corrupt == O.ekeys_sum(prm, cm, 0, ds)
     assert case.aver_corrupt == O.aver(prm, pk, cm, 0, ds, tag)
     assert isinstance(case.msgs, np.ndarray)
+
+
+def test_pooled_posloc_case_equals_sequential_oracle(O):
+    import oracle_fullsize as F
+    inst, l1, l2, L, key_first, msg_seed, n_u, flip_seed, kf = 0, 3, 2, 20, 0x33, 12, 3, 13, 2
+    k = 7
+    n = k * 4
+    c = F.full_case_c(inst, n, L, l1, l2, key_first, msg_seed, n_u, flip_seed, kf, nproc=3)
+    prm = O.Params(inst, l1, l2)
+    msgs = [bytes(r) for r in synthlog.messages_fixed(msg_seed, n, L)]
+    pk, s_list, ds, _ = O.posloc_sign_batch(prm, synthlog.key_seed_bytes(key_first), msgs)
+    assert c.pk[:32 + 32 * prm.n1] == pk and c.ds == ds and c.s_epochs == b"".join(s_list)
+    eps = [(i, msgs[i * 4:(i + 1) * 4]) for i in range(k)]
+    assert c.e == O.ekeys_sum(prm, msgs, 0, ds)
+    assert c.aver_honest == O.posloc_aver(prm, pk, eps, ds, c.s_total) is True
+    # the corruption: one bit of each planned epoch's messages || signature
+    plan = synthlog.corruption_plan(flip_seed, k, kf, 8 * (4 * L + 32))
+    assert c.plan == plan
+    cm, cs = list(msgs), list(s_list)
+    for i, bit in plan:
+        blob = bytearray(b"".join(cm[i * 4:(i + 1) * 4]) + cs[i])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        cm[i * 4:(i + 1) * 4] = [bytes(blob[j * L:(j + 1) * L]) for j in range(4)]
+        cs[i] = bytes(blob[4 * L:])
+    assert [bytes(r) for r in c.cmsgs] == cm and c.cs_epochs == b"".join(cs)
+    ccd = O.posloc_distill(prm, pk, cm, cs, 0, ds, n_u)
+    assert c.invalid == [i for i, _ in ccd.invalid] == sorted(i for i, _ in plan)
+    assert c.span == ccd.span and c.umbrellas == [u for u, _ in ccd.umbrellas]
+    assert c.valid_tag == ccd.valid_tag
+    assert c.e_corrupt == O.ekeys_sum(prm, cm, 0, ds)
+    cep = [(i, cm[i * 4:(i + 1) * 4]) for i in range(k)]
+    assert c.aver_corrupt == O.posloc_aver(prm, pk, cep, ds, O.posloc_agg_s(cs))

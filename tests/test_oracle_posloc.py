@@ -131,3 +131,16 @@ def test_signer_limits(O):
     signer2, _ = O.posloc_kg(prm2, synthlog.key_seed_bytes(1))
     with pytest.raises(ValueError):
         O.posloc_sig(signer2, msgs[:1])      # not a whole epoch
+
+
+def test_signer_at_and_commitments_continue_kg_and_sig(O):
+    prm, msgs, pk, s_list, ds, signer = _epochs(O, 1, 4, 16, 2, 2)
+    seed = synthlog.key_seed_bytes(0x50)
+    Yb, Rs = O.posloc_pk_parts(prm, pk)
+    st = O.posloc_signer_at(prm, seed, 0)
+    assert [O.posloc_commitment(prm, st.r, i) for i in range(prm.n1)] == Rs
+    for i in (0, 1, 3):
+        st = O.posloc_signer_at(prm, seed, i)
+        got = [O.posloc_sig(st, msgs[e * prm.n2:(e + 1) * prm.n2]) for e in range(i, 4)]
+        assert [g[0] for g in got] == s_list[i:], i
+        assert got[-1][1] == ds

@@ -76,19 +76,29 @@ typedef struct poslo_params {
     uint32_t bpv_k;   /* 16 in the paper */
 } poslo_params;
 
-/* A batch of consecutive log entries t0 .. t0+n-1 in device memory.
- * Fixed length: offsets == NULL, entry p occupies data[p*msg_len ..
- * (p+1)*msg_len).  Variable length: offsets (device, n+1 u64) gives entry p
- * as data[offsets[p] .. offsets[p+1]), msg_len is ignored.  data_bytes is the
+/* A batch of consecutive log entries t0 .. t0+n-1.  Fixed length:
+ * offsets == NULL, entry p occupies data[p*msg_len .. (p+1)*msg_len).
+ * Variable length: offsets (n+1 u64) gives entry p as
+ * data[offsets[p] .. offsets[p+1]), msg_len is ignored.  data_bytes is the
  * size of the data buffer (0 = unknown); when known, unaligned messages are
- * read with aligned word loads that stay inside it. */
+ * read with aligned word loads that stay inside it.
+ * host = 0: data and offsets are device pointers.  host = 1: they are host
+ * pointers (pinned memory makes the copy asynchronous; pageable memory
+ * works, with a synchronous copy), and the call copies the batch (and, for
+ * Distill, the signatures, which are then host pointers too) into the
+ * context's device staging buffers on its stream before hashing:
+ * data_bytes (or n*msg_len, or offsets[n]) bytes, the offsets, 80*n
+ * signature bytes.  The host buffers must stay unchanged until the call
+ * returns.  poslo_aver_fixed takes device batches only. */
 typedef struct poslo_msgs {
-    const uint8_t* data;     /* device */
-    const uint64_t* offsets; /* device or NULL */
+    const uint8_t* data;     /* device, or host when host = 1 */
+    const uint64_t* offsets; /* same memory as data, or NULL */
     uint64_t msg_len;
     uint64_t n;
     uint64_t t0;
     uint64_t data_bytes;
+    uint32_t host;           /* 0: device pointers; 1: host pointers */
+    uint32_t reserved;       /* 0 */
 } poslo_msgs;
 
 /* Library version string. */
@@ -250,12 +260,124 @@ int poslo_ccd_import(const uint8_t* buf, size_t len, poslo_ccd** out);
 void poslo_ccd_free(poslo_ccd* ccd);
 
 /* SeBVer over distilled data (the same batch: msgs t0 and n must match the
- * CCD).  mode 'V': one bit, AVer of all entries not in CCD^i against CCD^v.
+ * CCD; a POSLO-C CCD is refused, see poslo_c_sebver).  mode 'V': one bit,
+ * AVer of all entries not in CCD^i against CCD^v.
  * 'U': one bit per umbrella, AVer of its range minus CCD^i against its tag.
  * 'I': one bit per CCD^i entry, its individual verification (1 = valid).
  * bits: host, cap bytes; *n_bits gets the count. */
 int poslo_sebver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
                  const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream);
+
+/* ------------------------------------------------------------- POSLO-C */
+
+/* The coarse-grained variant POSLO-C (paper section "Coarse-grained
+ * signer-optimal POSLO (POSLO-C)", figure "Coarse-grained signer-optimal
+ * POSLO"): the public key holds Y and one aggregate commitment R~_i per
+ * epoch, and a signature covers a whole epoch: s~_i = sum over the epoch's
+ * entries of r_i^j - e_i^j * y.  Byte formats (readings; the paper fixes
+ * none): pk = enc(Y) || enc(R~_0) || ... || enc(R~_{n1-1}), 32 * (1 + n1)
+ * bytes; an epoch signature is LE32B(s~_i), with the signer's ds after the
+ * epoch.  Batches are whole epochs (msgs->t0 and msgs->n multiples of n2;
+ * E_INVAL otherwise, the paper's "return bottom"). */
+typedef struct poslo_c_key poslo_c_key;
+
+/* Load a POSLO-C public key (host, pk_len = 32 * (1 + 2^log2_n1) bytes,
+ * log2_n1 <= 20) into the context's device: Y's fixed-base table, the epoch
+ * commitments decoded once (kept as affine points on the device and as
+ * prefix sums on the host).  E_ENCODING if Y or an R~_i is not a point
+ * encoding.  Freed with poslo_c_key_free.  Synchronous. */
+int poslo_c_key_load(poslo_ctx* ctx, const poslo_params* params, const uint8_t* pk, size_t pk_len,
+                     poslo_c_key** out);
+void poslo_c_key_free(poslo_c_key* key);
+
+/* POSLO-C.AVer over the batch's epochs: e~ = sum over its entries of
+ * H(m_i^j || PRF_0(SR(ds, i) || j)) mod q, R~ = Agg of the epochs' R~_i in
+ * pk, accept iff s < q and R~ = e~*Y + s*G.  s: host, 32 bytes, the Agg
+ * (sum mod q) of the epochs' signatures.  Same errors and e_out as
+ * poslo_aver. */
+int poslo_c_aver(poslo_ctx* ctx, const poslo_params* params, const poslo_c_key* key, const poslo_msgs* msgs,
+                 const uint8_t* ds, size_t ds_len, const uint8_t s[32], void* stream, int* accept,
+                 uint8_t e_out[32]);
+
+/* POSLO-C.Distill: every epoch of the batch is verified on its own against
+ * (s~_i, R~_i); valid epochs are aggregated into CCD^v and umbrellas of
+ * U = ceil(k / n_umbrella) epochs (k epochs in the batch), invalid ones are
+ * listed.  s_epochs: host, 32 bytes per epoch in order.  The CCD is
+ * coarse: poslo_ccd_invalid gives sorted epoch indices i,
+ * poslo_ccd_invalid_sig gives LE32B(s~_i) || enc(R~_i) || 16 zero bytes,
+ * poslo_ccd_umbrellas' span counts epochs.  Errors as poslo_aver. */
+int poslo_c_distill(poslo_ctx* ctx, const poslo_params* params, const poslo_c_key* key, const poslo_msgs* msgs,
+                    const uint8_t* s_epochs, const uint8_t* ds, size_t ds_len, uint32_t n_umbrella, void* stream,
+                    poslo_ccd** out);
+
+/* POSLO-C.SeBVer over a coarse CCD of the same batch.  'V': AVer of every
+ * epoch not in CCD^i against CCD^v; 'U': one bit per umbrella, AVer of its
+ * epochs minus CCD^i against its tag; 'I': one bit per CCD^i epoch, AVer of
+ * that epoch against its own (s~_i, R~_i).  bits: host, cap bytes. */
+int poslo_c_sebver(poslo_ctx* ctx, const poslo_params* params, const poslo_c_key* key, const poslo_msgs* msgs,
+                   const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream);
+
+/* ------------------------------------------------------- streaming audit */
+
+/* AVer over a log fed in chunks, for logs too large to hold on the device
+ * at once (paper section "Experimental Evaluation on GPUs": a 1 TB log
+ * audited in 1 GB chunks).  e = sum of H(m_t || x_t) mod q is additive, so
+ * each chunk's digests fold into a running e mod q on the device and the
+ * check R = e*Y + s*G runs once, at poslo_audit_finish.  The running state
+ * (key, ds, first and next entry, e mod q) exports to bytes and resumes in
+ * another process or on another device.
+ * All calls on one audit use one stream (the chunks' kernels share the
+ * audit's buffers in stream order) and one host thread. */
+typedef struct poslo_audit poslo_audit;
+
+/* Start an audit of entries t0, t0+1, ... of the signer with public key pk
+ * (host, 32 bytes), whose ds (host) covers every epoch to be fed.  Errors:
+ * E_INVAL, E_ENCODING (pk not a point). */
+int poslo_audit_begin(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const uint8_t* ds,
+                      size_t ds_len, uint64_t t0, poslo_audit** out);
+/* Add the next chunk: chunk->t0 must equal the audit's next entry.  Device
+ * chunks are read by kernels queued on stream, so they must stay unchanged
+ * until the stream has passed them.  Host chunks (chunk->host = 1; pinned
+ * memory makes the copy asynchronous) are copied on the audit's own copy
+ * stream into one of two staging buffers, so that a chunk's copy overlaps
+ * the previous chunk's hashing; a host chunk must stay unchanged until the
+ * next call on the audit returns.  Returns without waiting for the device.
+ * E_SEED if the ds does not cover an epoch of the chunk. */
+int poslo_audit_feed(poslo_audit* audit, const poslo_msgs* chunk, void* stream);
+/* The next entry index (the first entry not yet fed). */
+int poslo_audit_position(const poslo_audit* audit, uint64_t* t_next);
+/* The check against the aggregate tag (host, 64 bytes) of entries t0 ..
+ * t_next-1: *accept and, if e_out is set, e mod q (32 bytes).  Synchronous;
+ * the audit stays usable (more chunks can follow for a later tag). */
+int poslo_audit_finish(poslo_audit* audit, const uint8_t tag[64], void* stream, int* accept, uint8_t e_out[32]);
+/* The running state as bytes: "PAUD", u32 version 1, u32 inst, log2_n1,
+ * log2_n2, pk (32), u64 t0, u64 t_next, e mod q (32, LE), u32 ds length,
+ * ds.  *len gets the size; E_INVAL when cap is too small.  Synchronizes
+ * stream. */
+int poslo_audit_export(poslo_audit* audit, void* stream, uint8_t* buf, size_t cap, size_t* len);
+/* An audit continued from exported state; params must match it. */
+int poslo_audit_resume(poslo_ctx* ctx, const uint8_t* state, size_t len, const poslo_params* params,
+                       poslo_audit** out);
+void poslo_audit_free(poslo_audit* audit);
+
+/* ------------------------------------------------ measurement utilities */
+
+/* Sustained issue rate of one 32-bit integer VALU instruction kind on the
+ * device: waves_per_simd (1-8) waves of 64 lanes on every SIMD, each lane
+ * running eight independent chains of iters * 16 instructions; the rate is
+ * lane operations per second (a v_mad_u64_u32 counts as one).  This is the
+ * measured ceiling beside the nominal 4 cycles per wave64 instruction that
+ * roofline fractions are quoted against.  Synchronous. */
+enum {
+    POSLO_PROBE_XOR = 0,      /* v_xor_b32 */
+    POSLO_PROBE_PERM = 1,     /* v_perm_b32 (T-table addresses, byte merges) */
+    POSLO_PROBE_BITOP3 = 2,   /* v_bitop3_b32 (three-input xor) */
+    POSLO_PROBE_ADD3 = 3,     /* v_add3_u32 (SHA-256 sums) */
+    POSLO_PROBE_ALIGNBIT = 4, /* v_alignbit_b32 (rotations) */
+    POSLO_PROBE_MAD64 = 5     /* v_mad_u64_u32 (field multiplication) */
+};
+int poslo_valu_probe(int device, int op, uint32_t waves_per_simd, uint32_t iters, double* lane_ops_per_s,
+                     double* ms);
 
 /* ------------------------------------------- synthetic data on the device */
 
@@ -442,10 +564,12 @@ typedef struct poslo_server_stats {
 /* device: HIP device index.  E_INVAL on a bad configuration. */
 int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out);
 /* Register n keys (ids and 32-byte encodings, host).  E_ENCODING if one is
- * not a point (none is registered then); an id registered again is
- * replaced (requests already queued keep the key they were submitted
- * with).  Synchronous.  E_BUSY when the key-state array must grow while
- * requests are queued or in flight: register keys before serving. */
+ * not a point (none is registered then).  An id registered again is
+ * replaced, with a fresh aggregate state, but only while none of its
+ * requests is queued or in flight (E_BUSY otherwise, and nothing is
+ * registered).  Synchronous.  E_BUSY also when the key-state array must
+ * grow while requests are queued or in flight: register keys before
+ * serving. */
 int poslo_server_register_keys(poslo_server* srv, const uint32_t* ids, const uint8_t* pks, size_t n);
 /* Queue a request; never waits for the device.  *ticket identifies its
  * result.  The request's own inputs are checked here: E_INVAL for an

@@ -45,7 +45,8 @@ class poslo_params(ctypes.Structure):
 
 class poslo_msgs(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("msg_len", ctypes.c_uint64),
-                ("n", ctypes.c_uint64), ("t0", ctypes.c_uint64), ("data_bytes", ctypes.c_uint64)]
+                ("n", ctypes.c_uint64), ("t0", ctypes.c_uint64), ("data_bytes", ctypes.c_uint64),
+                ("host", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class poslo_sign_job(ctypes.Structure):
@@ -154,6 +155,21 @@ def lib():
             "poslo_ccd_free": ([_VP], None),
             "poslo_sebver": ([_VP, P(poslo_params), _U8P, P(poslo_msgs), _VP, ctypes.c_char, _VP, _SZ, P(_SZ),
                               _VP], _I),
+            "poslo_c_key_load": ([_VP, P(poslo_params), _U8P, _SZ, P(_VP)], _I),
+            "poslo_c_key_free": ([_VP], None),
+            "poslo_c_aver": ([_VP, P(poslo_params), _VP, P(poslo_msgs), _U8P, _SZ, _U8P, _VP, P(_I), _VP], _I),
+            "poslo_c_distill": ([_VP, P(poslo_params), _VP, P(poslo_msgs), _U8P, _U8P, _SZ, _U32, _VP, P(_VP)],
+                                _I),
+            "poslo_c_sebver": ([_VP, P(poslo_params), _VP, P(poslo_msgs), _VP, ctypes.c_char, _VP, _SZ, P(_SZ),
+                                _VP], _I),
+            "poslo_audit_begin": ([_VP, P(poslo_params), _U8P, _U8P, _SZ, _U64, P(_VP)], _I),
+            "poslo_audit_feed": ([_VP, P(poslo_msgs), _VP], _I),
+            "poslo_audit_position": ([_VP, P(_U64)], _I),
+            "poslo_audit_finish": ([_VP, _U8P, _VP, P(_I), _VP], _I),
+            "poslo_audit_export": ([_VP, _VP, _VP, _SZ, P(_SZ)], _I),
+            "poslo_audit_resume": ([_VP, _U8P, _SZ, P(poslo_params), P(_VP)], _I),
+            "poslo_audit_free": ([_VP], None),
+            "poslo_valu_probe": ([_I, _I, _U32, _U32, P(ctypes.c_double), P(ctypes.c_double)], _I),
             "poslo_synth_messages": ([_U32, P(poslo_msgs), _VP, _VP], _I),
             "poslo_gpu_keys_create": ([_VP, P(poslo_params), _U8P, _U32, P(_VP), _VP], _I),
             "poslo_gpu_keys_free": ([_VP], None),
@@ -368,8 +384,13 @@ def _stream_ptr(stream):
 
 
 def make_msgs(data, offsets=None, msg_len: int = 0, n: int | None = None, t0: int = 0) -> poslo_msgs:
-    """Batch descriptor over torch CUDA tensors: data uint8 (n, L) or flat,
-    offsets uint64 (int64) (n+1) or None."""
+    """Batch descriptor over torch tensors: data uint8 (n, L) or flat,
+    offsets uint64 (int64) (n+1) or None.  CUDA tensors give a device batch;
+    CPU tensors (pinned for an asynchronous copy) a host batch, which the
+    library copies to the device itself."""
+    host = 0 if data.is_cuda else 1
+    if offsets is not None and offsets.is_cuda != data.is_cuda:
+        raise ValueError("data and offsets must be in the same memory")
     if offsets is None:
         if data.dim() == 2:
             n_, L = data.shape
@@ -377,9 +398,10 @@ def make_msgs(data, offsets=None, msg_len: int = 0, n: int | None = None, t0: in
             if n is None:
                 raise ValueError("n is required for a flat fixed-length buffer")
             n_, L = n, msg_len
-        return poslo_msgs(data.data_ptr() if data.numel() else None, None, L, n_, t0, data.numel())
+        return poslo_msgs(data.data_ptr() if data.numel() else None, None, L, n_, t0, data.numel(), host)
     n_ = offsets.numel() - 1
-    return poslo_msgs(data.data_ptr() if data.numel() else None, offsets.data_ptr(), 0, n_, t0, data.numel())
+    return poslo_msgs(data.data_ptr() if data.numel() else None, offsets.data_ptr(), 0, n_, t0, data.numel(),
+                      host)
 
 
 def poslo_aver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, ds: bytes, tag: bytes,
@@ -475,7 +497,8 @@ def poslo_ccd_import(data: bytes) -> CCD:
 
 def poslo_distill(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, sigs, ds: bytes,
                   n_umbrella: int, stream=None) -> CCD:
-    """Distill a device-resident batch; sigs is a CUDA uint8 tensor of 80*n bytes."""
+    """Distill a batch; sigs is a uint8 tensor of 80*n bytes in the batch's
+    memory (CUDA for a device batch, CPU for a host batch)."""
     h = ctypes.c_void_p()
     st = lib().poslo_distill(ctx.handle, ctypes.byref(params), bytes(pk), ctypes.byref(msgs),
                              sigs.data_ptr() if sigs.numel() else None, bytes(ds), len(ds), n_umbrella,
@@ -493,6 +516,131 @@ def poslo_sebver(ctx: Ctx, params: poslo_params, pk: bytes, msgs: poslo_msgs, cc
                             mode.encode(), bits, cap, ctypes.byref(nb), _stream_ptr(stream))
     _check(st, "poslo_sebver")
     return [bool(b) for b in bits.raw[:nb.value]]
+
+
+# ------------------------------------------------------------- POSLO-C
+
+class CKey:
+    """Owns a poslo_c_key* (a POSLO-C public key loaded on a device)."""
+
+    def __init__(self, handle):
+        self.handle = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and h.value and _lib is not None:
+            _lib.poslo_c_key_free(h)
+            self.handle = None
+
+
+def poslo_c_key_load(ctx: Ctx, params: poslo_params, pk: bytes) -> CKey:
+    h = ctypes.c_void_p()
+    _check(lib().poslo_c_key_load(ctx.handle, ctypes.byref(params), bytes(pk), len(pk), ctypes.byref(h)),
+           "poslo_c_key_load")
+    return CKey(h.value)
+
+
+def poslo_c_aver(ctx: Ctx, params: poslo_params, key: CKey, msgs: poslo_msgs, ds: bytes, s: bytes,
+                 stream=None) -> tuple[bool, bytes]:
+    """POSLO-C aggregate verification of whole epochs against the aggregate
+    s (32 bytes).  Returns (accept, e mod q)."""
+    acc = ctypes.c_int()
+    e = ctypes.create_string_buffer(32)
+    st = lib().poslo_c_aver(ctx.handle, ctypes.byref(params), key.handle, ctypes.byref(msgs), bytes(ds), len(ds),
+                            bytes(s), _stream_ptr(stream), ctypes.byref(acc), e)
+    _check(st, "poslo_c_aver")
+    return bool(acc.value), e.raw
+
+
+def poslo_c_distill(ctx: Ctx, params: poslo_params, key: CKey, msgs: poslo_msgs, s_epochs: bytes, ds: bytes,
+                    n_umbrella: int, stream=None) -> CCD:
+    """POSLO-C Distill; s_epochs holds 32 bytes per epoch of the batch."""
+    h = ctypes.c_void_p()
+    st = lib().poslo_c_distill(ctx.handle, ctypes.byref(params), key.handle, ctypes.byref(msgs), bytes(s_epochs),
+                               bytes(ds), len(ds), n_umbrella, _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "poslo_c_distill")
+    return CCD(h.value)
+
+
+def poslo_c_sebver(ctx: Ctx, params: poslo_params, key: CKey, msgs: poslo_msgs, ccd: CCD, mode: str,
+                   stream=None) -> list[bool]:
+    cap = max(1, len(ccd.invalid()), len(ccd.umbrellas()[0]))
+    bits = ctypes.create_string_buffer(cap)
+    nb = ctypes.c_size_t()
+    st = lib().poslo_c_sebver(ctx.handle, ctypes.byref(params), key.handle, ctypes.byref(msgs), ccd.handle,
+                              mode.encode(), bits, cap, ctypes.byref(nb), _stream_ptr(stream))
+    _check(st, "poslo_c_sebver")
+    return [bool(b) for b in bits.raw[:nb.value]]
+
+
+# ------------------------------------------------------- streaming audit
+
+class Audit:
+    """Owns a poslo_audit* (AVer over a log fed in chunks)."""
+
+    def __init__(self, handle):
+        self.handle = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and h.value and _lib is not None:
+            _lib.poslo_audit_free(h)
+            self.handle = None
+
+    def feed(self, msgs: poslo_msgs, stream=None) -> None:
+        _check(lib().poslo_audit_feed(self.handle, ctypes.byref(msgs), _stream_ptr(stream)), "poslo_audit_feed")
+
+    def position(self) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().poslo_audit_position(self.handle, ctypes.byref(t)), "poslo_audit_position")
+        return t.value
+
+    def finish(self, tag: bytes, stream=None) -> tuple[bool, bytes]:
+        acc = ctypes.c_int()
+        e = ctypes.create_string_buffer(32)
+        _check(lib().poslo_audit_finish(self.handle, bytes(tag), _stream_ptr(stream), ctypes.byref(acc), e),
+               "poslo_audit_finish")
+        return bool(acc.value), e.raw
+
+    def export(self, stream=None) -> bytes:
+        ln = ctypes.c_size_t()
+        lib().poslo_audit_export(self.handle, _stream_ptr(stream), None, 0, ctypes.byref(ln))
+        buf = ctypes.create_string_buffer(ln.value)
+        _check(lib().poslo_audit_export(self.handle, _stream_ptr(stream), buf, len(buf), ctypes.byref(ln)),
+               "poslo_audit_export")
+        return buf.raw[:ln.value]
+
+
+def poslo_audit_begin(ctx: Ctx, params: poslo_params, pk: bytes, ds: bytes, t0: int = 0) -> Audit:
+    h = ctypes.c_void_p()
+    _check(lib().poslo_audit_begin(ctx.handle, ctypes.byref(params), bytes(pk), bytes(ds), len(ds), t0,
+                                   ctypes.byref(h)), "poslo_audit_begin")
+    return Audit(h.value)
+
+
+def poslo_audit_resume(ctx: Ctx, state: bytes, params: poslo_params) -> Audit:
+    h = ctypes.c_void_p()
+    _check(lib().poslo_audit_resume(ctx.handle, bytes(state), len(state), ctypes.byref(params), ctypes.byref(h)),
+           "poslo_audit_resume")
+    return Audit(h.value)
+
+
+# ------------------------------------------------- measurement utilities
+
+PROBE_OPS = {"xor": 0, "perm": 1, "bitop3": 2, "add3": 3, "alignbit": 4, "mad64": 5}
+
+
+def poslo_valu_probe(op: str, waves_per_simd: int = 8, iters: int = 4096, device: int = 0) -> tuple[float, float]:
+    """Sustained lane operations per second of one VALU instruction kind at
+    the given occupancy, and the timed launch's milliseconds."""
+    rate = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(lib().poslo_valu_probe(device, PROBE_OPS[op], waves_per_simd, iters, ctypes.byref(rate),
+                                  ctypes.byref(ms)), "poslo_valu_probe")
+    return rate.value, ms.value
 
 
 # --------------------------------------------------- device-side test data

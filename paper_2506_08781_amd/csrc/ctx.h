@@ -136,4 +136,36 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
 bool fast_layout(const poslo_msgs* m, uint64_t align);
 int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s);
 
+// Launch shape of the fused per-entry kernel for a batch: the AES variant
+// (the any-layout form for offsets or unaligned messages), the SHA-256
+// layout, and the grid (the resident workgroups of every CU, fewer for small
+// batches)
+struct AggShape {
+    bool fast;
+    int variant;  // AES variant; -1 with fast = false: the any-layout form
+    int sha_layout;
+    uint32_t grid;
+};
+AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m);
+// launch the fused per-entry kernel (g.grid partials of 9 words into
+// partials); with e_out set, the emit form that also stores every entry's
+// e_t mod q and x_t (AES: the default variant's shape only)
+int launch_agg(poslo_ctx* c, const poslo_params* prm, const AggShape& g, const BatchArgs& a, uint32_t* partials,
+               uint32_t* e_out, uint32_t* x_out, hipStream_t s);
+
+// context scratch slots (ctx_scratch) of the POSLO-C entry points and of
+// the staging copies of host-resident batches
+constexpr int kSlotCEkeys = 20, kSlotCSigs = 21, kSlotCBits = 22;
+constexpr int kSlotStageData = 28, kSlotStageOffsets = 29, kSlotStageSigs = 30;
+
+// a host-resident batch (m->host) copied into the staging slots on s, dm
+// its device view; a device batch is passed through.  With sigs_out, the
+// batch's signatures (80 per entry, same memory kind) are staged too.
+int stage_msgs(poslo_ctx* c, const poslo_msgs* m, hipStream_t s, poslo_msgs& dm, const uint8_t* sigs,
+               const uint8_t** sigs_out);
+// the final fold of n_part partials (9 words each), mod q and the
+// aggregate check against tag; synchronizes s and returns accept and e
+int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uint32_t n_part,
+                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32]);
+
 }  // namespace poslo

@@ -22,6 +22,7 @@
 #include <new>
 #include <vector>
 
+#include "ccd.h"
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
@@ -391,16 +392,6 @@ __global__ void k_gather_sigs(const uint64_t* idx, uint64_t count, uint64_t t0, 
 
 using namespace poslo;
 
-struct poslo_ccd {
-    uint32_t inst = 0, log2_n1 = 0, log2_n2 = 0;
-    uint64_t t0 = 0, n = 0, span = 0;
-    std::vector<uint8_t> ds;
-    uint8_t valid_tag[64] = {};
-    std::vector<uint8_t> umb_tags;      // 64 bytes per umbrella
-    std::vector<uint64_t> invalid;      // sorted global indices t
-    std::vector<uint8_t> invalid_sigs;  // 80 bytes per invalid entry
-};
-
 namespace {
 
 #define HIP_TRY(x)                                     \
@@ -420,18 +411,23 @@ int checked_sigs(const uint8_t* sigs, uint64_t n) {
 
 }  // namespace
 
-extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
-                             const uint8_t* sigs, const uint8_t* ds, size_t ds_len, uint32_t n_umbrella, void* stream,
-                             poslo_ccd** out) {
-    if (!out || !pk || n_umbrella == 0) return POSLO_E_INVAL;
+extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m_in,
+                             const uint8_t* sigs_in, const uint8_t* ds, size_t ds_len, uint32_t n_umbrella,
+                             void* stream, poslo_ccd** out) {
+    if (!out || !pk || !m_in || n_umbrella == 0) return POSLO_E_INVAL;
     *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (m_in->n && !sigs_in) return POSLO_E_INVAL;
+    poslo_msgs dm;
+    const uint8_t* sigs;
+    int st = stage_msgs(c, m_in, s, dm, sigs_in, &sigs);
+    if (st) return st;
+    const poslo_msgs* m = &dm;
     BatchArgs a;
     DsArg dsa;
     uint32_t n_epochs;
-    int st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs);
-    if (st) return st;
+    if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
     if ((st = checked_sigs(sigs, m->n))) return st;
-    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     const KeyEntry* key = ctx_key(c, pk, &st);
     if (!key) return st;
@@ -637,10 +633,12 @@ extern "C" int poslo_ccd_export(const poslo_ccd* ccd, uint8_t* buf, size_t cap, 
     if (!ccd || !len) return POSLO_E_INVAL;
     std::vector<uint8_t> o;
     o.insert(o.end(), {'P', 'C', 'C', 'D'});
-    put32(o, 1);
+    // version 1: POSLO-F; version 2: POSLO-C, with a granularity word
+    put32(o, ccd->coarse ? 2 : 1);
     put32(o, ccd->inst);
     put32(o, ccd->log2_n1);
     put32(o, ccd->log2_n2);
+    if (ccd->coarse) put32(o, 1);
     put64(o, ccd->t0);
     put64(o, ccd->n);
     put64(o, ccd->span);
@@ -665,12 +663,16 @@ extern "C" int poslo_ccd_import(const uint8_t* buf, size_t len, poslo_ccd** out)
     *out = nullptr;
     Reader r{buf, len};
     uint8_t magic[4];
-    if (!r.bytes(magic, 4) || memcmp(magic, "PCCD", 4) != 0 || r.u32() != 1) return POSLO_E_INVAL;
+    if (!r.bytes(magic, 4) || memcmp(magic, "PCCD", 4) != 0) return POSLO_E_INVAL;
+    const uint32_t version = r.u32();
+    if (version != 1 && version != 2) return POSLO_E_INVAL;
     poslo_ccd* c = new (std::nothrow) poslo_ccd();
     if (!c) return POSLO_E_NOMEM;
     c->inst = r.u32();
     c->log2_n1 = r.u32();
     c->log2_n2 = r.u32();
+    if (version == 2 && r.u32() != 1) r.ok = false;
+    c->coarse = version == 2 ? 1 : 0;
     c->t0 = r.u64();
     c->n = r.u64();
     c->span = r.u64();
@@ -708,13 +710,17 @@ extern "C" int poslo_ccd_import(const uint8_t* buf, size_t len, poslo_ccd** out)
     return POSLO_OK;
 }
 
-// skip bitmap of the CCD's invalid entries over batch positions (device)
+// skip bitmap of the CCD's invalid entries over batch positions (device);
+// a coarse CCD's invalid epochs cover all their entries
 static int upload_skip(poslo_ctx* c, const poslo_ccd* ccd, hipStream_t s, const uint32_t** out) {
     uint64_t words = (ccd->n + 31) / 32;
     std::vector<uint32_t> bm(std::max<uint64_t>(words, 1), 0);
     for (uint64_t t : ccd->invalid) {
-        uint64_t p = t - ccd->t0;
-        bm[p >> 5] |= 1u << (p & 31);
+        // items outside the batch make the CCD malformed
+        const uint64_t unit = ccd->coarse ? ccd->log2_n2 : 0;
+        if (t < (ccd->t0 >> unit) || t - (ccd->t0 >> unit) >= (ccd->n >> unit)) return POSLO_E_INVAL;
+        const uint64_t first = t << unit, count = 1ull << unit;
+        for (uint64_t p = first - ccd->t0; p < first - ccd->t0 + count; p++) bm[p >> 5] |= 1u << (p & 31);
     }
     void* d;
     int st = scratch(c, S_AUX, bm.size() * 4, &d);
@@ -730,14 +736,29 @@ namespace poslo {
 int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m, const uint8_t* ds,
               size_t ds_len, const uint8_t tag[64], void* stream, const uint32_t* skip, int* accept,
               uint8_t e_out[32]);
+int sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
+                const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream);
 }
 
 extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
                             const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream) {
-    if (!c || !prm || !pk || !m || !ccd || !n_bits) return POSLO_E_INVAL;
+    if (!ccd || ccd->coarse) return POSLO_E_INVAL;
+    return sebver_impl(c, prm, pk, m, ccd, mode, bits, cap, n_bits, stream);
+}
+
+// SeBVer over a CCD; a coarse (POSLO-C) CCD takes modes V and U only, with
+// its invalid epochs left out entry by entry and umbrellas of span epochs
+int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m_in,
+                       const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream) {
+    if (!c || !prm || !pk || !m_in || !ccd || !n_bits) return POSLO_E_INVAL;
+    poslo_msgs dm;
+    int st0 = stage_msgs(c, m_in, (hipStream_t)stream, dm, nullptr, nullptr);
+    if (st0) return st0;
+    const poslo_msgs* m = &dm;
     if (m->t0 != ccd->t0 || m->n != ccd->n || prm->inst != ccd->inst || prm->log2_n2 != ccd->log2_n2 ||
         prm->log2_n1 != ccd->log2_n1)
         return POSLO_E_INVAL;
+    if (ccd->coarse && mode != 'V' && mode != 'U') return POSLO_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     int st;
@@ -763,7 +784,7 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
         *n_bits = n_umb;
         if (!bits || cap < n_umb) return POSLO_E_INVAL;
         if (n_umb == 0) return POSLO_OK;
-        uint64_t span = ccd->span;
+        uint64_t span = ccd->coarse ? ccd->span << ccd->log2_n2 : ccd->span;
         if (span == 0 || (m->n + span - 1) / span != n_umb) return POSLO_E_INVAL;
         const uint32_t* skip = nullptr;
         if (!ccd->invalid.empty() && (st = upload_skip(c, ccd, s, &skip))) return st;

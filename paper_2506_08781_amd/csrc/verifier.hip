@@ -415,17 +415,6 @@ static uint32_t variant_wg_per_cu(const poslo_ctx* c, int v) {
 
 namespace poslo {
 
-// Launch shape of the fused per-entry kernel for a batch: the AES variant
-// (the any-layout form for offsets or unaligned messages), workgroups
-// resident per CU and the grid (at most that many per CU, fewer for small
-// batches).
-struct AggShape {
-    bool fast;
-    int variant;  // AES variant; -1 with fast = false: the any-layout form
-    int sha_layout;
-    uint32_t grid;
-};
-
 AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m) {
     AggShape g{};
     if (prm->inst == POSLO_INST_AES) {
@@ -447,9 +436,6 @@ AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs
     return g;
 }
 
-// launch the fused per-entry kernel (g.grid partials of 9 words into
-// partials); with e_out set, the emit form that also stores every entry's
-// e_t mod q and x_t
 int launch_agg(poslo_ctx* c, const poslo_params* prm, const AggShape& g, const BatchArgs& a, uint32_t* partials,
                uint32_t* e_out, uint32_t* x_out, hipStream_t s) {
     int st;
@@ -490,33 +476,57 @@ namespace poslo {
 
 // AVer over a batch, optionally leaving out the entries set in a device
 // bitmap over batch positions (SeBVer mode V)
-int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m, const uint8_t* ds,
-              size_t ds_len, const uint8_t tag[64], void* stream, const uint32_t* skip, int* accept,
-              uint8_t e_out[32]) {
-    if (!pk || !tag || !accept) return POSLO_E_INVAL;
-    *accept = 0;
-    BatchArgs a;
-    DsArg dsa;
-    uint32_t n_epochs;
-    int st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs);
-    if (st) return st;
-    a.skip = skip;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipSetDevice(c->device));
-    const KeyEntry* key = ctx_key(c, pk, &st);
-    if (!key) return st;
-    prof_begin(c, POSLO_KT_SEED, s);
-    if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
-    prof_end(c, POSLO_KT_SEED, s);
-    uint32_t n_part = 0;
-    if (m->n > 0) {
-        const AggShape g = agg_shape(c, prm, m);
-        if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)g.grid * 9))) return st;
-        if ((st = launch_agg(c, prm, g, a, c->d_part, nullptr, nullptr, s))) return st;
-        n_part = g.grid;
+// Host-resident batches: copy the messages (and offsets) into the
+// context's staging buffers on the stream; dm then describes the device
+// copy.  A device batch is passed through.  sigs (80 per entry, may be null)
+// follow the batch's memory kind and are staged when sigs_out is given.
+int stage_msgs(poslo_ctx* c, const poslo_msgs* m, hipStream_t s, poslo_msgs& dm, const uint8_t* sigs,
+               const uint8_t** sigs_out) {
+    if (!c || !m) return POSLO_E_INVAL;
+    dm = *m;
+    if (sigs_out) *sigs_out = sigs;
+    if (!m->host) return POSLO_OK;
+    dm.host = 0;
+    if (m->n == 0) return POSLO_OK;
+    if (!m->data) return POSLO_E_INVAL;
+    uint64_t need;
+    if (m->offsets) {
+        need = m->offsets[m->n];
+        if (m->offsets[0] > need) return POSLO_E_INVAL;
+    } else {
+        if (m->msg_len && m->n > UINT64_MAX / m->msg_len) return POSLO_E_INVAL;
+        need = m->n * m->msg_len;
     }
+    uint64_t bytes = m->data_bytes ? m->data_bytes : need;
+    if (bytes < need) return POSLO_E_INVAL;
+    int st;
+    void* d;
+    if (hipSetDevice(c->device) != hipSuccess) return POSLO_E_DEVICE;
+    if ((st = ctx_scratch(c, kSlotStageData, std::max<uint64_t>(bytes, 1), &d))) return st;
+    HIP_TRY(hipMemcpyAsync(d, m->data, bytes, hipMemcpyHostToDevice, s));
+    dm.data = (const uint8_t*)d;
+    dm.data_bytes = bytes;
+    if (m->offsets) {
+        void* o;
+        if ((st = ctx_scratch(c, kSlotStageOffsets, (m->n + 1) * 8, &o))) return st;
+        HIP_TRY(hipMemcpyAsync(o, m->offsets, (m->n + 1) * 8, hipMemcpyHostToDevice, s));
+        dm.offsets = (const uint64_t*)o;
+    }
+    if (sigs_out && sigs) {
+        void* g;
+        if ((st = ctx_scratch(c, kSlotStageSigs, m->n * 80, &g))) return st;
+        HIP_TRY(hipMemcpyAsync(g, sigs, m->n * 80, hipMemcpyHostToDevice, s));
+        *sigs_out = (const uint8_t*)g;
+    }
+    return POSLO_OK;
+}
+
+// The final fold of n_part partials, mod q and the check R = e*Y + s*G
+// against the tag, with accept and e mod q read back (synchronizes s)
+int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uint32_t n_part,
+                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32]) {
     FinalArgs f;
-    f.partials = c->d_part;
+    f.partials = partials;
     f.n_part = n_part;
     f.ty = key->d_table;
     f.tg = c->d_gtable;
@@ -535,6 +545,37 @@ int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
     return POSLO_OK;
 }
 
+int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m_in, const uint8_t* ds,
+              size_t ds_len, const uint8_t tag[64], void* stream, const uint32_t* skip, int* accept,
+              uint8_t e_out[32]) {
+    if (!pk || !tag || !accept) return POSLO_E_INVAL;
+    *accept = 0;
+    hipStream_t s = (hipStream_t)stream;
+    poslo_msgs dm;
+    int st = stage_msgs(c, m_in, s, dm, nullptr, nullptr);
+    if (st) return st;
+    const poslo_msgs* m = &dm;
+    BatchArgs a;
+    DsArg dsa;
+    uint32_t n_epochs;
+    if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
+    a.skip = skip;
+    HIP_TRY(hipSetDevice(c->device));
+    const KeyEntry* key = ctx_key(c, pk, &st);
+    if (!key) return st;
+    prof_begin(c, POSLO_KT_SEED, s);
+    if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
+    prof_end(c, POSLO_KT_SEED, s);
+    uint32_t n_part = 0;
+    if (m->n > 0) {
+        const AggShape g = agg_shape(c, prm, m);
+        if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)g.grid * 9))) return st;
+        if ((st = launch_agg(c, prm, g, a, c->d_part, nullptr, nullptr, s))) return st;
+        n_part = g.grid;
+    }
+    return final_check(c, key, c->d_part, n_part, tag, s, accept, e_out);
+}
+
 }  // namespace poslo
 
 extern "C" int poslo_aver(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
@@ -543,16 +584,19 @@ extern "C" int poslo_aver(poslo_ctx* c, const poslo_params* prm, const uint8_t p
     return aver_impl(c, prm, pk, m, ds, ds_len, tag, stream, nullptr, accept, e_out);
 }
 
-extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds,
+extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m_in, const uint8_t* ds,
                            size_t ds_len, uint8_t* e_dev, uint8_t* x_dev, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    poslo_msgs dm;
+    int st = stage_msgs(c, m_in, s, dm, nullptr, nullptr);
+    if (st) return st;
+    const poslo_msgs* m = &dm;
     BatchArgs a;
     DsArg dsa;
     uint32_t n_epochs;
-    int st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs);
-    if (st) return st;
+    if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
     if (m->n == 0) return POSLO_OK;
     if (!e_dev) return POSLO_E_INVAL;
-    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
     // the AVer hot kernel's default shape, in its emit form
@@ -571,7 +615,7 @@ extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_ms
 extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m,
                                 const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                                 uint8_t e_out[32]) {
-    if (!c || !pk || !tag || !accept) return POSLO_E_INVAL;
+    if (!c || !pk || !tag || !accept || !m || m->host) return POSLO_E_INVAL;
     *accept = 0;
     if (!c->d_fixed) return POSLO_E_DEVICE;
     uint32_t* fx_tab = c->d_fixed;

@@ -13,7 +13,12 @@ oracle's results on the host cores in umbrella-sized chunks).  Compared:
 * Distill of the corrupted batch into 64 umbrellas: the sorted invalid set
   (the oracle verifies every corrupted entry individually, plus a sample of
   the others), CCD^v and all 64 umbrella tags (the oracle's Agg over each
-  umbrella's valid signatures), and SeBVer V/U/I.
+  umbrella's valid signatures), and SeBVer V/U/I;
+* the same batch signed under POSLO-C (one signature per epoch, the 4,096
+  epoch commitments in the public key): AVer of the honest and of the
+  corrupted batch (1% of epochs with one flipped bit of their messages or
+  signature), Distill's invalid epochs, CCD^v and umbrella tags, SeBVer
+  V/U/I, all against the oracle's POSLO-C over the whole batch.
 """
 
 import numpy as np
@@ -84,3 +89,36 @@ def test_full_distill_and_sebver(P, gpu, inst):
     assert P.poslo_sebver(ctx, params, c.pk, m, ccd, "V") == [True]
     assert P.poslo_sebver(ctx, params, c.pk, m, ccd, "U") == [True] * N_U
     assert P.poslo_sebver(ctx, params, c.pk, m, ccd, "I") == [False] * len(c.invalid)
+
+
+K_FLIP_EPOCHS = (N >> LOG2_N2) // 100
+
+
+@pytest.mark.parametrize("inst", [1, 0])
+def test_full_posloc(P, gpu, inst):
+    import oracle_fullsize as F
+    torch, ctx = gpu
+    print(f"POSLO-C oracle over the full batch, inst {inst}", flush=True)
+    c = F.full_case_c(inst, N, L, LOG2_N1, LOG2_N2, KEY_FIRST + 1, MSG_SEED, N_U, FLIP_SEED, K_FLIP_EPOCHS)
+    assert c.aver_honest and not c.aver_corrupt
+    assert c.invalid == sorted(i for i, _ in c.plan)
+    params = P.make_params(inst, LOG2_N1, LOG2_N2)
+    key = P.poslo_c_key_load(ctx, params, c.pk)
+    d = torch.from_numpy(c.msgs).cuda()
+    acc, e = P.poslo_c_aver(ctx, params, key, P.make_msgs(d), c.ds, c.s_total)
+    assert acc is True and int.from_bytes(e, "little") == c.e
+    dc = torch.from_numpy(c.cmsgs).cuda()
+    k = N >> LOG2_N2
+    cs = [c.cs_epochs[32 * i:32 * i + 32] for i in range(k)]
+    from oracle import oracle as O
+    acc, e = P.poslo_c_aver(ctx, params, key, P.make_msgs(dc), c.ds, O.posloc_agg_s(cs))
+    assert acc is False and int.from_bytes(e, "little") == c.e_corrupt
+    ccd = P.poslo_c_distill(ctx, params, key, P.make_msgs(dc), c.cs_epochs, c.ds, N_U)
+    assert ccd.invalid() == c.invalid
+    assert ccd.valid_tag() == c.valid_tag
+    umb, span = ccd.umbrellas()
+    assert span == c.span and umb == c.umbrellas
+    m = P.make_msgs(dc)
+    assert P.poslo_c_sebver(ctx, params, key, m, ccd, "V") == [True]
+    assert P.poslo_c_sebver(ctx, params, key, m, ccd, "U") == [True] * N_U
+    assert P.poslo_c_sebver(ctx, params, key, m, ccd, "I") == [False] * len(c.invalid)

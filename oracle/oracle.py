@@ -51,6 +51,16 @@ in the design notes of the repository):
       tag: LE32B(s) || encode(R) (64 bytes); ds wire format: one count byte,
       then per node {u8 depth, 3 zero bytes, u32 LE index, 16-byte value},
       bottom of the stack first.
+  R10 kappa = 127 (AES-based PRF only): a seed is a 127-bit value held in 16
+      bytes with bit 127 clear; the tree PRF of a seed x is one MMO block,
+      PRF_b(x) = (E_IV(x + b*2^127) xor (x + b*2^127)) mod 2^127 (the
+      paper's "x || j is exactly 128 bits"); every other PRF input (one-time
+      seeds, key derivation) appends b as a byte, as for kappa = 128, and
+      every PRF output is taken mod 2^127.
+  R11 POSLO++: H = Add_q, e_t = (LE(m_t) + LE(x_t)) mod q with the message
+      read as a little-endian integer; Add_q takes messages of at most 31
+      bytes (below 2^248 < q, "|m| < |q|"); the signing equation stays
+      s_t = r_t - e_t * y.
 """
 
 from __future__ import annotations
@@ -64,8 +74,22 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC_PATH = os.path.join(_HERE, "poslo_oracle.c")
 
-INST_SHA256 = 0  # POSLO: PRF and H from SHA-256
-INST_AES = 1     # POSLO+: PRF from MMO-AES-128, H = MDC-2-AES-128
+INST_SHA256 = 0    # POSLO: PRF and H from SHA-256
+INST_AES = 1       # POSLO+: PRF from MMO-AES-128, H = MDC-2-AES-128
+INST_AES_ADDQ = 2  # POSLO++: PRF from MMO-AES-128, H = Add_q (messages below 32 bytes)
+KAPPA127 = 4       # flag on an AES-based instantiation: kappa = 127 (reading R10)
+
+
+def inst_base(inst: int) -> int:
+    """The instantiation without the kappa flag."""
+    if inst & ~7 or (inst & 3) > 2 or (inst & KAPPA127 and (inst & 3) == INST_SHA256):
+        raise ValueError("unknown instantiation")
+    return inst & 3
+
+
+def kappa_of(inst: int) -> int:
+    inst_base(inst)
+    return 127 if inst & KAPPA127 else 128
 
 
 def build(force: bool = False) -> str:
@@ -127,23 +151,41 @@ def mdc2(data: bytes) -> bytes:
 def F(inst: int, z: bytes) -> bytes:
     """The PRF's underlying function (MMO-AES-128, or SHA-256 truncated)."""
     out = ctypes.create_string_buffer(16)
-    if _c().oracle_F(inst, bytes(z), len(z), out) != 0:
+    if _c().oracle_F(0 if inst_base(inst) == INST_SHA256 else 1, bytes(z), len(z), out) != 0:
         raise ValueError("unknown instantiation")
     return out.raw
 
 
 def H(inst: int, z: bytes) -> bytes:
-    """The message hash (MDC-2-AES-128, or SHA-256); 32 bytes."""
+    """The message hash (MDC-2-AES-128, or SHA-256); 32 bytes.  (Add_q
+    takes the message and the seed apart: see digest_int.)"""
+    base = inst_base(inst)
+    if base == INST_AES_ADDQ:
+        raise ValueError("Add_q is not a hash of a byte string")
     out = ctypes.create_string_buffer(32)
-    if _c().oracle_H(inst, bytes(z), len(z), out) != 0:
+    if _c().oracle_H(base, bytes(z), len(z), out) != 0:
         raise ValueError("unknown instantiation")
     return out.raw
 
 
+MASK127 = (1 << 127) - 1
+
+
 def prf(inst: int, b: int, z: bytes) -> bytes:
-    """PRF_b(z) = F(z || b) with b in {0, 1} appended as one byte."""
+    """PRF_b(z) = F(z || b) with b in {0, 1} appended as one byte; for
+    kappa = 127 (reading R10) a 16-byte z is a seed and b its 128th bit, and
+    the output is taken mod 2^127."""
     if b not in (0, 1):
         raise ValueError("PRF index must be 0 or 1")
+    if kappa_of(inst) == 127:
+        if len(z) == 16:
+            v = int.from_bytes(z, "little")
+            if v >> 127:
+                raise ValueError("a 127-bit seed has bit 127 clear")
+            out = F(inst, (v | (b << 127)).to_bytes(16, "little"))
+        else:
+            out = F(inst, bytes(z) + bytes([b]))
+        return (int.from_bytes(out, "little") & MASK127).to_bytes(16, "little")
     return F(inst, bytes(z) + bytes([b]))
 
 
@@ -399,6 +441,8 @@ def kg(params: Params, seed: bytes):
             break
         c += 1
     root = derive(params.inst, seed, b"x", 0)[:16]
+    if kappa_of(params.inst) == 127:
+        root = (int.from_bytes(root, "little") & MASK127).to_bytes(16, "little")
     signer = Signer(params=params, seed=seed, y=y, root=root)
     pk = encode(scalar_mult(y, G))
     return signer, pk
@@ -436,7 +480,12 @@ def one_time_seed(inst: int, x0_i: bytes, j: int) -> bytes:
 
 
 def digest_int(inst: int, m: bytes, x: bytes) -> int:
-    """H(m || x) as a little-endian integer, not yet reduced mod q."""
+    """H(m || x) as a little-endian integer, not yet reduced mod q; for
+    POSLO++ (reading R11) Add_q(m, x) = (LE(m) + LE(x)) mod q."""
+    if inst_base(inst) == INST_AES_ADDQ:
+        if len(m) > 31:
+            raise ValueError("Add_q takes messages of at most 31 bytes")
+        return (int.from_bytes(bytes(m), "little") + int.from_bytes(bytes(x), "little")) % Q
     return le256(H(inst, bytes(m) + bytes(x)))
 
 

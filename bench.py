@@ -14,6 +14,12 @@ The same run also measures, each on its own synthetic log:
    per AVer call, the kernels' durations and the launch overhead;
  - sha (or aes with --inst sha): the headline configuration under the other
    instantiation, with its own roofline;
+ - host: inputs in pinned host memory with the copies included (the
+   paper's convention): the headline batch per AVer call, the same batch
+   streamed through the chunked audit, and a 2^25 x 32-byte log streamed in
+   128 MiB chunks;
+ - variants: POSLO++ (H = Add_q) at kappa = 127 and 128 over 2^26 entries of
+   16-byte messages, and POSLO+ at kappa = 127 on the headline batch;
  - distill: Distill of 2^20 x 256-byte entries with 1% of entries carrying
    one flipped bit of m_t || sigma_t (exact invalid set, CCD);
  - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
@@ -57,6 +63,7 @@ CONFIGS = {
 CLOCK_WARMUP_S = 0.3
 DISTILL = dict(n=1 << 20, L=256, log2_n1=12, log2_n2=8, seed=3, frac=0.01, umbrellas=64)
 BATCHED = dict(signers=4096, max_batch=65536, len_lo=64, len_hi=512, frac=0.001, seed=4, log2_n1=8, log2_n2=8)
+VARIANT = dict(n=1 << 26, L=16, log2_n1=18, log2_n2=8, seed=6)
 SERVING = dict(keys=10000, distinct=1500, max_batch=1 << 18, L=128, p_corrupt=0.005, seed=5, submissions=4000,
                qps=(2000, 10000, 40000))
 
@@ -80,8 +87,17 @@ AES_OTF = AES_RK + 10 * 11        # with the schedule expanded on the fly
 SHA_COMP = 64 * 14 + 48 * 10 + 8
 
 
+# POSLO++ (H = Add_q): x_t by one AES under the epoch schedule, 1 xor of j,
+# 1 and of the kappa mask; e_t = LE(m) + LE(x) as an eight-word carry chain
+# (12); the 9-limb sum
+ADDQ_OPS = AES_RK + 2 + 12 + 9
+
+
 def ops_per_entry(inst: int, L):
     """Works on ints and numpy arrays of lengths."""
+    if inst & 3 == 2:
+        return ADDQ_OPS
+    inst &= 3
     if inst == 1:
         B = (L + 16 + 15) // 16
         # PRF (one AES + 1 xor), MDC-2 block 0 under the constant IV schedules,
@@ -93,8 +109,60 @@ def ops_per_entry(inst: int, L):
     return (1 + nb) * SHA_COMP + (L + 3) // 4 + 8 + 9
 
 
+# The same operations split by measured issue class: poslo_valu_probe shows
+# v_xor_b32 and v_bitop3_b32 (xor-class) issuing about 1.6 times faster than
+# v_perm_b32, v_alignbit_b32, v_add3_u32 and v_mad_u64_u32 (perm-class) on
+# MI355X.  AES: a full round is 24 perm-class (16 addresses, 8 rotations)
+# and 8 xor-class; the final round 24 and 8; a key-schedule round 6 and 5;
+# the key addition 0 and 4.  SHA-256: a round is 10 perm-class (six
+# rotations, four sums) and 4 xor-class (two three-input xors, Ch, Maj); a
+# schedule word 8 and 2; shifts and or-merges are counted perm-class.
+AES_RK_CLS = (9 * 24 + 24, 9 * 8 + 8 + 4)
+AES_OTF_CLS = (AES_RK_CLS[0] + 10 * 6, AES_RK_CLS[1] + 10 * 5)
+SHA_COMP_CLS = (64 * 10 + 48 * 8 + 8, 64 * 4 + 48 * 2)
+ADDQ_CLS = (AES_RK_CLS[0] + 1 + 12 + 9, AES_RK_CLS[1] + 1)
+assert sum(AES_RK_CLS) == AES_RK and sum(AES_OTF_CLS) == AES_OTF and sum(SHA_COMP_CLS) == SHA_COMP
+assert sum(ADDQ_CLS) == ADDQ_OPS
+
+
+def op_classes_per_entry(inst: int, L: int):
+    """(perm-class, xor-class) split of ops_per_entry."""
+    if inst & 3 == 2:
+        return ADDQ_CLS
+    inst &= 3
+    if inst == 1:
+        B = (L + 16 + 15) // 16
+        slow = AES_RK_CLS[0] + 2 * AES_RK_CLS[0] + (B - 1) * 2 * AES_OTF_CLS[0] + 9
+        fast = AES_RK_CLS[1] + 1 + 2 * AES_RK_CLS[1] + 8 + (B - 1) * (2 * AES_OTF_CLS[1] + 8)
+    else:
+        nb = (L + 16 + 9 + 63) // 64
+        slow = (1 + nb) * SHA_COMP_CLS[0] + (L + 3) // 4 + 8 + 9
+        fast = (1 + nb) * SHA_COMP_CLS[1]
+    assert slow + fast == ops_per_entry(inst, L)
+    return slow, fast
+
+
+def probe_rates(P):
+    """Sustained lane-ops/s of each probed instruction kind at 8 waves per
+    SIMD (poslo_valu_probe), in T/s."""
+    return {op: P.poslo_valu_probe(op, 8, 2048)[0] / 1e12 for op in P.PROBE_OPS}
+
+
+def mix_peak(rates, inst: int, L: int):
+    """Issue ceiling of the op model's mix: the operations of one entry at
+    the measured rates of their class (perm-class at the mean of perm,
+    alignbit, add3 and mad64; xor-class at the mean of xor and bitop3)."""
+    slow, fast = op_classes_per_entry(inst, L)
+    r_slow = sum(rates[k] for k in ("perm", "alignbit", "add3", "mad64")) / 4
+    r_fast = (rates["xor"] + rates["bitop3"]) / 2
+    return (slow + fast) / (slow / r_slow + fast / r_fast)
+
+
 def hash_calls_per_entry(inst: int, L):
-    """AES-128 block encryptions (POSLO+) or SHA-256 compressions (POSLO)."""
+    """AES-128 block encryptions (POSLO+, POSLO++) or SHA-256 compressions (POSLO)."""
+    if inst & 3 == 2:
+        return 1
+    inst &= 3
     if inst == 1:
         return 1 + 2 * ((L + 16 + 15) // 16)
     return 1 + (L + 16 + 9 + 63) // 64
@@ -274,7 +342,7 @@ def bench_small(P, torch, ctx, inst, calls):
             "launch_overhead_us": lat_us["p50"] - kernels_us}
 
 
-def bench_plain_other(P, torch, ctx, inst, steps, warmup):
+def bench_plain_other(P, torch, ctx, inst, steps, warmup, rates):
     """The headline configuration under the other instantiation, with its own
     roofline (the same measurement as the headline)."""
     cfg = CONFIGS["c2"]
@@ -285,6 +353,7 @@ def bench_plain_other(P, torch, ctx, inst, steps, warmup):
     achieved = n * ope / (kt["agg"] / 1e3) / 1e12
     name = "aes" if inst else "sha"
     value = n / (total / steps)
+    mp = mix_peak(rates, inst, cfg["L"])
     return {"workload": cfg["name"] + (", POSLO+ (MMO/MDC-2 over AES-128)" if inst else ", POSLO (SHA-256)"),
             "entries_per_s": value, "ms_per_step": 1e3 * total / steps, "latency_ms": lat_summary(lat),
             "hashes_per_s": value * hash_calls_per_entry(inst, cfg["L"]),
@@ -293,7 +362,105 @@ def bench_plain_other(P, torch, ctx, inst, steps, warmup):
                          "peak": INT32_PEAK_TOPS, "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS,
                          "ops_per_entry": ope, "traffic": traffic_bytes(name),
                          "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                         "algorithmic_bytes": n * cfg["L"], "hbm_GBs": n * cfg["L"] / (kt["agg"] / 1e3) / 1e9}}
+                         "algorithmic_bytes": n * cfg["L"], "hbm_GBs": n * cfg["L"] / (kt["agg"] / 1e3) / 1e9,
+                         "peak_measured_mix": mp, "frac_measured_mix": achieved / mp}}
+
+
+def bench_variants(P, torch, ctx, steps, warmup, rates):
+    """The parameter variants: POSLO++ (H = Add_q) at kappa = 127 and 128 on
+    2^26 entries of 16-byte messages (Add_q takes at most 31 bytes), and
+    POSLO+ at kappa = 127 on the headline configuration, whose seed walk is
+    one AES per tree level instead of two."""
+    out = {}
+    cfg = dict(VARIANT, name="plain AVer, 2^26 entries x 16 B, n2=256, n1=2^18")
+    for inst, key in ((2 | 4, "poslopp_k127"), (2, "poslopp")):
+        log, total, lat, kt = bench_plain(P, torch, ctx, cfg, inst, steps, warmup, False)
+        del log
+        torch.cuda.empty_cache()
+        n = cfg["n"]
+        ope = ops_per_entry(inst, cfg["L"])
+        achieved = n * ope / (kt["agg"] / 1e3) / 1e12
+        mp = mix_peak(rates, inst, cfg["L"])
+        hbm = n * cfg["L"] / (kt["agg"] / 1e3) / 1e9
+        out[key] = {
+            "workload": cfg["name"] + ", POSLO++ (MMO-AES-128 PRF, H = Add_q), kappa = "
+                        + ("127" if inst & 4 else "128"),
+            "entries_per_s": n / (total / steps), "ms_per_step": 1e3 * total / steps,
+            "latency_ms": lat_summary(lat), "kernel_ms": kt,
+            "roofline": {"bound": "alu", "kernel": "k_agg_addq", "achieved": achieved, "peak": INT32_PEAK_TOPS,
+                         "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops_per_entry": ope,
+                         "peak_measured_mix": mp, "frac_measured_mix": achieved / mp, "traffic": None,
+                         "algorithmic_bytes": n * cfg["L"], "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS}}
+    cfg2 = CONFIGS["c2"]
+    log, total, lat, kt = bench_plain(P, torch, ctx, cfg2, 1 | 4, steps, warmup, False)
+    del log
+    torch.cuda.empty_cache()
+    out["posloplus_k127"] = {"workload": cfg2["name"] + ", POSLO+ at kappa = 127",
+                             "entries_per_s": cfg2["n"] / (total / steps), "ms_per_step": 1e3 * total / steps,
+                             "latency_ms": lat_summary(lat), "kernel_ms": kt}
+    return out
+
+
+def bench_host(P, torch, ctx, inst, steps):
+    """Inputs resident in host memory, copies included (the paper's GPU
+    timings include the host-to-device copies): the headline batch in pinned
+    memory verified by one AVer call per step (copy, then hash); the same
+    batch streamed through the audit in 8 chunks (a chunk's copy overlaps
+    the previous chunk's hashing); and a 1 GiB log of 2^25 entries of 32
+    bytes, the entry size of the paper's 1 TB audit, streamed in 8 chunks
+    of 128 MiB."""
+    from paper_2506_08781_amd import workloads
+    out = {}
+    cfg = CONFIGS["c2"]
+    n, L = cfg["n"], cfg["L"]
+    log = workloads.single_signer_fixed(ctx, inst, n, L, cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
+    host = log.data.cpu().pin_memory()
+    stream = torch.cuda.current_stream()
+    hm = P.make_msgs(host)
+    for _ in range(3):
+        assert P.poslo_aver(ctx, log.params, log.pk, hm, log.ds, log.tag, stream)[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        assert P.poslo_aver(ctx, log.params, log.pk, hm, log.ds, log.tag, stream)[0]
+    dt = (time.perf_counter() - t0) / steps
+    out["aver_pinned_host"] = {"workload": cfg["name"] + ", messages in pinned host memory",
+                               "entries_per_s": n / dt, "ms_per_step": 1e3 * dt, "GBs_from_host": n * L / dt / 1e9}
+
+    def stream_run(lg, hbuf, chunks, reps):
+        nn = hbuf.shape[0]
+        step = nn // chunks
+        best = None
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            au = P.poslo_audit_begin(ctx, lg.params, lg.pk, lg.ds, 0)
+            for a in range(0, nn, step):
+                au.feed(P.make_msgs(hbuf[a:a + step], t0=a), stream)
+            ok, _ = au.finish(lg.tag, stream)
+            dt_ = time.perf_counter() - t
+            au.close()
+            assert ok, "streamed audit rejected an honest log"
+            if r and (best is None or dt_ < best):
+                best = dt_
+        return best
+
+    dt = stream_run(log, host, 8, steps // 4 + 1)
+    out["audit_stream_2p20x256"] = {"workload": cfg["name"] + ", streamed from pinned host memory in 8 chunks",
+                                    "entries_per_s": n / dt, "ms": 1e3 * dt, "GBs_from_host": n * L / dt / 1e9}
+    del log, host
+    torch.cuda.empty_cache()
+    n2, L2 = 1 << 25, 32
+    log = workloads.single_signer_fixed(ctx, inst, n2, L2, 17, 8, 6)
+    host = log.data.cpu().pin_memory()
+    log.sigs = log.data = None  # the audit reads the host copy only
+    torch.cuda.empty_cache()
+    dt = stream_run(log, host, 8, 2)
+    out["audit_stream_2p25x32"] = {"workload": "audit of 2^25 entries x 32 B (1 GiB), n2=256, n1=2^17, streamed "
+                                               "from pinned host memory in 8 chunks of 128 MiB",
+                                   "entries_per_s": n2 / dt, "ms": 1e3 * dt, "GBs_from_host": n2 * L2 / dt / 1e9}
+    del log, host
+    return out
 
 
 def bench_distill(P, torch, ctx, inst, steps):
@@ -339,7 +506,7 @@ def bench_distill(P, torch, ctx, inst, steps):
     return out
 
 
-def bench_batched(P, torch, ctx, inst, steps):
+def bench_batched(P, torch, ctx, inst, steps, rates):
     from paper_2506_08781_amd import workloads
     c = BATCHED
     t = time.perf_counter()
@@ -442,6 +609,11 @@ def bench_batched(P, torch, ctx, inst, steps):
     plain_total = time.perf_counter() - t0
 
     ops = int(np.sum(ops_per_entry(inst, log.lengths.astype(np.int64))))
+    uniq, cnt = np.unique(log.lengths.astype(np.int64), return_counts=True)
+    slow = sum(int(c) * op_classes_per_entry(inst, int(u))[0] for u, c in zip(uniq, cnt))
+    r_slow = sum(rates[k] for k in ("perm", "alignbit", "add3", "mad64")) / 4
+    r_fast = (rates["xor"] + rates["bitop3"]) / 2
+    mp = ops / (slow / r_slow + (ops - slow) / r_fast)
     hashes = int(np.sum(hash_calls_per_entry(inst, log.lengths.astype(np.int64))))
     achieved = ops / (hot_ms / 1e3) / 1e12
     graph_eps = total_entries * steps / graph_total
@@ -466,7 +638,8 @@ def bench_batched(P, torch, ctx, inst, steps):
         "kernel_ms": {"hot": hot_ms, "pipeline": pipe_ms},
         "roofline": {"bound": "alu", "kernel": "k_batch_hot", "achieved": achieved, "peak": INT32_PEAK_TOPS,
                      "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops": ops, "traffic": None,
-                     "hbm_GBs": int(log.offsets[-1]) / (hot_ms / 1e3) / 1e9},
+                     "hbm_GBs": int(log.offsets[-1]) / (hot_ms / 1e3) / 1e9,
+                     "peak_measured_mix": mp, "frac_measured_mix": achieved / mp},
     }
 
 
@@ -503,7 +676,22 @@ def bench_serving(P, torch, ctx, inst):
     n_entries = [q["n"] for q in log.requests]
     print(f"# serving: {len(log.requests)} distinct requests, {sum(n_entries)} entries, ready in "
           f"{time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
-    srv = P.Server(0, log.params, n_streams=4, max_group=256, distill=1)
+    # the hashing variant: the autotuner's choice on a group shaped like the
+    # groups the server launches (the pool's first requests, up to 256 and
+    # 2^21 entries)
+    jobs, ent = [], 0
+    for q in log.requests:
+        if len(jobs) == 256 or ent + q["n"] > (1 << 21):
+            break
+        jobs.append(dict(pk=log.pks[q["key"]], ds=q["ds"], tag=q["tag"], t0=q["t0"], n=q["n"],
+                         entry_base=q["base"]))
+        ent += q["n"]
+    total = log.data.shape[0]
+    offs = torch.arange(0, (total + 1) * log.L, log.L, dtype=torch.int64, device=log.data.device)
+    P.poslo_ctx_keys_load(ctx, [j["pk"] for j in jobs])
+    tuning, _ = P.poslo_autotune_batch(ctx, log.params, P.BatchJobs(jobs), log.data.reshape(-1), offs, reps=2)
+    del offs
+    srv = P.Server(0, log.params, n_streams=4, max_group=256, distill=1, variant=tuning.variant)
     srv.register_keys(list(range(c["keys"])), log.pks)
     L = log.L
     reqs = []
@@ -542,6 +730,7 @@ def bench_serving(P, torch, ctx, inst):
                     f"flipped bit, {len(reqs)} distinct requests resubmitted, invalid entries of rejected "
                     f"requests reported",
         "runs": runs,
+        "variant": P.poslo_batch_variant_name(tuning.variant),
         "groups_launched": st.groups_launched,
         "device_bytes_peak": st.bytes_peak,
     }
@@ -571,10 +760,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--inst", default="aes", choices=["aes", "sha"])
-    ap.add_argument("--sections", default="plain,small,other,distill,batched,serving",
+    ap.add_argument("--sections", default="plain,small,other,host,variants,distill,batched,serving",
                     help="comma list of plain, small (the 1,024 x 32-byte configuration), other (the headline "
-                         "configuration under the other instantiation), distill, batched, serving (plain always "
-                         "runs)")
+                         "configuration under the other instantiation), host (inputs in host memory, copies "
+                         "included), variants (POSLO++ and kappa = 127), distill, batched, serving (plain "
+                         "always runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
@@ -644,6 +834,11 @@ def main():
                      "algorithmic_bytes": n * cfg["L"],
                      "hbm_GBs": n * cfg["L"] / (agg_ms / 1e3) / 1e9},
     }
+    # the measured issue rates, and the ceiling of this kernel's op mix at them
+    rates = probe_rates(P)
+    mp = mix_peak(rates, inst, cfg["L"])
+    out["roofline"].update({"peak_basis": "256 CUs x 64 lanes x 2.4 GHz (one wave64 VALU op per 4 cycles per SIMD)",
+                            "probe_Tops": rates, "peak_measured_mix": mp, "frac_measured_mix": achieved / mp})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, inst, log, args.cpu_seconds)
     del log
@@ -651,13 +846,19 @@ def main():
     if "small" in sections:
         out["small"] = bench_small(P, torch, ctx, inst, 400)
     if "other" in sections:
-        out["sha" if inst else "aes"] = bench_plain_other(P, torch, ctx, 1 - inst, args.steps, args.warmup)
+        out["sha" if inst else "aes"] = bench_plain_other(P, torch, ctx, 1 - inst, args.steps, args.warmup, rates)
+        torch.cuda.empty_cache()
+    if "host" in sections:
+        out["host"] = bench_host(P, torch, ctx, inst, max(4, args.steps // 2))
+        torch.cuda.empty_cache()
+    if "variants" in sections:
+        out["variants"] = bench_variants(P, torch, ctx, args.steps, args.warmup, rates)
         torch.cuda.empty_cache()
     if "distill" in sections:
         out["distill"] = bench_distill(P, torch, ctx, inst, max(2, args.steps // 4))
         torch.cuda.empty_cache()
     if "batched" in sections:
-        out["multi_signer"] = bench_batched(P, torch, ctx, inst, max(3, args.steps // 2))
+        out["multi_signer"] = bench_batched(P, torch, ctx, inst, max(3, args.steps // 2), rates)
         torch.cuda.empty_cache()
     ctx.close()
     # serving in a process of its own, as a serving deployment runs: its

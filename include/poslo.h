@@ -60,14 +60,31 @@ enum {
     POSLO_E_BUSY = -7       /* resource temporarily unavailable */
 };
 
+/* Instantiations (paper, table "Instantiations of POSLO schemes").
+ * POSLO++ takes messages of at most 31 bytes: Add_q(m, x_t) = LE(m) + LE(x_t)
+ * stays below q, so e_t needs no reduction; longer messages are E_INVAL. */
 enum {
-    POSLO_INST_SHA256 = 0, /* POSLO: PRF and H from SHA-256 */
-    POSLO_INST_AES = 1     /* POSLO+: PRF from MMO-AES-128, H = MDC-2-AES-128 */
+    POSLO_INST_SHA256 = 0,   /* POSLO: PRF and H from SHA-256 */
+    POSLO_INST_AES = 1,      /* POSLO+: PRF from MMO-AES-128, H = MDC-2-AES-128 */
+    POSLO_INST_AES_ADDQ = 2  /* POSLO++: PRF from MMO-AES-128, H = Add_q */
 };
 
-/* Public parameters I (paper, POSLO-F.Kg): instantiation, n1 = 2^log2_n1
- * epochs of n2 = 2^log2_n2 entries each, kappa = 128.  BPV parameters (v, k)
- * are used by the signer only; v must be a power of two <= 65536. */
+/* Flag on an AES-based instantiation: kappa = 127 (paper, the remark on
+ * kappa = 127 under the instantiations).  Tree seeds are 127 bits (bit 127 of
+ * their 16 bytes clear) and a tree PRF call PRF_b(x) is the one MMO block
+ * x + b * 2^127; PRF inputs of any other length keep the byte suffix b.  Every
+ * PRF output, x_t included, is taken mod 2^127.  Without the flag kappa = 128. */
+#define POSLO_KAPPA127 4u
+
+/* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two
+ * optionally with POSLO_KAPPA127), else 0 */
+int poslo_inst_valid(uint32_t inst);
+
+/* Public parameters I (paper, POSLO-F.Kg): instantiation word, n1 =
+ * 2^log2_n1 epochs of n2 = 2^log2_n2 entries each.  BPV parameters (v, k)
+ * are used by the signer only; v must be a power of two <= 65536.  The
+ * multi-signer batch verifier and the serving loop take POSLO and POSLO+ at
+ * kappa = 128 only (E_INVAL otherwise). */
 typedef struct poslo_params {
     uint32_t inst;
     uint32_t log2_n1; /* 0..31 */
@@ -91,7 +108,7 @@ typedef struct poslo_params {
  * signature bytes.  The host buffers must stay unchanged until the call
  * returns.  poslo_aver_fixed takes device batches only. */
 typedef struct poslo_msgs {
-    const uint8_t* data;     /* device, or host when host = 1 */
+    const uint8_t* data;     /* device, or host when host = 1; may be NULL for a fixed length of 0 */
     const uint64_t* offsets; /* same memory as data, or NULL */
     uint64_t msg_len;
     uint64_t n;
@@ -144,7 +161,9 @@ int poslo_ds_export(const poslo_signer* sk, uint8_t* buf, size_t cap, size_t* le
 int poslo_agg(const uint8_t* sigs, size_t stride, uint64_t count, uint8_t tag[64]);
 
 /* Host reference of the instantiated functions, for tooling and tests:
- * out16 = PRF_b(in) (b in {0,1}); out32 = H(in). */
+ * out16 = PRF_b(in) (b in {0,1}; with POSLO_KAPPA127 a 16-byte input is a
+ * seed and must have bit 127 clear); out32 = H(in) (SHA-256 or MDC-2; E_INVAL
+ * for POSLO++, whose Add_q is not a hash of one byte string). */
 int poslo_prf_host(uint32_t inst, uint32_t b, const uint8_t* in, size_t len, uint8_t out16[16]);
 int poslo_hash_host(uint32_t inst, const uint8_t* in, size_t len, uint8_t out32[32]);
 
@@ -162,7 +181,10 @@ void poslo_ctx_destroy(poslo_ctx* ctx);
  * then the check R = e*Y + s*G).  pk, ds, tag: host.  *accept gets 1 or 0.
  * If e_out is not NULL it receives e mod q (32 bytes LE, host).
  * E_SEED if ds does not cover an epoch of the batch; E_ENCODING if pk is not
- * a point encoding; a non-canonical tag gives *accept = 0. */
+ * a point encoding; a non-canonical tag gives *accept = 0.  POSLO++: E_INVAL
+ * if a message is longer than 31 bytes (found on the host for a fixed
+ * length, by the kernels for an offsets batch).  kappa = 127: E_INVAL if a ds
+ * node that the batch's epochs descend from has bit 127 set. */
 int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
                const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                uint8_t e_out[32]);
@@ -183,7 +205,7 @@ int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32],
  * that follow each other are independent (nothing in the array needs to
  * start at zero). */
 #define POSLO_AVER_FIXED_MAX_EPOCHS 16384
-#define POSLO_AVER_FIXED_SCRATCH_BYTES 3293440
+#define POSLO_AVER_FIXED_SCRATCH_BYTES 3293696
 int poslo_aver_fixed(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
                      const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                      uint8_t e_out[32]);
@@ -342,7 +364,10 @@ int poslo_audit_begin(poslo_ctx* ctx, const poslo_params* params, const uint8_t 
  * stream into one of two staging buffers, so that a chunk's copy overlaps
  * the previous chunk's hashing; a host chunk must stay unchanged until the
  * next call on the audit returns.  Returns without waiting for the device.
- * E_SEED if the ds does not cover an epoch of the chunk. */
+ * E_SEED if the ds does not cover an epoch of the chunk.  POSLO++: a chunk
+ * of fixed length above 31 bytes is E_INVAL here; a longer message in an
+ * offsets chunk is found by the kernels and makes finish and export return
+ * E_INVAL from then on. */
 int poslo_audit_feed(poslo_audit* audit, const poslo_msgs* chunk, void* stream);
 /* The next entry index (the first entry not yet fed). */
 int poslo_audit_position(const poslo_audit* audit, uint64_t* t_next);
@@ -412,7 +437,8 @@ typedef struct poslo_sign_job {
  * offsets (n_total + 1 u64), sigs (80 per global entry): device.  tags
  * (64*njobs) and ds_out (ds_stride >= 769 bytes per job, may be NULL): host,
  * the aggregate tag of each job and the ds after its last entry.
- * Synchronous. */
+ * Synchronous.  POSLO++: E_INVAL if a message is longer than 31 bytes (its
+ * signature is left unwritten and the tags are not valid). */
 int poslo_gpu_sign(poslo_gpu_keys* keys, const poslo_sign_job* jobs, uint32_t njobs, const uint8_t* data,
                    const uint64_t* offsets, uint8_t* sigs, uint8_t* tags, uint8_t* ds_out, size_t ds_stride,
                    void* stream);

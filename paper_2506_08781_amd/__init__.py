@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libposlo.so")
 
 INST_SHA256 = 0
 INST_AES = 1
+INST_AES_ADDQ = 2  # POSLO++ (H = Add_q, messages of at most 31 bytes)
+KAPPA127 = 4       # flag on an AES-based instantiation: kappa = 127
 
 POSLO_OK = 0
 POSLO_E_INVAL = -1

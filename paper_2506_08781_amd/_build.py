@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposlo.so")
 
 SOURCES = [
-    "verifier.hip", "agg_aes.hip", "agg_sha.hip", "distill.hip", "posloc.hip", "audit.hip", "ubench.hip", "keys.hip", "batched.hip", "server.hip", "signer.hip",
+    "verifier.hip", "agg_aes.hip", "agg_sha.hip", "agg_addq.hip", "distill.hip", "posloc.hip", "audit.hip", "ubench.hip", "keys.hip", "batched.hip", "server.hip", "signer.hip",
     "signer_gpu.hip", "synth_gen.hip",
 ]
 

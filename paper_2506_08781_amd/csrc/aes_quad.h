@@ -82,6 +82,15 @@ __device__ __forceinline__ uint32_t quad_prf_node(const T& tb, uint32_t xc, uint
     return quad_encrypt_otf(tb, h1, bc, c) ^ bc;
 }
 
+// the same at kappa = 127: PRF_b(x) is the one MMO block x + b * 2^127
+// under the IV's schedule, reduced mod 2^127 (x has bit 127 clear)
+template <class T>
+__device__ __forceinline__ uint32_t quad_prf_node127(const T& tb, uint32_t xc, uint32_t b, uint32_t c) {
+    const uint32_t blk = c == 3 ? xc | (b << 31) : xc;
+    const uint32_t h = quad_encrypt_rk(tb, c_iv.a, blk, c) ^ blk;
+    return c == 3 ? h & 0x7fffffffu : h;
+}
+
 // the AES epoch row of seed x_0[i] (column c in xc): words 4r + c of the
 // schedule of the MMO chaining value after x_0[i]'s block, and word 44 + c
 // = column c of x_0[i]

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             x[0] = j, x[1] = 0u, x[2] = 0u, x[3] = 0u;
             penc_rk(tb, rk, x);
             x[0] ^= j;
+            x[3] &= a.xmask;
             if constexpr (EMIT)
 #pragma unroll
                 for (int w = 0; w < 4; w++) xo[w] = x[w];

@@ -23,8 +23,10 @@
 
 namespace poslo {
 
-// running e mod q (9 words, the top one zero) += the chunk's partials
-__global__ __launch_bounds__(256) void k_audit_fold(const uint32_t* partials, uint32_t n_part, uint32_t* run) {
+// running e mod q (9 words, the top one zero) += the chunk's partials;
+// run[9] keeps POSLO++'s long-message flag of every chunk (bad)
+__global__ __launch_bounds__(256) void k_audit_fold(const uint32_t* partials, uint32_t n_part, uint32_t* run,
+                                                    const uint32_t* bad) {
     __shared__ uint32_t total[9];
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t p = threadIdx.x; p < n_part; p += 256) acc288_add(acc, partials + (uint64_t)p * 9);
@@ -37,6 +39,7 @@ __global__ __launch_bounds__(256) void k_audit_fold(const uint32_t* partials, ui
         sc_reduce288(e, t);
         for (int k = 0; k < 8; k++) run[k] = e[k];
         run[8] = 0;
+        if (*bad) run[9] = 1u;
     }
 }
 
@@ -50,7 +53,7 @@ struct poslo_audit {
     uint8_t pk[32] = {};
     std::vector<uint8_t> ds;
     uint64_t t0 = 0, t_next = 0;
-    uint32_t* d_run = nullptr;  // running e mod q, 9 words
+    uint32_t* d_run = nullptr;  // running e mod q, 9 words, then the long-message flag
     uint32_t* d_tab = nullptr;  // epoch rows of the chunk being hashed
     size_t tab_rows = 0;
     uint32_t* d_part = nullptr;
@@ -117,7 +120,7 @@ int audit_new(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
     a->ds.assign(ds, ds + ds_len);
     a->t0 = t0;
     a->t_next = t_next;
-    uint32_t run[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t run[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (e)
         for (int k = 0; k < 8; k++) run[k] = e[k];
     st = POSLO_OK;
@@ -186,9 +189,9 @@ extern "C" int poslo_audit_feed(poslo_audit* a, const poslo_msgs* m, void* strea
     // the chunk's epoch rows in the audit's own table
     const uint64_t rows = ((m->t0 + m->n - 1) >> a->prm.log2_n2) - (m->t0 >> a->prm.log2_n2) + 1;
     if (a->tab_rows < rows) {
-        size_t have = a->tab_rows * kEpochWords * 4;
-        if ((st = grow((void**)&a->d_tab, &have, rows * kEpochWords * 4))) return st;
-        a->tab_rows = have / (kEpochWords * 4);
+        size_t have = a->tab_rows ? epoch_tab_words(a->tab_rows) * 4 : 0;
+        if ((st = grow((void**)&a->d_tab, &have, epoch_tab_words(rows) * 4))) return st;
+        a->tab_rows = (have / 4 - epoch_tab_words(0)) / kEpochWords;
     }
     BatchArgs ba;
     DsArg dsa;
@@ -200,7 +203,8 @@ extern "C" int poslo_audit_feed(poslo_audit* a, const poslo_msgs* m, void* strea
     const AggShape g = agg_shape(c, &a->prm, &dm);
     if ((st = grow((void**)&a->d_part, &a->part_bytes, (size_t)g.grid * 36))) return st;
     if ((st = launch_agg(c, &a->prm, g, ba, a->d_part, nullptr, nullptr, s))) return st;
-    hipLaunchKernelGGL(k_audit_fold, dim3(1), dim3(256), 0, s, (const uint32_t*)a->d_part, g.grid, a->d_run);
+    hipLaunchKernelGGL(k_audit_fold, dim3(1), dim3(256), 0, s, (const uint32_t*)a->d_part, g.grid, a->d_run,
+                       (const uint32_t*)ba.bad);
     HIP_TRY(hipGetLastError());
     if (b >= 0) {
         HIP_TRY(hipEventRecord(a->ev_used[b], s));
@@ -221,7 +225,7 @@ extern "C" int poslo_audit_finish(poslo_audit* a, const uint8_t tag[64], void* s
     HIP_TRY(hipSetDevice(c->device));
     const KeyEntry* key = ctx_key(c, a->pk, &st);
     if (!key) return st;
-    return final_check(c, key, a->d_run, 1, tag, (hipStream_t)stream, accept, e_out);
+    return final_check(c, key, a->d_run, 1, tag, (hipStream_t)stream, accept, e_out, a->d_run + 9);
 }
 
 extern "C" int poslo_audit_position(const poslo_audit* a, uint64_t* t_next) {
@@ -237,9 +241,10 @@ extern "C" int poslo_audit_export(poslo_audit* a, void* stream, uint8_t* buf, si
     int st;
     if ((st = release_host(a))) return st;
     HIP_TRY(hipSetDevice(a->c->device));
-    uint32_t run[9];
+    uint32_t run[10];
     HIP_TRY(hipMemcpyAsync(run, a->d_run, sizeof run, hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (run[9]) return POSLO_E_INVAL;  // a POSLO++ message longer than 31 bytes was fed
     uint8_t* p = buf;
     memcpy(p, "PAUD", 4);
     p += 4;

@@ -116,9 +116,10 @@ class BatchRunner {
     // device buffers (grown on demand, kept)
     void *d_jobs_ = nullptr, *d_ds_ = nullptr, *d_rows_ = nullptr, *d_items_ = nullptr, *d_tab_ = nullptr,
          *d_part_ = nullptr, *d_res_ = nullptr, *d_misc_ = nullptr, *d_rdec_ = nullptr, *d_vtiles_ = nullptr,
-         *d_idx_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr;
+         *d_idx_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr, *d_pair_ = nullptr;
     size_t n_jobs_b_ = 0, n_ds_b_ = 0, n_rows_b_ = 0, n_items_b_ = 0, n_tab_b_ = 0, n_part_b_ = 0, n_res_b_ = 0,
-           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0;
+           n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0,
+           n_pair_b_ = 0;
     uint64_t n_entries_ = 0;
     bool emitted_ = false;  // the last launch wrote e_t and the x checks
     // pinned staging

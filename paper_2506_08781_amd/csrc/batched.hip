@@ -120,6 +120,19 @@ __global__ __launch_bounds__(256) void k_batch_seeds(BSeeds S) {
 
 // ---- the persistent hashing kernel ------------------------------------------
 
+// a record every lane of the wave loaded from the same address, word by word
+// from the first lane, so that the compiler keeps it in scalar registers
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T out;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); k++) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
 struct BHot {
     const BJob* jobs;
     const BItem* items;
@@ -130,6 +143,7 @@ struct BHot {
     uint32_t* partials;  // 9 words per item
     uint32_t* e_out;     // optional: e_t mod q, 8 words per entry (job's ebase + offset)
     uint8_t* xbad;       // with e_out: 1 when x_t differs from the signature's
+    uint32_t* pair_tmp;  // PAIR variants: 16 words per thread of the grid
 };
 
 // INST 1: MDC-2-AES over the byte-addressed tables (NT = 1 or 2);
@@ -160,8 +174,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         // uniform across the workgroup: keeps the item's job record in scalar registers
         const uint32_t item = __builtin_amdgcn_readfirstlane(misc[0]);
         if (item >= A.n_items) break;
-        const BItem it = A.items[item];
-        const BJob J = A.jobs[it.job];
+        const BItem it = wave_uniform(A.items[item]);
+        const BJob J = wave_uniform(A.jobs[it.job]);
         const BatchArgs a = job_args(J, A.log2_n2, A.tab);
         if (SORT) {
             // counting sort of the item's slots by block count
@@ -190,16 +204,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             }
             __syncthreads();
         }
-        uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        // an item holds at most CHUNK entries: with CHUNK <= BLOCK a lane has
-        // at most one, so nothing accumulates across the digest
-        for (uint32_t s = threadIdx.x; s < it.count; s += BLOCK) {
-            if (CHUNK <= BLOCK && s >= BLOCK) break;
-            // slots [BLOCK, count) map to count - 1 - (s - BLOCK): the longest first
+        // the digest of the entry in sorted slot s (EMIT: its e_t and x check
+        // are stored as well)
+        // batch position of the entry in sorted slot s (slots [BLOCK, count)
+        // map to count - 1 - (s - BLOCK): the longest first)
+        auto pos_of = [&](uint32_t s) -> uint64_t {
             const uint32_t slot = (PAIR && s >= BLOCK) ? it.count - 1 - (s - BLOCK) : s;
-            uint64_t p = it.first + (SORT ? order[slot] : slot);
+            return it.first + (SORT ? order[slot] : slot);
+        };
+        // the digest of the entry in sorted slot s = tid + h * BLOCK (EMIT:
+        // its e_t and x check are stored as well).  The entry's position is
+        // looked up again after the digest from an opaque copy of the thread
+        // index, so that no per-entry address stays live across the digest.
+        auto entry = [&](uint32_t tid, uint32_t h, uint32_t dig[8]) {
+            const uint64_t p = pos_of(tid + h * BLOCK);
             EntryView ev = entry_view(a, p);
-            uint32_t x[4], dig[8];
+            uint32_t x[4];
             if constexpr (INST == INST_AES) {
                 const uint64_t t = a.t0 + p;
                 const uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
@@ -216,19 +236,66 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 #pragma unroll
                 for (int w = 0; w < 4; w++) x[w] = bswap32(x[w]);
             }
-            acc288_add256(acc, dig);
             if constexpr (EMIT) {
+                uint32_t t2 = tid;
+                asm volatile("" : "+v"(t2));
+                const uint64_t p2 = pos_of(t2 + h * BLOCK);
                 // x_t as little-endian words against the signature's x bytes
-                const uint8_t* sg = J.sigs + p * 80 + 64;
+                const uint8_t* sg = J.sigs + p2 * 80 + 64;
                 uint32_t d = 0;
 #pragma unroll
                 for (int w = 0; w < 4; w++) d |= x[w] ^ gload_le32(sg + 4 * w);
                 uint32_t e[8];
                 sc_reduce256(e, dig);
-                uint32_t* eo = A.e_out + (J.ebase + p) * 8;
+                uint32_t* eo = A.e_out + (J.ebase + p2) * 8;
 #pragma unroll
                 for (int w = 0; w < 8; w++) eo[w] = e[w];
-                A.xbad[J.ebase + p] = d ? 1 : 0;
+                A.xbad[J.ebase + p2] = d ? 1 : 0;
+            }
+        };
+        uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (PAIR) {
+            // two entries per thread, hashed by one loop over h; each digest
+            // goes to the thread's slot h of pair_tmp and the sum is formed
+            // after both, so that no accumulator stays live in registers
+            // across a digest
+#pragma unroll
+            for (uint32_t h = 0; h < 2; h++) {
+                if (threadIdx.x + h * BLOCK < it.count) {
+                    uint32_t dig[8];
+                    entry(threadIdx.x, h, dig);
+                    uint32_t t2 = threadIdx.x;
+                    asm volatile("" : "+v"(t2));
+                    uint32_t* tmp = A.pair_tmp + (((uint64_t)blockIdx.x * BLOCK + t2) * 2 + h) * 8;
+#pragma unroll
+                    for (int w = 0; w < 8; w++) tmp[w] = dig[w];
+                }
+            }
+#pragma unroll 1
+            for (uint32_t h = 0; h < 2; h++) {
+                if (threadIdx.x + h * BLOCK < it.count) {
+                    const uint32_t* tmp = A.pair_tmp + (((uint64_t)blockIdx.x * BLOCK + threadIdx.x) * 2 + h) * 8;
+                    uint32_t dig[8];
+#pragma unroll
+                    for (int w = 0; w < 8; w++) dig[w] = tmp[w];
+                    acc288_add256(acc, dig);
+                }
+            }
+        } else {
+            // an item holds at most CHUNK entries: with CHUNK <= BLOCK a lane
+            // has at most one, so nothing accumulates across the digest
+            if constexpr (CHUNK <= BLOCK) {
+                if (threadIdx.x < it.count) {
+                    uint32_t dig[8];
+                    entry(threadIdx.x, 0, dig);
+                    acc288_add256(acc, dig);
+                }
+            } else {
+                for (uint32_t h = 0; threadIdx.x + h * BLOCK < it.count; h++) {
+                    uint32_t dig[8];
+                    entry(threadIdx.x, h, dig);
+                    acc288_add256(acc, dig);
+                }
             }
         }
         block_reduce288_scratch<BLOCK>(acc, A.partials + (uint64_t)item * 9, red);
@@ -290,8 +357,8 @@ __global__ __launch_bounds__(PRE ? 256 / kVerifyNE : 256) void k_batch_verify(BV
         lds_tables_fill<4, 1>(lds);
         __syncthreads();
     }
-    const BItem it = V.tiles[blockIdx.x];
-    const BJob& J = V.jobs[it.job];
+    const BItem it = wave_uniform(V.tiles[blockIdx.x]);
+    const BJob J = wave_uniform(V.jobs[it.job]);
     if constexpr (PRE) {
         auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
             const uint32_t idx = threadIdx.x + (uint32_t)(VB * k);
@@ -406,7 +473,7 @@ BatchRunner::~BatchRunner() {
     forget_graphs();
     if (capture_) hipStreamDestroy(capture_);
     for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_,
-                    d_ekeys_, d_xbad_})
+                    d_ekeys_, d_xbad_, d_pair_})
         if (p) hipFree(p);
     if (h_res_) hipHostFree(h_res_);
     if (h_misc_) hipHostFree(h_misc_);
@@ -451,7 +518,7 @@ int BatchRunner::grow_pinned(void** p, size_t* have, size_t bytes) {
 
 int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njobs, const poslo_tuning& t,
                       int num_cu) {
-    if (!params_ok(prm) || (njobs && !jobs)) return POSLO_E_INVAL;
+    if (!params_ok(prm) || prm->inst > POSLO_INST_AES || (njobs && !jobs)) return POSLO_E_INVAL;
     if (t.variant < 0 || t.variant >= kNumHot || kHot[t.variant].inst != (int)prm->inst || t.wg_per_cu < 0 ||
         t.wg_per_cu > 64)
         return POSLO_E_INVAL;
@@ -573,6 +640,10 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     A.partials = (uint32_t*)d_part_;
     A.e_out = emit ? (uint32_t*)d_ekeys_ : nullptr;
     A.xbad = emit ? (uint8_t*)d_xbad_ : nullptr;
+    if (hv.pair) {
+        if ((st = grow(&d_pair_, &n_pair_b_, (size_t)grid * hv.block * 64))) return st;
+        A.pair_tmp = (uint32_t*)d_pair_;
+    }
     const uint32_t* tg = prof->d_gtable;
     auto launch_all = [&](hipStream_t q, bool timed) -> int {
         if (prm_.inst == POSLO_INST_AES)
@@ -809,7 +880,9 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
                                   const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes,
                                   const uint8_t* sigs, int distill, const poslo_tuning* tuning, void* stream,
                                   uint8_t* accept, uint64_t* invalid, size_t cap, size_t* n_invalid) {
-    if (!c || !params_ok(prm) || (njobs && (!jobs || !accept)) || distill < 0 || distill > 2) return POSLO_E_INVAL;
+    if (!c || !params_ok(prm) || prm->inst > POSLO_INST_AES || (njobs && (!jobs || !accept)) || distill < 0 ||
+        distill > 2)
+        return POSLO_E_INVAL;
     if (distill && (!sigs || !n_invalid || (cap && !invalid))) return POSLO_E_INVAL;
     if (n_invalid) *n_invalid = 0;
     hipStream_t s = (hipStream_t)stream;
@@ -855,7 +928,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
 extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs, uint32_t njobs,
                                     const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes, int reps,
                                     void* stream, poslo_tuning* best, double* best_ms) {
-    if (!c || !params_ok(prm) || !best || njobs == 0 || !jobs) return POSLO_E_INVAL;
+    if (!c || !params_ok(prm) || prm->inst > POSLO_INST_AES || !best || njobs == 0 || !jobs) return POSLO_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if (reps < 1) reps = 3;

@@ -41,6 +41,11 @@ int launch_agg_aes_emit(bool fast, uint32_t grid, const void* batch_args, uint32
 // threads per workgroup of the any-layout form (and of the emit launches)
 int agg_aes_any_block();
 size_t agg_aes_lds_bytes(int v);
+// the POSLO++ hot kernel (agg_addq.hip): layout as AggShape::addq_layout;
+// with e_out set also every entry's e_t and x_t.  a.bad must be set.
+int launch_agg_addq(int layout, uint32_t grid, const void* batch_args, uint32_t* partials, uint32_t* e_out,
+                    uint32_t* x_out, hipStream_t s);
+int agg_addq_block();
 // the POSLO hot kernel (agg_sha.hip): layout 2 = 16-byte aligned fixed
 // length, 1 = 4-byte aligned fixed length, 0 = any
 constexpr int kAggShaBlock = 256;
@@ -127,6 +132,10 @@ int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector
 struct BatchArgs;
 struct DsArg;
 bool params_ok(const poslo_params* p);
+// words of an epoch table of ne rows: the rows, then POSLO++'s long-message
+// flag word (padded to keep allocations aligned)
+constexpr size_t kTabRowWords = 48;  // one epoch row (kEpochWords)
+constexpr size_t epoch_tab_words(uint64_t ne) { return (size_t)ne * kTabRowWords + 64; }
 // host-side checks of a batch (parameters, ds parse, SR coverage of every
 // epoch); fills the kernel argument block and the by-value ds, sizes the
 // epoch table (the context's, or fixed_tab of fixed_epochs rows when set)
@@ -144,6 +153,7 @@ struct AggShape {
     bool fast;
     int variant;  // AES variant; -1 with fast = false: the any-layout form
     int sha_layout;
+    int addq_layout;  // POSLO++: 2 = 16-byte messages 16-byte aligned, 1 = 4-byte aligned fixed length, 0 = any
     uint32_t grid;
 };
 AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m);
@@ -164,8 +174,10 @@ constexpr int kSlotStageData = 28, kSlotStageOffsets = 29, kSlotStageSigs = 30;
 int stage_msgs(poslo_ctx* c, const poslo_msgs* m, hipStream_t s, poslo_msgs& dm, const uint8_t* sigs,
                const uint8_t** sigs_out);
 // the final fold of n_part partials (9 words each), mod q and the
-// aggregate check against tag; synchronizes s and returns accept and e
+// aggregate check against tag; synchronizes s and returns accept and e.
+// E_INVAL when bad (a device word, optional) is set.
 int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uint32_t n_part,
-                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32]);
+                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32],
+                const uint32_t* bad = nullptr);
 
 }  // namespace poslo

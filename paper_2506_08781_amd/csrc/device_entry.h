@@ -20,6 +20,11 @@ struct BatchArgs {
     const uint32_t* tab;   // per-epoch table, kEpochWords each
     const uint32_t* skip;  // optional bitmap over batch positions
     const uint8_t* end;    // end of the data buffer, or nullptr when unknown
+    // AES-based PRF: mask of x_t's top word (0x7fffffff at kappa = 127)
+    uint32_t xmask = 0xffffffffu;
+    // POSLO++: set to nonzero by any kernel that meets a (non-skipped) message
+    // longer than 31 bytes; zeroed by the seed-table kernel
+    uint32_t* bad = nullptr;
 };
 
 struct EntryView {
@@ -91,7 +96,7 @@ __device__ __forceinline__ void one_time_seed_aes(const T& tb, const BatchArgs& 
     x[0] = s[0] ^ j;
     x[1] = s[1];
     x[2] = s[2];
-    x[3] = s[3];
+    x[3] = s[3] & a.xmask;
 }
 
 // MDC-2 over m || x; FAST: 16-byte aligned message of a length divisible by 16
@@ -229,6 +234,52 @@ __device__ __forceinline__ void digest_sha(const EntryView& v, const uint32_t xw
     }
 #pragma unroll
     for (int w = 0; w < 8; w++) dig[w] = bswap32(H[w]);
+}
+
+// ---- POSLO++ (Add_q) ------------------------------------------------------
+
+// m_t (L <= 31 bytes) as eight little-endian words, zero past the message.
+// LAYOUT 2: L = 16 at a 16-byte aligned address (one 16-byte load);
+// 1: a multiple of 4 at a 4-byte aligned address; 0: anything, read as the
+// aligned words that hold a message byte (never a word past them, so no load
+// leaves the pages the message lies in) and funnel-shifted.
+template <int LAYOUT>
+__device__ __forceinline__ void addq_message(const uint8_t* m, uint32_t L, uint32_t w[8]) {
+    if constexpr (LAYOUT == 2) {
+        const uint4 v = gload(reinterpret_cast<const uint4*>(m));
+        w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+#pragma unroll
+        for (int k = 4; k < 8; k++) w[k] = 0u;
+    } else if constexpr (LAYOUT == 1) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(m);
+#pragma unroll
+        for (int k = 0; k < 8; k++) w[k] = 4u * k < L ? gload(p + k) : 0u;
+    } else {
+        const uintptr_t A = reinterpret_cast<uintptr_t>(m);
+        const uint32_t sh = (uint32_t)(A & 3u);
+        const uint32_t* base = reinterpret_cast<const uint32_t*>(A - sh);
+        const uint32_t nw = L ? (sh + L + 3u) >> 2 : 0u;
+        uint32_t d[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) d[k] = (uint32_t)k < nw ? gload(base + k) : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t v = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+            const int r = (int)L - 4 * k;  // message bytes in word k
+            w[k] = r >= 4 ? v : r <= 0 ? 0u : v & ((1u << (8 * r)) - 1u);
+        }
+    }
+}
+
+// Add_q(m, x) = LE(m) + LE(x) as eight words (below 2^249 < q for |m| <= 31)
+__device__ __forceinline__ void addq_digest(const uint32_t w[8], const uint32_t x[4], uint32_t e[8]) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        c += (uint64_t)w[k] + (k < 4 ? x[k] : 0u);
+        e[k] = (uint32_t)c;
+        c >>= 32;
+    }
 }
 
 // ---- reductions ------------------------------------------------------------

@@ -78,6 +78,19 @@ __device__ __forceinline__ void prf_node_aes(const T& tb, const uint32_t x[4], u
     out[3] = blk[3];
 }
 
+// the tree PRF at kappa = 127: one MMO block x + b * 2^127 under the IV's
+// schedule, reduced mod 2^127 (x has bit 127 clear)
+template <class T>
+__device__ __forceinline__ void prf_node_aes127(const T& tb, const uint32_t x[4], uint32_t b, uint32_t out[4]) {
+    const uint32_t blk[4] = {x[0], x[1], x[2], x[3] | (b << 31)};
+    uint32_t s[4] = {blk[0], blk[1], blk[2], blk[3]};
+    aes128_encrypt_rk(tb, c_iv.a, s);
+    out[0] = s[0] ^ blk[0];
+    out[1] = s[1] ^ blk[1];
+    out[2] = s[2] ^ blk[2];
+    out[3] = (s[3] ^ blk[3]) & 0x7fffffffu;
+}
+
 __device__ __forceinline__ void prf_node_sha(const uint32_t x[4], uint32_t b, uint32_t out[4]) {
     uint32_t W[16] = {bswap32(x[0]), bswap32(x[1]), bswap32(x[2]), bswap32(x[3]),
                       (b << 24) | 0x00800000u, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 17u * 8u};

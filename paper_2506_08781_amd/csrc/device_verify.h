@@ -304,7 +304,8 @@ __device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, const uint3
 // Individual verification of the entry at batch position pos with signature
 // bytes sg (80): x_t equals the re-derived one-time seed, s_t < q, and
 // encode(e_t*Y + s_t*G) equals the R_t bytes.  On success e (mod q) and s are
-// returned.
+// returned.  inst: the instantiation word.  A POSLO++ message longer than 31
+// bytes fails and sets a.bad.
 template <class T>
 __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
                                            uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg_wide,
@@ -313,7 +314,19 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
     for (int k = 0; k < 4; k++) xs[k] = gload_le32(sg + 64 + 4 * k);
     EntryView ev = entry_view(a, pos);
     uint32_t dig[8];
-    if (inst == INST_AES) {
+    if (inst_base(inst) == INST_AES_ADDQ) {
+        if (ev.L > kAddqMaxLen) {
+            if (a.bad) *a.bad = 1u;
+            return false;
+        }
+        one_time_seed_aes(tb, a, pos, x);
+        if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
+        uint32_t mw[8];
+        addq_message<0>(ev.m, (uint32_t)ev.L, mw);
+        addq_digest(mw, x, e);
+        return verify_sig(sg, e, ty, tg_wide, s);
+    }
+    if (inst_base(inst) == INST_AES) {
         one_time_seed_aes(tb, a, pos, x);
         if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
         digest_mdc2_any(tb, ev, end, x, dig, Mdc2BlockGeneric{});

@@ -73,18 +73,21 @@ __device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const Ve
 // of the AVer hot kernel, 1,024 threads per workgroup)
 // AES: one 64 KB table per workgroup and x_t derived only for the final
 // blocks, so two 1,024-thread workgroups fit per CU (eight waves per SIMD)
+// POSLO++ (INST_AES_ADDQ): e_t = Add_q(m_t, x_t); a message longer than 31
+// bytes is marked bad (its x check fails) and sets a.bad.
 template <int INST, int BLOCK, int WPE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_distill_hash(
     BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
-    constexpr int TW = INST == INST_AES ? 256 * 64 : 1;
+    constexpr bool AESP = INST != INST_SHA256;  // AES-based PRF
+    constexpr int TW = AESP ? 256 * 64 : 1;
     __shared__ uint32_t lds[TW];
-    if constexpr (INST == INST_AES) perm_tables_fill<1>(lds);
+    if constexpr (AESP) perm_tables_fill<1>(lds);
     __syncthreads();
     const PermTables<1> tb = perm_tables<1>(lds);
     for (uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; p < a.n; p += (uint64_t)gridDim.x * BLOCK) {
         EntryView ev = entry_view(a, p);
         uint32_t x[4], dig[8];
-        if constexpr (INST == INST_AES) {
+        if constexpr (AESP) {
             const uint64_t t = a.t0 + p;
             const uint32_t jj = (uint32_t)(t & ((1ull << a.log2_n2) - 1));
             const uint32_t* rk = a.tab + ((t >> a.log2_n2) - a.epoch_first) * kEpochWords;
@@ -92,8 +95,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 y[0] = jj, y[1] = 0, y[2] = 0, y[3] = 0;
                 penc_rk(tb, rk, y);
                 y[0] ^= jj;
+                y[3] &= a.xmask;
             };
-            digest_mdc2_any_late(tb, ev, a.end, xf, x, dig, Mdc2BlockPerm{});
+            if constexpr (INST == INST_AES_ADDQ) {
+                if (ev.L > kAddqMaxLen) {
+                    *a.bad = 1u;
+#pragma unroll
+                    for (int w = 0; w < 8; w++) ekeys[p * 8 + w] = 0xffffffffu;
+                    xbad[p] = 1;
+                    continue;
+                }
+                xf(x);
+                uint32_t mw[8];
+                addq_message<0>(ev.m, (uint32_t)ev.L, mw);
+                addq_digest(mw, x, dig);
+            } else {
+                digest_mdc2_any_late(tb, ev, a.end, xf, x, dig, Mdc2BlockPerm{});
+            }
         } else {
             one_time_seed_sha(a, p, x);
             digest_sha_any(ev, a.end, x, dig);
@@ -179,14 +197,25 @@ __global__ __launch_bounds__(kTile) void k_ekeys_tiles(BatchArgs a, TileGeom g, 
     if (any && pos < end && !skipped(a, pos)) {
         uint32_t x[4], dig[8];
         EntryView ev = entry_view(a, pos);
-        if (inst == INST_AES) {
+        if (inst_base(inst) == INST_AES_ADDQ) {
+            if (ev.L > kAddqMaxLen) {
+                *a.bad = 1u;
+            } else {
+                one_time_seed_aes(tb, a, pos, x);
+                uint32_t mw[8];
+                addq_message<0>(ev.m, (uint32_t)ev.L, mw);
+                addq_digest(mw, x, dig);
+                acc288_add256(acc, dig);
+            }
+        } else if (inst_base(inst) == INST_AES) {
             one_time_seed_aes(tb, a, pos, x);
             digest_mdc2_any(tb, ev, a.end, x, dig, Mdc2BlockGeneric{});
+            acc288_add256(acc, dig);
         } else {
             one_time_seed_sha(a, pos, x);
             digest_sha_any(ev, a.end, x, dig);
+            acc288_add256(acc, dig);
         }
-        acc288_add256(acc, dig);
     }
     block_reduce288_store<kTile>(acc, tile_part + (uint64_t)blockIdx.x * 18);
 }
@@ -488,9 +517,12 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         prof_begin(c, POSLO_KT_VERIFY, s);
         void *ek, *xb;
         if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
-        if (prm->inst == POSLO_INST_AES)
+        if (inst_base(prm->inst) == INST_AES)
             hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a, sigs,
                                (uint32_t*)ek, (uint8_t*)xb);
+        else if (inst_base(prm->inst) == INST_AES_ADDQ)
+            hipLaunchKernelGGL((k_distill_hash<INST_AES_ADDQ, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a,
+                               sigs, (uint32_t*)ek, (uint8_t*)xb);
         else
             hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256, 4>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
                                sigs, (uint32_t*)ek, (uint8_t*)xb);
@@ -530,7 +562,9 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
     if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     prof_end(c, POSLO_KT_COMPACT, s);
     uint64_t count = 0;
+    uint32_t bad = 0;  // POSLO++: a message longer than 31 bytes
     if ((n && hipMemcpyAsync(&count, d_count, 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        (n && hipMemcpyAsync(&bad, a.bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipMemcpyAsync(ccd->valid_tag, d_valid_tag, 64, hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(POSLO_E_DEVICE);
     ccd->umb_tags.resize(n_umb * 64);
@@ -538,6 +572,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         return fail(POSLO_E_DEVICE);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(POSLO_E_DEVICE);
     prof_collect(c);
+    if (bad) return fail(POSLO_E_INVAL);
     ccd->invalid.resize(count);
     ccd->invalid_sigs.resize(count * 80);
     if (count) {
@@ -828,8 +863,11 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
         HIP_TRY(hipGetLastError());
         std::vector<uint32_t> hb(n_umb);
+        uint32_t bad = 0;
         HIP_TRY(hipMemcpyAsync(hb.data(), dbits, n_umb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&bad, a.bad, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return POSLO_E_INVAL;
         for (uint64_t l = 0; l < n_umb; l++) bits[l] = (uint8_t)hb[l];
         return POSLO_OK;
     }
@@ -866,8 +904,11 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         hipLaunchKernelGGL(k_verify_list, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);
         HIP_TRY(hipGetLastError());
         std::vector<uint8_t> hf(ni);
+        uint32_t bad = 0;
         HIP_TRY(hipMemcpyAsync(hf.data(), dflags, ni, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&bad, a.bad, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return POSLO_E_INVAL;
         for (uint64_t k = 0; k < ni; k++) bits[k] = hf[k] ? 0 : 1;
         return POSLO_OK;
     }

@@ -250,9 +250,12 @@ extern "C" int poslo_c_distill(poslo_ctx* c, const poslo_params* prm, const posl
                            (const uint32_t*)ds_s, key->d_r + 16 * i0, ky->d_table, c->d_gtable, (uint32_t*)dres);
         HIP_TRY(hipGetLastError());
         prof_end(c, POSLO_KT_VERIFY, s);
+        uint32_t bad = 0;  // POSLO++: a message longer than 31 bytes
         HIP_TRY(hipMemcpyAsync(bits.data(), dres, k * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&bad, a.bad, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         prof_collect(c);
+        if (bad) return POSLO_E_INVAL;
     }
     poslo_ccd* ccd = new (std::nothrow) poslo_ccd();
     if (!ccd) return POSLO_E_NOMEM;

@@ -90,9 +90,10 @@ inline void sha256(const uint8_t* in, size_t len, uint8_t out[32]) {
     for (int w = 0; w < 8; w++) store_le32(out + 4 * w, bswap32(H[w]));
 }
 
-// F: MMO-AES-128 (POSLO+) or SHA-256 truncated to 16 bytes (POSLO)
-inline void F(uint32_t inst, const uint8_t* in, size_t len, uint8_t out[16]) {
-    if (inst == INST_AES) {
+// F: MMO-AES-128 (POSLO+, POSLO++) or SHA-256 truncated to 16 bytes (POSLO);
+// spec is the instantiation word (common.h)
+inline void F(uint32_t spec, const uint8_t* in, size_t len, uint8_t out[16]) {
+    if (prf_is_aes(spec)) {
         mmo(in, len, out);
     } else {
         uint8_t d[32];
@@ -101,19 +102,30 @@ inline void F(uint32_t inst, const uint8_t* in, size_t len, uint8_t out[16]) {
     }
 }
 
-inline void H(uint32_t inst, const uint8_t* in, size_t len, uint8_t out[32]) {
-    if (inst == INST_AES)
-        mdc2(in, len, out);
-    else
+// H over a byte string: MDC-2-AES-128 or SHA-256 (Add_q takes the message
+// and the seed apart: digest_e)
+inline void H(uint32_t spec, const uint8_t* in, size_t len, uint8_t out[32]) {
+    if (inst_base(spec) == INST_SHA256)
         sha256(in, len, out);
+    else
+        mdc2(in, len, out);
 }
 
-// PRF_b(z) = F(z || b), b one byte
-inline void prf(uint32_t inst, uint32_t b, const uint8_t* in, size_t len, uint8_t out[16]) {
-    std::vector<uint8_t> z(len + 1);
-    if (len) memcpy(z.data(), in, len);
-    z[len] = (uint8_t)b;
-    F(inst, z.data(), z.size(), out);
+// PRF_b(z) = F(z || b), b one byte.  With kappa = 127 a 16-byte z is a seed
+// and b its bit 127, one MMO block; every output is then taken mod 2^127.
+inline void prf(uint32_t spec, uint32_t b, const uint8_t* in, size_t len, uint8_t out[16]) {
+    if (kappa127(spec) && len == 16) {
+        uint8_t blk[16];
+        memcpy(blk, in, 16);
+        blk[15] = (uint8_t)((blk[15] & 0x7f) | (b << 7));
+        F(spec, blk, 16, out);
+    } else {
+        std::vector<uint8_t> z(len + 1);
+        if (len) memcpy(z.data(), in, len);
+        z[len] = (uint8_t)b;
+        F(spec, z.data(), z.size(), out);
+    }
+    if (kappa127(spec)) out[15] &= 0x7f;
 }
 
 // ---- seed tree (section "POSLO Data Types and Seed Management") ---------
@@ -211,6 +223,30 @@ inline void sc_from_bytes_reduce(uint32_t r[8], const uint8_t b[32]) {
     uint32_t x[8];
     for (int i = 0; i < 8; i++) x[i] = load_le32(b + 4 * i);
     sc_reduce256(r, x);
+}
+
+// e_t = H(m || x) mod q as eight LE words; POSLO++ takes Add_q(m, x) =
+// LE(m) + LE(x), below q for |m| <= 31 bytes (false for longer messages)
+inline bool digest_e(uint32_t spec, const uint8_t* m, size_t len, const uint8_t x[16], uint32_t e[8]) {
+    if (inst_base(spec) == INST_AES_ADDQ) {
+        if (len > kAddqMaxLen) return false;
+        uint8_t mb[32] = {0};
+        if (len) memcpy(mb, m, len);
+        uint64_t c = 0;
+        for (int w = 0; w < 8; w++) {
+            c += (uint64_t)load_le32(mb + 4 * w) + (w < 4 ? load_le32(x + 4 * w) : 0u);
+            e[w] = (uint32_t)c;
+            c >>= 32;
+        }
+        return true;
+    }
+    std::vector<uint8_t> mx(len + 16);
+    if (len) memcpy(mx.data(), m, len);
+    memcpy(mx.data() + len, x, 16);
+    uint8_t d[32];
+    H(spec, mx.data(), mx.size(), d);
+    sc_from_bytes_reduce(e, d);
+    return true;
 }
 
 // (a * b) mod q: schoolbook product, then shift-and-subtract reduction

@@ -434,7 +434,7 @@ void poslo_server::run() {
 }
 
 extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out) {
-    if (!cfg || !out || !params_ok(&cfg->params)) return POSLO_E_INVAL;
+    if (!cfg || !out || !params_ok(&cfg->params) || cfg->params.inst > POSLO_INST_AES) return POSLO_E_INVAL;
     if (cfg->distill < 0 || cfg->distill > 2) return POSLO_E_INVAL;
     if (cfg->variant >= batch_variant_count() ||
         (cfg->variant >= 0 && batch_variant(cfg->variant).inst != (int)cfg->params.inst))
@@ -483,6 +483,18 @@ extern "C" int poslo_server_register_keys(poslo_server* S, const uint32_t* ids, 
     int st = ctx_keys_bulk(S->ctx, pks, n, tables, &bad);
     if (st) return st;
     std::lock_guard<std::mutex> lk(S->mu);
+    // an id registered again is replaced only while none of its requests is
+    // queued, admitted or in flight: its key table and state slot are in use
+    for (size_t k = 0; k < n; k++) {
+        auto it = S->keys.find(ids[k]);
+        if (it == S->keys.end()) continue;
+        const uint32_t slot = it->second.first;
+        if (S->launching || S->key_busy[slot]) return POSLO_E_BUSY;
+        for (const Req* q : S->pending)
+            if (q->key_slot == slot) return POSLO_E_BUSY;
+        for (const Req* q : S->admitted)
+            if (q->key_slot == slot) return POSLO_E_BUSY;
+    }
     size_t need = S->n_slots;
     for (size_t k = 0; k < n; k++)
         if (!S->keys.count(ids[k])) need++;

@@ -77,7 +77,7 @@ void derive(uint32_t inst, const uint8_t seed[32], const char* label, uint32_t c
 
 bool params_valid(const poslo_params* p) {
     if (!p) return false;
-    if (p->inst != POSLO_INST_AES && p->inst != POSLO_INST_SHA256) return false;
+    if (!poslo_inst_valid(p->inst)) return false;
     if (p->log2_n1 > 31 || p->log2_n2 > 31 || p->log2_n1 + p->log2_n2 > 32) return false;
     if (p->bpv_v == 0 || p->bpv_v > 65536 || (p->bpv_v & (p->bpv_v - 1))) return false;
     if (p->bpv_k == 0 || p->bpv_k > p->bpv_v) return false;
@@ -124,13 +124,8 @@ void sign_entry(const poslo_signer* sk, uint64_t t, const uint8_t x0[16], const 
     store_le32(in20 + 16, j);
     uint8_t x[16];
     prf(p.inst, 0, in20, 20, x);
-    std::vector<uint8_t> mx(len + 16);
-    if (len) memcpy(mx.data(), m, len);
-    memcpy(mx.data() + len, x, 16);
-    uint8_t d[32];
-    H(p.inst, mx.data(), mx.size(), d);
     uint32_t e[8], ey[8], s[8];
-    sc_from_bytes_reduce(e, d);
+    digest_e(p.inst, m, len, x, e);  // message lengths are checked by the caller
     sc_mul(ey, e, sk->y);
     sc_sub(s, r, ey);
     for (int w = 0; w < 8; w++) store_le32(sig + 4 * w, s[w]);
@@ -159,6 +154,10 @@ const BaseTable& poslo::hostside::base_table() {
         }
     });
     return *T;
+}
+
+extern "C" int poslo_inst_valid(uint32_t inst) {
+    return (inst & ~7u) == 0 && (inst & 3u) <= 2u && !((inst & POSLO_KAPPA127) && (inst & 3u) == 0u);
 }
 
 extern "C" const char* poslo_version(void) { return "poslo-mi355x 0.1"; }
@@ -238,6 +237,7 @@ static void advance_epochs(poslo_signer* sk, uint64_t n, std::vector<uint8_t>& s
 
 extern "C" int poslo_sig(poslo_signer* sk, const uint8_t* m, size_t len, uint8_t sig[80]) {
     if (!sk || !sig || (len && !m)) return POSLO_E_INVAL;
+    if (inst_base(sk->prm.inst) == INST_AES_ADDQ && len > kAddqMaxLen) return POSLO_E_INVAL;
     uint64_t n = 1ull << (sk->prm.log2_n1 + sk->prm.log2_n2);
     if (sk->t >= n) return POSLO_E_EXHAUSTED;
     uint64_t t = sk->t, first;
@@ -253,6 +253,9 @@ extern "C" int poslo_sig_batch(poslo_signer* sk, const uint8_t* msgs, const uint
     if (n == 0) return POSLO_OK;
     uint64_t cap = 1ull << (sk->prm.log2_n1 + sk->prm.log2_n2);
     if (sk->t > cap || n > cap - sk->t) return POSLO_E_EXHAUSTED;
+    if (inst_base(sk->prm.inst) == INST_AES_ADDQ)
+        for (uint64_t p = 0; p < n; p++)
+            if ((offsets ? offsets[p + 1] - offsets[p] : msg_len) > kAddqMaxLen) return POSLO_E_INVAL;
     uint64_t t0 = sk->t, first;
     std::vector<uint8_t> seeds;
     advance_epochs(sk, n, seeds, first);
@@ -298,14 +301,14 @@ extern "C" int poslo_agg(const uint8_t* sigs, size_t stride, uint64_t count, uin
 }
 
 extern "C" int poslo_prf_host(uint32_t inst, uint32_t b, const uint8_t* in, size_t len, uint8_t out16[16]) {
-    if ((inst != POSLO_INST_AES && inst != POSLO_INST_SHA256) || b > 1 || !out16 || (len && !in))
-        return POSLO_E_INVAL;
+    if (!poslo_inst_valid(inst) || b > 1 || !out16 || (len && !in)) return POSLO_E_INVAL;
+    if (kappa127(inst) && len == 16 && (in[15] & 0x80)) return POSLO_E_INVAL;
     prf(inst, b, in, len, out16);
     return POSLO_OK;
 }
 
 extern "C" int poslo_hash_host(uint32_t inst, const uint8_t* in, size_t len, uint8_t out32[32]) {
-    if ((inst != POSLO_INST_AES && inst != POSLO_INST_SHA256) || !out32 || (len && !in)) return POSLO_E_INVAL;
+    if (!poslo_inst_valid(inst) || inst_base(inst) == INST_AES_ADDQ || !out32 || (len && !in)) return POSLO_E_INVAL;
     H(inst, in, len, out32);
     return POSLO_OK;
 }

@@ -26,11 +26,12 @@ namespace poslo {
 
 // ---- F over a short input given as little-endian words ----------------------
 // z holds bytes 0..len-1 (len <= 44, bytes beyond len zero); returns F(z) as
-// four little-endian words (MMO-AES-128, or SHA-256 truncated to 16 bytes)
+// four little-endian words (MMO-AES-128, or SHA-256 truncated to 16 bytes),
+// reduced mod 2^127 at kappa = 127 (inst: the instantiation word)
 template <class T>
 __device__ __forceinline__ void dev_F_words(const T& tb, uint32_t inst, const uint32_t z[12], int len,
                                             uint32_t out[4]) {
-    if (inst == INST_AES) {
+    if (prf_is_aes(inst)) {
         int nb = (len + 15) / 16;
         uint32_t h[4];
         for (int b = 0; b < nb; b++) {
@@ -43,6 +44,7 @@ __device__ __forceinline__ void dev_F_words(const T& tb, uint32_t inst, const ui
             for (int w = 0; w < 4; w++) h[w] = s[w] ^ m[w];
         }
         for (int w = 0; w < 4; w++) out[w] = h[w];
+        if (kappa127(inst)) out[3] &= 0x7fffffffu;
     } else {
         uint32_t W[16];
         for (int w = 0; w < 16; w++) W[w] = 0;
@@ -183,20 +185,23 @@ __global__ __launch_bounds__(256) void k_sign_epochs(const SignJob* jobs, const 
     __syncthreads();
     LdsTables<4, 1> tb{lds};
     uint64_t row = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row == 0) tab[n_rows * kEpochWords] = 0u;  // POSLO++'s long-message flag
     if (row >= n_rows) return;
     const SignJob& J = jobs[job_of_epoch[row]];
     uint64_t i = (J.t0 >> log2_n2) + (row - J.epoch_base);
     uint32_t x[4] = {keys[J.key].root[0], keys[J.key].root[1], keys[J.key].root[2], keys[J.key].root[3]};
     for (int j = (int)D - 1; j >= 0; j--) {
         uint32_t b = (uint32_t)((i >> j) & 1u), nx[4];
-        if (inst == INST_AES)
+        if (prf_is_aes(inst) && kappa127(inst))
+            prf_node_aes127(tb, x, b, nx);
+        else if (prf_is_aes(inst))
             prf_node_aes(tb, x, b, nx);
         else
             prf_node_sha(x, b, nx);
         x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
     }
     uint32_t* e = tab + row * kEpochWords;
-    if (inst == INST_AES) {
+    if (prf_is_aes(inst)) {
         uint32_t s[4] = {x[0], x[1], x[2], x[3]};
         aes128_encrypt_rk(tb, c_iv.a, s);
         uint32_t h1[4] = {s[0] ^ x[0], s[1] ^ x[1], s[2] ^ x[2], s[3] ^ x[3]};
@@ -229,6 +234,7 @@ struct SignArgs {
     const uint32_t* tab;      // epoch table rows
     uint8_t* sigs;            // 80 bytes per global entry
     uint32_t* tile_part;      // per tile: lazy sums of s_t [9] and r_t [9]
+    uint32_t* bad;            // set when a POSLO++ message is longer than 31 bytes
 };
 
 __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
@@ -240,7 +246,15 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
     const SignJob J = A.jobs[T.job];
     const DevKey& K = A.keys[J.key];
     uint32_t as_[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ar[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (threadIdx.x < T.count) {
+    bool live = threadIdx.x < T.count;
+    if (live && inst_base(A.inst) == INST_AES_ADDQ) {
+        const uint64_t g = J.entry_base + T.first + threadIdx.x;
+        if (A.offsets[g + 1] - A.offsets[g] > kAddqMaxLen) {
+            *A.bad = 1u;
+            live = false;
+        }
+    }
+    if (live) {
         uint64_t p = T.first + threadIdx.x;  // entry within the job
         uint64_t t = J.t0 + p;
         uint64_t gidx = J.entry_base + p;
@@ -289,9 +303,15 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
         ba.tab = A.tab + J.epoch_base * kEpochWords;
         ba.skip = nullptr;
         ba.end = A.data + A.offsets[A.n_total];
+        ba.xmask = kappa127(A.inst) ? 0x7fffffffu : 0xffffffffu;
         EntryView ev = entry_view(ba, p);
         uint32_t x[4], dig[8];
-        if (A.inst == INST_AES) {
+        if (inst_base(A.inst) == INST_AES_ADDQ) {
+            one_time_seed_aes(tb, ba, p, x);
+            uint32_t mw[8];
+            addq_message<0>(ev.m, (uint32_t)ev.L, mw);
+            addq_digest(mw, x, dig);
+        } else if (inst_base(A.inst) == INST_AES) {
             one_time_seed_aes(tb, ba, p, x);
             digest_mdc2_any(tb, ev, ba.end, x, dig, Mdc2BlockGeneric{});
         } else {
@@ -427,7 +447,7 @@ void to_mont(uint32_t out[8], const uint32_t y[8]) {
 extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, const uint8_t* seeds, uint32_t nkeys,
                                      poslo_gpu_keys** out, uint8_t* pks) {
     if (!c || !prm || !out || (nkeys && (!seeds || !pks))) return POSLO_E_INVAL;
-    if (prm->inst > 1 || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
+    if (!poslo_inst_valid(prm->inst) || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
         prm->bpv_k == 0 || prm->bpv_k > 16 || prm->bpv_k > prm->bpv_v || prm->log2_n1 + prm->log2_n2 > 32)
         return POSLO_E_INVAL;
     *out = nullptr;
@@ -551,7 +571,7 @@ extern "C" int poslo_gpu_sign(poslo_gpu_keys* K, const poslo_sign_job* jobs, uin
     if ((st = ctx_scratch(c, 8, std::max<size_t>(njobs, 1) * sizeof(SignJob), &d_jobs)) ||
         (st = ctx_scratch(c, 9, std::max<size_t>(tiles.size(), 1) * sizeof(SignTile), &d_tiles)) ||
         (st = ctx_scratch(c, 10, std::max<size_t>(rows, 1) * 4, &d_joe)) ||
-        (st = ctx_scratch(c, 11, std::max<size_t>(rows, 1) * kEpochWords * 4, &d_tab)) ||
+        (st = ctx_scratch(c, 11, epoch_tab_words(rows) * 4, &d_tab)) ||
         (st = ctx_scratch(c, 12, std::max<size_t>(tiles.size(), 1) * 72, &d_part)) ||
         (st = ctx_scratch(c, 13, std::max<size_t>(njobs, 1) * 8, &d_tend)) ||
         (st = ctx_scratch(c, 14, std::max<size_t>(njobs, 1) * 64, &d_tags)))
@@ -582,12 +602,15 @@ extern "C" int poslo_gpu_sign(poslo_gpu_keys* K, const poslo_sign_job* jobs, uin
         A.tab = (const uint32_t*)d_tab;
         A.sigs = sigs;
         A.tile_part = (uint32_t*)d_part;
+        A.bad = (uint32_t*)d_tab + rows * kEpochWords;
         hipLaunchKernelGGL(k_sign, dim3((uint32_t)tiles.size()), dim3(256), 0, s, A);
     }
     hipLaunchKernelGGL(k_sign_tags, dim3(njobs), dim3(256), 0, s, (const SignJob*)d_jobs, (const uint32_t*)d_part,
                        (const uint64_t*)d_tend, c->d_gtable, (uint8_t*)d_tags);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(tags, d_tags, (size_t)njobs * 64, hipMemcpyDeviceToHost, s));
+    uint32_t bad = 0;
+    if (rows) HIP_TRY(hipMemcpyAsync(&bad, (uint32_t*)d_tab + rows * kEpochWords, 4, hipMemcpyDeviceToHost, s));
     if (ds_out) {
         for (uint32_t j = 0; j < njobs; j++) {
             const DevKey& dk = K->host[jobs[j].key];
@@ -602,5 +625,5 @@ extern "C" int poslo_gpu_sign(poslo_gpu_keys* K, const poslo_sign_job* jobs, uin
         }
     }
     HIP_TRY(hipStreamSynchronize(s));
-    return POSLO_OK;
+    return bad ? POSLO_E_INVAL : POSLO_OK;
 }

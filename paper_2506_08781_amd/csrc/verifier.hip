@@ -33,14 +33,16 @@ namespace poslo {
 
 // AES: four lanes per epoch (aes_quad.h), so each link of the walk's chain
 // of dependent PRF calls costs about a third of a one-lane encryption;
-// SHA-256: one lane per epoch.
-template <int INST>
+// SHA-256: one lane per epoch.  K127: kappa = 127, one AES per tree level.
+// The first thread also clears the flag word after the last row (tab.bad).
+template <int INST, bool K127>
 __global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_first, uint32_t n_epochs, uint32_t* tab) {
     __shared__ uint32_t lds[INST == INST_AES ? 4 * 256 : 1];
     if constexpr (INST == INST_AES) lds_tables_fill<4, 1>(lds);
     __syncthreads();
     const LdsTables<4, 1> tb{lds};
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) tab[(uint64_t)n_epochs * kEpochWords] = 0u;
     const uint32_t ep = INST == INST_AES ? g >> 2 : g, c = g & 3u;
     if (ep >= n_epochs) return;  // whole quads leave together
     uint64_t i = epoch_first + ep;
@@ -50,7 +52,10 @@ __global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_firs
     if constexpr (INST == INST_AES) {
         uint32_t xc = ds.v[k][c];
         // SC: walk the bits of i below the node's depth, most significant first
-        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) xc = quad_prf_node(tb, xc, (uint32_t)((i >> j) & 1u), c);
+        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) {
+            const uint32_t b = (uint32_t)((i >> j) & 1u);
+            xc = K127 ? quad_prf_node127(tb, xc, b, c) : quad_prf_node(tb, xc, b, c);
+        }
         quad_epoch_row(tb, xc, c, e);
     } else {
         uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
@@ -85,6 +90,7 @@ struct FinalArgs {
     uint32_t rx[8];      // decoded R (affine)
     uint32_t ry[8];
     uint32_t* result;
+    const uint32_t* bad;  // POSLO++ long-message flag, or nullptr
 };
 
 static_assert(kBlock == kQuadBlock, "the aggregate check takes the whole block");
@@ -124,8 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f) {
     // e*Y + s*G == R, with R decoded on the host
     const bool eq = block_double_scalar_is(pts, f.ty, f.tg, e, sv, rx, ry);
     if (threadIdx.x == 0) {
-        f.result[8] = (f.checks_ok && eq) ? 1u : 0u;
-        f.result[9] = 0;
+        const uint32_t bad = f.bad ? *f.bad : 0u;
+        f.result[8] = (f.checks_ok && eq && !bad) ? 1u : 0u;
+        f.result[9] = bad ? 1u : 0u;
     }
 }
 
@@ -197,9 +204,10 @@ namespace poslo {
 // every GPU the library runs on holds until the process ends
 // ---------------------------------------------------------------------------
 
+static_assert(kTabRowWords == (size_t)kEpochWords, "epoch row size");
 constexpr uint64_t kFixedMaxEpochs = POSLO_AVER_FIXED_MAX_EPOCHS;
 constexpr uint32_t kFixedMaxGrid = 4096;
-constexpr size_t kFixedTabWords = (size_t)kFixedMaxEpochs * kEpochWords;
+constexpr size_t kFixedTabWords = epoch_tab_words(kFixedMaxEpochs);
 constexpr size_t kFixedPartWords = (size_t)kFixedMaxGrid * 9;
 constexpr size_t kFixedWords = kFixedTabWords + kFixedPartWords + 64;
 static_assert(kFixedWords * 4 == (size_t)POSLO_AVER_FIXED_SCRATCH_BYTES, "scratch size in the header");
@@ -326,18 +334,21 @@ extern "C" int poslo_ctx_set_tuning(poslo_ctx* c, int agg_variant, int wg_per_cu
 namespace poslo {
 
 bool params_ok(const poslo_params* p) {
-    return p && (p->inst == POSLO_INST_AES || p->inst == POSLO_INST_SHA256) && p->log2_n1 <= 31 &&
+    return p && poslo_inst_valid(p->inst) && p->log2_n1 <= 31 &&
            p->log2_n2 <= 31 && p->log2_n1 + p->log2_n2 <= 40;
 }
 
 // host-side checks shared by the verifier entry points; fills the kernel
 // argument block and the by-value ds.  The epoch table goes to the
 // context's buffer (grown as needed), or to fixed_tab when it is set (no
-// allocation; E_INVAL beyond fixed_epochs epochs).
+// allocation; E_INVAL beyond fixed_epochs epochs; fixed_tab holds
+// epoch_tab_words(fixed_epochs) words).  The word after the last epoch row
+// is POSLO++'s long-message flag (a.bad).
 int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, const uint8_t* ds, size_t ds_len,
                   BatchArgs& a, DsArg& dsa, uint32_t& n_epochs, uint32_t* fixed_tab, uint64_t fixed_epochs) {
     if (!c || !params_ok(prm) || !m) return POSLO_E_INVAL;
-    if (m->n > 0 && !m->data) return POSLO_E_INVAL;
+    // data may be null only for a fixed length of zero (nothing is read)
+    if (m->n > 0 && !m->data && (m->offsets || m->msg_len)) return POSLO_E_INVAL;
     uint64_t nmax = 1ull << (prm->log2_n1 + prm->log2_n2);
     if (m->t0 > nmax || m->n > nmax - m->t0) return POSLO_E_INVAL;
     if (m->n >= (1ull << 32)) return POSLO_E_INVAL;  // keeps the lazy sum below 2^288
@@ -359,6 +370,12 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     a.log2_n2 = prm->log2_n2;
     a.skip = nullptr;
     a.tab = nullptr;
+    a.bad = nullptr;
+    a.xmask = kappa127(prm->inst) ? 0x7fffffffu : 0xffffffffu;
+    // POSLO++ on a fixed-length batch: the length is checked here, a
+    // variable-length batch's lengths by the kernels (a.bad)
+    if (inst_base(prm->inst) == INST_AES_ADDQ && !m->offsets && m->msg_len > kAddqMaxLen && m->n > 0)
+        return POSLO_E_INVAL;
     if (m->data_bytes)
         a.end = m->data + m->data_bytes;
     else if (!m->offsets)
@@ -370,17 +387,22 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     if (m->n == 0) return POSLO_OK;
     uint64_t e_last = (m->t0 + m->n - 1) >> prm->log2_n2;
     uint64_t ne = e_last - a.epoch_first + 1;
-    // SR must succeed for every epoch of the batch (bottom is an error)
-    for (uint64_t i = a.epoch_first; i <= e_last; i++)
-        if (hostside::sr_node(nodes, count, i) < 0) return POSLO_E_SEED;
+    // SR must succeed for every epoch of the batch (bottom is an error); at
+    // kappa = 127 a node that is walked must be a 127-bit seed
+    for (uint64_t i = a.epoch_first; i <= e_last; i++) {
+        const int k = hostside::sr_node(nodes, count, i);
+        if (k < 0) return POSLO_E_SEED;
+        if (kappa127(prm->inst) && nodes[k].depth > 0 && (nodes[k].v[15] & 0x80)) return POSLO_E_INVAL;
+    }
     if (fixed_tab) {
         if (ne > fixed_epochs) return POSLO_E_INVAL;
         a.tab = fixed_tab;
     } else {
-        int st = ctx_ensure(&c->d_tab, &c->tab_words, (size_t)ne * kEpochWords);
+        int st = ctx_ensure(&c->d_tab, &c->tab_words, epoch_tab_words(ne));
         if (st) return st;
         a.tab = c->d_tab;
     }
+    a.bad = const_cast<uint32_t*>(a.tab) + ne * kEpochWords;
     n_epochs = (uint32_t)ne;
     return POSLO_OK;
 }
@@ -391,12 +413,16 @@ bool fast_layout(const poslo_msgs* m, uint64_t align) {
 
 int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s) {
     if (n_epochs == 0) return POSLO_OK;
-    if (inst == INST_AES)
-        hipLaunchKernelGGL(k_seed_table<INST_AES>, dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa, a.epoch_first,
-                           n_epochs, const_cast<uint32_t*>(a.tab));
+    uint32_t* tab = const_cast<uint32_t*>(a.tab);
+    if (prf_is_aes(inst) && kappa127(inst))
+        hipLaunchKernelGGL((k_seed_table<INST_AES, true>), dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa,
+                           a.epoch_first, n_epochs, tab);
+    else if (prf_is_aes(inst))
+        hipLaunchKernelGGL((k_seed_table<INST_AES, false>), dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa,
+                           a.epoch_first, n_epochs, tab);
     else
-        hipLaunchKernelGGL(k_seed_table<INST_SHA256>, dim3((n_epochs + 63) / 64), dim3(64), 0, s, dsa,
-                           a.epoch_first, n_epochs, const_cast<uint32_t*>(a.tab));
+        hipLaunchKernelGGL((k_seed_table<INST_SHA256, false>), dim3((n_epochs + 63) / 64), dim3(64), 0, s, dsa,
+                           a.epoch_first, n_epochs, tab);
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 
@@ -417,7 +443,14 @@ namespace poslo {
 
 AggShape agg_shape(const poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m) {
     AggShape g{};
-    if (prm->inst == POSLO_INST_AES) {
+    const uint32_t base = inst_base(prm->inst);
+    if (base == INST_AES_ADDQ) {
+        g.addq_layout = (fast_layout(m, 16) && m->msg_len == 16) ? 2 : fast_layout(m, 4) ? 1 : 0;
+        uint64_t want = (m->n + agg_addq_block() - 1) / agg_addq_block();
+        // two 1,024-thread workgroups (64 KB of tables each) per CU
+        uint64_t cap = (uint64_t)c->num_cu * (c->wg_per_cu > 0 ? c->wg_per_cu : 2);
+        g.grid = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    } else if (base == INST_AES) {
         g.fast = fast_layout(m, 16);
         g.variant = g.fast ? (c->agg_variant >= 0 ? c->agg_variant : agg_aes_default_variant()) : -1;
         // the any-layout form shares the default variant's shape
@@ -440,7 +473,9 @@ int launch_agg(poslo_ctx* c, const poslo_params* prm, const AggShape& g, const B
                uint32_t* e_out, uint32_t* x_out, hipStream_t s) {
     int st;
     prof_begin(c, POSLO_KT_AGG, s);
-    if (prm->inst == POSLO_INST_AES) {
+    if (inst_base(prm->inst) == INST_AES_ADDQ) {
+        st = launch_agg_addq(g.addq_layout, g.grid, &a, partials, e_out, x_out, s);
+    } else if (inst_base(prm->inst) == INST_AES) {
         if (e_out && g.fast && g.variant != agg_aes_default_variant()) return POSLO_E_INVAL;
         st = e_out ? launch_agg_aes_emit(g.fast, g.grid, &a, partials, e_out, x_out, s)
                    : launch_agg_aes(g.variant, g.fast, g.grid, &a, partials, s);
@@ -522,15 +557,18 @@ int stage_msgs(poslo_ctx* c, const poslo_msgs* m, hipStream_t s, poslo_msgs& dm,
 }
 
 // The final fold of n_part partials, mod q and the check R = e*Y + s*G
-// against the tag, with accept and e mod q read back (synchronizes s)
+// against the tag, with accept and e mod q read back (synchronizes s).
+// E_INVAL if the device flag bad (when given) is set: POSLO++ met a message
+// longer than 31 bytes.
 int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uint32_t n_part,
-                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32]) {
+                const uint8_t tag[64], hipStream_t s, int* accept, uint8_t e_out[32], const uint32_t* bad) {
     FinalArgs f;
     f.partials = partials;
     f.n_part = n_part;
     f.ty = key->d_table;
     f.tg = c->d_gtable;
     f.result = c->d_result;
+    f.bad = bad;
     tag_checks(tag, f);
     prof_begin(c, POSLO_KT_FINAL, s);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
@@ -539,6 +577,7 @@ int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uin
     HIP_TRY(hipMemcpyAsync(c->h_result, c->d_result, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     prof_collect(c);
+    if (c->h_result[9]) return POSLO_E_INVAL;
     *accept = c->h_result[8] ? 1 : 0;
     if (e_out)
         for (int w = 0; w < 8; w++) store_le32(e_out + 4 * w, c->h_result[w]);
@@ -573,7 +612,7 @@ int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
         if ((st = launch_agg(c, prm, g, a, c->d_part, nullptr, nullptr, s))) return st;
         n_part = g.grid;
     }
-    return final_check(c, key, c->d_part, n_part, tag, s, accept, e_out);
+    return final_check(c, key, c->d_part, n_part, tag, s, accept, e_out, n_epochs ? a.bad : nullptr);
 }
 
 }  // namespace poslo
@@ -642,8 +681,10 @@ extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uin
     if (m->n > 0) {
         AggShape g = agg_shape(c, prm, m);
         g.grid = std::min(g.grid, kFixedMaxGrid);
-        st = prm->inst == POSLO_INST_AES ? launch_agg_aes(g.variant, g.fast, g.grid, &a, fx_part, s)
-                                          : launch_agg_sha(g.sha_layout, g.grid, &a, fx_part, s);
+        const uint32_t base = inst_base(prm->inst);
+        st = base == INST_AES        ? launch_agg_aes(g.variant, g.fast, g.grid, &a, fx_part, s)
+             : base == INST_AES_ADDQ ? launch_agg_addq(g.addq_layout, g.grid, &a, fx_part, nullptr, nullptr, s)
+                                     : launch_agg_sha(g.sha_layout, g.grid, &a, fx_part, s);
         if (st) return st;
         n_part = g.grid;
     }
@@ -653,11 +694,13 @@ extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uin
     f.ty = key->d_table;
     f.tg = c->d_gtable;
     f.result = fx_result;
+    f.bad = n_epochs ? a.bad : nullptr;
     tag_checks(tag, f);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->h_result, fx_result, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (c->h_result[9]) return POSLO_E_INVAL;
     *accept = c->h_result[8] ? 1 : 0;
     if (e_out)
         for (int w = 0; w < 8; w++) store_le32(e_out + 4 * w, c->h_result[w]);

@@ -170,3 +170,33 @@ def test_server_rejects_bad_requests(P, gpu):
     assert res[1] == (P.POSLO_OK, True, [])  # no entries: the empty sum checks against the identity tag
     assert res[2] == (P.POSLO_OK, True, [])
     srv.close()
+
+
+def test_server_reregistration_waits_for_the_keys_requests(P, gpu):
+    """An id registered again while its requests are queued or in flight is
+    refused (E_BUSY, nothing registered); once they are done it is replaced
+    with a fresh aggregate state."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    jobs, data, off, sigs, *_ = corrupted_case(1)
+    j = jobs[0]
+    n = j["n"]
+    off = np.asarray(off, dtype=np.uint64)
+    m = np.frombuffer(data, dtype=np.uint8)[:int(off[n])].copy()
+    o = off[:n + 1].copy()
+    sg = np.frombuffer(sigs, dtype=np.uint8)[:80 * n].copy()
+    params = P.make_params(1, L1, L2)
+    srv = P.Server(0, params, n_streams=2, distill=1)
+    srv.register_keys([7, 9], [j["pk"], j["pk"]])
+    # one request per key is in flight at a time: the rest of the 500 wait
+    tickets = [srv.submit(P.Request(7, 0, n, m, o, 0, sg, j["ds"], j["tag"], user=k)) for k in range(500)]
+    with pytest.raises(P.PosloError) as ei:
+        srv.register_keys([9, 7], [j["pk"], j["pk"]])
+    assert ei.value.status == P.POSLO_E_BUSY
+    res = collect(srv, tickets)
+    assert all(r[:3] == (P.POSLO_OK, True, []) for r in res.values())
+    tag, entries = srv.key_state(7)
+    assert tag == O.agg([j["tag"]] * 500) and entries == 500 * n
+    srv.register_keys([7], [j["pk"]])
+    assert srv.key_state(7) == (O.agg([]), 0)
+    srv.close()

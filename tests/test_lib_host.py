@@ -57,6 +57,63 @@ def test_host_signer_matches_oracle(P, O, inst):
     assert P.poslo_signer_count(sk2) == len(lens)
 
 
+VARIANTS = [1 | 4, 2, 2 | 4]  # POSLO+ at kappa = 127, POSLO++ at 128 and 127
+
+
+@pytest.mark.parametrize("inst", VARIANTS)
+def test_host_prf_of_variants_matches_oracle(P, O, inst):
+    rng = random.Random(inst + 7)
+    for n in list(range(0, 40)) + [41, 42, 64]:
+        d = bytearray(rng.randrange(256) for _ in range(n))
+        if n == 16:
+            d[15] &= 0x7F  # a 127-bit seed
+        for b in (0, 1):
+            assert P.poslo_prf_host(inst, b, bytes(d)) == O.prf(inst, b, bytes(d)), (n, b)
+    if inst & 4:
+        with pytest.raises(P.PosloError):
+            P.poslo_prf_host(inst, 0, bytes(15) + b"\x80")
+    if inst & 3 == 2:
+        with pytest.raises(P.PosloError):
+            P.poslo_hash_host(inst, b"abc")
+    else:
+        assert P.poslo_hash_host(inst, b"abc") == O.H(inst, b"abc")
+
+
+@pytest.mark.parametrize("inst", VARIANTS)
+def test_host_signer_of_variants_matches_oracle(P, O, inst):
+    seed = synthlog.key_seed_bytes(0x41)
+    prm = P.make_params(inst, 3, 2)
+    sk, pk = P.poslo_kg(prm, seed)
+    osk, opk = O.kg(O.Params(inst, 3, 2), seed)
+    assert pk == opk
+    lens = [0, 5, 16, 17, 31, 30, 1, 3, 12, 9, 31]
+    data, off = synthlog.messages_var(10, np.array(lens))
+    msgs = [bytes(data[off[k]:off[k + 1]]) for k in range(len(lens))]
+    sigs = [P.poslo_sig(sk, m) for m in msgs]
+    for k, m in enumerate(msgs):
+        assert sigs[k] == O.sig(osk, m), k
+    assert P.poslo_ds_export(sk) == O.ds_encode(osk.ds)
+    sk2, _ = P.poslo_kg(prm, seed)
+    assert P.poslo_sig_batch(sk2, data, offsets=off, nthreads=3).tobytes() == b"".join(sigs)
+    if inst & 3 == 2:
+        # Add_q takes at most 31 bytes; the refused call leaves the state alone
+        with pytest.raises(P.PosloError) as ei:
+            P.poslo_sig(sk, bytes(32))
+        assert ei.value.status == P.POSLO_E_INVAL
+        assert P.poslo_signer_count(sk) == len(lens)
+        with pytest.raises(P.PosloError):
+            P.poslo_sig_batch(sk2, np.zeros((2, 32), np.uint8))
+        assert P.poslo_signer_count(sk2) == len(lens)
+
+
+def test_instantiation_words(P):
+    for inst in (0, 1, 2, 5, 6):
+        P.poslo_kg(P.make_params(inst, 1, 1), bytes(32))
+    for inst in (3, 4, 7, 8, 0x101):
+        with pytest.raises(P.PosloError):
+            P.poslo_kg(P.make_params(inst, 1, 1), bytes(32))
+
+
 def test_signer_exhaustion_and_bad_params(P):
     prm = P.make_params(1, 1, 1)
     sk, pk = P.poslo_kg(prm, bytes(32))

@@ -74,8 +74,9 @@ SERVING = dict(keys=10000, distinct=1500, max_batch=1 << 18, L=128, p_corrupt=0.
 # arithmetic for message pointers are not counted, so this is a lower bound
 # of the executed instruction count; rocprof's SQ_INSTS_VALU cross-checks it)
 # ---------------------------------------------------------------------------
-# AES-128 over byte-addressed T-tables: a full round is 16 table-address
-# v_perm, 8 rotations of the odd tables and 8 three-input xors (32); the
+# AES-128 over byte-addressed T-tables (te0 and te0 rotated by 16): a full
+# round is 16 table-address v_perm, 4 rotations, 4 xors and 8 xor-type ops
+# of three or two inputs (32); the
 # final round is 16 address v_perm, 8 byte-merge v_perm, 4 ors, 4 xors (32);
 # a key-schedule round is 4 address v_perm, 2 merge v_perm, 1 or, 1 xor3 and
 # 3 xors (11); the initial key addition is 4.
@@ -112,12 +113,13 @@ def ops_per_entry(inst: int, L):
 # The same operations split by measured issue class: poslo_valu_probe shows
 # v_xor_b32 and v_bitop3_b32 (xor-class) issuing about 1.6 times faster than
 # v_perm_b32, v_alignbit_b32, v_add3_u32 and v_mad_u64_u32 (perm-class) on
-# MI355X.  AES: a full round is 24 perm-class (16 addresses, 8 rotations)
-# and 8 xor-class; the final round 24 and 8; a key-schedule round 6 and 5;
-# the key addition 0 and 4.  SHA-256: a round is 10 perm-class (six
+# MI355X.  AES (two tables, aes_perm.h): a full round is 20 perm-class (16
+# addresses, 4 rotations) and 12 xor-class (T1[y] ^ T3[z] is taken as
+# rot8(T0[y] ^ T2[z])); the final round 24 and 8; a key-schedule round 6
+# and 5; the key addition 0 and 4.  SHA-256: a round is 10 perm-class (six
 # rotations, four sums) and 4 xor-class (two three-input xors, Ch, Maj); a
 # schedule word 8 and 2; shifts and or-merges are counted perm-class.
-AES_RK_CLS = (9 * 24 + 24, 9 * 8 + 8 + 4)
+AES_RK_CLS = (9 * 20 + 24, 9 * 12 + 8 + 4)
 AES_OTF_CLS = (AES_RK_CLS[0] + 10 * 6, AES_RK_CLS[1] + 10 * 5)
 SHA_COMP_CLS = (64 * 10 + 48 * 8 + 8, 64 * 4 + 48 * 2)
 ADDQ_CLS = (AES_RK_CLS[0] + 1 + 12 + 9, AES_RK_CLS[1] + 1)

@@ -11,6 +11,12 @@
 //
 // NT = 2 keeps te0 and te0 rotated by 16 (128 KB); the odd rotations are one
 // v_alignbit away.  NT = 1 keeps te0 only (64 KB) and rotates for the rest.
+//
+// CP = 32 copies (NT <= 2): entry x of copy c at (x << 8) | (t << 7) | (c << 2),
+// lane l reading copy l mod 32, so NT = 2 fits in 64 KB.  The two lanes of a
+// wave that share a copy (l and l + 32) are served in different halves of
+// the wave's LDS access when the LDS takes 32 lanes per cycle, which is what
+// the PMC counters confirm (no bank conflicts on gfx950).
 // S-box bytes for the key schedule and the final round come out of te0 (S
 // sits in bytes 1 and 2) and are merged with v_perm_b32.  Three-input XORs
 // use v_bitop3_b32.
@@ -28,8 +34,9 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-template <int NT>
+template <int NT, int CP = 64>
 struct PermTables {
+    static_assert(CP == 64 || (CP == 32 && NT <= 2), "64 copies, or 32 copies of at most two tables");
     const uint8_t* lds;
     uint32_t base0;  // lane offset, table 0
     uint32_t base2;  // lane offset | 1 << 16, table 1 (te0 rotated by 16)
@@ -52,8 +59,14 @@ struct PermTables {
 // once; then, per entry, the owning lane's word is read into a scalar
 // register and the wave writes the entry's 64 copies (64 consecutive words,
 // one store).  Needs a workgroup size that is a multiple of 64.
-template <int NT>
+template <int NT, int CP = 64>
 __device__ __forceinline__ void perm_tables_fill(uint32_t* lds) {
+    if constexpr (CP == 32) {
+        // word (x << 6) | (t << 5) | c holds te0[x] rotated by 16 t
+        for (uint32_t w = threadIdx.x; w < NT * 256u * 32u; w += blockDim.x)
+            lds[w] = rotl32(c_aes.te0[w >> 6], 16 * ((w >> 5) & 1u));
+        return;
+    }
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const uint32_t v0 = c_aes.te0[4 * lane], v1 = c_aes.te0[4 * lane + 1], v2 = c_aes.te0[4 * lane + 2],
                    v3 = c_aes.te0[4 * lane + 3];
@@ -65,23 +78,31 @@ __device__ __forceinline__ void perm_tables_fill(uint32_t* lds) {
     }
 }
 
-template <int NT>
-__device__ __forceinline__ PermTables<NT> perm_tables(const uint32_t* lds) {
-    uint32_t lane4 = (threadIdx.x & 63u) << 2;
-    return PermTables<NT>{reinterpret_cast<const uint8_t*>(lds), lane4, lane4 | (1u << 16)};
+template <int NT, int CP = 64>
+__device__ __forceinline__ PermTables<NT, CP> perm_tables(const uint32_t* lds) {
+    uint32_t lane4 = (threadIdx.x & (CP - 1u)) << 2;
+    return PermTables<NT, CP>{reinterpret_cast<const uint8_t*>(lds), lane4, lane4 | (CP == 64 ? 1u << 16 : 0x80u)};
 }
 
 // full round: out_c = T0[s_c.b0] ^ T1[s_{c+1}.b1] ^ T2[s_{c+2}.b2] ^ T3[s_{c+3}.b3] ^ k_c
-template <int NT>
-__device__ __forceinline__ void pround(const PermTables<NT>& tb, uint32_t s[4], const uint32_t k[4]) {
+template <int NT, int CP>
+__device__ __forceinline__ void pround(const PermTables<NT, CP>& tb, uint32_t s[4], const uint32_t k[4]) {
     uint32_t n[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        uint32_t a = tb.T0(s[c], 0);
-        uint32_t b = rotl32(tb.T0(s[(c + 1) & 3], 1), 8);
-        uint32_t d = tb.T2(s[(c + 2) & 3], 2);
-        uint32_t e = rotl32(tb.T2(s[(c + 3) & 3], 3), 8);
-        n[c] = xor3(xor3(a, b, d), e, k[c]);
+        if constexpr (NT == 2) {
+            // T1[y] ^ T3[z] = rot8(T0[y] ^ T2[z]): one rotation, and the
+            // xors (which issue faster than rotations) take the rest
+            const uint32_t a = tb.T0(s[c], 0), d = tb.T2(s[(c + 2) & 3], 2);
+            const uint32_t v = tb.T0(s[(c + 1) & 3], 1) ^ tb.T2(s[(c + 3) & 3], 3);
+            n[c] = xor3(a, d, k[c]) ^ rotl32(v, 8);
+        } else {
+            uint32_t a = tb.T0(s[c], 0);
+            uint32_t b = rotl32(tb.T0(s[(c + 1) & 3], 1), 8);
+            uint32_t d = tb.T2(s[(c + 2) & 3], 2);
+            uint32_t e = rotl32(tb.T2(s[(c + 3) & 3], 3), 8);
+            n[c] = xor3(xor3(a, b, d), e, k[c]);
+        }
     }
 #pragma unroll
     for (int c = 0; c < 4; c++) s[c] = n[c];
@@ -96,8 +117,8 @@ __device__ __forceinline__ uint32_t sbytes(uint32_t ta, uint32_t tb_, uint32_t t
 }
 
 // final round: S bytes, ShiftRows, AddRoundKey
-template <int NT>
-__device__ __forceinline__ void pround_final(const PermTables<NT>& tb, uint32_t s[4], const uint32_t k[4]) {
+template <int NT, int CP>
+__device__ __forceinline__ void pround_final(const PermTables<NT, CP>& tb, uint32_t s[4], const uint32_t k[4]) {
     uint32_t n[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
@@ -110,8 +131,8 @@ __device__ __forceinline__ void pround_final(const PermTables<NT>& tb, uint32_t 
 }
 
 // next round key: w0 ^= SubWord(RotWord(w3)) ^ rcon, then the chain
-template <int NT>
-__device__ __forceinline__ void pnext_key(const PermTables<NT>& tb, uint32_t k[4], uint32_t rcon) {
+template <int NT, int CP>
+__device__ __forceinline__ void pnext_key(const PermTables<NT, CP>& tb, uint32_t k[4], uint32_t rcon) {
     uint32_t w3 = k[3];
     uint32_t sub = sbytes(tb.T0(w3, 1), tb.T0(w3, 2), tb.T0(w3, 3), tb.T0(w3, 0));
     k[0] = xor3(k[0], sub, rcon);
@@ -128,8 +149,8 @@ __device__ __forceinline__ constexpr uint32_t prcon(int r) {
 
 // E_key(s) with the key schedule on the fly; two independent encryptions
 // interleaved (the two MDC-2 lanes), rounds fully unrolled
-template <int NT>
-__device__ __forceinline__ void penc2_otf(const PermTables<NT>& tb, const uint32_t keya[4], uint32_t sa[4],
+template <int NT, int CP>
+__device__ __forceinline__ void penc2_otf(const PermTables<NT, CP>& tb, const uint32_t keya[4], uint32_t sa[4],
                                           const uint32_t keyb[4], uint32_t sb[4]) {
     uint32_t ka[4] = {keya[0], keya[1], keya[2], keya[3]};
     uint32_t kb[4] = {keyb[0], keyb[1], keyb[2], keyb[3]};
@@ -152,8 +173,8 @@ __device__ __forceinline__ void penc2_otf(const PermTables<NT>& tb, const uint32
 }
 
 // E with a precomputed schedule rk[44]
-template <int NT>
-__device__ __forceinline__ void penc_rk(const PermTables<NT>& tb, const uint32_t* rk, uint32_t s[4]) {
+template <int NT, int CP>
+__device__ __forceinline__ void penc_rk(const PermTables<NT, CP>& tb, const uint32_t* rk, uint32_t s[4]) {
 #pragma unroll
     for (int c = 0; c < 4; c++) s[c] ^= rk[c];
 #pragma unroll
@@ -162,8 +183,8 @@ __device__ __forceinline__ void penc_rk(const PermTables<NT>& tb, const uint32_t
 }
 
 // two encryptions under two precomputed schedules, interleaved
-template <int NT>
-__device__ __forceinline__ void penc2_rk(const PermTables<NT>& tb, const uint32_t* rka, uint32_t sa[4],
+template <int NT, int CP>
+__device__ __forceinline__ void penc2_rk(const PermTables<NT, CP>& tb, const uint32_t* rka, uint32_t sa[4],
                                          const uint32_t* rkb, uint32_t sb[4]) {
 #pragma unroll
     for (int c = 0; c < 4; c++) {

@@ -34,10 +34,10 @@ __device__ __forceinline__ uint32_t uload(const uint32_t* p) {
 template <int LAYOUT, bool UNI, bool EMIT>
 __global__ __launch_bounds__(kAddqBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_agg_addq(
     BatchArgs a, uint32_t* partials, uint32_t* e_out, uint32_t* x_out) {
-    __shared__ uint32_t lds[256 * 64];
-    perm_tables_fill<1>(lds);
+    __shared__ uint32_t lds[2 * 256 * 32];
+    perm_tables_fill<2, 32>(lds);
     __syncthreads();
-    const PermTables<1> tb = perm_tables<1>(lds);
+    const PermTables<2, 32> tb = perm_tables<2, 32>(lds);
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     bool bad = false;
     const uint32_t lane = threadIdx.x & 63u;

@@ -38,8 +38,8 @@ __global__ __launch_bounds__(BLOCK) void k_agg_ekeys_aes(BatchArgs a, uint32_t* 
 // one v_perm_b32 per lookup address, fully unrolled rounds, three-input xors.
 
 // one MDC-2 block: (h, h') <- (E_h(m) ^ m, E_h'(m) ^ m) with the half swap
-template <int NT>
-__device__ __forceinline__ void mdc2_block_perm(const PermTables<NT>& tb, uint32_t h[4], uint32_t hp[4],
+template <int NT, int CP>
+__device__ __forceinline__ void mdc2_block_perm(const PermTables<NT, CP>& tb, uint32_t h[4], uint32_t hp[4],
                                                 const uint32_t m[4], bool first) {
     uint32_t sa[4] = {m[0], m[1], m[2], m[3]}, sb[4] = {m[0], m[1], m[2], m[3]};
     if (first)
@@ -61,8 +61,8 @@ __device__ __forceinline__ void mdc2_block_perm(const PermTables<NT>& tb, uint32
 // four blocks (64 bytes, one L2 sector) at a time instead and
 // derives x_t only for the final block: about half the live registers, so
 // twice the resident waves where LDS allows.  xf(x) writes x_t.
-template <int NT, bool FAST, bool LEAN, class XF>
-__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const EntryView& v, const uint8_t* end,
+template <int NT, int CP, bool FAST, bool LEAN, class XF>
+__device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT, CP>& tb, const EntryView& v, const uint8_t* end,
                                                  const XF& xf, uint32_t dig[8]) {
     uint32_t h[4], hp[4];
     uint64_t b = 0;
@@ -121,14 +121,15 @@ __device__ __forceinline__ void digest_mdc2_perm(const PermTables<NT>& tb, const
 
 // EMIT: also store every entry's e_t = H(m_t || x_t) mod q (eight LE words)
 // and x_t (four LE words, when x_out is set); the hashing is the same code.
-template <int NT, int BLOCK, bool FAST, bool LEAN, int WPE, bool EMIT = false>
+// CP: table copies (aes_perm.h).
+template <int NT, int BLOCK, bool FAST, bool LEAN, int WPE, bool EMIT = false, int CP = 64>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_agg_ekeys_aes_perm(
     BatchArgs a, uint32_t* partials, uint32_t* e_out, uint32_t* x_out) {
     // the kernel's only LDS allocation: tables first, then reduction scratch
-    __shared__ uint32_t lds[NT * 256 * 64];
-    perm_tables_fill<NT>(lds);
+    __shared__ uint32_t lds[NT * 256 * CP];
+    perm_tables_fill<NT, CP>(lds);
     __syncthreads();
-    const PermTables<NT> tb = perm_tables<NT>(lds);
+    const PermTables<NT, CP> tb = perm_tables<NT, CP>(lds);
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint64_t pos = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; pos < a.n; pos += (uint64_t)gridDim.x * BLOCK) {
         if (skipped(a, pos)) continue;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 for (int w = 0; w < 4; w++) xo[w] = x[w];
         };
         uint32_t dig[8];
-        digest_mdc2_perm<NT, FAST, LEAN>(tb, entry_view(a, pos), a.end, xf, dig);
+        digest_mdc2_perm<NT, CP, FAST, LEAN>(tb, entry_view(a, pos), a.end, xf, dig);
         acc288_add256(acc, dig);
         if constexpr (EMIT) {
             uint32_t e[8];
@@ -169,12 +170,15 @@ static const AggVariant kVariants[] = {
     {"nt2_c32_b512", 2, 32, 512, 0},   {"perm2_c64_b1024", 2, 64, 1024, 1}, {"perm1_c64_b1024", 1, 64, 1024, 1},
     {"perm1_c64_b512", 1, 64, 512, 1}, {"perm2_c64_b512", 2, 64, 512, 1},
     {"perm2_lean_b1024", 2, 64, 1024, 1}, {"perm1_lean_b1024_w8", 1, 64, 1024, 1},
-    {"perm1_lean_b512_w8", 1, 64, 512, 1},
+    {"perm1_lean_b512_w8", 1, 64, 512, 1},   {"perm2x32_lean_b1024_w8", 2, 32, 1024, 1},
 };
 
 int agg_aes_variant_count() { return (int)(sizeof kVariants / sizeof kVariants[0]); }
 const AggVariant& agg_aes_variant(int v) { return kVariants[v]; }
-int agg_aes_default_variant() { return 15; }  // perm1_lean_b1024_w8: fastest in the sweep on MI355X
+// perm2x32_lean_b1024_w8: fastest in the sweep on MI355X (0.47 ms against
+// 0.51 ms for perm1_lean_b1024_w8 at 2^20 x 256 B: the two-table layout
+// needs a third of the rotations, and 32 copies keep it in 64 KB)
+int agg_aes_default_variant() { return 17; }
 size_t agg_aes_lds_bytes(int v) { return (size_t)kVariants[v].nt * 256 * kVariants[v].copies * 4; }
 
 #define LAUNCH(NT, C, B)                                                                              \
@@ -192,8 +196,8 @@ int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* 
     const BatchArgs& a = *static_cast<const BatchArgs*>(args);
     if (!fast) {
         // any layout: the default variant's tables and shape with word loads
-        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, false, true, 8>), dim3(grid), dim3(1024), 0, s, a,
-                           partials, nullptr, nullptr);
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<2, 1024, false, true, 8, false, 32>), dim3(grid), dim3(1024), 0,
+                           s, a, partials, nullptr, nullptr);
         return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
     }
     switch (v) {
@@ -214,6 +218,10 @@ int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* 
         case 14: LAUNCHP(2, 1024, true, 4);
         case 15: LAUNCHP(1, 1024, true, 8);
         case 16: LAUNCHP(1, 512, true, 8);
+        case 17:
+            hipLaunchKernelGGL((k_agg_ekeys_aes_perm<2, 1024, true, true, 8, false, 32>), dim3(grid), dim3(1024), 0,
+                               s, a, partials, nullptr, nullptr);
+            break;
         default: return POSLO_E_INVAL;
     }
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
@@ -225,11 +233,11 @@ int launch_agg_aes_emit(bool fast, uint32_t grid, const void* args, uint32_t* pa
                         uint32_t* x_out, hipStream_t s) {
     const BatchArgs& a = *static_cast<const BatchArgs*>(args);
     if (fast)
-        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, true, true, 8, true>), dim3(grid), dim3(1024), 0, s, a,
-                           partials, e_out, x_out);
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<2, 1024, true, true, 8, true, 32>), dim3(grid), dim3(1024), 0, s,
+                           a, partials, e_out, x_out);
     else
-        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<1, 1024, false, true, 8, true>), dim3(grid), dim3(1024), 0, s, a,
-                           partials, e_out, x_out);
+        hipLaunchKernelGGL((k_agg_ekeys_aes_perm<2, 1024, false, true, 8, true, 32>), dim3(grid), dim3(1024), 0, s,
+                           a, partials, e_out, x_out);
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 

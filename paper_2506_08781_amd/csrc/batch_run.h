@@ -58,7 +58,8 @@ struct JobSpec {
 struct HotVariant {
     const char* name;
     int inst, nt, block, chunk, sort, waves_per_simd;
-    int pair;  // chunk = 2 * block: a lane takes the k-th shortest and the k-th longest entry
+    int pair;    // chunk = 2 * block: a lane takes the k-th shortest and the k-th longest entry
+    int copies;  // AES table copies (0: 64; 32: two tables in 64 KB, aes_perm.h)
 };
 int batch_variant_count();
 const HotVariant& batch_variant(int v);

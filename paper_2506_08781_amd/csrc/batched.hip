@@ -151,21 +151,21 @@ struct BHot {
 // PAIR (SORT, CHUNK == 2 * BLOCK): thread g takes the g-th shortest and the
 // g-th longest entry of the sorted item, so every lane and wave gets about
 // the same total length and waves do not idle at the item's closing barrier.
-template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT, bool PAIR = false>
+template <int INST, int NT, int BLOCK, int CHUNK, bool SORT, int WPE, bool EMIT, bool PAIR = false, int CP = 64>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_batch_hot(BHot A) {
     static_assert(!PAIR || (SORT && CHUNK == 2 * BLOCK), "pairing needs sorted items of two entries per thread");
-    constexpr int TW = INST == INST_AES ? NT * 256 * 64 : 0;  // table words
+    constexpr int TW = INST == INST_AES ? NT * 256 * CP : 0;  // table words
     constexpr int SW = 64 + 16 + CHUNK / 2 + CHUNK / 4;       // counts, misc, order (u16), keys (u8)
     __shared__ uint32_t lds[TW + SW + (BLOCK / 64) * 9];
     if constexpr (INST == INST_AES) {
-        perm_tables_fill<NT>(lds);
+        perm_tables_fill<NT, CP>(lds);
     }
     uint32_t* counts = lds + TW;                                // 64 bucket counters
     uint32_t* misc = counts + 64;                               // [0] item id
     uint16_t* order = reinterpret_cast<uint16_t*>(misc + 16);   // CHUNK slots
     uint8_t* keys = reinterpret_cast<uint8_t*>(order + CHUNK);  // CHUNK block counts
     uint32_t* red = lds + TW + SW;
-    const PermTables<NT> tb = perm_tables<NT>(lds);
+    const PermTables<NT, CP> tb = perm_tables<NT, CP>(lds);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) misc[0] = atomicAdd(A.counter, 1u);
@@ -405,6 +405,8 @@ static const HotVariant kHot[] = {
     {"aes_perm2_b1024_c2048_paired", 1, 2, 1024, 2048, 1, 4, 1},
     {"sha_b256_c512_paired_w3", 0, 1, 256, 512, 1, 3, 1},
     {"sha_b512_c1024_paired_w3", 0, 1, 512, 1024, 1, 3, 1},
+    {"aes_p2x32_b1024_c1024_sorted_w8", 1, 2, 1024, 1024, 1, 8, 0, 32},
+    {"aes_p2x32_b1024_c2048_paired_w8", 1, 2, 1024, 2048, 1, 8, 1, 32},
 };
 constexpr int kNumHot = sizeof kHot / sizeof kHot[0];
 
@@ -413,7 +415,7 @@ const HotVariant& batch_variant(int v) { return kHot[v]; }
 int batch_default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 0 : 5; }
 
 size_t hot_lds_bytes(const HotVariant& v) {
-    size_t tw = v.inst == 1 ? (size_t)v.nt * 256 * 64 : 0;
+    size_t tw = v.inst == 1 ? (size_t)v.nt * 256 * (v.copies ? v.copies : 64) : 0;
     return 4 * (tw + 64 + 16 + v.chunk / 2 + v.chunk / 4 + (v.block / 64) * 9);
 }
 
@@ -446,6 +448,22 @@ static int launch_hot(int v, uint32_t grid, const BHot& A, hipStream_t s) {
         case 12: HOTP(1, 2, 1024, 2048, 4);
         case 13: HOTP(0, 1, 256, 512, 3);
         case 14: HOTP(0, 1, 512, 1024, 3);
+        case 15:
+            if (A.e_out)
+                hipLaunchKernelGGL((k_batch_hot<1, 2, 1024, 1024, true, 8, true, false, 32>), dim3(grid), dim3(1024),
+                                   0, s, A);
+            else
+                hipLaunchKernelGGL((k_batch_hot<1, 2, 1024, 1024, true, 8, false, false, 32>), dim3(grid), dim3(1024),
+                                   0, s, A);
+            break;
+        case 16:
+            if (A.e_out)
+                hipLaunchKernelGGL((k_batch_hot<1, 2, 1024, 2048, true, 8, true, true, 32>), dim3(grid), dim3(1024), 0,
+                                   s, A);
+            else
+                hipLaunchKernelGGL((k_batch_hot<1, 2, 1024, 2048, true, 8, false, true, 32>), dim3(grid), dim3(1024),
+                                   0, s, A);
+            break;
         default: return POSLO_E_INVAL;
     }
 #undef HOT

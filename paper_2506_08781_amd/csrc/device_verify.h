@@ -119,8 +119,8 @@ struct Mdc2BlockGeneric {
 
 // one MDC-2 block with the byte-addressed LDS tables
 struct Mdc2BlockPerm {
-    template <int NT>
-    __device__ __forceinline__ void operator()(const PermTables<NT>& tb, uint32_t h[4], uint32_t hp[4],
+    template <int NT, int CP>
+    __device__ __forceinline__ void operator()(const PermTables<NT, CP>& tb, uint32_t h[4], uint32_t hp[4],
                                                const uint32_t m[4], bool first) const {
         uint32_t sa[4] = {m[0], m[1], m[2], m[3]}, sb[4] = {m[0], m[1], m[2], m[3]};
         if (first)

@@ -79,11 +79,11 @@ template <int INST, int BLOCK, int WPE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_distill_hash(
     BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
     constexpr bool AESP = INST != INST_SHA256;  // AES-based PRF
-    constexpr int TW = AESP ? 256 * 64 : 1;
+    constexpr int TW = AESP ? 2 * 256 * 32 : 1;
     __shared__ uint32_t lds[TW];
-    if constexpr (AESP) perm_tables_fill<1>(lds);
+    if constexpr (AESP) perm_tables_fill<2, 32>(lds);
     __syncthreads();
-    const PermTables<1> tb = perm_tables<1>(lds);
+    const PermTables<2, 32> tb = perm_tables<2, 32>(lds);
     for (uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; p < a.n; p += (uint64_t)gridDim.x * BLOCK) {
         EntryView ev = entry_view(a, p);
         uint32_t x[4], dig[8];

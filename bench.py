@@ -19,7 +19,8 @@ The same run also measures, each on its own synthetic log:
    streamed through the chunked audit, and a 2^25 x 32-byte log streamed in
    128 MiB chunks;
  - variants: POSLO++ (H = Add_q) at kappa = 127 and 128 over 2^26 entries of
-   16-byte messages, and POSLO+ at kappa = 127 on the headline batch;
+   16-byte messages, and POSLO+ at kappa = 127 and on the FourQ group on the
+   headline batch;
  - distill: Distill of 2^20 x 256-byte entries with 1% of entries carrying
    one flipped bit of m_t || sigma_t (exact invalid set, CCD);
  - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
@@ -170,17 +171,22 @@ def hash_calls_per_entry(inst: int, L):
     return 1 + (L + 16 + 9 + 63) // 64
 
 
-# HBM traffic of the headline kernels from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over the plain-large
-# workload, each scaled by what the counter read for a plain 256 MiB device
-# copy in the same runs (FETCH_SIZE 131,092 KiB -> x2.0, WRITE_SIZE
-# 262,144 KiB -> x1.0).  Valid only for the kernel sources they were taken
-# on: the sha256 prefix of those files must match, else traffic is null.
+# HBM traffic of the hot kernels from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged) over the
+# benchmark's plain and variants sections, each scaled by what the counter
+# read for a plain 256 MiB device copy in the same runs (FETCH_SIZE
+# 131,087 KiB -> x2.0, WRITE_SIZE 262,144 KiB -> x1.0).  Valid only for the
+# kernel sources they were taken on: the sha256 prefix of those files must
+# match, else traffic is null.
 TRAFFIC = {
-    "aes": {"fetch_kib": 171894.6, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
-            "files": ["agg_aes.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "common.h",
-                      "sc25519.h"],
-            "sha256": "5454882c36454807", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "aes": {"fetch_kib": 190964.4, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
+            "files": ["agg_aes.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "device_verify.h",
+                      "common.h", "sc25519.h"],
+            "sha256": "e3d5aca08eff9a80", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "addq": {"fetch_kib": 573536.7, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
+             "files": ["agg_addq.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "common.h",
+                       "sc25519.h"],
+             "sha256": "cefb9c9c94a6d710", "profile": "profiles/pmc_aver_2p20x256.md"},
     "sha": {"fetch_kib": 133146.0, "write_kib": 1088.0, "fetch_scale": 2.0, "write_scale": 1.0,
             "files": ["agg_sha.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h"],
             "sha256": "7c64ae117806ead6", "profile": "profiles/pmc_aver_2p20x256.md"},
@@ -266,7 +272,9 @@ def host_info():
 def bench_plain(P, torch, ctx, cfg, inst, steps, warmup, calib_copy):
     from paper_2506_08781_amd import workloads
     t = time.perf_counter()
-    log = workloads.single_signer_fixed(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
+    # the device signer takes edwards25519 only; FourQ logs are signed on the host
+    build = workloads.single_signer_fixed_host if inst & P.GROUP_FOURQ else workloads.single_signer_fixed
+    log = build(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
     print(f"# plain: inputs ready in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     msgs = P.make_msgs(log.data)
     stream = torch.cuda.current_stream()
@@ -370,9 +378,10 @@ def bench_plain_other(P, torch, ctx, inst, steps, warmup, rates):
 
 def bench_variants(P, torch, ctx, steps, warmup, rates):
     """The parameter variants: POSLO++ (H = Add_q) at kappa = 127 and 128 on
-    2^26 entries of 16-byte messages (Add_q takes at most 31 bytes), and
-    POSLO+ at kappa = 127 on the headline configuration, whose seed walk is
-    one AES per tree level instead of two."""
+    2^26 entries of 16-byte messages (Add_q takes at most 31 bytes); on the
+    headline configuration, POSLO+ at kappa = 127 (a seed walk of one AES per
+    tree level instead of two) and POSLO+ on the FourQ group (the same
+    hashing, the final check on FourQ; signed by the host signer)."""
     out = {}
     cfg = dict(VARIANT, name="plain AVer, 2^26 entries x 16 B, n2=256, n1=2^18")
     for inst, key in ((2 | 4, "poslopp_k127"), (2, "poslopp")):
@@ -391,7 +400,8 @@ def bench_variants(P, torch, ctx, steps, warmup, rates):
             "latency_ms": lat_summary(lat), "kernel_ms": kt,
             "roofline": {"bound": "alu", "kernel": "k_agg_addq", "achieved": achieved, "peak": INT32_PEAK_TOPS,
                          "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops_per_entry": ope,
-                         "peak_measured_mix": mp, "frac_measured_mix": achieved / mp, "traffic": None,
+                         "peak_measured_mix": mp, "frac_measured_mix": achieved / mp, "traffic": traffic_bytes("addq"),
+                         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                          "algorithmic_bytes": n * cfg["L"], "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS}}
     cfg2 = CONFIGS["c2"]
     log, total, lat, kt = bench_plain(P, torch, ctx, cfg2, 1 | 4, steps, warmup, False)
@@ -400,6 +410,12 @@ def bench_variants(P, torch, ctx, steps, warmup, rates):
     out["posloplus_k127"] = {"workload": cfg2["name"] + ", POSLO+ at kappa = 127",
                              "entries_per_s": cfg2["n"] / (total / steps), "ms_per_step": 1e3 * total / steps,
                              "latency_ms": lat_summary(lat), "kernel_ms": kt}
+    log, total, lat, kt = bench_plain(P, torch, ctx, cfg2, 1 | P.GROUP_FOURQ, steps, warmup, False)
+    del log
+    torch.cuda.empty_cache()
+    out["posloplus_fourq"] = {"workload": cfg2["name"] + ", POSLO+ on the FourQ group",
+                              "entries_per_s": cfg2["n"] / (total / steps), "ms_per_step": 1e3 * total / steps,
+                              "latency_ms": lat_summary(lat), "kernel_ms": kt}
     return out
 
 
@@ -767,6 +783,9 @@ def main():
                          "configuration under the other instantiation), host (inputs in host memory, copies "
                          "included), variants (POSLO++ and kappa = 127), distill, batched, serving (plain "
                          "always runs)")
+    ap.add_argument("--aes-variant", type=int, default=-1,
+                    help="POSLO+ AVer hot-kernel variant for the plain section (poslo_ctx_set_tuning; -1: the "
+                         "library's default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
@@ -795,6 +814,8 @@ def main():
     cfg = CONFIGS[args.config]
     inst = 1 if args.inst == "aes" else 0
     ctx = P.poslo_ctx_create(0)
+    if args.aes_variant >= 0:
+        P.poslo_ctx_set_tuning(ctx, agg_variant=args.aes_variant)
     if args.serving_only:
         serving = bench_serving(P, torch, ctx, inst)
         ctx.close()

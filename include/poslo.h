@@ -76,8 +76,20 @@ enum {
  * PRF output, x_t included, is taken mod 2^127.  Without the flag kappa = 128. */
 #define POSLO_KAPPA127 4u
 
+/* Flag: the FourQ group (the paper's curve) instead of edwards25519, with
+ * POSLO or POSLO+.  FourQ is -x^2 + y^2 = 1 + d x^2 y^2 over GF(p^2),
+ * p = 2^127 - 1, with FourQ's published d, subgroup order N (246 bits) and
+ * generator; scalars (y, r_t, s_t, e_t = LE256(H) mod N) are taken mod N.
+ * A point encodes as y0 || y1 (16-byte little-endian halves of
+ * y = y0 + y1 i, each below p) with bit 255 holding the sign of x (x0 mod 2
+ * if x0 != 0, else x1 mod 2).  Taken by the signer (poslo_kg, poslo_sig,
+ * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed and the
+ * streaming audit; the other entry points return E_INVAL. */
+#define POSLO_GROUP_FOURQ 8u
+
 /* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two
- * optionally with POSLO_KAPPA127), else 0 */
+ * optionally with POSLO_KAPPA127; SHA256 or AES optionally with
+ * POSLO_GROUP_FOURQ), else 0 */
 int poslo_inst_valid(uint32_t inst);
 
 /* Public parameters I (paper, POSLO-F.Kg): instantiation word, n1 =
@@ -159,6 +171,8 @@ int poslo_ds_export(const poslo_signer* sk, uint8_t* buf, size_t cap, size_t* le
  * of stride bytes (>= 80).  tag: host, 64 bytes out.  E_ENCODING if an R_t
  * does not decode. */
 int poslo_agg(const uint8_t* sigs, size_t stride, uint64_t count, uint8_t tag[64]);
+/* The same in the group of an instantiation word (poslo_agg is edwards25519). */
+int poslo_agg_inst(uint32_t inst, const uint8_t* sigs, size_t stride, uint64_t count, uint8_t tag[64]);
 
 /* Host reference of the instantiated functions, for tooling and tests:
  * out16 = PRF_b(in) (b in {0,1}; with POSLO_KAPPA127 a 16-byte input is a

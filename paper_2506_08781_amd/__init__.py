@@ -21,6 +21,7 @@ INST_SHA256 = 0
 INST_AES = 1
 INST_AES_ADDQ = 2  # POSLO++ (H = Add_q, messages of at most 31 bytes)
 KAPPA127 = 4       # flag on an AES-based instantiation: kappa = 127
+GROUP_FOURQ = 8    # flag: the FourQ group (POSLO and POSLO+)
 
 POSLO_OK = 0
 POSLO_E_INVAL = -1
@@ -134,6 +135,8 @@ def lib():
             "poslo_signer_count": ([_VP], _U64),
             "poslo_ds_export": ([_VP, _VP, _SZ, P(_SZ)], _I),
             "poslo_agg": ([_VP, _SZ, _U64, _VP], _I),
+            "poslo_agg_inst": ([_U32, _VP, _SZ, _U64, _VP], _I),
+            "poslo_inst_valid": ([_U32], _I),
             "poslo_prf_host": ([_U32, _U32, _U8P, _SZ, _VP], _I),
             "poslo_hash_host": ([_U32, _U8P, _SZ, _VP], _I),
             "poslo_ctx_create": ([_I, P(_VP)], _I),
@@ -286,11 +289,17 @@ def poslo_ds_export(sk: Signer) -> bytes:
     return buf.raw[:ln.value]
 
 
-def poslo_agg(sigs) -> bytes:
+def poslo_agg(sigs, inst: int | None = None) -> bytes:
+    """The aggregate tag; inst (an instantiation word) selects the group,
+    edwards25519 when absent."""
     arr = np.ascontiguousarray(np.frombuffer(bytes(sigs), dtype=np.uint8) if isinstance(sigs, (bytes, bytearray))
                                else sigs, dtype=np.uint8).reshape(-1, 80)
     tag = ctypes.create_string_buffer(64)
-    _check(lib().poslo_agg(arr.ctypes.data if arr.size else None, 80, arr.shape[0], tag), "poslo_agg")
+    ptr = arr.ctypes.data if arr.size else None
+    if inst is None:
+        _check(lib().poslo_agg(ptr, 80, arr.shape[0], tag), "poslo_agg")
+    else:
+        _check(lib().poslo_agg_inst(inst, ptr, 80, arr.shape[0], tag), "poslo_agg_inst")
     return tag.raw
 
 

@@ -12,8 +12,10 @@
 // NT = 2 keeps te0 and te0 rotated by 16 (128 KB); the odd rotations are one
 // v_alignbit away.  NT = 1 keeps te0 only (64 KB) and rotates for the rest.
 //
-// CP = 32 copies (NT <= 2): entry x of copy c at (x << 8) | (t << 7) | (c << 2),
-// lane l reading copy l mod 32, so NT = 2 fits in 64 KB.  The two lanes of a
+// CP = 32 copies: entry x of copy c of table t at (t1 << 16) | (x << 8) |
+// (t0 << 7) | (c << 2) with t = t0 + 2 t1, lane l reading copy l mod 32, so
+// NT = 2 (te0, te0 rotated by 16) fits in 64 KB and NT = 4 (all four
+// rotations, no rotate instructions) in 128 KB.  The two lanes of a
 // wave that share a copy (l and l + 32) are served in different halves of
 // the wave's LDS access when the LDS takes 32 lanes per cycle, which is what
 // the PMC counters confirm (no bank conflicts on gfx950).
@@ -36,10 +38,13 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 template <int NT, int CP = 64>
 struct PermTables {
-    static_assert(CP == 64 || (CP == 32 && NT <= 2), "64 copies, or 32 copies of at most two tables");
+    static_assert((CP == 64 && NT <= 2) || (CP == 32 && (NT == 1 || NT == 2 || NT == 4)),
+                  "64 copies of one or two tables, or 32 copies of one, two or four");
     const uint8_t* lds;
-    uint32_t base0;  // lane offset, table 0
-    uint32_t base2;  // lane offset | 1 << 16, table 1 (te0 rotated by 16)
+    uint32_t base0;  // lane offset: te0
+    uint32_t base1;  // te0 rotated by 8 (NT = 4)
+    uint32_t base2;  // te0 rotated by 16 (NT >= 2)
+    uint32_t base3;  // te0 rotated by 24 (NT = 4)
 
     __device__ __forceinline__ uint32_t ld(uint32_t addr) const {
         return *reinterpret_cast<const uint32_t*>(lds + addr);
@@ -48,10 +53,20 @@ struct PermTables {
     __device__ __forceinline__ uint32_t T0(uint32_t w, int k) const {
         return ld(__builtin_amdgcn_perm(w, base0, perm_sel(k)));
     }
+    // te0[byte k of w] rotated left by 8
+    __device__ __forceinline__ uint32_t T1(uint32_t w, int k) const {
+        if constexpr (NT == 4) return ld(__builtin_amdgcn_perm(w, base1, perm_sel(k)));
+        else return rotl32(T0(w, k), 8);
+    }
     // te0[byte k of w] rotated left by 16
     __device__ __forceinline__ uint32_t T2(uint32_t w, int k) const {
-        if constexpr (NT == 2) return ld(__builtin_amdgcn_perm(w, base2, perm_sel(k)));
+        if constexpr (NT >= 2) return ld(__builtin_amdgcn_perm(w, base2, perm_sel(k)));
         else return rotl32(T0(w, k), 16);
+    }
+    // te0[byte k of w] rotated left by 24
+    __device__ __forceinline__ uint32_t T3(uint32_t w, int k) const {
+        if constexpr (NT == 4) return ld(__builtin_amdgcn_perm(w, base3, perm_sel(k)));
+        else return rotl32(T2(w, k), 8);
     }
 };
 
@@ -62,9 +77,12 @@ struct PermTables {
 template <int NT, int CP = 64>
 __device__ __forceinline__ void perm_tables_fill(uint32_t* lds) {
     if constexpr (CP == 32) {
-        // word (x << 6) | (t << 5) | c holds te0[x] rotated by 16 t
-        for (uint32_t w = threadIdx.x; w < NT * 256u * 32u; w += blockDim.x)
-            lds[w] = rotl32(c_aes.te0[w >> 6], 16 * ((w >> 5) & 1u));
+        // word (t1 << 14) | (x << 6) | (t0 << 5) | c holds te0[x] rotated by
+        // 16 t0 (NT = 2) or by 8 (t0 + 2 t1) (NT = 4)
+        for (uint32_t w = threadIdx.x; w < NT * 256u * 32u; w += blockDim.x) {
+            const uint32_t x = (w >> 6) & 255u, t0 = (w >> 5) & 1u, t1 = (w >> 14) & 1u;
+            lds[w] = rotl32(c_aes.te0[x], NT == 4 ? 8 * (t0 + 2 * t1) : 16 * t0);
+        }
         return;
     }
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -80,8 +98,12 @@ __device__ __forceinline__ void perm_tables_fill(uint32_t* lds) {
 
 template <int NT, int CP = 64>
 __device__ __forceinline__ PermTables<NT, CP> perm_tables(const uint32_t* lds) {
-    uint32_t lane4 = (threadIdx.x & (CP - 1u)) << 2;
-    return PermTables<NT, CP>{reinterpret_cast<const uint8_t*>(lds), lane4, lane4 | (CP == 64 ? 1u << 16 : 0x80u)};
+    const uint32_t lane4 = (threadIdx.x & (CP - 1u)) << 2;
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(lds);
+    if constexpr (CP == 64) return PermTables<NT, CP>{p, lane4, 0u, lane4 | (1u << 16), 0u};
+    else if constexpr (NT == 4)
+        return PermTables<NT, CP>{p, lane4, lane4 | 0x80u, lane4 | (1u << 16), lane4 | 0x80u | (1u << 16)};
+    else return PermTables<NT, CP>{p, lane4, 0u, lane4 | 0x80u, 0u};
 }
 
 // full round: out_c = T0[s_c.b0] ^ T1[s_{c+1}.b1] ^ T2[s_{c+2}.b2] ^ T3[s_{c+3}.b3] ^ k_c
@@ -90,7 +112,10 @@ __device__ __forceinline__ void pround(const PermTables<NT, CP>& tb, uint32_t s[
     uint32_t n[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        if constexpr (NT == 2) {
+        if constexpr (NT == 4) {
+            n[c] = xor3(xor3(tb.T0(s[c], 0), tb.T1(s[(c + 1) & 3], 1), tb.T2(s[(c + 2) & 3], 2)),
+                        tb.T3(s[(c + 3) & 3], 3), k[c]);
+        } else if constexpr (NT == 2) {
             // T1[y] ^ T3[z] = rot8(T0[y] ^ T2[z]): one rotation, and the
             // xors (which issue faster than rotations) take the rest
             const uint32_t a = tb.T0(s[c], 0), d = tb.T2(s[(c + 2) & 3], 2);

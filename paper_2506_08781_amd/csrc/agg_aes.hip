@@ -171,6 +171,7 @@ static const AggVariant kVariants[] = {
     {"perm1_c64_b512", 1, 64, 512, 1}, {"perm2_c64_b512", 2, 64, 512, 1},
     {"perm2_lean_b1024", 2, 64, 1024, 1}, {"perm1_lean_b1024_w8", 1, 64, 1024, 1},
     {"perm1_lean_b512_w8", 1, 64, 512, 1},   {"perm2x32_lean_b1024_w8", 2, 32, 1024, 1},
+    {"perm4x32_b1024", 4, 32, 1024, 1},      {"perm4x32_lean_b1024", 4, 32, 1024, 1},
 };
 
 int agg_aes_variant_count() { return (int)(sizeof kVariants / sizeof kVariants[0]); }
@@ -220,6 +221,14 @@ int launch_agg_aes(int v, bool fast, uint32_t grid, const void* args, uint32_t* 
         case 16: LAUNCHP(1, 512, true, 8);
         case 17:
             hipLaunchKernelGGL((k_agg_ekeys_aes_perm<2, 1024, true, true, 8, false, 32>), dim3(grid), dim3(1024), 0,
+                               s, a, partials, nullptr, nullptr);
+            break;
+        case 18:
+            hipLaunchKernelGGL((k_agg_ekeys_aes_perm<4, 1024, true, false, 4, false, 32>), dim3(grid), dim3(1024), 0,
+                               s, a, partials, nullptr, nullptr);
+            break;
+        case 19:
+            hipLaunchKernelGGL((k_agg_ekeys_aes_perm<4, 1024, true, true, 4, false, 32>), dim3(grid), dim3(1024), 0,
                                s, a, partials, nullptr, nullptr);
             break;
         default: return POSLO_E_INVAL;

@@ -19,12 +19,15 @@
 
 #include "ctx.h"
 #include "device_entry.h"
+#include "fourq.h"
 #include "scheme_host.h"
 
 namespace poslo {
 
 // running e mod q (9 words, the top one zero) += the chunk's partials;
-// run[9] keeps POSLO++'s long-message flag of every chunk (bad)
+// run[9] keeps POSLO++'s long-message flag of every chunk (bad).  FQ: mod N
+// (the FourQ group order) instead of q.
+template <bool FQ>
 __global__ __launch_bounds__(256) void k_audit_fold(const uint32_t* partials, uint32_t n_part, uint32_t* run,
                                                     const uint32_t* bad) {
     __shared__ uint32_t total[9];
@@ -36,7 +39,8 @@ __global__ __launch_bounds__(256) void k_audit_fold(const uint32_t* partials, ui
         uint32_t t[9], e[8];
         for (int k = 0; k < 9; k++) t[k] = total[k];
         acc288_add(t, run);
-        sc_reduce288(e, t);
+        if (FQ) scN_reduce<9>(e, t);
+        else sc_reduce288(e, t);
         for (int k = 0; k < 8; k++) run[k] = e[k];
         run[8] = 0;
         if (*bad) run[9] = 1u;
@@ -111,7 +115,7 @@ int audit_new(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
     if (t0 > nmax || t_next < t0 || t_next > nmax) return POSLO_E_INVAL;
     int st;
     if (hipSetDevice(c->device) != hipSuccess) return POSLO_E_DEVICE;
-    if (!ctx_key(c, pk, &st)) return st;  // E_ENCODING when pk is not a point
+    if (!ctx_key_of(c, prm->inst, pk, &st)) return st;  // E_ENCODING when pk is not a point
     poslo_audit* a = new (std::nothrow) poslo_audit();
     if (!a) return POSLO_E_NOMEM;
     a->c = c;
@@ -203,8 +207,12 @@ extern "C" int poslo_audit_feed(poslo_audit* a, const poslo_msgs* m, void* strea
     const AggShape g = agg_shape(c, &a->prm, &dm);
     if ((st = grow((void**)&a->d_part, &a->part_bytes, (size_t)g.grid * 36))) return st;
     if ((st = launch_agg(c, &a->prm, g, ba, a->d_part, nullptr, nullptr, s))) return st;
-    hipLaunchKernelGGL(k_audit_fold, dim3(1), dim3(256), 0, s, (const uint32_t*)a->d_part, g.grid, a->d_run,
-                       (const uint32_t*)ba.bad);
+    if (a->prm.inst & POSLO_GROUP_FOURQ)
+        hipLaunchKernelGGL(k_audit_fold<true>, dim3(1), dim3(256), 0, s, (const uint32_t*)a->d_part, g.grid, a->d_run,
+                           (const uint32_t*)ba.bad);
+    else
+        hipLaunchKernelGGL(k_audit_fold<false>, dim3(1), dim3(256), 0, s, (const uint32_t*)a->d_part, g.grid,
+                           a->d_run, (const uint32_t*)ba.bad);
     HIP_TRY(hipGetLastError());
     if (b >= 0) {
         HIP_TRY(hipEventRecord(a->ev_used[b], s));
@@ -223,7 +231,7 @@ extern "C" int poslo_audit_finish(poslo_audit* a, const uint8_t tag[64], void* s
     if ((st = release_host(a))) return st;
     poslo_ctx* c = a->c;
     HIP_TRY(hipSetDevice(c->device));
-    const KeyEntry* key = ctx_key(c, a->pk, &st);
+    const KeyEntry* key = ctx_key_of(c, a->prm.inst, a->pk, &st);
     if (!key) return st;
     return final_check(c, key, a->d_run, 1, tag, (hipStream_t)stream, accept, e_out, a->d_run + 9);
 }
@@ -286,7 +294,7 @@ extern "C" int poslo_audit_resume(poslo_ctx* c, const uint8_t* buf, size_t len, 
     p += 16;
     uint32_t e[8];
     for (int k = 0; k < 8; k++) e[k] = load_le32(p + 4 * k);
-    if (!sc_is_canonical(e)) return POSLO_E_INVAL;
+    if (!((prm->inst & POSLO_GROUP_FOURQ) ? scN_is_canonical(e) : sc_is_canonical(e))) return POSLO_E_INVAL;
     p += 32;
     const uint32_t dl = load_le32(p);
     p += 4;

@@ -54,7 +54,8 @@ int launch_agg_sha_emit(int layout, uint32_t grid, const void* batch_args, uint3
                         uint32_t* x_out, hipStream_t s);
 
 struct KeyEntry {
-    std::string pk;
+    std::string pk;               // cache id: the 32 key bytes (FourQ keys: plus one tag byte)
+    bool fourq = false;           // a FourQ key (fourq.h) rather than an edwards25519 one
     uint32_t* d_table = nullptr;  // comb table of Y on the device
     std::shared_ptr<void> slab;   // allocation holding d_table (shared by a bulk load)
     std::shared_ptr<void> wide;   // Y's wide table (comb.h), built on demand
@@ -90,6 +91,7 @@ struct poslo_ctx {
     // comb tables: G (static) and per-key Y, LRU-bounded
     uint32_t* d_gtable = nullptr;
     uint32_t* d_gtable_wide = nullptr;  // built on first use (ctx_gtable_wide)
+    uint32_t* d_gtable_fq = nullptr;    // FourQ generator's comb table, built on first use
     std::mutex wide_mu;
     size_t key_cap = 4096;
     std::list<poslo::KeyEntry> keys;  // front = most recent
@@ -111,6 +113,15 @@ void prof_collect(poslo_ctx* c);
 // device comb table of the key (built on first use); nullptr and
 // *status = POSLO_E_ENCODING if pk is not a point encoding
 const KeyEntry* ctx_key(poslo_ctx* c, const uint8_t pk[32], int* status);
+// FourQ keys (fourq.h): the key's comb table, built on first use and kept
+// in the same cache; E_ENCODING when pk is not a FourQ point encoding
+const KeyEntry* ctx_key_fq(poslo_ctx* c, const uint8_t pk[32], int* status);
+// the key of an instantiation word's group
+const KeyEntry* ctx_key_of(poslo_ctx* c, uint32_t inst, const uint8_t pk[32], int* status);
+// FourQ generator's comb table (built on first use), or nullptr
+const uint32_t* ctx_gtable_fq(poslo_ctx* c);
+// the cache id of a FourQ key
+inline std::string fq_key_id(const uint8_t pk[32]) { return std::string((const char*)pk, 32) + '\x01'; }
 // device comb tables of many keys (built on the device for the missing
 // ones); tables[k] is key k's table.  Keys that are not point encodings get
 // nullptr and are counted in *n_bad (the call then returns E_ENCODING).

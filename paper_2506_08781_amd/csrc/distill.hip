@@ -445,6 +445,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
                              void* stream, poslo_ccd** out) {
     if (!out || !pk || !m_in || n_umbrella == 0) return POSLO_E_INVAL;
     *out = nullptr;
+    if (prm && (prm->inst & POSLO_GROUP_FOURQ)) return POSLO_E_INVAL;  // per-entry checks: edwards25519 only
     hipStream_t s = (hipStream_t)stream;
     if (m_in->n && !sigs_in) return POSLO_E_INVAL;
     poslo_msgs dm;
@@ -786,6 +787,7 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
 int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m_in,
                        const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream) {
     if (!c || !prm || !pk || !m_in || !ccd || !n_bits) return POSLO_E_INVAL;
+    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;
     poslo_msgs dm;
     int st0 = stage_msgs(c, m_in, (hipStream_t)stream, dm, nullptr, nullptr);
     if (st0) return st0;

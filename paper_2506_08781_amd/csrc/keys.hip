@@ -15,6 +15,7 @@
 #include "comb.h"
 #include "ctx.h"
 #include "device_ec.h"
+#include "fourq.h"
 #include "ge25519.h"
 
 namespace poslo {
@@ -43,6 +44,35 @@ __global__ __launch_bounds__(kCombPerWindow) void k_comb_build(const uint8_t* pk
         for (int k = 0; k < kCombEntryWords / 4; k++) q[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
         if (w + 1 < kCombWindows)
             for (int k = 0; k < 8; k++) ge_dbl(P, P);
+    }
+}
+
+// The same table for a FourQ key (fourq.h: GF(p^2) coordinates in the same
+// 24-word entries)
+__global__ __launch_bounds__(kCombPerWindow) void k_comb_build_fq(const uint8_t* pks, uint32_t* tables, uint32_t* ok) {
+    const uint32_t key = blockIdx.x;
+    uint8_t b[32];
+    for (int k = 0; k < 32; k++) b[k] = pks[(uint64_t)key * 32 + k];
+    gq Y;
+    const bool good = fq_decode(Y, b);
+    if (threadIdx.x == 0) ok[key] = good ? 1u : 0u;
+    if (!good) return;
+    const uint32_t m = threadIdx.x + 1;  // 1..128
+    gq P;
+    gq_identity(P);
+    for (int bit = 7; bit >= 0; bit--) {
+        gq_dbl(P, P);
+        if ((m >> bit) & 1u) gq_add(P, P, Y);
+    }
+    uint32_t* dst = tables + (uint64_t)key * kCombWords + (uint64_t)threadIdx.x * kCombEntryWords;
+    for (int w = 0; w < kCombWindows; w++) {
+        uint32_t o[kCombEntryWords];
+        fq_comb_entry_of(o, P);
+        uint4* q = reinterpret_cast<uint4*>(dst + (uint64_t)w * kCombPerWindow * kCombEntryWords);
+#pragma unroll
+        for (int k = 0; k < kCombEntryWords / 4; k++) q[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+        if (w + 1 < kCombWindows)
+            for (int k = 0; k < 8; k++) gq_dbl(P, P);
     }
 }
 
@@ -108,7 +138,7 @@ const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]) {
     return d;
 }
 
-int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {
+static int build_tables(bool fourq, const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {
     ok.assign(m, 0);
     if (m == 0) return POSLO_OK;
     void *d_pks = nullptr, *d_ok = nullptr;
@@ -119,14 +149,84 @@ int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector
     }
     bool fail = hipMemcpy(d_pks, pks, m * 32, hipMemcpyHostToDevice) != hipSuccess;
     if (!fail) {
-        hipLaunchKernelGGL(k_comb_build, dim3((uint32_t)m), dim3(kCombPerWindow), 0, 0, (const uint8_t*)d_pks, d_tab,
-                           (uint32_t*)d_ok);
+        if (fourq)
+            hipLaunchKernelGGL(k_comb_build_fq, dim3((uint32_t)m), dim3(kCombPerWindow), 0, 0, (const uint8_t*)d_pks,
+                               d_tab, (uint32_t*)d_ok);
+        else
+            hipLaunchKernelGGL(k_comb_build, dim3((uint32_t)m), dim3(kCombPerWindow), 0, 0, (const uint8_t*)d_pks,
+                               d_tab, (uint32_t*)d_ok);
         fail = hipGetLastError() != hipSuccess ||
                hipMemcpy(ok.data(), d_ok, m * 4, hipMemcpyDeviceToHost) != hipSuccess;
     }
     hipFree(d_pks);
     hipFree(d_ok);
     return fail ? POSLO_E_DEVICE : POSLO_OK;
+}
+
+const uint32_t* ctx_gtable_fq(poslo_ctx* c) {
+    std::lock_guard<std::mutex> lk(c->wide_mu);
+    if (c->d_gtable_fq) return c->d_gtable_fq;
+    fp2 gx, gy;
+    fq_gen_xy(gx, gy);
+    gq G;
+    gq_from_affine(G, gx, gy);
+    uint8_t enc[32];
+    fq_encode(enc, G);
+    uint32_t* d = nullptr;
+    if (hipMalloc((void**)&d, (size_t)kCombWords * 4) != hipSuccess) return nullptr;
+    std::vector<uint32_t> ok;
+    if (build_tables(true, enc, 1, d, ok) || !ok[0]) {
+        hipFree(d);
+        return nullptr;
+    }
+    c->d_gtable_fq = d;
+    return d;
+}
+
+const KeyEntry* ctx_key_fq(poslo_ctx* c, const uint8_t pk[32], int* status) {
+    const std::string id = fq_key_id(pk);
+    auto it = c->key_index.find(id);
+    if (it != c->key_index.end()) {
+        c->keys.splice(c->keys.begin(), c->keys, it->second);
+        *status = POSLO_OK;
+        return &*it->second;
+    }
+    void* d_tab = nullptr;
+    if (hipMalloc(&d_tab, (size_t)kCombWords * 4) != hipSuccess) {
+        *status = POSLO_E_NOMEM;
+        return nullptr;
+    }
+    std::shared_ptr<void> slab(d_tab, [](void* q) { hipFree(q); });
+    std::vector<uint32_t> ok;
+    if ((*status = build_tables(true, pk, 1, (uint32_t*)d_tab, ok))) return nullptr;
+    if (!ok[0]) {
+        *status = POSLO_E_ENCODING;
+        return nullptr;
+    }
+    if (c->keys.size() + 1 > c->key_cap) {
+        hipDeviceSynchronize();  // queued work may still read evicted tables
+        while (c->keys.size() + 1 > c->key_cap && !c->keys.empty()) {
+            c->key_index.erase(c->keys.back().pk);
+            c->keys.pop_back();
+        }
+    }
+    KeyEntry ke;
+    ke.pk = id;
+    ke.fourq = true;
+    ke.d_table = (uint32_t*)d_tab;
+    ke.slab = slab;
+    c->keys.push_front(ke);
+    c->key_index[id] = c->keys.begin();
+    *status = POSLO_OK;
+    return &c->keys.front();
+}
+
+const KeyEntry* ctx_key_of(poslo_ctx* c, uint32_t inst, const uint8_t pk[32], int* status) {
+    return (inst & POSLO_GROUP_FOURQ) ? ctx_key_fq(c, pk, status) : ctx_key(c, pk, status);
+}
+
+int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {
+    return build_tables(false, pks, m, d_tab, ok);
 }
 
 int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad) {

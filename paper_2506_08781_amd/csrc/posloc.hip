@@ -146,6 +146,7 @@ extern "C" int poslo_c_key_load(poslo_ctx* c, const poslo_params* prm, const uin
                                 poslo_c_key** out) {
     if (!c || !params_ok(prm) || !pk || !out || prm->log2_n1 > 20) return POSLO_E_INVAL;
     *out = nullptr;
+    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;  // POSLO-C: edwards25519 only
     const uint64_t n1 = 1ull << prm->log2_n1;
     if (pk_len != 32 * (1 + n1)) return POSLO_E_INVAL;
     poslo_c_key* key = new (std::nothrow) poslo_c_key();

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "aes128.h"
+#include "fourq.h"
 #include "ge25519.h"
 #include "sc25519.h"
 #include "sha256.h"
@@ -225,7 +226,7 @@ inline void sc_from_bytes_reduce(uint32_t r[8], const uint8_t b[32]) {
     sc_reduce256(r, x);
 }
 
-// e_t = H(m || x) mod q as eight LE words; POSLO++ takes Add_q(m, x) =
+// e_t = H(m || x) mod q (mod N for FourQ) as eight LE words; POSLO++ takes Add_q(m, x) =
 // LE(m) + LE(x), below q for |m| <= 31 bytes (false for longer messages)
 inline bool digest_e(uint32_t spec, const uint8_t* m, size_t len, const uint8_t x[16], uint32_t e[8]) {
     if (inst_base(spec) == INST_AES_ADDQ) {
@@ -245,8 +246,25 @@ inline bool digest_e(uint32_t spec, const uint8_t* m, size_t len, const uint8_t 
     memcpy(mx.data() + len, x, 16);
     uint8_t d[32];
     H(spec, mx.data(), mx.size(), d);
-    sc_from_bytes_reduce(e, d);
+    if (spec & POSLO_GROUP_FOURQ) {  // LE256(H) mod N
+        uint32_t w[8];
+        for (int i = 0; i < 8; i++) w[i] = load_le32(d + 4 * i);
+        scN_reduce<8>(e, w);
+    } else {
+        sc_from_bytes_reduce(e, d);
+    }
     return true;
+}
+
+// LE256(b) reduced mod the group order of the instantiation word
+inline void scalar_from_bytes(uint32_t spec, uint32_t r[8], const uint8_t b[32]) {
+    if (spec & POSLO_GROUP_FOURQ) {
+        uint32_t w[8];
+        for (int i = 0; i < 8; i++) w[i] = load_le32(b + 4 * i);
+        scN_reduce<8>(r, w);
+    } else {
+        sc_from_bytes_reduce(r, b);
+    }
 }
 
 // (a * b) mod q: schoolbook product, then shift-and-subtract reduction
@@ -321,6 +339,27 @@ inline void ge_scalarmult_base(ge& r, const uint32_t k[8]) {
     }
     r = R;
 }
+
+// FourQ (fourq.h): the same fixed-base scheme over FourQ's generator
+struct FqBaseTable {
+    gq t[64][16];  // t[w][d] = d * 16^w * G
+};
+
+const FqBaseTable& fq_base_table();  // built once per process
+
+inline void fq_scalarmult_base(gq& r, const uint32_t k[8]) {
+    const FqBaseTable& T = fq_base_table();
+    gq R;
+    gq_identity(R);
+    for (int w = 0; w < 64; w++) {
+        uint32_t d = (k[w >> 3] >> (4 * (w & 7))) & 15u;
+        if (d) gq_add(R, R, T.t[w][d]);
+    }
+    r = R;
+}
+
+// the instantiation word selects FourQ
+inline bool group_fourq(uint32_t spec) { return (spec & POSLO_GROUP_FOURQ) != 0; }
 
 }  // namespace hostside
 }  // namespace poslo

@@ -33,7 +33,9 @@ struct poslo_signer {
     std::vector<DsNode> ds;
     uint8_t x0[16];
     std::vector<uint32_t> bpv_r;  // v scalars, 8 limbs each
-    std::vector<ge> bpv_R;        // v points
+    std::vector<ge> bpv_R;        // v points (edwards25519)
+    std::vector<gq> bpv_Rq;       // v points (FourQ)
+    bool fourq = false;
 };
 
 namespace {
@@ -112,11 +114,18 @@ void sign_entry(const poslo_signer* sk, uint64_t t, const uint8_t x0[16], const 
     uint32_t r[8] = {0};
     ge R;
     ge_identity(R);
+    gq Rq;
+    gq_identity(Rq);
     for (uint32_t k : S) {
         uint32_t tmp[8];
-        sc_add(tmp, r, &sk->bpv_r[8 * k]);
+        if (sk->fourq) {
+            scN_add(tmp, r, &sk->bpv_r[8 * k]);
+            gq_add(Rq, Rq, sk->bpv_Rq[k]);
+        } else {
+            sc_add(tmp, r, &sk->bpv_r[8 * k]);
+            ge_add(R, R, sk->bpv_R[k]);
+        }
         memcpy(r, tmp, sizeof r);
-        ge_add(R, R, sk->bpv_R[k]);
     }
     // x_t = PRF_0(x_0[i] || LE32(j)); e_t = H(m || x_t) mod q
     uint8_t in20[20];
@@ -126,10 +135,16 @@ void sign_entry(const poslo_signer* sk, uint64_t t, const uint8_t x0[16], const 
     prf(p.inst, 0, in20, 20, x);
     uint32_t e[8], ey[8], s[8];
     digest_e(p.inst, m, len, x, e);  // message lengths are checked by the caller
-    sc_mul(ey, e, sk->y);
-    sc_sub(s, r, ey);
+    if (sk->fourq) {
+        scN_mul(ey, e, sk->y);
+        scN_sub(s, r, ey);
+    } else {
+        sc_mul(ey, e, sk->y);
+        sc_sub(s, r, ey);
+    }
     for (int w = 0; w < 8; w++) store_le32(sig + 4 * w, s[w]);
-    ge_encode(sig + 32, R);
+    if (sk->fourq) fq_encode(sig + 32, Rq);
+    else ge_encode(sig + 32, R);
     memcpy(sig + 64, x, 16);
 }
 
@@ -156,8 +171,29 @@ const BaseTable& poslo::hostside::base_table() {
     return *T;
 }
 
+const FqBaseTable& poslo::hostside::fq_base_table() {
+    static FqBaseTable* T = nullptr;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        T = new FqBaseTable();
+        fp2 gx, gy;
+        fq_gen_xy(gx, gy);
+        gq P;
+        gq_from_affine(P, gx, gy);
+        for (int w = 0; w < 64; w++) {
+            gq_identity(T->t[w][0]);
+            T->t[w][1] = P;
+            for (int d = 2; d < 16; d++) gq_add(T->t[w][d], T->t[w][d - 1], P);
+            for (int k = 0; k < 4; k++) gq_dbl(P, P);
+        }
+    });
+    return *T;
+}
+
 extern "C" int poslo_inst_valid(uint32_t inst) {
-    return (inst & ~7u) == 0 && (inst & 3u) <= 2u && !((inst & POSLO_KAPPA127) && (inst & 3u) == 0u);
+    const uint32_t base = inst & 3u;
+    return (inst & ~15u) == 0 && base <= 2u && !((inst & POSLO_KAPPA127) && base == 0u) &&
+           !((inst & POSLO_GROUP_FOURQ) && base == 2u);
 }
 
 extern "C" const char* poslo_version(void) { return "poslo-mi355x 0.1"; }
@@ -182,11 +218,12 @@ extern "C" int poslo_kg(const poslo_params* prm, const uint8_t seed[32], poslo_s
     poslo_signer* sk = new (std::nothrow) poslo_signer();
     if (!sk) return POSLO_E_NOMEM;
     sk->prm = *prm;
+    sk->fourq = group_fourq(prm->inst);
     memcpy(sk->seed, seed, 32);
     for (uint32_t c = 0;; c++) {
         uint8_t d[32];
         derive(prm->inst, seed, "y", c, d);
-        sc_from_bytes_reduce(sk->y, d);
+        scalar_from_bytes(prm->inst, sk->y, d);
         uint32_t o = 0;
         for (int w = 0; w < 8; w++) o |= sk->y[w];
         if (o) break;
@@ -196,17 +233,29 @@ extern "C" int poslo_kg(const poslo_params* prm, const uint8_t seed[32], poslo_s
     memcpy(sk->root, xd, 16);
     uint32_t v = prm->bpv_v;
     sk->bpv_r.resize((size_t)v * 8);
-    sk->bpv_R.resize(v);
-    base_table();
+    if (sk->fourq) {
+        sk->bpv_Rq.resize(v);
+        fq_base_table();
+    } else {
+        sk->bpv_R.resize(v);
+        base_table();
+    }
     parallel_for(v, 0, [&](uint64_t k) {
         uint8_t d[32];
         derive(prm->inst, seed, "bpv", (uint32_t)k, d);
-        sc_from_bytes_reduce(&sk->bpv_r[8 * k], d);
-        ge_scalarmult_base(sk->bpv_R[k], &sk->bpv_r[8 * k]);
+        scalar_from_bytes(prm->inst, &sk->bpv_r[8 * k], d);
+        if (sk->fourq) fq_scalarmult_base(sk->bpv_Rq[k], &sk->bpv_r[8 * k]);
+        else ge_scalarmult_base(sk->bpv_R[k], &sk->bpv_r[8 * k]);
     });
-    ge Y;
-    ge_scalarmult_base(Y, sk->y);
-    ge_encode(pk, Y);
+    if (sk->fourq) {
+        gq Y;
+        fq_scalarmult_base(Y, sk->y);
+        fq_encode(pk, Y);
+    } else {
+        ge Y;
+        ge_scalarmult_base(Y, sk->y);
+        ge_encode(pk, Y);
+    }
     *out = sk;
     return POSLO_OK;
 }
@@ -277,6 +326,29 @@ extern "C" int poslo_ds_export(const poslo_signer* sk, uint8_t* buf, size_t cap,
     *len = out.size();
     if (!buf || cap < out.size()) return POSLO_E_INVAL;
     memcpy(buf, out.data(), out.size());
+    return POSLO_OK;
+}
+
+extern "C" int poslo_agg_inst(uint32_t inst, const uint8_t* sigs, size_t stride, uint64_t count, uint8_t tag[64]) {
+    if (!poslo_inst_valid(inst)) return POSLO_E_INVAL;
+    if (!group_fourq(inst)) return poslo_agg(sigs, stride, count, tag);
+    if (!tag || stride < 80 || (count && !sigs)) return POSLO_E_INVAL;
+    uint32_t s[8] = {0};
+    gq R;
+    gq_identity(R);
+    for (uint64_t k = 0; k < count; k++) {
+        const uint8_t* sg = sigs + k * stride;
+        gq Rt;
+        if (!fq_decode(Rt, sg + 32)) return POSLO_E_ENCODING;
+        uint32_t st[8], w[8], tmp[8];
+        for (int i = 0; i < 8; i++) w[i] = load_le32(sg + 4 * i);
+        scN_reduce<8>(st, w);
+        scN_add(tmp, s, st);
+        memcpy(s, tmp, sizeof s);
+        gq_add(R, R, Rt);
+    }
+    for (int w = 0; w < 8; w++) store_le32(tag + 4 * w, s[w]);
+    fq_encode(tag + 32, R);
     return POSLO_OK;
 }
 

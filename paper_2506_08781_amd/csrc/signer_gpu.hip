@@ -447,7 +447,7 @@ void to_mont(uint32_t out[8], const uint32_t y[8]) {
 extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, const uint8_t* seeds, uint32_t nkeys,
                                      poslo_gpu_keys** out, uint8_t* pks) {
     if (!c || !prm || !out || (nkeys && (!seeds || !pks))) return POSLO_E_INVAL;
-    if (!poslo_inst_valid(prm->inst) || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
+    if (!poslo_inst_valid(prm->inst) || (prm->inst & POSLO_GROUP_FOURQ) || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
         prm->bpv_k == 0 || prm->bpv_k > 16 || prm->bpv_k > prm->bpv_v || prm->log2_n1 + prm->log2_n2 > 32)
         return POSLO_E_INVAL;
     *out = nullptr;

@@ -22,6 +22,7 @@
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
+#include "fourq.h"
 #include "ge25519.h"
 #include "scheme_host.h"
 
@@ -132,6 +133,69 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f) {
     if (threadIdx.x == 0) {
         const uint32_t bad = f.bad ? *f.bad : 0u;
         f.result[8] = (f.checks_ok && eq && !bad) ? 1u : 0u;
+        f.result[9] = bad ? 1u : 0u;
+    }
+}
+
+// The same check on FourQ (fourq.h): e = fold mod N; then wave 0 looks up
+// one point per lane (lanes 0..31: window w of e on Y's table, lanes 32..63:
+// window w of s on G's table), sums the 64 points in a butterfly of
+// complete additions, and compares with the host-decoded R in projective
+// form (X = x_R Z, Y = y_R Z).
+__global__ __launch_bounds__(kBlock) void k_finalize_fq(FinalArgs f) {
+    __shared__ uint32_t total[9];
+    __shared__ uint32_t sh_es[16];
+    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t p = threadIdx.x; p < f.n_part; p += kBlock) acc288_add(acc, f.partials + (uint64_t)p * 9);
+    block_reduce288_store<kBlock>(acc, total);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t[9], e[8];
+        for (int k = 0; k < 9; k++) t[k] = total[k];
+        scN_reduce<9>(e, t);
+        for (int k = 0; k < 8; k++) {
+            sh_es[k] = e[k];
+            sh_es[8 + k] = f.s[k];  // s < N, checked on the host
+            f.result[k] = e[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x >= 64) return;  // wave 0 does the curve part
+    const uint32_t lane = threadIdx.x, w = lane & 31u;
+    uint32_t k[8];
+    for (int i = 0; i < 8; i++) k[i] = sh_es[(lane < 32 ? 0 : 8) + i];
+    uint32_t carry = 0;
+    int dg = 0;
+    for (int i = 0; i <= (int)w; i++) dg = comb_digit(k, i, carry);
+    gq P;
+    gq_identity(P);
+    if (dg != 0) {
+        const uint32_t mag = (uint32_t)(dg < 0 ? -dg : dg);
+        const uint32_t* tab = lane < 32 ? f.ty : f.tg;
+        gnq q;
+        fq_load_entry(q, tab + ((uint64_t)w * kCombPerWindow + mag - 1) * kCombEntryWords, dg < 0);
+        gq_madd(P, P, q);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        gq Q;
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&Q);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&P);
+#pragma unroll
+        for (int i = 0; i < 32; i++) dst[i] = __shfl_xor(src[i], off);
+        gq_add(P, P, Q);
+    }
+    if (lane == 0) {
+        fp2 xr, yr, t;
+        for (int i = 0; i < 4; i++) {
+            xr.a.v[i] = f.rx[i], xr.b.v[i] = f.rx[4 + i];
+            yr.a.v[i] = f.ry[i], yr.b.v[i] = f.ry[4 + i];
+        }
+        f2_mul(t, xr, P.Z);
+        const bool eqx = f2_eq(t, P.X);
+        f2_mul(t, yr, P.Z);
+        const bool eqy = f2_eq(t, P.Y);
+        const uint32_t bad = f.bad ? *f.bad : 0u;
+        f.result[8] = (f.checks_ok && eqx && eqy && !bad) ? 1u : 0u;
         f.result[9] = bad ? 1u : 0u;
     }
 }
@@ -287,6 +351,7 @@ extern "C" void poslo_ctx_destroy(poslo_ctx* c) {
     if (c->h_result) hipHostFree(c->h_result);
     if (c->d_gtable) hipFree(c->d_gtable);
     if (c->d_gtable_wide) hipFree(c->d_gtable_wide);
+    if (c->d_gtable_fq) hipFree(c->d_gtable_fq);
     batch_release(c);
     c->key_index.clear();
     c->keys.clear();
@@ -507,6 +572,21 @@ static void tag_checks(const uint8_t tag[64], FinalArgs& f) {
     }
 }
 
+// the same for FourQ: s < N, R decodes on FourQ (rx, ry: x and y as GF(p^2)
+// words, real part first)
+static void tag_checks_fq(const uint8_t tag[64], FinalArgs& f) {
+    for (int w = 0; w < 8; w++) f.s[w] = load_le32(tag + 4 * w);
+    gq R;
+    const bool r_ok = fq_decode(R, tag + 32);
+    f.checks_ok = (scN_is_canonical(f.s) && r_ok) ? 1u : 0u;
+    for (int k = 0; k < 4; k++) {
+        f.rx[k] = r_ok ? R.X.a.v[k] : 0u;
+        f.rx[4 + k] = r_ok ? R.X.b.v[k] : 0u;
+        f.ry[k] = r_ok ? R.Y.a.v[k] : 0u;
+        f.ry[4 + k] = r_ok ? R.Y.b.v[k] : 0u;
+    }
+}
+
 namespace poslo {
 
 // AVer over a batch, optionally leaving out the entries set in a device
@@ -566,12 +646,15 @@ int final_check(poslo_ctx* c, const KeyEntry* key, const uint32_t* partials, uin
     f.partials = partials;
     f.n_part = n_part;
     f.ty = key->d_table;
-    f.tg = c->d_gtable;
+    f.tg = key->fourq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!f.tg) return POSLO_E_NOMEM;
     f.result = c->d_result;
     f.bad = bad;
-    tag_checks(tag, f);
+    if (key->fourq) tag_checks_fq(tag, f);
+    else tag_checks(tag, f);
     prof_begin(c, POSLO_KT_FINAL, s);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
+    if (key->fourq) hipLaunchKernelGGL(k_finalize_fq, dim3(1), dim3(kBlock), 0, s, f);
+    else hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
     HIP_TRY(hipGetLastError());
     prof_end(c, POSLO_KT_FINAL, s);
     HIP_TRY(hipMemcpyAsync(c->h_result, c->d_result, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -600,7 +683,7 @@ int aver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const
     if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
     a.skip = skip;
     HIP_TRY(hipSetDevice(c->device));
-    const KeyEntry* key = ctx_key(c, pk, &st);
+    const KeyEntry* key = ctx_key_of(c, prm->inst, pk, &st);
     if (!key) return st;
     prof_begin(c, POSLO_KT_SEED, s);
     if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
@@ -634,6 +717,7 @@ extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_ms
     DsArg dsa;
     uint32_t n_epochs;
     if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
+    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;  // e_t is emitted mod q
     if (m->n == 0) return POSLO_OK;
     if (!e_dev) return POSLO_E_INVAL;
     HIP_TRY(hipSetDevice(c->device));
@@ -667,13 +751,16 @@ extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uin
     if (st) return st;
     // the key's comb table must be resident (poslo_ctx_keys_load): a lookup
     // that neither builds nor reorders anything
+    const bool fourq = (prm->inst & POSLO_GROUP_FOURQ) != 0;
+    const std::string id = fourq ? fq_key_id(pk) : std::string((const char*)pk, 32);
     const KeyEntry* key = nullptr;
     for (const KeyEntry& k : c->keys)
-        if (memcmp(k.pk.data(), pk, 32) == 0) {
+        if (k.pk == id) {
             key = &k;
             break;
         }
     if (!key) return POSLO_E_INVAL;
+    if (fourq && !c->d_gtable_fq) return POSLO_E_INVAL;  // built by a poslo_aver call on FourQ
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
@@ -695,8 +782,14 @@ extern "C" int poslo_aver_fixed(poslo_ctx* c, const poslo_params* prm, const uin
     f.tg = c->d_gtable;
     f.result = fx_result;
     f.bad = n_epochs ? a.bad : nullptr;
-    tag_checks(tag, f);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
+    if (fourq) {
+        f.tg = c->d_gtable_fq;
+        tag_checks_fq(tag, f);
+        hipLaunchKernelGGL(k_finalize_fq, dim3(1), dim3(kBlock), 0, s, f);
+    } else {
+        tag_checks(tag, f);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, f);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->h_result, fx_result, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -106,10 +106,39 @@ def test_host_signer_of_variants_matches_oracle(P, O, inst):
         assert P.poslo_signer_count(sk2) == len(lens)
 
 
+@pytest.mark.parametrize("inst", [1 | 8, 0 | 8, 1 | 4 | 8])
+def test_host_signer_fourq_matches_oracle(P, O, inst):
+    """The host signer over FourQ gives the oracle's key, signatures, ds and
+    aggregate tag byte for byte."""
+    seed = synthlog.key_seed_bytes(0x42)
+    prm = P.make_params(inst, 3, 2, bpv_v=64, bpv_k=8)
+    sk, pk = P.poslo_kg(prm, seed)
+    osk, opk = O.kg(O.Params(inst, 3, 2, v=64, k=8), seed)
+    assert pk == opk
+    lens = [0, 5, 16, 17, 31, 48, 3, 100, 9]
+    data, off = synthlog.messages_var(13, np.array(lens))
+    msgs = [bytes(data[off[k]:off[k + 1]]) for k in range(len(lens))]
+    sigs = [P.poslo_sig(sk, m) for m in msgs]
+    for k, m in enumerate(msgs):
+        assert sigs[k] == O.sig(osk, m), k
+    assert P.poslo_ds_export(sk) == O.ds_encode(osk.ds)
+    assert P.poslo_agg(b"".join(sigs), inst) == O.agg(sigs, inst)
+    sk2, _ = P.poslo_kg(prm, seed)
+    assert P.poslo_sig_batch(sk2, data, offsets=off, nthreads=3).tobytes() == b"".join(sigs)
+    # a commitment that is not a FourQ point
+    bad = bytearray(sigs[0])
+    bad[32:48] = (2 ** 127 - 1).to_bytes(16, "little")
+    with pytest.raises(P.PosloError) as ei:
+        P.poslo_agg(bytes(bad), inst)
+    assert ei.value.status == P.POSLO_E_ENCODING
+
+
 def test_instantiation_words(P):
-    for inst in (0, 1, 2, 5, 6):
-        P.poslo_kg(P.make_params(inst, 1, 1), bytes(32))
-    for inst in (3, 4, 7, 8, 0x101):
+    for inst in (0, 1, 2, 5, 6, 8, 9, 13):
+        assert P.lib().poslo_inst_valid(inst) == 1
+        P.poslo_kg(P.make_params(inst, 1, 1, bpv_v=16, bpv_k=4), bytes(32))
+    for inst in (3, 4, 7, 10, 12, 14, 16, 0x101):
+        assert P.lib().poslo_inst_valid(inst) == 0
         with pytest.raises(P.PosloError):
             P.poslo_kg(P.make_params(inst, 1, 1), bytes(32))
 

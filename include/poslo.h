@@ -219,7 +219,7 @@ int poslo_aver(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32],
  * that follow each other are independent (nothing in the array needs to
  * start at zero). */
 #define POSLO_AVER_FIXED_MAX_EPOCHS 16384
-#define POSLO_AVER_FIXED_SCRATCH_BYTES 3293696
+#define POSLO_AVER_FIXED_SCRATCH_BYTES 3310112
 int poslo_aver_fixed(poslo_ctx* ctx, const poslo_params* params, const uint8_t pk[32], const poslo_msgs* msgs,
                      const uint8_t* ds, size_t ds_len, const uint8_t tag[64], void* stream, int* accept,
                      uint8_t e_out[32]);

@@ -195,7 +195,9 @@ extern "C" int poslo_audit_feed(poslo_audit* a, const poslo_msgs* m, void* strea
     if (a->tab_rows < rows) {
         size_t have = a->tab_rows ? epoch_tab_words(a->tab_rows) * 4 : 0;
         if ((st = grow((void**)&a->d_tab, &have, epoch_tab_words(rows) * 4))) return st;
-        a->tab_rows = (have / 4 - epoch_tab_words(0)) / kEpochWords;
+        size_t r = (have / 4 - epoch_tab_words(0)) / kEpochWords;
+        while (r > 0 && epoch_tab_words(r) * 4 > have) r--;
+        a->tab_rows = r;
     }
     BatchArgs ba;
     DsArg dsa;

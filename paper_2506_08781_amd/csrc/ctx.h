@@ -144,9 +144,14 @@ struct BatchArgs;
 struct DsArg;
 bool params_ok(const poslo_params* p);
 // words of an epoch table of ne rows: the rows, then POSLO++'s long-message
-// flag word (padded to keep allocations aligned)
+// flag word (padded to keep allocations aligned), then the seeds of the
+// rows' subtrees of height kSeedMidHeight (4 words each) that the seed walk
+// of large batches passes through
 constexpr size_t kTabRowWords = 48;  // one epoch row (kEpochWords)
-constexpr size_t epoch_tab_words(uint64_t ne) { return (size_t)ne * kTabRowWords + 64; }
+constexpr int kSeedMidHeight = 4;
+constexpr size_t epoch_tab_words(uint64_t ne) {
+    return (size_t)ne * kTabRowWords + 64 + ((ne >> kSeedMidHeight) + 2) * 4;
+}
 // host-side checks of a batch (parameters, ds parse, SR coverage of every
 // epoch); fills the kernel argument block and the by-value ds, sizes the
 // epoch table (the context's, or fixed_tab of fixed_epochs rows when set)

@@ -36,8 +36,60 @@ namespace poslo {
 // of dependent PRF calls costs about a third of a one-lane encryption;
 // SHA-256: one lane per epoch.  K127: kappa = 127, one AES per tree level.
 // The first thread also clears the flag word after the last row (tab.bad).
+// SC from node value x (column c of it for AES, all four words for SHA-256)
+// down the bits hi-1 .. lo of epoch index i
+template <int INST, bool K127, class T>
+__device__ __forceinline__ void seed_walk_dev(const T& tb, uint32_t x[4], uint32_t c, uint64_t i, int hi, int lo) {
+    for (int j = hi - 1; j >= lo; j--) {
+        const uint32_t b = (uint32_t)((i >> j) & 1u);
+        if constexpr (INST == INST_AES) {
+            x[0] = K127 ? quad_prf_node127(tb, x[0], b, c) : quad_prf_node(tb, x[0], b, c);
+        } else {
+            uint32_t nx[4];
+            prf_node_sha(x, b, nx);
+            x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
+        }
+    }
+}
+
+// Many epochs: the seeds of their subtrees of height h = kSeedMidHeight
+// first (k_seed_mid), then each epoch walks the last h levels from its
+// subtree's seed.  The work drops from depth to h tree PRFs per epoch (plus
+// depth - h per 2^h epochs); the chain is as long as before.  mid holds 4
+// words per subtree (i >> h) - (epoch_first >> h) whose covering ds node
+// lies above height h.
+constexpr int kMidHeight = kSeedMidHeight;
+constexpr uint32_t kMidMinEpochs = 1u << 15;  // below this the one-pass walk is as fast
+
+inline uint32_t seed_mid_count(uint64_t epoch_first, uint32_t n_epochs) {
+    return n_epochs ? (uint32_t)(((epoch_first + n_epochs - 1) >> kMidHeight) - (epoch_first >> kMidHeight) + 1) : 0u;
+}
+
 template <int INST, bool K127>
-__global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_first, uint32_t n_epochs, uint32_t* tab) {
+__global__ __launch_bounds__(64) void k_seed_mid(DsArg ds, uint64_t epoch_first, uint32_t n_mid, uint32_t* mid) {
+    __shared__ uint32_t lds[INST == INST_AES ? 4 * 256 : 1];
+    if constexpr (INST == INST_AES) lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    const LdsTables<4, 1> tb{lds};
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t m = INST == INST_AES ? g >> 2 : g, c = g & 3u;
+    if (m >= n_mid) return;  // whole quads leave together
+    const uint64_t sub = (epoch_first >> kMidHeight) + m;
+    const uint64_t i = (sub << kMidHeight) > epoch_first ? (sub << kMidHeight) : epoch_first;
+    int k = ds_cover(ds, i);
+    if (k < 0) k = 0;  // coverage is validated on the host before launch
+    if ((int)ds.depth[k] <= kMidHeight) return;  // its epochs walk from the ds node
+    uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
+    if constexpr (INST == INST_AES) x[0] = ds.v[k][c];
+    seed_walk_dev<INST, K127>(tb, x, c, i, (int)ds.depth[k], kMidHeight);
+    uint32_t* o = mid + (uint64_t)m * 4;
+    if constexpr (INST == INST_AES) o[c] = x[0];
+    else o[0] = x[0], o[1] = x[1], o[2] = x[2], o[3] = x[3];
+}
+
+template <int INST, bool K127>
+__global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_first, uint32_t n_epochs, uint32_t* tab,
+                                                   const uint32_t* mid) {
     __shared__ uint32_t lds[INST == INST_AES ? 4 * 256 : 1];
     if constexpr (INST == INST_AES) lds_tables_fill<4, 1>(lds);
     __syncthreads();
@@ -50,21 +102,21 @@ __global__ __launch_bounds__(64) void k_seed_table(DsArg ds, uint64_t epoch_firs
     int k = ds_cover(ds, i);
     if (k < 0) k = 0;  // coverage is validated on the host before launch
     uint32_t* e = tab + (uint64_t)ep * kEpochWords;
+    // SC: walk the bits of i below the node's depth, most significant first
+    // (from the subtree's seed when k_seed_mid has walked the upper levels)
+    uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
+    int hi = (int)ds.depth[k];
+    if (mid && hi > kMidHeight) {
+        const uint32_t* ms = mid + ((i >> kMidHeight) - (epoch_first >> kMidHeight)) * 4;
+        x[0] = ms[0], x[1] = ms[1], x[2] = ms[2], x[3] = ms[3];
+        hi = kMidHeight;
+    }
     if constexpr (INST == INST_AES) {
-        uint32_t xc = ds.v[k][c];
-        // SC: walk the bits of i below the node's depth, most significant first
-        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) {
-            const uint32_t b = (uint32_t)((i >> j) & 1u);
-            xc = K127 ? quad_prf_node127(tb, xc, b, c) : quad_prf_node(tb, xc, b, c);
-        }
-        quad_epoch_row(tb, xc, c, e);
+        uint32_t xc[4] = {c == 0 ? x[0] : c == 1 ? x[1] : c == 2 ? x[2] : x[3], 0u, 0u, 0u};
+        seed_walk_dev<INST, K127>(tb, xc, c, i, hi, 0);
+        quad_epoch_row(tb, xc[0], c, e);
     } else {
-        uint32_t x[4] = {ds.v[k][0], ds.v[k][1], ds.v[k][2], ds.v[k][3]};
-        for (int j = (int)ds.depth[k] - 1; j >= 0; j--) {
-            uint32_t nx[4];
-            prf_node_sha(x, (uint32_t)((i >> j) & 1u), nx);
-            x[0] = nx[0], x[1] = nx[1], x[2] = nx[2], x[3] = nx[3];
-        }
+        seed_walk_dev<INST, K127>(tb, x, c, i, hi, 0);
         e[44] = x[0];
         e[45] = x[1];
         e[46] = x[2];
@@ -476,18 +528,27 @@ bool fast_layout(const poslo_msgs* m, uint64_t align) {
     return !m->offsets && m->msg_len > 0 && m->msg_len % align == 0 && ((uintptr_t)m->data % align) == 0;
 }
 
+template <int INST, bool K127>
+static void launch_seeds(const DsArg& dsa, const BatchArgs& a, uint32_t n_epochs, uint32_t* tab, hipStream_t s) {
+    const uint32_t per_block = INST == INST_AES ? 16 : 64;
+    uint32_t* mid = nullptr;
+    if (n_epochs >= kMidMinEpochs) {
+        // the subtree seeds sit after the rows and the flag word (epoch_tab_words)
+        mid = tab + (size_t)n_epochs * kEpochWords + 64;
+        const uint32_t n_mid = seed_mid_count(a.epoch_first, n_epochs);
+        hipLaunchKernelGGL((k_seed_mid<INST, K127>), dim3((n_mid + per_block - 1) / per_block), dim3(64), 0, s, dsa,
+                           a.epoch_first, n_mid, mid);
+    }
+    hipLaunchKernelGGL((k_seed_table<INST, K127>), dim3((n_epochs + per_block - 1) / per_block), dim3(64), 0, s, dsa,
+                       a.epoch_first, n_epochs, tab, (const uint32_t*)mid);
+}
+
 int launch_seed_table(const DsArg& dsa, uint32_t inst, const BatchArgs& a, uint32_t n_epochs, hipStream_t s) {
     if (n_epochs == 0) return POSLO_OK;
     uint32_t* tab = const_cast<uint32_t*>(a.tab);
-    if (prf_is_aes(inst) && kappa127(inst))
-        hipLaunchKernelGGL((k_seed_table<INST_AES, true>), dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa,
-                           a.epoch_first, n_epochs, tab);
-    else if (prf_is_aes(inst))
-        hipLaunchKernelGGL((k_seed_table<INST_AES, false>), dim3((n_epochs + 15) / 16), dim3(64), 0, s, dsa,
-                           a.epoch_first, n_epochs, tab);
-    else
-        hipLaunchKernelGGL((k_seed_table<INST_SHA256, false>), dim3((n_epochs + 63) / 64), dim3(64), 0, s, dsa,
-                           a.epoch_first, n_epochs, tab);
+    if (prf_is_aes(inst) && kappa127(inst)) launch_seeds<INST_AES, true>(dsa, a, n_epochs, tab, s);
+    else if (prf_is_aes(inst)) launch_seeds<INST_AES, false>(dsa, a, n_epochs, tab, s);
+    else launch_seeds<INST_SHA256, false>(dsa, a, n_epochs, tab, s);
     return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
 }
 

@@ -258,3 +258,33 @@ def test_aggregate_check_doubling_and_cancelling(P, gpu):
     off = torch.arange(0, len(tags) * n * L + 1, L, dtype=torch.int64, device="cuda")
     acc, _ = P.poslo_verify_batch(ctx, params, bj, flat, off)
     assert acc == want
+
+
+@pytest.mark.parametrize("inst", [1, 0, 1 | 4])
+def test_many_epochs_two_level_seed_walk(P, gpu, inst):
+    """Batches of at least 2^15 epochs derive the seeds of their height-4
+    subtrees first and walk the last 4 levels per epoch.  n2 = 1 and 40,000
+    epochs from epoch 5, with the signer's ds after epoch 40,004: nodes of
+    depth 15, 12, 11, 10 and 6 (walked through subtree seeds) and 2 and 0
+    (walked directly).  e and sampled x_t equal the oracle's."""
+    from oracle import oracle as O
+    torch, ctx = gpu
+    prm = O.Params(inst, 17, 0)
+    t0, n = 5, 40000
+    ds = O.ds_encode(O.signer_at(prm, synthlog.key_seed_bytes(0x77), t0 + n).ds)
+    depths = sorted(nd.depth for nd in O.ds_decode(ds))
+    assert depths[0] <= 4 < depths[-1]
+    arr = synthlog.messages_fixed(77, n, 16)
+    msgs = [bytes(r) for r in arr]
+    params = P.make_params(inst, 17, 0)
+    d = torch.from_numpy(arr.copy()).cuda()
+    m = P.make_msgs(d, t0=t0)
+    pk = O.encode(O.scalar_mult(12345, O.G))  # any key: only e is compared
+    print(f"inst {inst}: aver over {n} epochs", flush=True)
+    _, e = P.poslo_aver(ctx, params, pk, m, ds, bytes(64))
+    assert int.from_bytes(e, "little") == O.ekeys_sum(prm, msgs, t0, ds)
+    _, xg = P.poslo_ekeys(ctx, params, m, ds)
+    xg = xg.cpu().numpy()
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), t0, n)
+    for p in list(range(0, n, 997)) + [n - 1]:
+        assert bytes(xg[p]) == O.one_time_seed(inst, seeds[t0 + p], 0), p

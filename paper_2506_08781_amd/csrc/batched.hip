@@ -412,7 +412,9 @@ constexpr int kNumHot = sizeof kHot / sizeof kHot[0];
 
 int batch_variant_count() { return kNumHot; }
 const HotVariant& batch_variant(int v) { return kHot[v]; }
-int batch_default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 0 : 5; }
+// AES: aes_p2x32_b1024_c2048_paired_w8, the autotuner's pick on the
+// 4,096-signer log (1.52 G entries/s); SHA-256: sha_b256_c1024_sorted_w3
+int batch_default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 16 : 5; }
 
 size_t hot_lds_bytes(const HotVariant& v) {
     size_t tw = v.inst == 1 ? (size_t)v.nt * 256 * (v.copies ? v.copies : 64) : 0;

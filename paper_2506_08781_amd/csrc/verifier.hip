@@ -189,14 +189,144 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f) {
     }
 }
 
-// The same check on FourQ (fourq.h): e = fold mod N; then wave 0 looks up
-// one point per lane (lanes 0..31: window w of e on Y's table, lanes 32..63:
-// window w of s on G's table), sums the 64 points in a butterfly of
-// complete additions, and compares with the host-decoded R in projective
-// form (X = x_R Z, Y = y_R Z).
+// The same check on FourQ (fourq.h), with the quad-split tree of
+// block_double_scalar_is: quad k of the block owns point k of 64 (k < 32:
+// window k of e on Y's table, k >= 32: window k - 32 of s on G's), lane c
+// coordinate c (X, Y, Z, T) as 8 words in LDS.  Per tree level lane 0 forms
+// A = (Y1 - X1)(Y2 - X2), lane 1 B = (Y1 + X1)(Y2 + X2), lane 2
+// C = 2d T1 T2 (one more product: 2d is a full GF(p^2) element here),
+// lane 3 D = 2 Z1 Z2; the quad shares them by DPP moves, and lane c forms
+// output coordinate c (X3 = EF, Y3 = GH, Z3 = FG, T3 = EH).  Then the sum
+// is compared with the host-decoded R in projective form.
+__device__ __forceinline__ void lds_load_f2(fp2& a, const uint32_t* p) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) a.a.v[k] = p[k], a.b.v[k] = p[4 + k];
+}
+
+__device__ __forceinline__ void lds_store_f2(uint32_t* p, const fp2& a) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) p[k] = a.a.v[k], p[4 + k] = a.b.v[k];
+}
+
+__device__ __forceinline__ bool block_double_scalar_is_fq(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
+                                                          const uint32_t e[8], const uint32_t s[8], const fp2& rx,
+                                                          const fp2& ry) {
+    const int k = (int)(threadIdx.x >> 2), c = (int)(threadIdx.x & 3);
+    const uint32_t* sc = k < 32 ? e : s;
+    const int w = k & 31;
+    uint32_t carry = 0;
+    int d = 0;
+    for (int i = 0; i < kCombWindows; i++) {  // fixed trip count: the scalar stays in registers
+        const int di = comb_digit(sc, i, carry);
+        if (i == w) d = di;
+    }
+    // the affine point (x, y) as (4x : 4y : 4 : 4xy) from y + x and y - x
+    // (the identity (0 : 4 : 4 : 0) for a zero digit)
+    fp2 a, b, m, v;
+    if (d != 0) {
+        const uint32_t mag = (uint32_t)(d < 0 ? -d : d);
+        gnq q;
+        fq_load_entry(q, (k < 32 ? ty : tg) + ((uint64_t)w * kCombPerWindow + mag - 1) * kCombEntryWords, d < 0);
+        f2_sub(a, q.yp, q.ym);
+        f2_add(b, q.yp, q.ym);
+    } else {
+        f2_zero(a);
+        f2_one(b);
+        f2_add(b, b, b);
+    }
+    f2_mul(m, a, b);
+    if (c == 0) {
+        f2_add(v, a, a);
+    } else if (c == 1) {
+        f2_add(v, b, b);
+    } else if (c == 2) {
+        f2_zero(v);
+        v.a.v[0] = 4;
+    } else {
+        v = m;
+    }
+    lds_store_f2(lds + (k * 4 + c) * 8, v);
+    const fp2 d2 = fq_d2();
+    for (int o = 32; o >= 1; o >>= 1) {
+        __syncthreads();
+        if (k < o) {
+            const uint32_t* p1 = lds + k * 32;
+            const uint32_t* p2 = lds + (k + o) * 32;
+            const int co = c < 2 ? 0 : c == 2 ? 3 : 2;
+            fp2 u1, u2, y1, y2;
+            lds_load_f2(u1, p1 + co * 8);
+            lds_load_f2(u2, p2 + co * 8);
+            if (c < 2) {
+                lds_load_f2(y1, p1 + 8);
+                lds_load_f2(y2, p2 + 8);
+                if (c == 0) {
+                    f2_sub(u1, y1, u1);
+                    f2_sub(u2, y2, u2);
+                } else {
+                    f2_add(u1, y1, u1);
+                    f2_add(u2, y2, u2);
+                }
+            }
+            f2_mul(m, u1, u2);
+            if (c == 2) f2_mul(m, m, d2);
+            else if (c == 3) f2_add(m, m, m);
+            // every lane of the quad gets A, B, C, D (the word of lane L
+            // sits (L - c) & 3 lanes to the right)
+            fp2 A, B, C, D;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t r0 = j < 4 ? m.a.v[j & 3] : m.b.v[j & 3];
+                const uint32_t r1 = ec_quad_rot<1>(r0), r2 = ec_quad_rot<2>(r0), r3 = ec_quad_rot<3>(r0);
+                const uint32_t wa = c == 0 ? r0 : c == 1 ? r3 : c == 2 ? r2 : r1;
+                const uint32_t wb = c == 1 ? r0 : c == 2 ? r3 : c == 3 ? r2 : r1;
+                const uint32_t wc = c == 2 ? r0 : c == 3 ? r3 : c == 0 ? r2 : r1;
+                const uint32_t wd = c == 3 ? r0 : c == 0 ? r3 : c == 1 ? r2 : r1;
+                if (j < 4) {
+                    A.a.v[j & 3] = wa, B.a.v[j & 3] = wb, C.a.v[j & 3] = wc, D.a.v[j & 3] = wd;
+                } else {
+                    A.b.v[j & 3] = wa, B.b.v[j & 3] = wb, C.b.v[j & 3] = wc, D.b.v[j & 3] = wd;
+                }
+            }
+            fp2 E, F, G, H;
+            f2_sub(E, B, A);
+            f2_sub(F, D, C);
+            f2_add(G, D, C);
+            f2_add(H, B, A);
+            // lane 0: X3 = EF, lane 1: Y3 = GH, lane 2: Z3 = FG, lane 3: T3 = EH
+            fp2 l, r;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                l.a.v[j] = c == 1 ? G.a.v[j] : c == 2 ? F.a.v[j] : E.a.v[j];
+                l.b.v[j] = c == 1 ? G.b.v[j] : c == 2 ? F.b.v[j] : E.b.v[j];
+                r.a.v[j] = c == 0 ? F.a.v[j] : c == 2 ? G.a.v[j] : H.a.v[j];
+                r.b.v[j] = c == 0 ? F.b.v[j] : c == 2 ? G.b.v[j] : H.b.v[j];
+            }
+            f2_mul(v, l, r);
+            lds_store_f2(lds + (k * 4 + c) * 8, v);
+        }
+    }
+    __syncthreads();
+    bool ok = true;
+    if (k == 0 && c < 2) {
+        fp2 Z, V, R;
+        lds_load_f2(Z, lds + 2 * 8);
+        lds_load_f2(V, lds + c * 8);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            R.a.v[j] = c == 0 ? rx.a.v[j] : ry.a.v[j];
+            R.b.v[j] = c == 0 ? rx.b.v[j] : ry.b.v[j];
+        }
+        f2_mul(m, R, Z);
+        ok = f2_eq(m, V);
+    }
+    const uint64_t bad = __ballot(!ok);
+    return (bad & 3u) == 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize_fq(FinalArgs f) {
     __shared__ uint32_t total[9];
     __shared__ uint32_t sh_es[16];
+    __shared__ uint32_t pts[kQuadLdsWords];
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t p = threadIdx.x; p < f.n_part; p += kBlock) acc288_add(acc, f.partials + (uint64_t)p * 9);
     block_reduce288_store<kBlock>(acc, total);
@@ -212,42 +342,17 @@ __global__ __launch_bounds__(kBlock) void k_finalize_fq(FinalArgs f) {
         }
     }
     __syncthreads();
-    if (threadIdx.x >= 64) return;  // wave 0 does the curve part
-    const uint32_t lane = threadIdx.x, w = lane & 31u;
-    uint32_t k[8];
-    for (int i = 0; i < 8; i++) k[i] = sh_es[(lane < 32 ? 0 : 8) + i];
-    uint32_t carry = 0;
-    int dg = 0;
-    for (int i = 0; i <= (int)w; i++) dg = comb_digit(k, i, carry);
-    gq P;
-    gq_identity(P);
-    if (dg != 0) {
-        const uint32_t mag = (uint32_t)(dg < 0 ? -dg : dg);
-        const uint32_t* tab = lane < 32 ? f.ty : f.tg;
-        gnq q;
-        fq_load_entry(q, tab + ((uint64_t)w * kCombPerWindow + mag - 1) * kCombEntryWords, dg < 0);
-        gq_madd(P, P, q);
+    uint32_t e[8], sv[8];
+    for (int k = 0; k < 8; k++) e[k] = sh_es[k], sv[k] = sh_es[8 + k];
+    fp2 xr, yr;
+    for (int i = 0; i < 4; i++) {
+        xr.a.v[i] = f.rx[i], xr.b.v[i] = f.rx[4 + i];
+        yr.a.v[i] = f.ry[i], yr.b.v[i] = f.ry[4 + i];
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        gq Q;
-        uint32_t* dst = reinterpret_cast<uint32_t*>(&Q);
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(&P);
-#pragma unroll
-        for (int i = 0; i < 32; i++) dst[i] = __shfl_xor(src[i], off);
-        gq_add(P, P, Q);
-    }
-    if (lane == 0) {
-        fp2 xr, yr, t;
-        for (int i = 0; i < 4; i++) {
-            xr.a.v[i] = f.rx[i], xr.b.v[i] = f.rx[4 + i];
-            yr.a.v[i] = f.ry[i], yr.b.v[i] = f.ry[4 + i];
-        }
-        f2_mul(t, xr, P.Z);
-        const bool eqx = f2_eq(t, P.X);
-        f2_mul(t, yr, P.Z);
-        const bool eqy = f2_eq(t, P.Y);
+    const bool eq = block_double_scalar_is_fq(pts, f.ty, f.tg, e, sv, xr, yr);
+    if (threadIdx.x == 0) {
         const uint32_t bad = f.bad ? *f.bad : 0u;
-        f.result[8] = (f.checks_ok && eqx && eqy && !bad) ? 1u : 0u;
+        f.result[8] = (f.checks_ok && eq && !bad) ? 1u : 0u;
         f.result[9] = bad ? 1u : 0u;
     }
 }

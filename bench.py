@@ -18,9 +18,9 @@ The same run also measures, each on its own synthetic log:
    paper's convention): the headline batch per AVer call, the same batch
    streamed through the chunked audit, and a 2^25 x 32-byte log streamed in
    128 MiB chunks;
- - variants: POSLO++ (H = Add_q) at kappa = 127 and 128 over 2^26 entries of
-   16-byte messages, and POSLO+ at kappa = 127 and on the FourQ group on the
-   headline batch;
+ - variants: POSLO++ (H = Add_q) at kappa = 127 and 128 and POSLO+ over 2^26
+   entries of 16-byte messages, and POSLO+ at kappa = 127 and on the FourQ
+   group on the headline batch;
  - distill: Distill of 2^20 x 256-byte entries with 1% of entries carrying
    one flipped bit of m_t || sigma_t (exact invalid set, CCD);
  - batched: 4,096 signers with log-uniform [1, 65,536] entries of uniform
@@ -403,6 +403,20 @@ def bench_variants(P, torch, ctx, steps, warmup, rates):
                          "peak_measured_mix": mp, "frac_measured_mix": achieved / mp, "traffic": traffic_bytes("addq"),
                          "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                          "algorithmic_bytes": n * cfg["L"], "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS}}
+    # POSLO+ on the same 2^26 x 16-byte log: the paper's small-message case
+    log, total, lat, kt = bench_plain(P, torch, ctx, cfg, 1, steps, warmup, False)
+    del log
+    torch.cuda.empty_cache()
+    n = cfg["n"]
+    ope = ops_per_entry(1, cfg["L"])
+    achieved = n * ope / (kt["agg"] / 1e3) / 1e12
+    out["posloplus_2p26x16"] = {
+        "workload": cfg["name"] + ", POSLO+ (MMO/MDC-2 over AES-128)",
+        "entries_per_s": n / (total / steps), "ms_per_step": 1e3 * total / steps, "latency_ms": lat_summary(lat),
+        "kernel_ms": kt, "hashes_per_s": n / (total / steps) * hash_calls_per_entry(1, cfg["L"]),
+        "roofline": {"bound": "alu", "kernel": "k_agg_ekeys_aes", "achieved": achieved, "peak": INT32_PEAK_TOPS,
+                     "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops_per_entry": ope,
+                     "hbm_GBs": n * cfg["L"] / (kt["agg"] / 1e3) / 1e9}}
     cfg2 = CONFIGS["c2"]
     log, total, lat, kt = bench_plain(P, torch, ctx, cfg2, 1 | 4, steps, warmup, False)
     del log

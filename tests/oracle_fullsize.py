@@ -202,6 +202,89 @@ def full_case(inst: int, n: int, L: int, log2_n1: int, log2_n2: int, key_first: 
 
 
 # ---------------------------------------------------------------------------
+# one signer's job of a multi-signer log (variable-length messages)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class JobCase:
+    n: int
+    pk: bytes
+    ds: bytes
+    tag: bytes                      # Agg over the job's honest signatures
+    sigs: bytes                     # honest signatures, 80 bytes each
+    invalid: list                   # job-local t the oracle finds invalid after the plan
+    aver_corrupt: bool              # AVer of the corrupted job under the honest tag
+
+
+def _job_chunk(args):
+    from oracle import oracle as O
+    (inst, log2_n1, log2_n2, seed, ds, msg_seed, lens, base, a, b, plan, gamma) = args
+    prm = O.Params(inst, log2_n1, log2_n2)
+    data, off = synthlog.messages_var(msg_seed, np.asarray(lens[a:b], dtype=np.int64), t0=base + a)
+    msgs = [bytes(data[int(off[i]):int(off[i + 1])]) for i in range(b - a)]
+    signer = O.signer_at(prm, seed, a)
+    signer._gamma = gamma
+    pk = O.encode(O.scalar_mult(signer.y, O.G))
+    sigs = [O.sig(signer, m) for m in msgs]
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), a, b - a)
+    xs = [O.one_time_seed(inst, seeds[t >> log2_n2], t & (prm.n2 - 1)) for t in range(a, b)]
+    raw = sum(O.digest_int(inst, m, x) for m, x in zip(msgs, xs))
+    cm, cs = list(msgs), list(sigs)
+    for t, bit in plan:
+        p = t - a
+        blob = bytearray(cm[p] + cs[p])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        L = len(msgs[p])
+        cm[p], cs[p] = bytes(blob[:L]), bytes(blob[L:])
+    flipped = sorted({t - a for t, _ in plan})
+    bad = [a + p for p in flipped
+           if not O.entry_valid(prm, pk, cm[p], a + p, cs[p], seeds[(a + p) >> log2_n2])]
+    raw_c = raw + sum(O.digest_int(inst, cm[p], xs[p]) - O.digest_int(inst, msgs[p], xs[p]) for p in flipped)
+    rng = random.Random(base + a)
+    fl = set(flipped)
+    unplanned = [p for p in range(b - a) if p not in fl]
+    sample_bad = [a + p for p in rng.sample(unplanned, min(2, len(unplanned)))
+                  if not O.entry_valid(prm, pk, cm[p], a + p, cs[p], seeds[(a + p) >> log2_n2])]
+    return dict(sigs=b"".join(sigs), tag=O.agg(sigs), raw=raw, raw_c=raw_c, bad=bad, sample_bad=sample_bad)
+
+
+@functools.lru_cache(maxsize=None)
+def job_case(inst: int, log2_n1: int, log2_n2: int, key_seed: bytes, msg_seed: int, lens: tuple, base: int,
+             plan: tuple, nproc: int | None = None) -> JobCase:
+    """A signer (key seed bytes key_seed) whose entries t = 0 .. n-1 are the
+    multi-signer log's global entries base + t: messages of lens[t] bytes
+    from synthlog stream msg_seed at sid base + t, signed by the oracle from
+    t = 0.  plan: job-local (t, bit) flips of m_t || sigma_t.  Returns the
+    honest signatures and tag and the oracle's results on the corrupted
+    job."""
+    from oracle import oracle as O
+    prm = O.Params(inst, log2_n1, log2_n2)
+    n = len(lens)
+    signer = O.signer_at(prm, key_seed, n)
+    ds = O.ds_encode(signer.ds)
+    pk = O.encode(O.scalar_mult(signer.y, O.G))
+    nproc = nproc or workers()
+    span = max(1, -(-n // (2 * nproc)))
+    with _pool(nproc) as pool:
+        ks = list(range(prm.v))
+        parts = pool.map(_bpv_part, [(inst, log2_n1, log2_n2, key_seed, ks[i::nproc]) for i in range(nproc)])
+        gamma = {}
+        for part in parts:
+            gamma.update(part)
+        jobs = [(inst, log2_n1, log2_n2, key_seed, ds, msg_seed, lens, base, a, min(n, a + span),
+                 [(t, bit) for t, bit in plan if a <= t < min(n, a + span)], gamma) for a in range(0, n, span)]
+        res = pool.map(_job_chunk, jobs, chunksize=1)
+    sample_bad = [t for r in res for t in r["sample_bad"]]
+    if sample_bad:
+        raise AssertionError(f"honest entries the oracle rejects: {sample_bad[:8]}")
+    tag = O.agg([r["tag"] for r in res]) if res else O.agg([])
+    e_c = sum(r["raw_c"] for r in res) % O.Q
+    return JobCase(n=n, pk=pk, ds=ds, tag=tag, sigs=b"".join(r["sigs"] for r in res),
+                   invalid=sorted(t for r in res for t in r["bad"]),
+                   aver_corrupt=O.aggregate_check(pk, e_c, tag))
+
+
+# ---------------------------------------------------------------------------
 # POSLO-C: one signature per epoch
 # ---------------------------------------------------------------------------
 

@@ -79,3 +79,24 @@ def test_pooled_posloc_case_equals_sequential_oracle(O):
     assert c.e_corrupt == O.ekeys_sum(prm, cm, 0, ds)
     cep = [(i, cm[i * 4:(i + 1) * 4]) for i in range(k)]
     assert c.aver_corrupt == O.posloc_aver(prm, pk, cep, ds, O.posloc_agg_s(cs))
+
+
+def test_pooled_job_case_equals_sequential_oracle(O):
+    """One signer's job of a multi-signer log: messages of varying length
+    at global stream ids base + t, signed from t = 0; the pooled results
+    equal sign_batch, aver and distill run in order."""
+    import oracle_fullsize as F
+    inst, l1, l2, n, base, msg_seed = 1, 4, 3, 97, 1234, 21
+    key_seed = synthlog.derived_key_seed(22, 5)
+    lens = synthlog.uniform_per_stream(23, np.arange(base, base + n), 0, 70)
+    flips = synthlog.corruption_plan_var(24, n, 5, 8 * (lens.astype(np.int64) + 80))
+    case = F.job_case(inst, l1, l2, key_seed, msg_seed, tuple(int(x) for x in lens), base, tuple(flips), nproc=3)
+    prm = O.Params(inst, l1, l2)
+    data, off = synthlog.messages_var(msg_seed, lens, t0=base)
+    msgs = [bytes(data[off[t]:off[t + 1]]) for t in range(n)]
+    pk, sigs, ds, tag, _ = O.sign_batch(prm, key_seed, msgs)
+    assert (case.pk, case.ds, case.tag, case.sigs) == (pk, ds, tag, b"".join(sigs))
+    cm, cs = _corrupt(msgs, sigs, flips)
+    assert case.aver_corrupt == O.aver(prm, pk, cm, 0, ds, tag)
+    ccd = O.distill(prm, pk, cm, cs, 0, ds, 1)
+    assert case.invalid == [t for t, _ in ccd.invalid] == sorted(t for t, _ in flips)

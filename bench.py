@@ -625,6 +625,32 @@ def bench_batched(P, torch, ctx, inst, steps, rates):
             "check_kernels_ms": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
             "rejected": acc.count(False), "invalid": len(inv)}
 
+    # the same after giving the keys of jobs of 2^14 entries or more their
+    # wide tables (resident key state, built before timing)
+    big = [k for k in range(c["signers"]) if log.counts[k] >= 1 << 14]
+    t = time.perf_counter()
+    P.poslo_ctx_keys_widen(ctx, [log.jobs[k]["pk"] for k in big])
+    widen_s = time.perf_counter() - t
+    P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2, tuning=graph,
+                         cap=len(want_inv) + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        acc, inv = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2,
+                                        tuning=graph, cap=len(want_inv) + 16)
+    dt = (time.perf_counter() - t0) / reps
+    assert acc == want_acc and inv == want_inv, "batched invalid set (wide keys) differs from the injected flips"
+    P.poslo_ctx_profile(ctx, [P.POSLO_KT_VERIFY])
+    reset_times(P, ctx)
+    P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs, distill=2, tuning=graph,
+                         cap=len(want_inv) + 16)
+    torch.cuda.synchronize()
+    P.poslo_ctx_profile(ctx, False)
+    sets_wide = {"entries_per_s": total_entries / dt, "ms": 1e3 * dt,
+                 "check_kernels_ms": kernel_ms(P, ctx, P.POSLO_KT_VERIFY),
+                 "widened_keys": len(big), "widened_entries": int(sum(log.counts[k] for k in big)),
+                 "wide_table_bytes": len(big) * 48 * 2 ** 20, "widen_s": widen_s}
+
     # plain path: one AVer call per signer on the same device buffers
     plain_lat = []
     stream = torch.cuda.current_stream()
@@ -664,6 +690,7 @@ def bench_batched(P, torch, ctx, inst, steps, rates):
                     "eager_latency_ms": lat_summary(lat),
                     "hashes_per_s": hashes * steps / graph_total},
         "batched_with_invalid_sets": sets,
+        "batched_with_invalid_sets_wide_keys": sets_wide,
         "plain": {"entries_per_s": total_entries / plain_total, "ms_per_pass": 1e3 * plain_total,
                   "per_signer_latency_ms": lat_summary(plain_lat)},
         "speedup_vs_plain": graph_eps / (total_entries / plain_total),

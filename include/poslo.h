@@ -460,13 +460,25 @@ int poslo_gpu_sign(poslo_gpu_keys* keys, const poslo_sign_job* jobs, uint32_t nj
 /* ------------------------------------------------ many signers per launch */
 
 /* Load public keys into the context's device-resident key cache (comb
- * tables built on the device, 128 KiB per key), so that later calls with
+ * tables built on the device, 384 KiB per key), so that later calls with
  * these keys start without a host-side table build.  pks: host, 32*n.
  * *n_bad (may be NULL) gets the number of keys that are not point
  * encodings; those are skipped and the call returns POSLO_E_ENCODING.
  * The cache holds at least the keys of the largest batch seen and evicts
  * the least recently used beyond that.  Synchronous. */
 int poslo_ctx_keys_load(poslo_ctx* ctx, const uint8_t* pks, size_t n, size_t* n_bad);
+
+/* Give resident edwards25519 keys a wide table as well: 16 windows of
+ * 32,768 points m * 65536^w * Y (48 MiB per key, built on the device),
+ * loading keys that are not yet in the cache.  The individual checks of a
+ * key with a wide table (poslo_verify_batch with distill set, poslo_distill)
+ * then add 16 points of it instead of 32 of its 8-bit table, besides 16 of
+ * G's wide table; results do not change.  A widened key keeps its table
+ * until the key leaves the cache or the context is destroyed.  pks: host,
+ * 32*n.  E_ENCODING: some key is not a point encoding (the others are
+ * widened); E_NOMEM: a table could not be allocated or built (the tables
+ * built before it stay).  Synchronous. */
+int poslo_ctx_keys_widen(poslo_ctx* ctx, const uint8_t* pks, size_t n);
 
 /* One signer's batch inside a multi-signer verification: entries t0 ..
  * t0+n-1 of the signer with public key pk, whose messages are entries

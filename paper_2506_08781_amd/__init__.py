@@ -180,6 +180,7 @@ def lib():
             "poslo_gpu_keys_free": ([_VP], None),
             "poslo_gpu_sign": ([_VP, P(poslo_sign_job), _U32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
             "poslo_ctx_keys_load": ([_VP, _U8P, _SZ, P(_SZ)], _I),
+            "poslo_ctx_keys_widen": ([_VP, _U8P, _SZ], _I),
             "poslo_batch_variant_count": ([], _I),
             "poslo_batch_variant_name": ([_I], ctypes.c_char_p),
             "poslo_verify_batch": ([_VP, P(poslo_params), P(poslo_batch_job), _U32, _VP, _VP, _U64, _VP, _I,
@@ -727,6 +728,13 @@ def poslo_ctx_keys_load(ctx: Ctx, pks: list[bytes]) -> int:
     if st not in (POSLO_OK, POSLO_E_ENCODING):
         _check(st, "poslo_ctx_keys_load")
     return bad.value
+
+
+def poslo_ctx_keys_widen(ctx: Ctx, pks: list[bytes]) -> None:
+    """Give resident keys their wide table (48 MiB each) for the individual
+    checks; raises on a non-point key or when device memory runs out."""
+    blob = b"".join(bytes(p) for p in pks)
+    _check(lib().poslo_ctx_keys_widen(ctx.handle, blob, len(pks)), "poslo_ctx_keys_widen")
 
 
 def poslo_batch_variant_count() -> int:

@@ -21,6 +21,7 @@ namespace poslo {
 // device record of one job
 struct BJob {
     const uint32_t* ty;       // comb table of the key
+    const uint32_t* tyw;      // the key's wide table (comb.h), or nullptr
     const uint8_t* data;      // message bytes
     const uint64_t* offsets;  // job-local offsets (n + 1) into data, or nullptr: fixed msg_len
     uint64_t msg_len;
@@ -44,6 +45,7 @@ struct BItem {
 // one job as the host hands it in
 struct JobSpec {
     const uint32_t* ty;
+    const uint32_t* tyw = nullptr;  // the key's resident wide table, if it has one
     const uint8_t* data;
     const uint64_t* offsets;
     uint64_t msg_len;
@@ -117,10 +119,10 @@ class BatchRunner {
     // device buffers (grown on demand, kept)
     void *d_jobs_ = nullptr, *d_ds_ = nullptr, *d_rows_ = nullptr, *d_items_ = nullptr, *d_tab_ = nullptr,
          *d_part_ = nullptr, *d_res_ = nullptr, *d_misc_ = nullptr, *d_rdec_ = nullptr, *d_vtiles_ = nullptr,
-         *d_idx_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr, *d_pair_ = nullptr;
+         *d_idx_ = nullptr, *d_ekeys_ = nullptr, *d_xbad_ = nullptr, *d_pair_ = nullptr, *d_stash_ = nullptr;
     size_t n_jobs_b_ = 0, n_ds_b_ = 0, n_rows_b_ = 0, n_items_b_ = 0, n_tab_b_ = 0, n_part_b_ = 0, n_res_b_ = 0,
            n_misc_b_ = 0, n_rdec_b_ = 0, n_vtiles_b_ = 0, n_idx_b_ = 0, n_ekeys_b_ = 0, n_xbad_b_ = 0,
-           n_pair_b_ = 0;
+           n_pair_b_ = 0, n_stash_b_ = 0;
     uint64_t n_entries_ = 0;
     bool emitted_ = false;  // the last launch wrote e_t and the x checks
     // pinned staging

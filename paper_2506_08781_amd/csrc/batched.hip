@@ -343,25 +343,32 @@ struct BVerify {
     const uint8_t* xbad;    // PRE: x checks from the hashing kernel
     uint64_t* idx;    // appended slots (job's vbase + entry offset) of invalid entries
     uint32_t* count;  // number appended
+    uint32_t* stash;  // PRE: kVerifyStashWords per workgroup
+    uint32_t* next;   // PRE: tile queue head (zero at launch)
+    uint32_t ntiles;
 };
 
-// PRE: e_t and the x checks come from the hashing kernel (launch with
-// emit); each thread then checks entries i + 64 k (k < 4) of its tile with
-// one shared inversion
-constexpr int kVerifyNE = 4;
-template <bool PRE>
-__global__ __launch_bounds__(PRE ? 256 / kVerifyNE : 256) void k_batch_verify(BVerify V) {
-    constexpr int VB = 256 / kVerifyNE;
-    __shared__ uint32_t lds[PRE ? verify_batch_lds_words<kVerifyNE, VB>() : 4 * 256];
-    if constexpr (!PRE) {
-        lds_tables_fill<4, 1>(lds);
-        __syncthreads();
-    }
-    const BItem it = wave_uniform(V.tiles[blockIdx.x]);
-    const BJob J = wave_uniform(V.jobs[it.job]);
-    if constexpr (PRE) {
+// The individual checks of the listed jobs' entries.
+// With e_t and the x checks from the hashing kernel (launch with emit):
+// k_batch_verify_pre, persistent, one wave per workgroup pulling tiles from
+// a queue (largest first; every wave leaves once the queue is drained).  A
+// tile holds up to verify_tile_len entries of one job; thread i checks
+// entries i + 64 k, k < ne = ceil(count / 64), with one shared inversion,
+// the points waiting in the workgroup's slice of the stash.  A
+// key with a resident wide table (J.tyw) takes 16 + 16 mixed additions per
+// entry instead of 32 + 16.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_verify_pre(BVerify V) {
+    uint32_t* st = V.stash + (uint64_t)blockIdx.x * kVerifyStashWords + threadIdx.x;
+#pragma unroll 1
+    for (;;) {
+        uint32_t t = threadIdx.x == 0 ? atomicAdd(V.next, 1u) : 0u;
+        t = (uint32_t)__shfl((int)t, 0);
+        if (t >= V.ntiles) break;
+        const BItem it = wave_uniform(V.tiles[t]);
+        const BJob J = wave_uniform(V.jobs[it.job]);
+        const int ne = (int)((it.count + 63) / 64);
         auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
-            const uint32_t idx = threadIdx.x + (uint32_t)(VB * k);
+            const uint32_t idx = threadIdx.x + 64u * (uint32_t)k;
             const uint64_t p = it.first + (idx < it.count ? idx : 0);
             go = idx < it.count && !gload(V.xbad + J.ebase + p);
             // skipped entries point at the tile's first entry (in bounds)
@@ -369,28 +376,40 @@ __global__ __launch_bounds__(PRE ? 256 / kVerifyNE : 256) void k_batch_verify(BV
             sg = J.sigs + q * 80;
             e = V.ekeys + (J.ebase + q) * 8;
         };
-        const uint32_t okmask = verify_sig_batch<false, kVerifyNE, VB>(ent, J.ty, V.tg, lds);
+        const uint32_t okmask = J.tyw ? verify_sig_batch<true>(ent, ne, J.tyw, V.tg, st, 64)
+                                      : verify_sig_batch<false>(ent, ne, J.ty, V.tg, st, 64);
 #pragma unroll 1
-        for (int k = 0; k < kVerifyNE; k++) {
-            const uint32_t idx = threadIdx.x + (uint32_t)(VB * k);
+        for (int k = 0; k < ne; k++) {
+            const uint32_t idx = threadIdx.x + 64u * (uint32_t)k;
             wave_append(idx < it.count && !((okmask >> k) & 1u), J.vbase + it.first + idx, V.idx, V.count);
         }
-    } else {
-        LdsTables<4, 1> tb{lds};
-        bool bad = false;
-        uint64_t slot = 0;
-        if (threadIdx.x < it.count) {
-            uint64_t p = it.first + threadIdx.x;
-            uint32_t e[8], s[8];
-            BatchArgs a = job_args(J, V.log2_n2, V.tab);
-            bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
-            slot = J.vbase + p;
-        }
-        wave_append(bad, slot, V.idx, V.count);
     }
 }
 
-__global__ void k_zero_u32(uint32_t* p) { p[0] = 0; }
+// Without them (tiles of 256): one entry per thread, hashing included.
+__global__ __launch_bounds__(256) void k_batch_verify(BVerify V) {
+    __shared__ uint32_t lds[4 * 256];
+    lds_tables_fill<4, 1>(lds);
+    __syncthreads();
+    const BItem it = wave_uniform(V.tiles[blockIdx.x]);
+    const BJob J = wave_uniform(V.jobs[it.job]);
+    LdsTables<4, 1> tb{lds};
+    bool bad = false;
+    uint64_t slot = 0;
+    if (threadIdx.x < it.count) {
+        uint64_t p = it.first + threadIdx.x;
+        uint32_t e[8], s[8];
+        BatchArgs a = job_args(J, V.log2_n2, V.tab);
+        bad = !verify_one(tb, a, a.end, V.inst, p, J.sigs + p * 80, J.ty, V.tg, e, s);
+        slot = J.vbase + p;
+    }
+    wave_append(bad, slot, V.idx, V.count);
+}
+
+__global__ void k_zero_u32x2(uint32_t* p, uint32_t* q) {
+    p[0] = 0;
+    q[0] = 0;
+}
 
 // ---- tuning --------------------------------------------------------------------
 
@@ -493,7 +512,7 @@ BatchRunner::~BatchRunner() {
     forget_graphs();
     if (capture_) hipStreamDestroy(capture_);
     for (void* p : {d_jobs_, d_ds_, d_rows_, d_items_, d_tab_, d_part_, d_res_, d_misc_, d_rdec_, d_vtiles_, d_idx_,
-                    d_ekeys_, d_xbad_, d_pair_})
+                    d_ekeys_, d_xbad_, d_pair_, d_stash_})
         if (p) hipFree(p);
     if (h_res_) hipHostFree(h_res_);
     if (h_misc_) hipHostFree(h_misc_);
@@ -570,6 +589,7 @@ int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njo
         }
         BJob& J = jobs_[j];
         J.ty = in.ty;
+        J.tyw = in.tyw;
         J.data = in.data;
         J.offsets = in.offsets;
         J.msg_len = in.offsets ? 0 : in.msg_len;
@@ -726,27 +746,39 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     vtiles_.clear();
     vbase_.clear();
     n_checked_ = 0;
+    uint64_t n_all = 0;
     for (uint32_t j : which) {
         if (j >= jobs_.size()) return POSLO_E_INVAL;
+        n_all += jobs_[j].n;
+    }
+    const uint64_t tile = emitted_ ? verify_tile_len(n_all, prof->num_cu) : 256;
+    for (uint32_t j : which) {
         BJob& J = jobs_[j];
         if (J.n && !J.sigs) return POSLO_E_INVAL;
         J.vbase = n_checked_;
         vbase_.push_back({n_checked_, j});
-        for (uint64_t f = 0; f < J.n; f += 256)
-            vtiles_.push_back(BItem{j, (uint32_t)std::min<uint64_t>(256, J.n - f), f});
+        for (uint64_t f = 0; f < J.n; f += tile)
+            vtiles_.push_back(BItem{j, (uint32_t)std::min<uint64_t>(tile, J.n - f), f});
         n_checked_ += J.n;
     }
     if (n_checked_ >= (1ull << 32)) return POSLO_E_INVAL;
+    // largest tiles first: the persistent waves then finish together
+    if (emitted_)
+        std::stable_sort(vtiles_.begin(), vtiles_.end(),
+                         [](const BItem& x, const BItem& y) { return x.count > y.count; });
+    const uint32_t grid = (uint32_t)std::min<size_t>(vtiles_.size(), (size_t)prof->num_cu * kVerifyWgPerCu);
     int st;
     if ((st = grow(&d_vtiles_, &n_vtiles_b_, vtiles_.size() * sizeof(BItem))) ||
         (st = grow(&d_idx_, &n_idx_b_, n_checked_ * 8)) || (st = grow_pinned((void**)&h_misc_, &h_misc_b_, 64)))
         return st;
+    if (emitted_ && grid && (st = grow(&d_stash_, &n_stash_b_, (size_t)grid * kVerifyStashWords * 4))) return st;
     h_misc_[0] = 0;
     if (vtiles_.empty()) return POSLO_OK;
     HIP_TRY(hipMemcpyAsync(d_jobs_, jobs_.data(), jobs_.size() * sizeof(BJob), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_vtiles_, vtiles_.data(), vtiles_.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
     uint32_t* cnt = (uint32_t*)d_misc_ + 4;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, cnt);
+    uint32_t* next = (uint32_t*)d_misc_ + 8;
+    hipLaunchKernelGGL(k_zero_u32x2, dim3(1), dim3(1), 0, s, cnt, next);
     BVerify V;
     V.jobs = (const BJob*)d_jobs_;
     V.tiles = (const BItem*)d_vtiles_;
@@ -759,11 +791,14 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.xbad = emitted_ ? (const uint8_t*)d_xbad_ : nullptr;
     V.idx = (uint64_t*)d_idx_;
     V.count = cnt;
+    V.stash = emitted_ ? (uint32_t*)d_stash_ : nullptr;
+    V.next = next;
+    V.ntiles = (uint32_t)vtiles_.size();
     prof_begin(prof, POSLO_KT_VERIFY, s);
     if (emitted_)
-        hipLaunchKernelGGL(k_batch_verify<true>, dim3((uint32_t)vtiles_.size()), dim3(256 / kVerifyNE), 0, s, V);
+        hipLaunchKernelGGL(k_batch_verify_pre, dim3(grid), dim3(64), 0, s, V);
     else
-        hipLaunchKernelGGL(k_batch_verify<false>, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
+        hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
     prof_end(prof, POSLO_KT_VERIFY, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h_misc_, cnt, 4, hipMemcpyDeviceToHost, s));
@@ -852,6 +887,7 @@ int make_specs(poslo_ctx* c, const poslo_batch_job* jobs, uint32_t njobs, const 
         const poslo_batch_job& in = jobs[j];
         JobSpec& sp = specs[j];
         sp.ty = tables[j];
+        sp.tyw = ctx_key_wide_resident(c, jobs[j].pk);
         sp.data = data;
         sp.offsets = offsets ? offsets + in.entry_base : nullptr;
         sp.msg_len = 0;

@@ -17,13 +17,12 @@ constexpr int kWideWindows = 16;        // signed 16-bit digits of a scalar belo
 constexpr int kWidePerWindow = 32768;  // digit magnitudes 1..32768
 constexpr uint64_t kWideWords = (uint64_t)kWideWindows * kWidePerWindow * kCombEntryWords;
 
-// table entry of P
-PD void comb_entry_of(uint32_t o[kCombEntryWords], const ge& P) {
+// table entry of the point (X : Y : Z) given zi = 1 / Z
+PD void comb_entry_zinv(uint32_t o[kCombEntryWords], const fe& X, const fe& Y, const fe& zi) {
     const fe d2 = POSLO_FE_D2;
-    fe zi, x, y, a, b, t;
-    fe_inv(zi, P.Z);
-    fe_mul(x, P.X, zi);
-    fe_mul(y, P.Y, zi);
+    fe x, y, a, b, t;
+    fe_mul(x, X, zi);
+    fe_mul(y, Y, zi);
     fe_add(a, y, x);
     fe_sub(b, y, x);
     fe_mul(t, x, y);
@@ -36,6 +35,13 @@ PD void comb_entry_of(uint32_t o[kCombEntryWords], const ge& P) {
         o[8 + k] = b.v[k];
         o[16 + k] = t.v[k];
     }
+}
+
+// table entry of P
+PD void comb_entry_of(uint32_t o[kCombEntryWords], const ge& P) {
+    fe zi;
+    fe_inv(zi, P.Z);
+    comb_entry_zinv(o, P.X, P.Y, zi);
 }
 
 }  // namespace poslo

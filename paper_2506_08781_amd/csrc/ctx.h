@@ -59,9 +59,10 @@ struct KeyEntry {
     uint32_t* d_table = nullptr;  // comb table of Y on the device
     std::shared_ptr<void> slab;   // allocation holding d_table (shared by a bulk load)
     std::shared_ptr<void> wide;   // Y's wide table (comb.h), built on demand
+    bool wide_pinned = false;     // wide table asked for by poslo_ctx_keys_widen: kept with the key
 };
 
-constexpr size_t kMaxWideKeys = 8;  // wide key tables kept per context (48 MiB each)
+constexpr size_t kMaxWideKeys = 8;  // wide key tables built on demand kept per context (48 MiB each)
 
 }  // namespace poslo
 
@@ -131,8 +132,12 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
 // nullptr if it cannot be allocated
 const uint32_t* ctx_gtable_wide(poslo_ctx* c);
 // Y's wide table for a resident key (ctx_key first), built on first use
-// and kept for the kMaxWideKeys most recently used keys; nullptr on failure
+// and kept for the kMaxWideKeys most recently used keys (besides those
+// widened by poslo_ctx_keys_widen); nullptr on failure
 const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]);
+// Y's wide table of a resident edwards25519 key if it has one, else nullptr
+// (builds nothing)
+const uint32_t* ctx_key_wide_resident(poslo_ctx* c, const uint8_t pk[32]);
 // per-context state of the multi-signer path, released with the context
 void batch_release(poslo_ctx* c);
 // comb tables (comb.h layout) of the m encoded points pks (host, 32 bytes

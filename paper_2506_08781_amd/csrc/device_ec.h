@@ -85,6 +85,48 @@ PD int wide_digit(const uint32_t k[8], int w, uint32_t& carry) {
     return v > 32768 ? v - 65536 : v;
 }
 
+// the words of t[w][|d| - 1] (of t[w][0] for d = 0) and d, fetched ahead
+// of their use so that the load overlaps other work
+struct CombRaw {
+    uint32_t v[kCombEntryWords];
+    int d;
+};
+
+template <int PER = kCombPerWindow>
+PD void comb_fetch(CombRaw& r, const uint32_t* table, int w, int d) {
+    const uint32_t m = (uint32_t)(d < 0 ? -d : d);
+    const uint32_t* p = table + ((uint64_t)w * PER + (m ? m - 1 : 0)) * kCombEntryWords;
+#pragma unroll
+    for (int k = 0; k < kCombEntryWords; k++) r.v[k] = p[k];
+    r.d = d;
+}
+
+// the fetched entry with the sign of d applied; the identity for d = 0
+PD void comb_apply(gn& q, const CombRaw& r) {
+    const int d = r.d;
+    fe a, b, t;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        a.v[k] = r.v[k];
+        b.v[k] = r.v[8 + k];
+        t.v[k] = r.v[16 + k];
+    }
+    if (d == 0) {
+        fe_set(a, 1);
+        fe_set(b, 1);
+        fe_set(t, 0);
+    }
+    if (d < 0) {
+        q.yp = b;
+        q.ym = a;
+        fe_neg(q.t2d, t);
+    } else {
+        q.yp = a;
+        q.ym = b;
+        q.t2d = t;
+    }
+}
+
 // t[w][|d| - 1] with the sign of d applied; the identity for d = 0
 template <int PER = kCombPerWindow>
 PD void comb_lookup(gn& q, const uint32_t* table, int w, int d) {
@@ -174,16 +216,21 @@ __device__ __forceinline__ void lane_double_scalar_wide(ge& P, const uint32_t* t
 }
 
 // e*Y + s*G by one lane with both wide tables: 16 + 16 lookups and mixed
-// additions; e, s < 2^253
+// additions; e, s < 2^253.  Each table point is fetched one mixed addition
+// ahead of its use (both tables are far larger than the L2).
 __device__ __forceinline__ void lane_double_scalar_wide2(ge& P, const uint32_t* ty_wide, const uint32_t* tg_wide,
                                                          const uint32_t e[8], const uint32_t s[8]) {
     ge_identity(P);
     uint32_t ce = 0, cs = 0;
+    CombRaw r;
+    comb_fetch<kWidePerWindow>(r, ty_wide, 0, wide_digit(e, 0, ce));
     for (int w = 0; w < kWideWindows; w++) {
         gn q;
-        comb_lookup<kWidePerWindow>(q, ty_wide, w, wide_digit(e, w, ce));
+        comb_apply(q, r);
+        comb_fetch<kWidePerWindow>(r, tg_wide, w, wide_digit(s, w, cs));
         ge_madd(P, P, q);
-        comb_lookup<kWidePerWindow>(q, tg_wide, w, wide_digit(s, w, cs));
+        comb_apply(q, r);
+        if (w + 1 < kWideWindows) comb_fetch<kWidePerWindow>(r, ty_wide, w + 1, wide_digit(e, w + 1, ce));
         ge_madd(P, P, q);
     }
 }

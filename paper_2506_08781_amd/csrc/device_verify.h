@@ -214,29 +214,26 @@ __device__ __forceinline__ bool sig_encodes(const uint8_t* sg, bool c, const ge&
     return c && encodes_to_zinv(P, zi, r);
 }
 
-// The curve part of NE entries' checks per thread with one inversion for all
-// of them (Montgomery's trick).  Entries 0 .. NE-2 wait in the workgroup's
-// LDS as (X, Y, Z), 24 words each at lds[(24 k + w) * BLOCK + thread]; the
-// last stays in registers.  With c_k = Z_0 ... Z_k and inv = 1 / c_{NE-1},
-// entry k takes 1/Z_k = inv * c_{k-1} and then inv *= Z_k, going down.
-// ent(k, sg, e, go) names entry k: signature, e_t in memory, and whether to
-// check it (go = false reports it invalid; its pointers must still be
-// readable).  Bit k of the result is set when entry k is valid.
-template <int NE, int BLOCK>
-constexpr int verify_batch_lds_words() {
-    return (NE - 1) * 24 * BLOCK;
-}
-
-template <bool WY, int NE, int BLOCK, class ENT>
-__device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, const uint32_t* ty, const uint32_t* tg_wide,
-                                                     uint32_t* lds) {
-    static_assert(NE >= 2 && NE <= 32, "entries per thread");
-    uint32_t* my = lds + threadIdx.x;
+// The curve part of ne entries' checks per thread (1 <= ne <= 32, uniform
+// across the wave) with one inversion for all of them (Montgomery's trick).
+// Entries 0 .. ne-2 wait in global memory: entry k keeps X, Y, Z and
+// c_{k-1} = Z_0 ... Z_{k-1} at st[(32 k + w) * stride], w < 32, where st is
+// the thread's own base (only the thread itself reads its slots back); the
+// last stays in registers.  With inv = 1 / c_{ne-1}, entry k takes
+// 1/Z_k = inv * c_{k-1} and then inv *= Z_k, going down.  ent(k, sg, e, go)
+// names entry k: signature, e_t in memory, and whether to check it
+// (go = false reports it invalid; its pointers must still be readable).
+// Bit k of the result is set when entry k is valid.
+template <bool WY, class ENT>
+__device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, int ne, const uint32_t* ty,
+                                                       const uint32_t* tg_wide, uint32_t* st, uint32_t stride) {
+    if (ne <= 0) return 0;
     uint32_t okmask = 0;
-    fe c, c_prev;  // running product of the Z coordinates, and the one before the last entry
+    fe c, c_prev;
+    fe_set(c_prev, 1);
     ge P;
 #pragma unroll 1
-    for (int k = 0; k < NE; k++) {
+    for (int k = 0; k < ne; k++) {
         const uint8_t* sg;
         const uint32_t* e;
         bool go;
@@ -248,45 +245,45 @@ __device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, const uint3
             c_prev = c;
             fe_mul(c, c, P.Z);
         }
-        if (k < NE - 1) {
-            uint32_t* o = my + 24 * k * BLOCK;
+        if (k < ne - 1) {
+            uint32_t* o = st + (uint64_t)32 * k * stride;
+#pragma unroll
             for (int w = 0; w < 8; w++) {
-                o[w * BLOCK] = P.X.v[w];
-                o[(8 + w) * BLOCK] = P.Y.v[w];
-                o[(16 + w) * BLOCK] = P.Z.v[w];
+                o[w * stride] = P.X.v[w];
+                o[(8 + w) * stride] = P.Y.v[w];
+                o[(16 + w) * stride] = P.Z.v[w];
+                o[(24 + w) * stride] = c_prev.v[w];
             }
         }
     }
     fe inv, zi;
-    fe_inv(inv, c);  // 1 / (Z_0 ... Z_{NE-1})
+    fe_inv(inv, c);  // 1 / (Z_0 ... Z_{ne-1})
     {
         // the last entry, from registers
-        fe_mul(zi, inv, c_prev);
-        fe_mul(inv, inv, P.Z);
+        if (ne > 1) {
+            fe_mul(zi, inv, c_prev);
+            fe_mul(inv, inv, P.Z);
+        } else {
+            zi = inv;
+        }
         const uint8_t* sg;
         const uint32_t* e;
         bool go;
-        ent(NE - 1, sg, e, go);
-        if (!sig_encodes(sg, (okmask >> (NE - 1)) & 1u, P, zi)) okmask &= ~(1u << (NE - 1));
+        ent(ne - 1, sg, e, go);
+        if (!sig_encodes(sg, (okmask >> (ne - 1)) & 1u, P, zi)) okmask &= ~(1u << (ne - 1));
     }
 #pragma unroll 1
-    for (int k = NE - 2; k >= 0; k--) {
-        const uint32_t* o = my + 24 * k * BLOCK;
-        fe z;
+    for (int k = ne - 2; k >= 0; k--) {
+        const uint32_t* o = st + (uint64_t)32 * k * stride;
+        fe z, ck;
+#pragma unroll
         for (int w = 0; w < 8; w++) {
-            P.X.v[w] = o[w * BLOCK];
-            P.Y.v[w] = o[(8 + w) * BLOCK];
-            z.v[w] = o[(16 + w) * BLOCK];
+            P.X.v[w] = o[w * stride];
+            P.Y.v[w] = o[(8 + w) * stride];
+            z.v[w] = o[(16 + w) * stride];
+            ck.v[w] = o[(24 + w) * stride];
         }
         if (k > 0) {
-            // c_{k-1} = Z_0 ... Z_{k-1}, again from LDS
-            fe ck;
-            for (int w = 0; w < 8; w++) ck.v[w] = my[16 * BLOCK + w * BLOCK];
-            for (int j = 1; j < k; j++) {
-                fe zj;
-                for (int w = 0; w < 8; w++) zj.v[w] = my[(24 * j + 16 + w) * BLOCK];
-                fe_mul(ck, ck, zj);
-            }
             fe_mul(zi, inv, ck);
             fe_mul(inv, inv, z);
         } else {
@@ -299,6 +296,22 @@ __device__ __forceinline__ uint32_t verify_sig_batch(const ENT& ent, const uint3
         if (!sig_encodes(sg, (okmask >> k) & 1u, P, zi)) okmask &= ~(1u << k);
     }
     return okmask;
+}
+
+// Launch shape of the persistent check kernels: one wave per workgroup,
+// two per SIMD (their register budget), each thread checking up to
+// kVerifyNEMax entries of a tile with one shared inversion, the points
+// waiting in kVerifyStashWords of global memory per wave.
+constexpr int kVerifyNEMax = 16;
+constexpr uint64_t kVerifyStashWords = (uint64_t)(kVerifyNEMax - 1) * 32 * 64;
+constexpr int kVerifyWgPerCu = 8;
+
+// entries per tile (a multiple of 64, at most 64 * kVerifyNEMax) for n
+// entries: as many per thread as keeps every wave slot of the chip busy
+inline uint32_t verify_tile_len(uint64_t n, int num_cu) {
+    const uint64_t lanes = (uint64_t)num_cu * kVerifyWgPerCu * 64;
+    const uint64_t per = (n + lanes - 1) / lanes;
+    return 64u * (uint32_t)(per < 1 ? 1 : per > kVerifyNEMax ? kVerifyNEMax : per);
 }
 
 // Individual verification of the entry at batch position pos with signature

@@ -31,21 +31,23 @@
 
 namespace poslo {
 
-constexpr int kTile = 256;  // entries per verification tile (one workgroup)
+constexpr int kTile = 256;  // entries per tile of SeBVer's e-key sums (one workgroup)
 constexpr uint64_t kWideKeyMinEntries = 1u << 18;  // Distill batches that use Y's wide table
 
-// tiles never straddle an umbrella: umbrella l covers [l*span, min(n, (l+1)*span))
+// tiles of `len` entries never straddle an umbrella: umbrella l covers
+// [l*span, min(n, (l+1)*span))
 struct TileGeom {
     uint64_t n;
     uint64_t span;
     uint32_t tiles_per_umb;
+    uint32_t len;
 };
 
 __device__ __forceinline__ bool tile_range(const TileGeom& g, uint32_t tile, uint64_t& start, uint64_t& end) {
     uint64_t l = tile / g.tiles_per_umb, k = tile % g.tiles_per_umb;
     uint64_t u0 = l * g.span, u1 = u0 + g.span < g.n ? u0 + g.span : g.n;
-    start = u0 + k * kTile;
-    end = start + kTile < u1 ? start + kTile : u1;
+    start = u0 + k * g.len;
+    end = start + g.len < u1 ? start + g.len : u1;
     return start < end;
 }
 
@@ -60,6 +62,9 @@ struct VerifyArgs {
     const uint32_t* tg;    // G's wide table (the per-entry checks)
     uint8_t* flags;        // 1 = invalid, per batch position (tile mode) or list item
     uint32_t* tile_part;   // 18 words per tile: lazy sums of e_t and s_t over valid entries
+    uint32_t* stash;       // tile mode: kVerifyStashWords per wave
+    uint32_t* next;        // tile mode: tile queue head (zero at launch)
+    uint32_t n_tiles;
 };
 
 // individual verification of the entry at batch position pos (device_verify.h)
@@ -132,44 +137,54 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 
 // the curve part of every entry's check, with e_t and the x check from
 // k_distill_hash; valid entries' (e_t, s_t) go into the tile's partials.
-// Each thread checks entries i + 64 k (k < 4) of its tile with one shared
-// inversion.  WY: v.ty is Y's wide table.
-constexpr int kVerifyNE = 4;
-constexpr int kVerifyBlock = kTile / kVerifyNE;
-template <bool WY>
-__global__ __launch_bounds__(kVerifyBlock) void k_verify_tiles(VerifyArgs v, const uint32_t* ekeys,
-                                                               const uint8_t* xbad) {
-    __shared__ uint32_t pts[verify_batch_lds_words<kVerifyNE, kVerifyBlock>()];
-    uint64_t start, end;
-    const bool any = tile_range(v.g, blockIdx.x, start, end);
-    auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
-        const uint64_t pos = start + threadIdx.x + (uint64_t)k * kVerifyBlock;
-        go = any && pos < end && !xbad[pos];
-        // skipped entries point at entry 0 (read by nothing that matters)
-        sg = v.sigs + (go ? 80 * pos : 0);
-        e = ekeys + (go ? pos * 8 : 0);
-    };
-    const uint32_t okmask = verify_sig_batch<WY, kVerifyNE, kVerifyBlock>(ent, v.ty, v.tg, pts);
-    uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+// Persistent, one wave per workgroup pulling tiles from a queue; thread i
+// checks entries i + 64 k of its tile (k < ceil(len / 64)) with one shared
+// inversion, the points waiting in the wave's slice of the stash.  ty_wide:
+// v.ty is Y's wide table (else its 8-bit one).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_verify_tiles(
+    VerifyArgs v, const uint32_t* ekeys, const uint8_t* xbad, uint32_t ty_wide) {
+    uint32_t* st = v.stash + (uint64_t)blockIdx.x * kVerifyStashWords + threadIdx.x;
 #pragma unroll 1
-    for (int k = 0; k < kVerifyNE; k++) {
-        const uint64_t pos = start + threadIdx.x + (uint64_t)k * kVerifyBlock;
-        if (!any || pos >= end) continue;
-        const bool ok = (okmask >> k) & 1u;
-        v.flags[pos] = ok ? 0 : 1;
-        if (ok) {
-            uint32_t w8[8];
-            for (int w = 0; w < 8; w++) w8[w] = gload(ekeys + pos * 8 + w);
-            acc288_add256(ae, w8);
-            for (int w = 0; w < 8; w++) w8[w] = gload_le32(v.sigs + 80 * pos + 4 * w);
-            acc288_add256(as, w8);
+    for (;;) {
+        uint32_t tile = threadIdx.x == 0 ? atomicAdd(v.next, 1u) : 0u;
+        tile = (uint32_t)__shfl((int)tile, 0);
+        if (tile >= v.n_tiles) break;
+        uint64_t start, end;
+        const bool any = tile_range(v.g, tile, start, end);
+        const int ne = any ? (int)((end - start + 63) / 64) : 0;
+        auto ent = [&](int k, const uint8_t*& sg, const uint32_t*& e, bool& go) {
+            const uint64_t pos = start + threadIdx.x + 64 * (uint64_t)k;
+            go = any && pos < end && !xbad[pos];
+            // skipped entries point at entry 0 (read by nothing that matters)
+            sg = v.sigs + (go ? 80 * pos : 0);
+            e = ekeys + (go ? pos * 8 : 0);
+        };
+        const uint32_t okmask = ty_wide ? verify_sig_batch<true>(ent, ne, v.ty, v.tg, st, 64)
+                                        : verify_sig_batch<false>(ent, ne, v.ty, v.tg, st, 64);
+        uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+        for (int k = 0; k < ne; k++) {
+            const uint64_t pos = start + threadIdx.x + 64 * (uint64_t)k;
+            if (pos >= end) continue;
+            const bool ok = (okmask >> k) & 1u;
+            v.flags[pos] = ok ? 0 : 1;
+            if (ok) {
+                uint32_t w8[8];
+                for (int w = 0; w < 8; w++) w8[w] = gload(ekeys + pos * 8 + w);
+                acc288_add256(ae, w8);
+                for (int w = 0; w < 8; w++) w8[w] = gload_le32(v.sigs + 80 * pos + 4 * w);
+                acc288_add256(as, w8);
+            }
         }
+        uint32_t* out = v.tile_part + (uint64_t)tile * 18;
+        block_reduce288_store<64>(ae, out);
+        __syncthreads();
+        block_reduce288_store<64>(as, out + 9);
+        __syncthreads();
     }
-    uint32_t* out = v.tile_part + (uint64_t)blockIdx.x * 18;
-    block_reduce288_store<kVerifyBlock>(ae, out);
-    __syncthreads();
-    block_reduce288_store<kVerifyBlock>(as, out + 9);
 }
+
+__global__ void k_zero_word(uint32_t* p) { p[0] = 0; }
 
 // list mode (SeBVer I): flags[i] = 1 when list item i is invalid
 __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
@@ -430,7 +445,7 @@ namespace {
 
 int scratch(poslo_ctx* c, int slot, size_t bytes, void** out) { return ctx_scratch(c, slot, bytes, out); }
 
-enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_EK = 16, S_XB };
+enum { S_FLAGS = 0, S_TILES, S_UMB_ES, S_UMB_TAGS, S_IDX, S_MISC, S_SIGS, S_AUX, S_EK = 16, S_XB, S_STASH };
 
 int checked_sigs(const uint8_t* sigs, uint64_t n) {
     if (n && !sigs) return POSLO_E_INVAL;
@@ -476,7 +491,8 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
     ccd->span = span;
 
     void *flags, *tiles, *umb_es, *umb_tags, *idx, *misc, *gsigs;
-    uint32_t tpu = (uint32_t)((span + kTile - 1) / kTile);
+    const uint32_t vlen = verify_tile_len(n, c->num_cu);
+    uint32_t tpu = (uint32_t)((span + vlen - 1) / vlen);
     uint64_t n_tiles = n_umb * tpu;
     if (n_tiles > 0x7fffffffull) {
         delete ccd;
@@ -502,11 +518,12 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         prof_end(c, POSLO_KT_SEED, s);
         const uint32_t* gw = ctx_gtable_wide(c);
         if (!gw) return fail(POSLO_E_NOMEM);
-        // large batches also use Y's wide table (built once per key, 1.5 ms)
-        const uint32_t* yw = n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : nullptr;
+        // Y's wide table: the key's resident one, else built for large
+        // batches (once per key, about 0.2 ms) and kept in a small LRU set
+        const uint32_t* yw = n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : ctx_key_wide_resident(c, pk);
         VerifyArgs v;
         v.a = a;
-        v.g = TileGeom{n, span, tpu};
+        v.g = TileGeom{n, span, tpu, vlen};
         v.inst = prm->inst;
         v.sigs = sigs;
         v.list = nullptr;
@@ -515,9 +532,16 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         v.tg = gw;
         v.flags = (uint8_t*)flags;
         v.tile_part = (uint32_t*)tiles;
+        const uint32_t vgrid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)c->num_cu * kVerifyWgPerCu);
+        v.next = (uint32_t*)((uint8_t*)misc + 192);
+        v.n_tiles = (uint32_t)n_tiles;
         prof_begin(c, POSLO_KT_VERIFY, s);
-        void *ek, *xb;
-        if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb))) return fail(st);
+        void *ek, *xb, *stash;
+        if ((st = scratch(c, S_EK, n * 32, &ek)) || (st = scratch(c, S_XB, n, &xb)) ||
+            (st = scratch(c, S_STASH, (size_t)vgrid * kVerifyStashWords * 4, &stash)))
+            return fail(st);
+        v.stash = (uint32_t*)stash;
+        hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, v.next);
         if (inst_base(prm->inst) == INST_AES)
             hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a, sigs,
                                (uint32_t*)ek, (uint8_t*)xb);
@@ -527,12 +551,8 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         else
             hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256, 4>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
                                sigs, (uint32_t*)ek, (uint8_t*)xb);
-        if (yw)
-            hipLaunchKernelGGL(k_verify_tiles<true>, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v,
-                               (const uint32_t*)ek, (const uint8_t*)xb);
-        else
-            hipLaunchKernelGGL(k_verify_tiles<false>, dim3((uint32_t)n_tiles), dim3(kVerifyBlock), 0, s, v,
-                               (const uint32_t*)ek, (const uint8_t*)xb);
+        hipLaunchKernelGGL(k_verify_tiles, dim3(vgrid), dim3(64), 0, s, v, (const uint32_t*)ek, (const uint8_t*)xb,
+                           yw ? 1u : 0u);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);
         FoldArgs f;
@@ -848,7 +868,7 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
             return st;
         HIP_TRY(hipMemcpyAsync(dchk, chk.data(), chk.size() * 4, hipMemcpyHostToDevice, s));
         if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
-        hipLaunchKernelGGL(k_ekeys_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, a, TileGeom{m->n, span, tpu},
+        hipLaunchKernelGGL(k_ekeys_tiles, dim3((uint32_t)n_tiles), dim3(kTile), 0, s, a, TileGeom{m->n, span, tpu, (uint32_t)kTile},
                            prm->inst, (uint32_t*)tiles);
         FoldArgs f;
         f.tile_part = (uint32_t*)tiles;
@@ -894,7 +914,7 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return st;
         VerifyArgs v;
         v.a = a;
-        v.g = TileGeom{m->n, 1, 1};
+        v.g = TileGeom{m->n, 1, 1, (uint32_t)kTile};
         v.inst = prm->inst;
         v.sigs = (const uint8_t*)dsig;
         v.list = (const uint64_t*)dpos;

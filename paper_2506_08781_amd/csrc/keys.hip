@@ -76,33 +76,86 @@ __global__ __launch_bounds__(kCombPerWindow) void k_comb_build_fq(const uint8_t*
     }
 }
 
-// Wide table of a point P from its 8-bit table t8: thread (w, i) forms
-// (i + 1) * 65536^w * P by double-and-add over the 16 bits of i + 1 from
-// B_w = 65536^w * P, which is t8's entry for window 2w, digit 1 (exact for
-// any point), and stores it in affine form.
-__global__ __launch_bounds__(256) void k_wide_build(const uint32_t* t8, uint32_t* wide) {
-    const uint32_t g = blockIdx.x * 256 + threadIdx.x;  // < kWideWindows * kWidePerWindow
-    const uint32_t w = g / kWidePerWindow, m = g % kWidePerWindow + 1;
-    gn B;
-    comb_lookup(B, t8, 2 * (int)w, 1);
-    ge P;
-    ge_identity(P);
-    for (int bit = 15; bit >= 0; bit--) {
-        ge_dbl(P, P);
-        if ((m >> bit) & 1u) ge_madd(P, P, B);
-    }
-    uint32_t o[kCombEntryWords];
-    comb_entry_of(o, P);
-    uint4* q = reinterpret_cast<uint4*>(wide + (uint64_t)g * kCombEntryWords);
+// Wide table of a point P from its 8-bit table t8.  Entry (w, m - 1) is
+// m * 65536^w * P for m = 1 .. 32768; written m = 256 d1 + d0 with d0 in
+// [-127, 128] and d1 in [0, 128], it is the sum of t8's entries (2w, d0) and
+// (2w + 1, d1): two lookups and two mixed additions.  Each thread forms
+// kWideBuildK consecutive entries of one window and converts them to affine
+// form with one inversion (Montgomery's trick): the projective X, Y, Z wait
+// in the entries' own table slots, the running products of the Z's in LDS.
+constexpr int kWideBuildK = 8;
+constexpr int kWideBuildBlock = 128;
+static_assert(kWidePerWindow % kWideBuildK == 0, "a thread's entries share one window");
+
+__global__ __launch_bounds__(kWideBuildBlock) void k_wide_build(const uint32_t* t8, uint32_t* wide) {
+    __shared__ uint32_t cs[kWideBuildK * 8 * kWideBuildBlock];  // c_k = Z_0 ... Z_k, word j at (8k + j) * block
+    uint32_t* my = cs + threadIdx.x;
+    const uint32_t first = (blockIdx.x * kWideBuildBlock + threadIdx.x) * kWideBuildK;
+    const int w = (int)(first / kWidePerWindow);
+    fe c;
+#pragma unroll 1
+    for (int k = 0; k < kWideBuildK; k++) {
+        const uint32_t m = first % kWidePerWindow + k + 1;
+        int d0 = (int)(m & 255u), d1 = (int)(m >> 8);
+        if (d0 > 128) {
+            d0 -= 256;
+            d1 += 1;
+        }
+        ge P;
+        ge_identity(P);
+        gn q;
+        comb_lookup(q, t8, 2 * w, d0);
+        ge_madd(P, P, q);
+        comb_lookup(q, t8, 2 * w + 1, d1);
+        ge_madd(P, P, q);
+        uint4* o = reinterpret_cast<uint4*>(wide + (uint64_t)(first + k) * kCombEntryWords);
+        o[0] = make_uint4(P.X.v[0], P.X.v[1], P.X.v[2], P.X.v[3]);
+        o[1] = make_uint4(P.X.v[4], P.X.v[5], P.X.v[6], P.X.v[7]);
+        o[2] = make_uint4(P.Y.v[0], P.Y.v[1], P.Y.v[2], P.Y.v[3]);
+        o[3] = make_uint4(P.Y.v[4], P.Y.v[5], P.Y.v[6], P.Y.v[7]);
+        o[4] = make_uint4(P.Z.v[0], P.Z.v[1], P.Z.v[2], P.Z.v[3]);
+        o[5] = make_uint4(P.Z.v[4], P.Z.v[5], P.Z.v[6], P.Z.v[7]);
+        if (k == 0)
+            c = P.Z;
+        else
+            fe_mul(c, c, P.Z);
 #pragma unroll
-    for (int t = 0; t < kCombEntryWords / 4; t++) q[t] = make_uint4(o[4 * t], o[4 * t + 1], o[4 * t + 2], o[4 * t + 3]);
+        for (int j = 0; j < 8; j++) my[(8 * k + j) * kWideBuildBlock] = c.v[j];
+    }
+    fe inv;
+    fe_inv(inv, c);  // 1 / (Z_0 ... Z_{K-1})
+#pragma unroll 1
+    for (int k = kWideBuildK - 1; k >= 0; k--) {
+        uint32_t* o = wide + (uint64_t)(first + k) * kCombEntryWords;
+        fe X, Y, Z, zi;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            X.v[j] = o[j];
+            Y.v[j] = o[8 + j];
+            Z.v[j] = o[16 + j];
+        }
+        if (k > 0) {
+            fe ck;
+#pragma unroll
+            for (int j = 0; j < 8; j++) ck.v[j] = my[(8 * (k - 1) + j) * kWideBuildBlock];
+            fe_mul(zi, inv, ck);
+            fe_mul(inv, inv, Z);
+        } else {
+            zi = inv;
+        }
+        uint32_t e[kCombEntryWords];
+        comb_entry_zinv(e, X, Y, zi);
+        uint4* q4 = reinterpret_cast<uint4*>(o);
+#pragma unroll
+        for (int t = 0; t < kCombEntryWords / 4; t++) q4[t] = make_uint4(e[4 * t], e[4 * t + 1], e[4 * t + 2], e[4 * t + 3]);
+    }
 }
 
 static uint32_t* build_wide(const uint32_t* t8) {
     uint32_t* d = nullptr;
     if (hipMalloc((void**)&d, kWideWords * 4) != hipSuccess) return nullptr;
-    const uint32_t blocks = (uint32_t)(kWideWindows * kWidePerWindow / 256);
-    hipLaunchKernelGGL(k_wide_build, dim3(blocks), dim3(256), 0, 0, t8, d);
+    const uint32_t blocks = (uint32_t)(kWideWindows * kWidePerWindow / (kWideBuildK * kWideBuildBlock));
+    hipLaunchKernelGGL(k_wide_build, dim3(blocks), dim3(kWideBuildBlock), 0, 0, t8, d);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
         hipFree(d);
         return nullptr;
@@ -121,13 +174,14 @@ const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]) {
     if (it == c->key_index.end()) return nullptr;
     KeyEntry& ke = *it->second;
     if (ke.wide) return (const uint32_t*)ke.wide.get();
-    // keep at most kMaxWideKeys wide key tables: drop the least recently used
+    // keep at most kMaxWideKeys wide key tables built on demand: drop the
+    // least recently used (widened keys keep theirs)
     size_t have = 0;
-    for (const KeyEntry& k : c->keys) have += k.wide != nullptr;
+    for (const KeyEntry& k : c->keys) have += k.wide != nullptr && !k.wide_pinned;
     if (have >= kMaxWideKeys) {
         hipDeviceSynchronize();  // queued work may still read them
         for (auto r = c->keys.rbegin(); r != c->keys.rend() && have >= kMaxWideKeys; ++r)
-            if (r->wide && &*r != &ke) {
+            if (r->wide && !r->wide_pinned && &*r != &ke) {
                 r->wide.reset();
                 have--;
             }
@@ -136,6 +190,11 @@ const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]) {
     if (!d) return nullptr;
     ke.wide = std::shared_ptr<void>(d, [](void* q) { hipFree(q); });
     return d;
+}
+
+const uint32_t* ctx_key_wide_resident(poslo_ctx* c, const uint8_t pk[32]) {
+    auto it = c->key_index.find(std::string((const char*)pk, 32));
+    return it == c->key_index.end() ? nullptr : (const uint32_t*)it->second->wide.get();
 }
 
 static int build_tables(bool fourq, const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector<uint32_t>& ok) {
@@ -300,4 +359,26 @@ extern "C" int poslo_ctx_keys_load(poslo_ctx* c, const uint8_t* pks, size_t n, s
     if (hipSetDevice(c->device) != hipSuccess) return POSLO_E_DEVICE;
     std::vector<const uint32_t*> t;
     return ctx_keys_bulk(c, pks, n, t, n_bad);
+}
+
+extern "C" int poslo_ctx_keys_widen(poslo_ctx* c, const uint8_t* pks, size_t n) {
+    if (!c || (n && !pks)) return POSLO_E_INVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return POSLO_E_DEVICE;
+    std::vector<const uint32_t*> t;
+    size_t n_bad = 0;
+    const int st = ctx_keys_bulk(c, pks, n, t, &n_bad);
+    if (st != POSLO_OK && st != POSLO_E_ENCODING) return st;
+    for (size_t k = 0; k < n; k++) {
+        if (!t[k]) continue;  // not a point encoding
+        auto it = c->key_index.find(std::string((const char*)pks + 32 * k, 32));
+        if (it == c->key_index.end()) return POSLO_E_DEVICE;
+        KeyEntry& ke = *it->second;
+        if (!ke.wide) {
+            uint32_t* d = build_wide(ke.d_table);
+            if (!d) return POSLO_E_NOMEM;
+            ke.wide = std::shared_ptr<void>(d, [](void* q) { hipFree(q); });
+        }
+        ke.wide_pinned = true;
+    }
+    return st;
 }

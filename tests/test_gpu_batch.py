@@ -110,6 +110,34 @@ def test_verify_batch_equals_oracle(P, gpu, inst):
 
 
 @pytest.mark.parametrize("inst", [1, 0])
+def test_verify_batch_wide_keys_equal_oracle(P, gpu, inst):
+    """Keys given a wide table (poslo_ctx_keys_widen) are checked with it;
+    the accept bits and invalid pairs stay the oracle's, with widened and
+    plain keys mixed in one launch."""
+    torch, _ = gpu
+    jobs, data, off, sigs, want_acc, want_inv, want_all, plan = corrupted_case(inst)
+    params = P.make_params(inst, L1, L2)
+    d, o, s = to_dev(torch, data, off, sigs)
+    bj = P.BatchJobs(jobs)
+    ctx = P.poslo_ctx_create(0)
+    try:
+        pks = sorted({j["pk"] for j in jobs})
+        print(f"inst {inst}: widening {len(pks) - 1} of {len(pks)} keys", flush=True)
+        P.poslo_ctx_keys_widen(ctx, pks[:-1])
+        for mode, want in ((1, want_inv), (2, want_all)):
+            print(f"inst {inst}: distill {mode} with wide keys", flush=True)
+            assert P.poslo_verify_batch(ctx, params, bj, d, o, s, distill=mode) == (want_acc, want)
+        P.poslo_ctx_keys_widen(ctx, pks)
+        assert P.poslo_verify_batch(ctx, params, bj, d, o, s, distill=2) == (want_acc, want_all)
+        with pytest.raises(P.PosloError) as ei:
+            P.poslo_ctx_keys_widen(ctx, [bytes([0xff] * 31 + [0x7f])])
+        assert ei.value.status == P.POSLO_E_ENCODING
+        P.poslo_ctx_keys_widen(ctx, [])
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("inst", [1, 0])
 def test_graph_replays_and_honest_jobs(P, gpu, inst):
     """Replays of one captured graph, with unrelated eager work and
     synchronizations between them, give the eager result every time; the
@@ -207,6 +235,56 @@ def test_full_size_multi_signer(P, gpu, inst):
         assert acc == [k not in msg_flipped for k in range(4096)]
         # mode 1 checks the entries of rejected jobs only
         assert inv == (want if mode == 2 else [p for p in want if p[0] in msg_flipped])
+    # the same with the keys of jobs of 2^14 entries or more widened
+    big = [k for k in range(4096) if log.counts[k] >= 1 << 14]
+    print(f"inst {inst}: widening {len(big)} keys", flush=True)
+    P.poslo_ctx_keys_widen(ctx, [log.jobs[k]["pk"] for k in big])
+    results = {}
+    for mode in (1, 2):
+        results[mode] = P.poslo_verify_batch(ctx, log.params, bj, log.data, log.d_offsets, log.sigs,
+                                             distill=mode, cap=len(want) + 16)
+        print(f"inst {inst}: verified with wide keys (distill {mode})", flush=True)
+        assert results[mode][0] == acc
+        assert results[mode][1] == (want if mode == 2 else [p for p in want if p[0] in msg_flipped])
+    # whole jobs against the oracle: the smallest, the largest, the one
+    # whose last check tile is the most ragged, and a corrupted mid-size one;
+    # the oracle signs each from synthlog's bytes and the plan is applied on
+    # the host, so the GPU's inputs are checked byte for byte first
+    import oracle_fullsize as F
+    counts = log.counts
+    nonempty = [k for k in range(4096) if counts[k]]
+    pick = {min(nonempty, key=lambda k: counts[k]), max(nonempty, key=lambda k: counts[k]),
+            min((k for k in nonempty if counts[k] > 1024 and counts[k] % 1024),
+                key=lambda k: (counts[k] % 1024, counts[k]))}
+    mid = [k for k in flipped if 1024 < counts[k] <= 8192]
+    if mid:
+        pick.add(mid[0])
+    for k in sorted(pick):
+        j = log.jobs[k]
+        base, n = j["entry_base"], j["n"]
+        lens = tuple(int(x) for x in log.lengths[base:base + n])
+        plan = tuple((e - base, bit) for e, bit in log.plan if base <= e < base + n)
+        print(f"inst {inst}: oracle over job {k} ({n} entries, {len(plan)} flips)", flush=True)
+        case = F.job_case(inst, 8, 8, synthlog.derived_key_seed(7000 + inst + 3, k), 7000 + inst + 2, lens, base,
+                          plan)
+        assert (case.pk, case.ds, case.tag) == (j["pk"], j["ds"], j["tag"])
+        msgs, _ = synthlog.messages_var(7000 + inst + 2, np.asarray(lens, dtype=np.int64), t0=base)
+        blob_m = bytearray(msgs.tobytes())
+        blob_s = bytearray(case.sigs)
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        for t, bit in plan:
+            if bit < 8 * lens[t]:
+                blob_m[offs[t] + bit // 8] ^= 1 << (bit % 8)
+            else:
+                b = bit - 8 * lens[t]
+                blob_s[80 * t + b // 8] ^= 1 << (b % 8)
+        o0, o1 = int(log.offsets[base]), int(log.offsets[base + n])
+        assert log.data[o0:o1].cpu().numpy().tobytes() == bytes(blob_m)
+        assert log.sigs[80 * base:80 * (base + n)].cpu().numpy().tobytes() == bytes(blob_s)
+        assert acc[k] == case.aver_corrupt
+        got = [t for kk, t in results[2][1] if kk == k]
+        assert got == case.invalid
+        assert [t for kk, t in results[1][1] if kk == k] == ([] if case.aver_corrupt else case.invalid)
     # sampled entries re-verified one by one by the oracle
     prm = O.Params(inst, 8, 8)
     hs_idx = [e for e, _ in log.plan[:3]] + [int(bases[k]) for k in (0, 1, 4095) if k not in flipped]

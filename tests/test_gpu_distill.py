@@ -201,3 +201,14 @@ def test_table_digit_extremes(P, gpu, inst):
     off = torch.arange(0, 65 * 40, 40, dtype=torch.int64, device="cuda")
     acc, inv = P.poslo_verify_batch(ctx, params, bj, dm.reshape(-1), off, dsig, distill=2)
     assert acc == [True] and inv == [(0, t) for t in sorted(bad)]
+    # the same with the key's wide table (16 + 16 additions per entry)
+    ctx2 = P.poslo_ctx_create(0)
+    try:
+        P.poslo_ctx_keys_widen(ctx2, [pk])
+        print(f"inst {inst}: digit extremes with a wide key table", flush=True)
+        ccd2 = P.poslo_distill(ctx2, params, pk, P.make_msgs(dm), dsig, ds, 1)
+        assert ccd2.invalid() == sorted(bad) and ccd2.valid_tag() == want.valid_tag
+        acc, inv = P.poslo_verify_batch(ctx2, params, bj, dm.reshape(-1), off, dsig, distill=2)
+        assert acc == [True] and inv == [(0, t) for t in sorted(bad)]
+    finally:
+        ctx2.close()

@@ -83,8 +83,10 @@ enum {
  * A point encodes as y0 || y1 (16-byte little-endian halves of
  * y = y0 + y1 i, each below p) with bit 255 holding the sign of x (x0 mod 2
  * if x0 != 0, else x1 mod 2).  Taken by the signer (poslo_kg, poslo_sig,
- * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed and the
- * streaming audit; the other entry points return E_INVAL. */
+ * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed, the
+ * streaming audit, poslo_distill and poslo_sebver (the individual checks
+ * with FourQ's 8-bit comb tables of Y and G); the other entry points return
+ * E_INVAL. */
 #define POSLO_GROUP_FOURQ 8u
 
 /* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two
@@ -273,8 +275,9 @@ int poslo_ekeys(poslo_ctx* ctx, const poslo_params* params, const poslo_msgs* ms
 typedef struct poslo_ccd poslo_ccd;
 
 /* POSLO-F Distill over a batch: every entry is verified individually (x_t
- * equals PRF_0(x_0[i] || j), s_t < q, enc(e_t*Y + s_t*G) equals the R_t
- * bytes); valid entries are aggregated into CCD^v and their umbrella,
+ * equals PRF_0(x_0[i] || j), s_t below the group order (q; N on FourQ),
+ * enc(e_t*Y + s_t*G) equals the R_t bytes); valid entries are aggregated
+ * into CCD^v and their umbrella,
  * invalid ones are listed (sorted) with their signatures.  sigs: device,
  * 80*n bytes, 4-byte aligned, entry p at 80*p.  n_umbrella >= 1.  *out is
  * freed with poslo_ccd_free.  Errors as poslo_aver. */

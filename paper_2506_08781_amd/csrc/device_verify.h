@@ -314,19 +314,17 @@ inline uint32_t verify_tile_len(uint64_t n, int num_cu) {
     return 64u * (uint32_t)(per < 1 ? 1 : per > kVerifyNEMax ? kVerifyNEMax : per);
 }
 
-// Individual verification of the entry at batch position pos with signature
-// bytes sg (80): x_t equals the re-derived one-time seed, s_t < q, and
-// encode(e_t*Y + s_t*G) equals the R_t bytes.  On success e (mod q) and s are
-// returned.  inst: the instantiation word.  A POSLO++ message longer than 31
-// bytes fails and sets a.bad.
+// The hashing part of the check of the entry at batch position pos with
+// signature bytes sg (80): false when x_t differs from the re-derived
+// one-time seed (or, POSLO++, when the message is longer than 31 bytes,
+// which also sets a.bad); else dig = H(m_t || x_t) as eight little-endian
+// words (POSLO++: Add_q(m_t, x_t), already below q).
 template <class T>
-__device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
-                                           uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg_wide,
-                                           uint32_t e[8], uint32_t s[8]) {
+__device__ __forceinline__ bool entry_digest(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
+                                             uint64_t pos, const uint8_t* sg, uint32_t dig[8]) {
     uint32_t x[4], xs[4];
     for (int k = 0; k < 4; k++) xs[k] = gload_le32(sg + 64 + 4 * k);
     EntryView ev = entry_view(a, pos);
-    uint32_t dig[8];
     if (inst_base(inst) == INST_AES_ADDQ) {
         if (ev.L > kAddqMaxLen) {
             if (a.bad) *a.bad = 1u;
@@ -336,8 +334,8 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
         if ((x[0] ^ xs[0]) | (x[1] ^ xs[1]) | (x[2] ^ xs[2]) | (x[3] ^ xs[3])) return false;
         uint32_t mw[8];
         addq_message<0>(ev.m, (uint32_t)ev.L, mw);
-        addq_digest(mw, x, e);
-        return verify_sig(sg, e, ty, tg_wide, s);
+        addq_digest(mw, x, dig);
+        return true;
     }
     if (inst_base(inst) == INST_AES) {
         one_time_seed_aes(tb, a, pos, x);
@@ -349,7 +347,24 @@ __device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, cons
             return false;
         digest_sha_any(ev, end, x, dig);
     }
-    sc_reduce256(e, dig);
+    return true;
+}
+
+// Individual verification of the entry at batch position pos with signature
+// bytes sg (80) on edwards25519: x_t equals the re-derived one-time seed,
+// s_t < q, and encode(e_t*Y + s_t*G) equals the R_t bytes.  On success e
+// (mod q) and s are returned.  inst: the instantiation word.  A POSLO++
+// message longer than 31 bytes fails and sets a.bad.
+template <class T>
+__device__ __forceinline__ bool verify_one(const T& tb, const BatchArgs& a, const uint8_t* end, uint32_t inst,
+                                           uint64_t pos, const uint8_t* sg, const uint32_t* ty, const uint32_t* tg_wide,
+                                           uint32_t e[8], uint32_t s[8]) {
+    uint32_t dig[8];
+    if (!entry_digest(tb, a, end, inst, pos, sg, dig)) return false;
+    if (inst_base(inst) == INST_AES_ADDQ)
+        for (int k = 0; k < 8; k++) e[k] = dig[k];
+    else
+        sc_reduce256(e, dig);
     return verify_sig(sg, e, ty, tg_wide, s);
 }
 

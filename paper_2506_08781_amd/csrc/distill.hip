@@ -26,6 +26,7 @@
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
+#include "device_fq.h"
 #include "device_verify.h"
 #include "scheme_host.h"
 
@@ -79,8 +80,9 @@ __device__ __forceinline__ bool verify_entry(const LdsTables<4, 1>& tb, const Ve
 // AES: one 64 KB table per workgroup and x_t derived only for the final
 // blocks, so two 1,024-thread workgroups fit per CU (eight waves per SIMD)
 // POSLO++ (INST_AES_ADDQ): e_t = Add_q(m_t, x_t); a message longer than 31
-// bytes is marked bad (its x check fails) and sets a.bad.
-template <int INST, int BLOCK, int WPE>
+// bytes is marked bad (its x check fails) and sets a.bad.  FQ: the group is
+// FourQ, e_t is reduced mod N.
+template <int INST, int BLOCK, int WPE, bool FQ = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_distill_hash(
     BatchArgs a, const uint8_t* sigs, uint32_t* ekeys, uint8_t* xbad) {
     constexpr bool AESP = INST != INST_SHA256;  // AES-based PRF
@@ -128,7 +130,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 #pragma unroll
         for (int w = 0; w < 4; w++) d |= x[w] ^ gload_le32(sx + 4 * w);
         uint32_t e[8];
-        sc_reduce256(e, dig);
+        if constexpr (FQ)
+            scN_reduce<8>(e, dig);
+        else if constexpr (INST == INST_AES_ADDQ)
+            for (int w = 0; w < 8; w++) e[w] = dig[w];
+        else
+            sc_reduce256(e, dig);
 #pragma unroll
         for (int w = 0; w < 8; w++) ekeys[p * 8 + w] = e[w];
         xbad[p] = d ? 1 : 0;
@@ -140,7 +147,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 // Persistent, one wave per workgroup pulling tiles from a queue; thread i
 // checks entries i + 64 k of its tile (k < ceil(len / 64)) with one shared
 // inversion, the points waiting in the wave's slice of the stash.  ty_wide:
-// v.ty is Y's wide table (else its 8-bit one).
+// v.ty is Y's wide table (else its 8-bit one).  FQ: the group is FourQ
+// (8-bit tables of Y and G, scalars mod N).
+template <bool FQ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_verify_tiles(
     VerifyArgs v, const uint32_t* ekeys, const uint8_t* xbad, uint32_t ty_wide) {
     uint32_t* st = v.stash + (uint64_t)blockIdx.x * kVerifyStashWords + threadIdx.x;
@@ -159,8 +168,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             sg = v.sigs + (go ? 80 * pos : 0);
             e = ekeys + (go ? pos * 8 : 0);
         };
-        const uint32_t okmask = ty_wide ? verify_sig_batch<true>(ent, ne, v.ty, v.tg, st, 64)
-                                        : verify_sig_batch<false>(ent, ne, v.ty, v.tg, st, 64);
+        uint32_t okmask;
+        if constexpr (FQ)
+            okmask = verify_sig_batch_fq(ent, ne, v.ty, v.tg, st, 64);
+        else
+            okmask = ty_wide ? verify_sig_batch<true>(ent, ne, v.ty, v.tg, st, 64)
+                             : verify_sig_batch<false>(ent, ne, v.ty, v.tg, st, 64);
         uint32_t ae[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, as[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
         for (int k = 0; k < ne; k++) {
@@ -186,7 +199,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 __global__ void k_zero_word(uint32_t* p) { p[0] = 0; }
 
-// list mode (SeBVer I): flags[i] = 1 when list item i is invalid
+// list mode (SeBVer I): flags[i] = 1 when list item i is invalid.  FQ: the
+// group is FourQ (v.tg is G's 8-bit table, scalars mod N).
+template <bool FQ>
 __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
     __shared__ uint32_t lds[4 * 256];
     lds_tables_fill<4, 1>(lds);
@@ -194,8 +209,28 @@ __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
     LdsTables<4, 1> tb{lds};
     uint64_t i = (uint64_t)blockIdx.x * kTile + threadIdx.x;
     if (i >= v.list_n) return;
-    uint32_t e[8], s[8];
-    bool ok = verify_entry(tb, v, v.list[i], v.sigs + 80 * i, e, s);
+    const uint8_t* sg = v.sigs + 80 * i;
+    bool ok;
+    if constexpr (FQ) {
+        uint32_t dig[8], e[8], sc[8], r[8];
+        ok = entry_digest(tb, v.a, v.a.end, v.inst, v.list[i], sg, dig);
+        if (ok) {
+            scN_reduce<8>(e, dig);
+            for (int k = 0; k < 8; k++) sc[k] = gload_le32(sg + 4 * k);
+            ok = scN_is_canonical(sc);
+        }
+        if (ok) {
+            gq P;
+            lane_double_scalar_fq(P, v.ty, v.tg, e, sc);
+            fp2 zi;
+            f2_inv(zi, P.Z);
+            for (int k = 0; k < 8; k++) r[k] = gload_le32(sg + 32 + 4 * k);
+            ok = fq_encodes_zinv(P, zi, r);
+        }
+    } else {
+        uint32_t e[8], sc[8];
+        ok = verify_entry(tb, v, v.list[i], sg, e, sc);
+    }
     v.flags[i] = ok ? 0 : 1;
 }
 
@@ -254,7 +289,77 @@ struct FoldArgs {
 
 // Block n_umb (mode 0, valid_tag set) folds every tile instead: CCD^v, the
 // aggregate of all valid entries, computed beside the umbrellas rather than
-// after them (each block's curve work is one wave's latency).
+// after them (each block's curve work is one wave's latency).  FQ: the group
+// is FourQ (scalars mod N; chk holds x_R, y_R as GF(p^2) words).
+template <bool FQ>
+__device__ __forceinline__ void fold_reduce(uint32_t r[8], const uint32_t t[9]) {
+    if constexpr (FQ)
+        scN_reduce<9>(r, t);
+    else
+        sc_reduce288(r, t);
+}
+
+template <bool FQ>
+__device__ __forceinline__ void fold_curve(const FoldArgs& f, uint32_t l, bool valid_block, const uint32_t e[8],
+                                           const uint32_t s[8]) {
+    if constexpr (FQ) {
+        gq P;
+        wave_double_scalar_fq(P, f.ty, f.tg, e, s);
+        if (threadIdx.x != 0) return;
+        if (valid_block) {
+            for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
+            fq_encode(f.valid_tag + 32, P);
+        } else if (f.mode == 0) {
+            uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
+            for (int k = 0; k < 8; k++) {
+                store_le32(tag + 4 * k, s[k]);
+                f.umb_es[l * 16 + k] = e[k];
+                f.umb_es[l * 16 + 8 + k] = s[k];
+            }
+            fq_encode(tag + 32, P);
+        } else {
+            const uint32_t* c = f.chk + l * 25;
+            fp2 rx, ry, t0, t1;
+            for (int k = 0; k < 4; k++) {
+                rx.a.v[k] = c[8 + k];
+                rx.b.v[k] = c[12 + k];
+                ry.a.v[k] = c[16 + k];
+                ry.b.v[k] = c[20 + k];
+            }
+            f2_mul(t0, rx, P.Z);
+            f2_mul(t1, ry, P.Z);
+            f.umb_bits[l] = (c[24] && f2_eq(t0, P.X) && f2_eq(t1, P.Y)) ? 1u : 0u;
+        }
+    } else {
+        ge P;
+        wave_double_scalar(P, f.ty, f.tg, e, s);
+        if (threadIdx.x != 0) return;
+        if (valid_block) {
+            for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
+            ge_encode(f.valid_tag + 32, P);
+        } else if (f.mode == 0) {
+            uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
+            for (int k = 0; k < 8; k++) {
+                store_le32(tag + 4 * k, s[k]);
+                f.umb_es[l * 16 + k] = e[k];
+                f.umb_es[l * 16 + 8 + k] = s[k];
+            }
+            ge_encode(tag + 32, P);
+        } else {
+            const uint32_t* c = f.chk + l * 25;
+            fe rx, ry, t0, t1;
+            for (int k = 0; k < 8; k++) {
+                rx.v[k] = c[8 + k];
+                ry.v[k] = c[16 + k];
+            }
+            fe_mul(t0, rx, P.Z);
+            fe_mul(t1, ry, P.Z);
+            f.umb_bits[l] = (c[24] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
+        }
+    }
+}
+
+template <bool FQ>
 __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
     __shared__ uint32_t tot_e[9], tot_s[9];
     __shared__ uint32_t sh[16];
@@ -274,9 +379,9 @@ __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t e[8], s[8];
-        sc_reduce288(e, tot_e);
+        fold_reduce<FQ>(e, tot_e);
         if (f.mode == 0) {
-            sc_reduce288(s, tot_s);
+            fold_reduce<FQ>(s, tot_s);
         } else {
             for (int k = 0; k < 8; k++) s[k] = f.chk[l * 25 + k];
         }
@@ -292,36 +397,12 @@ __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
             e[k] = sh[k];
             s[k] = sh[8 + k];
         }
-        ge P;
-        wave_double_scalar(P, f.ty, f.tg, e, s);
-        if (threadIdx.x == 0) {
-            if (valid_block) {
-                for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
-                ge_encode(f.valid_tag + 32, P);
-            } else if (f.mode == 0) {
-                uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
-                for (int k = 0; k < 8; k++) {
-                    store_le32(tag + 4 * k, s[k]);
-                    f.umb_es[l * 16 + k] = e[k];
-                    f.umb_es[l * 16 + 8 + k] = s[k];
-                }
-                ge_encode(tag + 32, P);
-            } else {
-                const uint32_t* c = f.chk + l * 25;
-                fe rx, ry, t0, t1;
-                for (int k = 0; k < 8; k++) {
-                    rx.v[k] = c[8 + k];
-                    ry.v[k] = c[16 + k];
-                }
-                fe_mul(t0, rx, P.Z);
-                fe_mul(t1, ry, P.Z);
-                f.umb_bits[l] = (c[24] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
-            }
-        }
+        fold_curve<FQ>(f, l, valid_block, e, s);
     }
 }
 
-// CCD^v: fold the umbrellas' (e, s) mod q and encode e*Y + s*G
+// CCD^v: fold the umbrellas' (e, s) mod q (FQ: mod N) and encode e*Y + s*G
+template <bool FQ>
 __global__ __launch_bounds__(kTile) void k_valid_fold(const uint32_t* umb_es, uint32_t n_umb, const uint32_t* ty,
                                                       const uint32_t* tg, uint8_t* tag) {
     __shared__ uint32_t tot_e[9], tot_s[9];
@@ -337,8 +418,8 @@ __global__ __launch_bounds__(kTile) void k_valid_fold(const uint32_t* umb_es, ui
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t e[8], s[8];
-        sc_reduce288(e, tot_e);
-        sc_reduce288(s, tot_s);
+        fold_reduce<FQ>(e, tot_e);
+        fold_reduce<FQ>(s, tot_s);
         for (int k = 0; k < 8; k++) {
             sh[k] = e[k];
             sh[8 + k] = s[k];
@@ -351,12 +432,11 @@ __global__ __launch_bounds__(kTile) void k_valid_fold(const uint32_t* umb_es, ui
             e[k] = sh[k];
             s[k] = sh[8 + k];
         }
-        ge P;
-        wave_double_scalar(P, ty, tg, e, s);
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < 8; k++) store_le32(tag + 4 * k, s[k]);
-            ge_encode(tag + 32, P);
-        }
+        FoldArgs f{};
+        f.ty = ty;
+        f.tg = tg;
+        f.valid_tag = tag;
+        fold_curve<FQ>(f, 0, true, e, s);
     }
 }
 
@@ -460,7 +540,6 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
                              void* stream, poslo_ccd** out) {
     if (!out || !pk || !m_in || n_umbrella == 0) return POSLO_E_INVAL;
     *out = nullptr;
-    if (prm && (prm->inst & POSLO_GROUP_FOURQ)) return POSLO_E_INVAL;  // per-entry checks: edwards25519 only
     hipStream_t s = (hipStream_t)stream;
     if (m_in->n && !sigs_in) return POSLO_E_INVAL;
     poslo_msgs dm;
@@ -474,8 +553,11 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
     if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
     if ((st = checked_sigs(sigs, m->n))) return st;
     HIP_TRY(hipSetDevice(c->device));
-    const KeyEntry* key = ctx_key(c, pk, &st);
+    const bool fq = (prm->inst & POSLO_GROUP_FOURQ) != 0;
+    const KeyEntry* key = ctx_key_of(c, prm->inst, pk, &st);
     if (!key) return st;
+    const uint32_t* gtab = fq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!gtab) return POSLO_E_NOMEM;
 
     poslo_ccd* ccd = new (std::nothrow) poslo_ccd();
     if (!ccd) return POSLO_E_NOMEM;
@@ -516,11 +598,13 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         prof_begin(c, POSLO_KT_SEED, s);
         if ((st = launch_seed_table(dsa, prm->inst, a, n_epochs, s))) return fail(st);
         prof_end(c, POSLO_KT_SEED, s);
-        const uint32_t* gw = ctx_gtable_wide(c);
+        // edwards25519: G's wide table, and Y's wide table if the key has a
+        // resident one, else built for large batches (once per key, about
+        // 0.3 ms) and kept in a small LRU set.  FourQ: the 8-bit tables.
+        const uint32_t* gw = fq ? gtab : ctx_gtable_wide(c);
         if (!gw) return fail(POSLO_E_NOMEM);
-        // Y's wide table: the key's resident one, else built for large
-        // batches (once per key, about 0.2 ms) and kept in a small LRU set
-        const uint32_t* yw = n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : ctx_key_wide_resident(c, pk);
+        const uint32_t* yw =
+            fq ? nullptr : n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : ctx_key_wide_resident(c, pk);
         VerifyArgs v;
         v.a = a;
         v.g = TileGeom{n, span, tpu, vlen};
@@ -542,17 +626,27 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
             return fail(st);
         v.stash = (uint32_t*)stash;
         hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, v.next);
-        if (inst_base(prm->inst) == INST_AES)
-            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a, sigs,
-                               (uint32_t*)ek, (uint8_t*)xb);
-        else if (inst_base(prm->inst) == INST_AES_ADDQ)
+        if (inst_base(prm->inst) == INST_AES_ADDQ)
             hipLaunchKernelGGL((k_distill_hash<INST_AES_ADDQ, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a,
                                sigs, (uint32_t*)ek, (uint8_t*)xb);
+        else if (inst_base(prm->inst) == INST_AES && fq)
+            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8, true>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a,
+                               sigs, (uint32_t*)ek, (uint8_t*)xb);
+        else if (inst_base(prm->inst) == INST_AES)
+            hipLaunchKernelGGL((k_distill_hash<INST_AES, 1024, 8>), dim3(c->num_cu * 2), dim3(1024), 0, s, v.a, sigs,
+                               (uint32_t*)ek, (uint8_t*)xb);
+        else if (fq)
+            hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256, 4, true>), dim3(c->num_cu * 4), dim3(256), 0, s,
+                               v.a, sigs, (uint32_t*)ek, (uint8_t*)xb);
         else
             hipLaunchKernelGGL((k_distill_hash<INST_SHA256, 256, 4>), dim3(c->num_cu * 4), dim3(256), 0, s, v.a,
                                sigs, (uint32_t*)ek, (uint8_t*)xb);
-        hipLaunchKernelGGL(k_verify_tiles, dim3(vgrid), dim3(64), 0, s, v, (const uint32_t*)ek, (const uint8_t*)xb,
-                           yw ? 1u : 0u);
+        if (fq)
+            hipLaunchKernelGGL(k_verify_tiles<true>, dim3(vgrid), dim3(64), 0, s, v, (const uint32_t*)ek,
+                               (const uint8_t*)xb, 0u);
+        else
+            hipLaunchKernelGGL(k_verify_tiles<false>, dim3(vgrid), dim3(64), 0, s, v, (const uint32_t*)ek,
+                               (const uint8_t*)xb, yw ? 1u : 0u);
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
         prof_end(c, POSLO_KT_VERIFY, s);
         FoldArgs f;
@@ -560,7 +654,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         f.tiles_per_umb = tpu;
         f.mode = 0;
         f.ty = key->d_table;
-        f.tg = c->d_gtable;
+        f.tg = gtab;
         f.chk = nullptr;
         f.umb_es = (uint32_t*)umb_es;
         f.umb_tags = (uint8_t*)umb_tags;
@@ -568,7 +662,10 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         f.n_umb = (uint32_t)n_umb;
         f.valid_tag = d_valid_tag;
         prof_begin(c, POSLO_KT_COMPACT, s);
-        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb + 1), dim3(kTile), 0, s, f);
+        if (fq)
+            hipLaunchKernelGGL(k_umbrella_fold<true>, dim3((uint32_t)n_umb + 1), dim3(kTile), 0, s, f);
+        else
+            hipLaunchKernelGGL(k_umbrella_fold<false>, dim3((uint32_t)n_umb + 1), dim3(kTile), 0, s, f);
         const uint32_t nblk = (uint32_t)((n + kCmpBlock - 1) / kCmpBlock);
         uint32_t* blk = (uint32_t*)((uint8_t*)misc + 256);  // per-block counts after the tag and count
         hipLaunchKernelGGL(k_flag_count, dim3(nblk), dim3(kCmpThreads), 0, s, (const uint8_t*)flags, n, blk);
@@ -577,8 +674,12 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     } else {
         prof_begin(c, POSLO_KT_COMPACT, s);
-        hipLaunchKernelGGL(k_valid_fold, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es, (uint32_t)n_umb,
-                           key->d_table, c->d_gtable, d_valid_tag);
+        if (fq)
+            hipLaunchKernelGGL(k_valid_fold<true>, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es,
+                               (uint32_t)n_umb, key->d_table, gtab, d_valid_tag);
+        else
+            hipLaunchKernelGGL(k_valid_fold<false>, dim3(1), dim3(kTile), 0, s, (const uint32_t*)umb_es,
+                               (uint32_t)n_umb, key->d_table, gtab, d_valid_tag);
     }
     if (hipGetLastError() != hipSuccess) return fail(POSLO_E_DEVICE);
     prof_end(c, POSLO_KT_COMPACT, s);
@@ -807,7 +908,7 @@ extern "C" int poslo_sebver(poslo_ctx* c, const poslo_params* prm, const uint8_t
 int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[32], const poslo_msgs* m_in,
                        const poslo_ccd* ccd, char mode, uint8_t* bits, size_t cap, size_t* n_bits, void* stream) {
     if (!c || !prm || !pk || !m_in || !ccd || !n_bits) return POSLO_E_INVAL;
-    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;
+    const bool fq = (prm->inst & POSLO_GROUP_FOURQ) != 0;
     poslo_msgs dm;
     int st0 = stage_msgs(c, m_in, (hipStream_t)stream, dm, nullptr, nullptr);
     if (st0) return st0;
@@ -834,8 +935,10 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
     DsArg dsa;
     uint32_t n_epochs;
     if ((st = prepare_batch(c, prm, m, ccd->ds.data(), ccd->ds.size(), a, dsa, n_epochs))) return st;
-    const KeyEntry* key = ctx_key(c, pk, &st);
+    const KeyEntry* key = ctx_key_of(c, prm->inst, pk, &st);
     if (!key) return st;
+    const uint32_t* gtab = fq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!gtab) return POSLO_E_NOMEM;
     if (mode == 'U') {
         uint64_t n_umb = ccd->umb_tags.size() / 64;
         *n_bits = n_umb;
@@ -848,17 +951,30 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         a.skip = skip;
         uint32_t tpu = (uint32_t)((span + kTile - 1) / kTile);
         uint64_t n_tiles = n_umb * tpu;
-        // host checks of each umbrella tag: s < q and R decodes
+        // host checks of each umbrella tag: s below the group order and R
+        // decodes (its affine x and y go to the device)
         std::vector<uint32_t> chk(n_umb * 25);
         for (uint64_t l = 0; l < n_umb; l++) {
             const uint8_t* tg = ccd->umb_tags.data() + 64 * l;
             uint32_t* ck = &chk[l * 25];
             for (int k = 0; k < 8; k++) ck[k] = load_le32(tg + 4 * k);
-            ge R;
-            bool ok = sc_is_canonical(ck) && ge_decode(R, tg + 32);
-            for (int k = 0; k < 8; k++) {
-                ck[8 + k] = ok ? R.X.v[k] : 0;
-                ck[16 + k] = ok ? R.Y.v[k] : 0;
+            bool ok;
+            if (fq) {
+                gq R;
+                ok = scN_is_canonical(ck) && fq_decode(R, tg + 32);
+                for (int k = 0; k < 4; k++) {
+                    ck[8 + k] = ok ? R.X.a.v[k] : 0;
+                    ck[12 + k] = ok ? R.X.b.v[k] : 0;
+                    ck[16 + k] = ok ? R.Y.a.v[k] : 0;
+                    ck[20 + k] = ok ? R.Y.b.v[k] : 0;
+                }
+            } else {
+                ge R;
+                ok = sc_is_canonical(ck) && ge_decode(R, tg + 32);
+                for (int k = 0; k < 8; k++) {
+                    ck[8 + k] = ok ? R.X.v[k] : 0;
+                    ck[16 + k] = ok ? R.Y.v[k] : 0;
+                }
             }
             ck[24] = ok ? 1 : 0;
         }
@@ -875,14 +991,17 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         f.tiles_per_umb = tpu;
         f.mode = 1;
         f.ty = key->d_table;
-        f.tg = c->d_gtable;
+        f.tg = gtab;
         f.chk = (const uint32_t*)dchk;
         f.umb_es = nullptr;
         f.umb_tags = nullptr;
         f.umb_bits = (uint32_t*)dbits;
         f.n_umb = (uint32_t)n_umb;
         f.valid_tag = nullptr;
-        hipLaunchKernelGGL(k_umbrella_fold, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
+        if (fq)
+            hipLaunchKernelGGL(k_umbrella_fold<true>, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
+        else
+            hipLaunchKernelGGL(k_umbrella_fold<false>, dim3((uint32_t)n_umb), dim3(kTile), 0, s, f);
         HIP_TRY(hipGetLastError());
         std::vector<uint32_t> hb(n_umb);
         uint32_t bad = 0;
@@ -903,7 +1022,7 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
             if (ccd->invalid[k] < m->t0 || ccd->invalid[k] - m->t0 >= m->n) return POSLO_E_INVAL;
             pos[k] = ccd->invalid[k] - m->t0;
         }
-        const uint32_t* gw = ctx_gtable_wide(c);
+        const uint32_t* gw = fq ? gtab : ctx_gtable_wide(c);
         if (!gw) return POSLO_E_NOMEM;
         void *dpos, *dsig, *dflags;
         if ((st = scratch(c, S_IDX, ni * 8, &dpos)) || (st = scratch(c, S_SIGS, ni * 80, &dsig)) ||
@@ -923,7 +1042,10 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
         v.tg = gw;
         v.flags = (uint8_t*)dflags;
         v.tile_part = nullptr;
-        hipLaunchKernelGGL(k_verify_list, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);
+        if (fq)
+            hipLaunchKernelGGL(k_verify_list<true>, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);
+        else
+            hipLaunchKernelGGL(k_verify_list<false>, dim3((uint32_t)((ni + kTile - 1) / kTile)), dim3(kTile), 0, s, v);
         HIP_TRY(hipGetLastError());
         std::vector<uint8_t> hf(ni);
         uint32_t bad = 0;

@@ -3,8 +3,9 @@ oracle, through the C ABI: the aggregate check on the device (comb tables of
 the key and of FourQ's generator built by the device, e folded mod N, the
 64-point sum) under POSLO+ and POSLO at kappa = 128 and POSLO+ at kappa =
 127; the allocation-free AVer and the streaming audit on FourQ; the tag
-checks (s >= N, R not a FourQ point); and the entry points that take
-edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
+checks (s >= N, R not a FourQ point); Distill and SeBVer V/U/I on FourQ
+(invalid sets, invalid signatures, valid and umbrella tags); and the entry
+points that take edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
 FourQ signer."""
 
 import functools
@@ -132,6 +133,74 @@ def test_fourq_audit(P, O, gpu):
     au2.close()
 
 
+def corrupt(msgs, sigs, plan):
+    msgs, sigs = list(msgs), list(sigs)
+    for e, bit in plan:
+        L = len(msgs[e])
+        blob = bytearray(msgs[e] + sigs[e])
+        blob[bit // 8] ^= 1 << (bit % 8)
+        msgs[e], sigs[e] = bytes(blob[:L]), bytes(blob[L:])
+    return msgs, sigs
+
+
+DISTILL_CASES = [
+    # inst, n, L, log2_n1, log2_n2, corrupted entries, umbrellas
+    (1 | FQ, 200, 48, 4, 4, 7, 5),
+    (0 | FQ, 130, 37, 3, 5, 4, 3),
+    (1 | 4 | FQ, 256, 32, 2, 8, 5, 4),
+    (1 | FQ, 65, 16, 3, 4, 65, 1),   # every entry corrupted, one umbrella
+]
+
+
+@pytest.mark.parametrize("case", DISTILL_CASES, ids=lambda c: f"{NAMES[c[0]]}-n{c[1]}-k{c[5]}-u{c[6]}")
+def test_fourq_distill_sebver(P, O, gpu, case):
+    """Distill on FourQ (per-entry checks with FourQ's comb tables, scalars
+    mod N, umbrella and valid tags as FourQ aggregates) and SeBVer V/U/I
+    equal the oracle's."""
+    torch, ctx = gpu
+    inst, n, L, l1, l2, k, nu = case
+    prm, arr, msgs, pk, sigs, ds, tag = signed(inst, n, L, l1, l2, 0x62, 5)
+    plan = synthlog.corruption_plan(60 + k, n, k, 8 * (L + 80))
+    cm, cs = corrupt(msgs, [bytes(r) for r in sigs], plan)
+    params = P.make_params(inst, l1, l2)
+    dm = torch.from_numpy(np.frombuffer(b"".join(cm), dtype=np.uint8).reshape(n, L).copy()).cuda()
+    dsig = torch.from_numpy(np.frombuffer(b"".join(cs), dtype=np.uint8).copy()).cuda()
+    print(f"case {case}: distill", flush=True)
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(dm), dsig, ds, nu)
+    want = O.distill(prm, pk, cm, cs, 0, ds, nu)
+    got = ccd.invalid()
+    assert got == [t for t, _ in want.invalid]
+    assert got == sorted(e for e, _ in plan)
+    for i, (t, sg) in enumerate(want.invalid):
+        assert ccd.invalid_sig(i) == sg
+    assert ccd.valid_tag() == want.valid_tag
+    tags, span = ccd.umbrellas()
+    assert span == want.span and tags == [t for t, _ in want.umbrellas]
+    m = P.make_msgs(dm)
+    for mode in "VUI":
+        print(f"case {case}: sebver {mode}", flush=True)
+        assert P.poslo_sebver(ctx, params, pk, m, ccd, mode) == O.sebver(prm, pk, cm, want, mode), mode
+    # a tampered umbrella tag fails that umbrella only
+    blob = bytearray(ccd.export())
+    hdr = 4 + 4 + 4 * 3 + 8 * 3
+    ds_len = int.from_bytes(blob[hdr:hdr + 4], "little")
+    umb0 = hdr + 4 + ds_len + 64 + 8
+    blob[umb0 + 3] ^= 1
+    bits = P.poslo_sebver(ctx, params, pk, m, P.poslo_ccd_import(bytes(blob)), "U")
+    assert bits[0] is False and all(bits[1:])
+
+
+def test_fourq_distill_empty_batch(P, O, gpu):
+    torch, ctx = gpu
+    inst = 1 | FQ
+    prm, arr, msgs, pk, sigs, ds, tag = signed(inst, 200, 48, 4, 4, 0x62, 5)
+    params = P.make_params(inst, 4, 4)
+    empty = torch.zeros((0, 48), dtype=torch.uint8, device="cuda")
+    nosig = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    ccd = P.poslo_distill(ctx, params, pk, P.make_msgs(empty), nosig, ds, 3)
+    assert ccd.invalid() == [] and ccd.valid_tag() == O.agg([], inst)
+
+
 def test_fourq_refused_where_not_built(P, gpu):
     torch, ctx = gpu
     inst = 1 | FQ
@@ -141,7 +210,6 @@ def test_fourq_refused_where_not_built(P, gpu):
     dsig = torch.from_numpy(sigs.reshape(-1).copy()).cuda()
     calls = {
         "ekeys": lambda: P.poslo_ekeys(ctx, params, P.make_msgs(d), ds),
-        "distill": lambda: P.poslo_distill(ctx, params, pk, P.make_msgs(d), dsig, ds, 4),
         "c_key_load": lambda: P.poslo_c_key_load(ctx, P.make_params(inst, 2, 4), bytes(32 * 5)),
         "gpu_keys": lambda: P.poslo_gpu_keys_create(ctx, params, [bytes(32)]),
         "server": lambda: P.Server(0, params),

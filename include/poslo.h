@@ -84,9 +84,9 @@ enum {
  * y = y0 + y1 i, each below p) with bit 255 holding the sign of x (x0 mod 2
  * if x0 != 0, else x1 mod 2).  Taken by the signer (poslo_kg, poslo_sig,
  * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed, the
- * streaming audit, poslo_distill and poslo_sebver (the individual checks
- * with FourQ's 8-bit comb tables of Y and G); the other entry points return
- * E_INVAL. */
+ * streaming audit, poslo_ekeys (e_t mod N), poslo_distill and poslo_sebver
+ * (the individual checks with FourQ's 8-bit comb tables of Y and G); the
+ * other entry points return E_INVAL. */
 #define POSLO_GROUP_FOURQ 8u
 
 /* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two
@@ -257,7 +257,7 @@ int poslo_agg_variant_count(void);
 const char* poslo_agg_variant_name(int v);
 int poslo_ctx_set_tuning(poslo_ctx* ctx, int agg_variant, int wg_per_cu);
 
-/* Per-entry digests e_t mod q (32 bytes LE each) of a batch into e_dev
+/* Per-entry digests e_t mod q (mod N on FourQ; 32 bytes LE each) of a batch into e_dev
  * (device, 32*n bytes) and the one-time seeds x_t (16 bytes each) into
  * x_dev (device, 16*n bytes, may be NULL): the per-entry stage of AVer,
  * computed by poslo_aver's hot kernel (its default variant and launch

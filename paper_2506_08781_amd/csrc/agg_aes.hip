@@ -13,6 +13,7 @@
 #include "ctx.h"
 #include "aes_perm.h"
 #include "device_entry.h"
+#include "fourq.h"
 #include "device_verify.h"
 
 namespace poslo {
@@ -151,7 +152,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         acc288_add256(acc, dig);
         if constexpr (EMIT) {
             uint32_t e[8];
-            sc_reduce256(e, dig);
+            if (a.emit_fq)
+                scN_reduce<8>(e, dig);
+            else
+                sc_reduce256(e, dig);
 #pragma unroll
             for (int w = 0; w < 8; w++) e_out[pos * 8 + w] = e[w];
             if (x_out)

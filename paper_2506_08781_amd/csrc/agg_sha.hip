@@ -5,6 +5,7 @@
 // and workgroup reductions to one partial per workgroup.
 #include "ctx.h"
 #include "device_entry.h"
+#include "fourq.h"
 #include "device_verify.h"
 
 namespace poslo {
@@ -30,7 +31,10 @@ __global__ __launch_bounds__(kAggShaBlock) __attribute__((amdgpu_waves_per_eu(4)
         acc288_add256(acc, dig);
         if constexpr (EMIT) {
             uint32_t e[8];
-            sc_reduce256(e, dig);
+            if (a.emit_fq)
+                scN_reduce<8>(e, dig);
+            else
+                sc_reduce256(e, dig);
 #pragma unroll
             for (int w = 0; w < 8; w++) e_out[pos * 8 + w] = e[w];
             if (x_out)

@@ -25,6 +25,8 @@ struct BatchArgs {
     // POSLO++: set to nonzero by any kernel that meets a (non-skipped) message
     // longer than 31 bytes; zeroed by the seed-table kernel
     uint32_t* bad = nullptr;
+    // emitted e_t are reduced mod FourQ's N instead of q
+    uint32_t emit_fq = 0;
 };
 
 struct EntryView {

@@ -594,6 +594,7 @@ int prepare_batch(poslo_ctx* c, const poslo_params* prm, const poslo_msgs* m, co
     a.tab = nullptr;
     a.bad = nullptr;
     a.xmask = kappa127(prm->inst) ? 0x7fffffffu : 0xffffffffu;
+    a.emit_fq = (prm->inst & POSLO_GROUP_FOURQ) ? 1u : 0u;
     // POSLO++ on a fixed-length batch: the length is checked here, a
     // variable-length batch's lengths by the kernels (a.bad)
     if (inst_base(prm->inst) == INST_AES_ADDQ && !m->offsets && m->msg_len > kAddqMaxLen && m->n > 0)
@@ -883,7 +884,6 @@ extern "C" int poslo_ekeys(poslo_ctx* c, const poslo_params* prm, const poslo_ms
     DsArg dsa;
     uint32_t n_epochs;
     if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
-    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;  // e_t is emitted mod q
     if (m->n == 0) return POSLO_OK;
     if (!e_dev) return POSLO_E_INVAL;
     HIP_TRY(hipSetDevice(c->device));

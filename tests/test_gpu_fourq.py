@@ -2,7 +2,8 @@
 oracle, through the C ABI: the aggregate check on the device (comb tables of
 the key and of FourQ's generator built by the device, e folded mod N, the
 64-point sum) under POSLO+ and POSLO at kappa = 128 and POSLO+ at kappa =
-127; the allocation-free AVer and the streaming audit on FourQ; the tag
+127; the allocation-free AVer, per-entry e_t mod N and x_t, and the
+streaming audit on FourQ; the tag
 checks (s >= N, R not a FourQ point); Distill and SeBVer V/U/I on FourQ
 (invalid sets, invalid signatures, valid and umbrella tags); and the entry
 points that take edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
@@ -67,6 +68,14 @@ def test_fourq_aver_parity(P, O, gpu, case):
     assert O.aggregate_check(pk, want, tag, inst)
     # the allocation-free entry point, now that the key and G tables are resident
     assert P.poslo_aver_fixed(ctx, params, pk, m, ds, tag) == (True, e)
+    # per-entry e_t mod N and x_t
+    eg, xg = P.poslo_ekeys(ctx, params, m, ds)
+    eg, xg = eg.cpu().numpy(), xg.cpu().numpy()
+    seeds = O.epoch_seeds(prm, O.ds_decode(ds), 0, n)
+    for t in range(n):
+        x = O.one_time_seed(inst, seeds[t >> l2], t & (prm.n2 - 1))
+        assert bytes(xg[t]) == x
+        assert int.from_bytes(bytes(eg[t]), "little") == O.digest_int(inst, msgs[t], x) % O.FQ_N
     # a flipped tag bit, a flipped message bit, s + N (same residue, not
     # canonical), and an R that is not a FourQ point are rejected
     bad = bytearray(tag)
@@ -209,7 +218,6 @@ def test_fourq_refused_where_not_built(P, gpu):
     d = torch.from_numpy(arr.copy()).cuda()
     dsig = torch.from_numpy(sigs.reshape(-1).copy()).cuda()
     calls = {
-        "ekeys": lambda: P.poslo_ekeys(ctx, params, P.make_msgs(d), ds),
         "c_key_load": lambda: P.poslo_c_key_load(ctx, P.make_params(inst, 2, 4), bytes(32 * 5)),
         "gpu_keys": lambda: P.poslo_gpu_keys_create(ctx, params, [bytes(32)]),
         "server": lambda: P.Server(0, params),

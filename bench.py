@@ -272,9 +272,7 @@ def host_info():
 def bench_plain(P, torch, ctx, cfg, inst, steps, warmup, calib_copy):
     from paper_2506_08781_amd import workloads
     t = time.perf_counter()
-    # the device signer takes edwards25519 only; FourQ logs are signed on the host
-    build = workloads.single_signer_fixed_host if inst & P.GROUP_FOURQ else workloads.single_signer_fixed
-    log = build(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
+    log = workloads.single_signer_fixed(ctx, inst, cfg["n"], cfg["L"], cfg["log2_n1"], cfg["log2_n2"], cfg["seed"])
     print(f"# plain: inputs ready in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     msgs = P.make_msgs(log.data)
     stream = torch.cuda.current_stream()
@@ -381,7 +379,7 @@ def bench_variants(P, torch, ctx, steps, warmup, rates):
     2^26 entries of 16-byte messages (Add_q takes at most 31 bytes); on the
     headline configuration, POSLO+ at kappa = 127 (a seed walk of one AES per
     tree level instead of two) and POSLO+ on the FourQ group (the same
-    hashing, the final check on FourQ; signed by the host signer)."""
+    hashing, the final check on FourQ)."""
     out = {}
     cfg = dict(VARIANT, name="plain AVer, 2^26 entries x 16 B, n2=256, n1=2^18")
     for inst, key in ((2 | 4, "poslopp_k127"), (2, "poslopp")):

@@ -9,7 +9,8 @@
 // R_t = sum R_k, x_t = PRF_0(x_0[i] || j), e_t = H(m_t || x_t) mod q and
 // s_t = r_t - e_t * y mod q (Montgomery multiplication by y * 2^256 mod q).
 // Per batch the aggregate tag is (sum s_t mod q, (sum r_t mod q) * G), which
-// equals (sum s_t, sum R_t) since every R_t = r_t * G.
+// equals (sum s_t, sum R_t) since every R_t = r_t * G.  On the FourQ group
+// (fourq.h) the same steps run with FourQ's points and scalars mod N.
 #include <string.h>
 
 #include <algorithm>
@@ -19,6 +20,7 @@
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
+#include "device_fq.h"
 #include "device_verify.h"
 #include "scheme_host.h"
 
@@ -133,11 +135,39 @@ __device__ __forceinline__ void sc_sub_dev(uint32_t r[8], const uint32_t a[8], c
 struct DevKey {
     uint32_t seed[8];    // the 32-byte key seed as LE words
     uint32_t root[4];    // x_D[0]
-    uint32_t y_mont[8];  // y * 2^256 mod q
+    uint32_t y_mont[8];  // y * 2^256 mod q (edwards25519)
+    uint32_t y_n[8];     // y (FourQ: below N)
 };
+
+// k*G on FourQ by one lane: 32 lookups and mixed additions; k < N
+__device__ __forceinline__ void lane_scalar_fq(gq& P, const uint32_t* t, const uint32_t k[8]) {
+    gq_identity(P);
+    uint32_t c = 0;
+    for (int w = 0; w < kCombWindows; w++) {
+        gnq q;
+        fq_comb_lookup(q, t, w, comb_digit(k, w, c));
+        gq_madd(P, P, q);
+    }
+}
+
+__device__ __forceinline__ void store_point_fq(uint32_t* p, const gq& P) {
+    stash_f2(p, 1, P.X);
+    stash_f2(p + 8, 1, P.Y);
+    stash_f2(p + 16, 1, P.Z);
+    stash_f2(p + 24, 1, P.T);
+}
+
+__device__ __forceinline__ void load_point_fq(gq& P, const uint32_t* p) {
+    unstash_f2(P.X, p, 1);
+    unstash_f2(P.Y, p + 8, 1);
+    unstash_f2(P.Z, p + 16, 1);
+    unstash_f2(P.T, p + 24, 1);
+}
 
 // BPV offline table: r_k = LE256(derive("bpv", k)) mod q, R_k = r_k * G, with
 // derive(label, c) = PRF_0(seed || label || LE32(2c)) || PRF_0(... LE32(2c+1))
+// (FQ: mod N on FourQ)
+template <bool FQ>
 __global__ __launch_bounds__(256) void k_bpv_table(const DevKey* keys, uint32_t nkeys, uint32_t v, uint32_t inst,
                                                    const uint32_t* tg, uint32_t* bpv_r, uint32_t* bpv_R) {
     __shared__ uint32_t lds[4 * 256];
@@ -158,12 +188,18 @@ __global__ __launch_bounds__(256) void k_bpv_table(const DevKey* keys, uint32_t 
         dev_F_words(tb, inst, z, 40, d + 4 * half);
     }
     uint32_t r[8];
-    sc_reduce256(r, d);
-    uint32_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    ge R;
-    lane_scalar(R, tg, r);
+    if constexpr (FQ) {
+        scN_reduce<8>(r, d);
+        gq R;
+        lane_scalar_fq(R, tg, r);
+        store_point_fq(bpv_R + g * 32, R);
+    } else {
+        sc_reduce256(r, d);
+        ge R;
+        lane_scalar(R, tg, r);
+        store_point(bpv_R + g * 32, R);
+    }
     for (int w = 0; w < 8; w++) bpv_r[g * 8 + w] = r[w];
-    store_point(bpv_R + g * 32, R);
 }
 
 // per-(job, epoch) seed table for signing: x_0[i] = leaf i of the key's tree
@@ -237,6 +273,7 @@ struct SignArgs {
     uint32_t* bad;            // set when a POSLO++ message is longer than 31 bytes
 };
 
+template <bool FQ>
 __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
     __shared__ uint32_t lds[4 * 256];
     lds_tables_fill<4, 1>(lds);
@@ -264,6 +301,8 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
         uint32_t r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         ge R;
         ge_identity(R);
+        gq Rq;
+        gq_identity(Rq);
         for (uint32_t c = 0; cnt < A.k; c++) {
             uint32_t z[12] = {0};
             for (int w = 0; w < 8; w++) z[w] = K.seed[w];
@@ -284,11 +323,20 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
                 cnt++;
                 const uint64_t bi = (uint64_t)J.key * A.v + val;
                 uint32_t tmp[8];
-                sc_add(tmp, r, A.bpv_r + bi * 8);
+                if constexpr (FQ) {
+                    uint32_t rk[8];
+                    for (int w = 0; w < 8; w++) rk[w] = A.bpv_r[bi * 8 + w];
+                    scN_add(tmp, r, rk);
+                    gq Q;
+                    load_point_fq(Q, A.bpv_R + bi * 32);
+                    gq_add(Rq, Rq, Q);
+                } else {
+                    sc_add(tmp, r, A.bpv_r + bi * 8);
+                    ge Q;
+                    load_point(Q, A.bpv_R + bi * 32);
+                    ge_add(R, R, Q);
+                }
                 for (int w = 0; w < 8; w++) r[w] = tmp[w];
-                ge Q;
-                load_point(Q, A.bpv_R + bi * 32);
-                ge_add(R, R, Q);
             }
         }
         // x_t and e_t
@@ -320,12 +368,21 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
             for (int w = 0; w < 4; w++) x[w] = bswap32(x[w]);
         }
         uint32_t e[8], ey[8], s[8];
-        sc_reduce256(e, dig);
-        sc_mont_mul(ey, e, K.y_mont);
-        sc_sub_dev(s, r, ey);
-        uint8_t* out = A.sigs + gidx * 80;
         uint8_t enc[32];
-        ge_encode(enc, R);
+        if constexpr (FQ) {
+            scN_reduce<8>(e, dig);
+            uint32_t y[8];
+            for (int w = 0; w < 8; w++) y[w] = K.y_n[w];
+            scN_mul(ey, e, y);
+            scN_sub(s, r, ey);
+            fq_encode(enc, Rq);
+        } else {
+            sc_reduce256(e, dig);
+            sc_mont_mul(ey, e, K.y_mont);
+            sc_sub_dev(s, r, ey);
+            ge_encode(enc, R);
+        }
+        uint8_t* out = A.sigs + gidx * 80;
         for (int w = 0; w < 8; w++) {
             store_le32(out + 4 * w, s[w]);
             store_le32(out + 32 + 4 * w, load_le32(enc + 4 * w));
@@ -340,7 +397,8 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs A) {
     block_reduce288_store<256>(ar, tp + 9);
 }
 
-// per job: tag = (sum s mod q, enc((sum r mod q) * G))
+// per job: tag = (sum s mod q, enc((sum r mod q) * G)) (FQ: mod N, on FourQ)
+template <bool FQ>
 __global__ __launch_bounds__(256) void k_sign_tags(const SignJob* jobs, const uint32_t* tile_part,
                                                    const uint64_t* tile_end, const uint32_t* tg, uint8_t* tags) {
     __shared__ uint32_t ts[9], tr[9];
@@ -358,8 +416,13 @@ __global__ __launch_bounds__(256) void k_sign_tags(const SignJob* jobs, const ui
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s[8], r[8];
-        sc_reduce288(s, ts);
-        sc_reduce288(r, tr);
+        if constexpr (FQ) {
+            scN_reduce<9>(s, ts);
+            scN_reduce<9>(r, tr);
+        } else {
+            sc_reduce288(s, ts);
+            sc_reduce288(r, tr);
+        }
         for (int k = 0; k < 8; k++) {
             sh[k] = s[k];
             sh[8 + k] = r[k];
@@ -369,13 +432,18 @@ __global__ __launch_bounds__(256) void k_sign_tags(const SignJob* jobs, const ui
     if (threadIdx.x < 64) {
         uint32_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0}, r[8];
         for (int k = 0; k < 8; k++) r[k] = sh[8 + k];
-        ge P;
-        wave_double_scalar(P, tg, tg, zero, r);
-        if (threadIdx.x == 0) {
-            uint8_t* tag = tags + (uint64_t)blockIdx.x * 64;
-            for (int k = 0; k < 8; k++) store_le32(tag + 4 * k, sh[k]);
-            ge_encode(tag + 32, P);
+        uint8_t* tag = tags + (uint64_t)blockIdx.x * 64;
+        if constexpr (FQ) {
+            gq P;
+            wave_double_scalar_fq(P, tg, tg, zero, r);
+            if (threadIdx.x == 0) fq_encode(tag + 32, P);
+        } else {
+            ge P;
+            wave_double_scalar(P, tg, tg, zero, r);
+            if (threadIdx.x == 0) ge_encode(tag + 32, P);
         }
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 8; k++) store_le32(tag + 4 * k, sh[k]);
     }
 }
 
@@ -447,7 +515,7 @@ void to_mont(uint32_t out[8], const uint32_t y[8]) {
 extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, const uint8_t* seeds, uint32_t nkeys,
                                      poslo_gpu_keys** out, uint8_t* pks) {
     if (!c || !prm || !out || (nkeys && (!seeds || !pks))) return POSLO_E_INVAL;
-    if (!poslo_inst_valid(prm->inst) || (prm->inst & POSLO_GROUP_FOURQ) || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
+    if (!poslo_inst_valid(prm->inst) || prm->bpv_v == 0 || prm->bpv_v > 65536 || (prm->bpv_v & (prm->bpv_v - 1)) ||
         prm->bpv_k == 0 || prm->bpv_k > 16 || prm->bpv_k > prm->bpv_v || prm->log2_n1 + prm->log2_n2 > 32)
         return POSLO_E_INVAL;
     *out = nullptr;
@@ -457,16 +525,26 @@ extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, cons
     K->ctx = c;
     K->prm = *prm;
     K->host.resize(nkeys);
-    base_table();
+    const bool fq = group_fourq(prm->inst);
+    const uint32_t* gtab = fq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!gtab) {
+        delete K;
+        return POSLO_E_NOMEM;
+    }
+    if (fq)
+        fq_base_table();
+    else
+        base_table();
     for (uint32_t k = 0; k < nkeys; k++) {
         const uint8_t* sd = seeds + 32 * (size_t)k;
         DevKey& dk = K->host[k];
+        memset(&dk, 0, sizeof dk);
         for (int w = 0; w < 8; w++) dk.seed[w] = load_le32(sd + 4 * w);
         uint32_t y[8];
         for (uint32_t cc = 0;; cc++) {
             uint8_t d[32];
             derive_host(prm->inst, sd, "y", cc, d);
-            sc_from_bytes_reduce(y, d);
+            scalar_from_bytes(prm->inst, y, d);
             uint32_t o = 0;
             for (int w = 0; w < 8; w++) o |= y[w];
             if (o) break;
@@ -474,10 +552,17 @@ extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, cons
         uint8_t xd[32];
         derive_host(prm->inst, sd, "x", 0, xd);
         for (int w = 0; w < 4; w++) dk.root[w] = load_le32(xd + 4 * w);
-        to_mont(dk.y_mont, y);
-        ge Y;
-        ge_scalarmult_base(Y, y);
-        ge_encode(pks + 32 * (size_t)k, Y);
+        if (fq) {
+            memcpy(dk.y_n, y, sizeof y);
+            gq Y;
+            fq_scalarmult_base(Y, y);
+            fq_encode(pks + 32 * (size_t)k, Y);
+        } else {
+            to_mont(dk.y_mont, y);
+            ge Y;
+            ge_scalarmult_base(Y, y);
+            ge_encode(pks + 32 * (size_t)k, Y);
+        }
     }
     size_t v = prm->bpv_v;
     if (hipMalloc((void**)&K->d_keys, std::max<size_t>(nkeys, 1) * sizeof(DevKey)) != hipSuccess ||
@@ -492,8 +577,12 @@ extern "C" int poslo_gpu_keys_create(poslo_ctx* c, const poslo_params* prm, cons
             return POSLO_E_DEVICE;
         }
         uint64_t lanes = (uint64_t)nkeys * v;
-        hipLaunchKernelGGL(k_bpv_table, dim3((uint32_t)((lanes + 255) / 256)), dim3(256), 0, 0, K->d_keys, nkeys,
-                           (uint32_t)v, prm->inst, c->d_gtable, K->d_bpv_r, K->d_bpv_R);
+        if (fq)
+            hipLaunchKernelGGL(k_bpv_table<true>, dim3((uint32_t)((lanes + 255) / 256)), dim3(256), 0, 0, K->d_keys,
+                               nkeys, (uint32_t)v, prm->inst, gtab, K->d_bpv_r, K->d_bpv_R);
+        else
+            hipLaunchKernelGGL(k_bpv_table<false>, dim3((uint32_t)((lanes + 255) / 256)), dim3(256), 0, 0, K->d_keys,
+                               nkeys, (uint32_t)v, prm->inst, gtab, K->d_bpv_r, K->d_bpv_R);
         if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
             poslo_gpu_keys_free(K);
             return POSLO_E_DEVICE;
@@ -538,6 +627,9 @@ extern "C" int poslo_gpu_sign(poslo_gpu_keys* K, const poslo_sign_job* jobs, uin
     const poslo_params& p = K->prm;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
+    const bool fq = group_fourq(p.inst);
+    const uint32_t* gtab = fq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!gtab) return POSLO_E_NOMEM;
     uint64_t cap = 1ull << (p.log2_n1 + p.log2_n2);
     std::vector<SignJob> sj(njobs);
     std::vector<SignTile> tiles;
@@ -603,10 +695,17 @@ extern "C" int poslo_gpu_sign(poslo_gpu_keys* K, const poslo_sign_job* jobs, uin
         A.sigs = sigs;
         A.tile_part = (uint32_t*)d_part;
         A.bad = (uint32_t*)d_tab + rows * kEpochWords;
-        hipLaunchKernelGGL(k_sign, dim3((uint32_t)tiles.size()), dim3(256), 0, s, A);
+        if (fq)
+            hipLaunchKernelGGL(k_sign<true>, dim3((uint32_t)tiles.size()), dim3(256), 0, s, A);
+        else
+            hipLaunchKernelGGL(k_sign<false>, dim3((uint32_t)tiles.size()), dim3(256), 0, s, A);
     }
-    hipLaunchKernelGGL(k_sign_tags, dim3(njobs), dim3(256), 0, s, (const SignJob*)d_jobs, (const uint32_t*)d_part,
-                       (const uint64_t*)d_tend, c->d_gtable, (uint8_t*)d_tags);
+    if (fq)
+        hipLaunchKernelGGL(k_sign_tags<true>, dim3(njobs), dim3(256), 0, s, (const SignJob*)d_jobs,
+                           (const uint32_t*)d_part, (const uint64_t*)d_tend, gtab, (uint8_t*)d_tags);
+    else
+        hipLaunchKernelGGL(k_sign_tags<false>, dim3(njobs), dim3(256), 0, s, (const SignJob*)d_jobs,
+                           (const uint32_t*)d_part, (const uint64_t*)d_tend, gtab, (uint8_t*)d_tags);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(tags, d_tags, (size_t)njobs * 64, hipMemcpyDeviceToHost, s));
     uint32_t bad = 0;

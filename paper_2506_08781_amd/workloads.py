@@ -14,8 +14,7 @@ import numpy as np
 
 import synthlog
 
-from . import (BatchJobs, make_params, poslo_agg, poslo_ds_export, poslo_gpu_keys_create, poslo_gpu_sign,
-               poslo_kg, poslo_msgs, poslo_sig_batch, poslo_synth_messages)
+from . import BatchJobs, make_params, poslo_gpu_keys_create, poslo_gpu_sign, poslo_msgs, poslo_synth_messages
 
 
 @dataclass
@@ -147,26 +146,6 @@ def single_signer_fixed(ctx, inst: int, n: int, L: int, log2_n1: int, log2_n2: i
         view = MultiSignerLog(params=params, counts=[n], lengths=np.full(n, L), offsets=np.arange(n + 1) * L,
                               data=flat, d_offsets=offs, sigs=sigs, pks=[log.pk], jobs=[])
         _flip(torch, view, log.plan)
-    torch.cuda.synchronize(dev)
-    return log
-
-
-def single_signer_fixed_host(ctx, inst: int, n: int, L: int, log2_n1: int, log2_n2: int,
-                             seed: int) -> SingleSignerLog:
-    """single_signer_fixed signed by the host signer (every host thread), for
-    the instantiations the device signer does not take (FourQ)."""
-    import torch
-
-    params = make_params(inst, log2_n1, log2_n2)
-    dev = torch.device("cuda", ctx.device)
-    data = torch.empty((n, L), dtype=torch.uint8, device=dev)
-    poslo_synth_messages(seed, poslo_msgs(data.data_ptr(), None, L, n, 0, n * L), data)
-    host = data.cpu().numpy()
-    sk, pk = poslo_kg(params, synthlog.derived_key_seed(seed + 3, 0))
-    sigs = poslo_sig_batch(sk, host)
-    tag = poslo_agg(sigs.tobytes(), inst)
-    log = SingleSignerLog(params=params, data=data, sigs=torch.from_numpy(sigs.reshape(-1)).to(dev), pk=pk,
-                          ds=poslo_ds_export(sk), tag=tag)
     torch.cuda.synchronize(dev)
     return log
 

@@ -5,8 +5,8 @@ the key and of FourQ's generator built by the device, e folded mod N, the
 127; the allocation-free AVer, per-entry e_t mod N and x_t, and the
 streaming audit on FourQ; the tag
 checks (s >= N, R not a FourQ point); Distill and SeBVer V/U/I on FourQ
-(invalid sets, invalid signatures, valid and umbrella tags); and the entry
-points that take edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
+(invalid sets, invalid signatures, valid and umbrella tags); the device
+signer on FourQ; and the entry points that take edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
 FourQ signer."""
 
 import functools
@@ -210,6 +210,43 @@ def test_fourq_distill_empty_batch(P, O, gpu):
     assert ccd.invalid() == [] and ccd.valid_tag() == O.agg([], inst)
 
 
+@pytest.mark.parametrize("inst", [1 | FQ, 0 | FQ, 1 | 4 | FQ], ids=lambda i: NAMES[i])
+def test_fourq_device_signer_equals_oracle(P, O, gpu, inst):
+    """The device signer on FourQ (BPV table R_k = r_k * G with FourQ's comb
+    table, s_t = r_t - e_t * y mod N, tags from the sums) gives the oracle
+    signer's keys, signatures, tags and ds byte for byte, for jobs of two
+    keys starting at t = 0 and mid-epoch, over messages of 0 to 70 bytes."""
+    torch, ctx = gpu
+    l1, l2 = 3, 4
+    prm = O.Params(inst, l1, l2, v=64, k=8)
+    params = P.make_params(inst, l1, l2, 64, 8)
+    seeds = [synthlog.derived_key_seed(81, k) for k in range(2)]
+    jobs = [(0, 0, 40), (1, 5, 33), (0, 40, 1)]
+    total = sum(n for _, _, n in jobs)
+    lens = synthlog.uniform_per_stream(82, np.arange(total), 0, 70)
+    data, off = synthlog.messages_var(83, lens)
+    msgs = [bytes(data[off[e]:off[e + 1]]) for e in range(total)]
+    print(f"inst {inst}: device keys and signer", flush=True)
+    keys = P.poslo_gpu_keys_create(ctx, params, seeds)
+    d = torch.from_numpy(data.copy()).cuda()
+    o = torch.from_numpy(off.view(np.int64).copy()).cuda()
+    sigs = torch.zeros(80 * total, dtype=torch.uint8, device="cuda")
+    sj, base = [], 0
+    for key, t0, n in jobs:
+        sj.append((key, t0, n, base))
+        base += n
+    tags, ds = P.poslo_gpu_sign(keys, sj, d, o, sigs)
+    hs = sigs.cpu().numpy().tobytes()
+    for key in range(2):
+        assert keys.pks[key] == O.kg(prm, seeds[key])[1]
+    for k, (key, t0, n, b) in enumerate(sj):
+        signer = O.signer_at(prm, seeds[key], t0)
+        want = [O.sig(signer, msgs[b + p]) for p in range(n)]
+        assert [hs[80 * (b + p):80 * (b + p + 1)] for p in range(n)] == want, f"job {k}"
+        assert tags[k] == O.agg(want, inst), f"job {k}"
+        assert ds[k] == O.ds_encode(signer.ds), f"job {k}"
+
+
 def test_fourq_refused_where_not_built(P, gpu):
     torch, ctx = gpu
     inst = 1 | FQ
@@ -219,7 +256,6 @@ def test_fourq_refused_where_not_built(P, gpu):
     dsig = torch.from_numpy(sigs.reshape(-1).copy()).cuda()
     calls = {
         "c_key_load": lambda: P.poslo_c_key_load(ctx, P.make_params(inst, 2, 4), bytes(32 * 5)),
-        "gpu_keys": lambda: P.poslo_gpu_keys_create(ctx, params, [bytes(32)]),
         "server": lambda: P.Server(0, params),
     }
     for name, call in calls.items():

@@ -85,9 +85,11 @@ enum {
  * if x0 != 0, else x1 mod 2).  Taken by the signer (poslo_kg, poslo_sig,
  * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed, the
  * streaming audit, poslo_ekeys (e_t mod N), poslo_distill and poslo_sebver
- * (the individual checks with FourQ's 8-bit comb tables of Y and G), and
- * the device signer (poslo_gpu_keys_create, poslo_gpu_sign); the other
- * entry points return E_INVAL. */
+ * (the individual checks with FourQ's 8-bit comb tables of Y and G),
+ * POSLO-C (poslo_c_key_load with FourQ commitments, poslo_c_aver,
+ * poslo_c_distill, poslo_c_sebver) and the device signer
+ * (poslo_gpu_keys_create, poslo_gpu_sign); the multi-signer batch and the
+ * serving loop return E_INVAL. */
 #define POSLO_GROUP_FOURQ 8u
 
 /* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two

@@ -11,7 +11,8 @@
 // e_t mod q, and one wave per epoch sums the epoch's e_t (the paper's
 // per-block sub-aggregates e~_i) and checks e~_i*Y + s~_i*G = R~_i with the
 // fixed-base tables.  SeBVer V and U are the POSLO-F ones over the entries
-// of the valid epochs; I re-verifies each invalid epoch.
+// of the valid epochs; I re-verifies each invalid epoch.  On the FourQ group
+// (fourq.h) the same steps run with FourQ's points and scalars mod N.
 #include <string.h>
 
 #include <algorithm>
@@ -22,12 +23,15 @@
 #include "ctx.h"
 #include "device_ec.h"
 #include "device_entry.h"
+#include "device_fq.h"
 #include "scheme_host.h"
 
 namespace poslo {
 
 // e~_i = sum of the epoch's e_t mod q, then e~_i*Y + s~_i*G = R~_i (R~_i
-// affine, 16 words per epoch) and s~_i < q: one wave per epoch
+// affine, 16 words per epoch) and s~_i < q: one wave per epoch.  FQ: on
+// FourQ (mod N; x and y of R~_i as GF(p^2) words)
+template <bool FQ>
 __global__ __launch_bounds__(64) void k_c_epoch_check(const uint32_t* ek, uint32_t log2_n2, const uint32_t* s_ep,
                                                       const uint32_t* r_aff, const uint32_t* ty, const uint32_t* tg,
                                                       uint32_t* res) {
@@ -42,19 +46,36 @@ __global__ __launch_bounds__(64) void k_c_epoch_check(const uint32_t* ek, uint32
     }
     wave_reduce288(acc);
     uint32_t e[8], s[8];
-    sc_reduce288(e, acc);
     for (int k = 0; k < 8; k++) s[k] = s_ep[p * 8 + k];
-    ge P;
-    wave_double_scalar(P, ty, tg, e, s);
-    if (threadIdx.x == 0) {
-        fe rx, ry, t0, t1;
-        for (int k = 0; k < 8; k++) {
-            rx.v[k] = r_aff[p * 16 + k];
-            ry.v[k] = r_aff[p * 16 + 8 + k];
+    if constexpr (FQ) {
+        scN_reduce<9>(e, acc);
+        const bool canon = scN_is_canonical(s);
+        if (!canon)
+            for (int k = 0; k < 8; k++) s[k] = 0;  // any in-range digits; the result is 0 anyway
+        gq P;
+        wave_double_scalar_fq(P, ty, tg, e, s);
+        if (threadIdx.x == 0) {
+            fp2 rx, ry, t0, t1;
+            unstash_f2(rx, r_aff + p * 16, 1);
+            unstash_f2(ry, r_aff + p * 16 + 8, 1);
+            f2_mul(t0, rx, P.Z);
+            f2_mul(t1, ry, P.Z);
+            res[p] = (canon && f2_eq(t0, P.X) && f2_eq(t1, P.Y)) ? 1u : 0u;
         }
-        fe_mul(t0, rx, P.Z);
-        fe_mul(t1, ry, P.Z);
-        res[p] = (sc_is_canonical(s) && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
+    } else {
+        sc_reduce288(e, acc);
+        ge P;
+        wave_double_scalar(P, ty, tg, e, s);
+        if (threadIdx.x == 0) {
+            fe rx, ry, t0, t1;
+            for (int k = 0; k < 8; k++) {
+                rx.v[k] = r_aff[p * 16 + k];
+                ry.v[k] = r_aff[p * 16 + 8 + k];
+            }
+            fe_mul(t0, rx, P.Z);
+            fe_mul(t1, ry, P.Z);
+            res[p] = (sc_is_canonical(s) && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
+        }
     }
 }
 
@@ -71,10 +92,13 @@ using namespace poslo;
 struct poslo_c_key {
     int device = 0;
     uint32_t log2_n1 = 0;
+    bool fq = false;             // FourQ key: the gq vectors hold the points
     uint8_t y[32] = {};
     std::vector<uint8_t> r_enc;  // enc(R~_i), 32 bytes per epoch
     std::vector<ge> prefix;      // prefix[k] = R~_0 + ... + R~_{k-1}
     std::vector<ge> r;           // R~_i decoded (Z = 1)
+    std::vector<gq> prefix_q;    // the same on FourQ
+    std::vector<gq> r_q;
     uint32_t* d_r = nullptr;     // affine (x, y) of R~_i, 16 words per epoch
 };
 
@@ -96,35 +120,67 @@ int epoch_range(const poslo_params* prm, const poslo_c_key* key, const poslo_msg
     return POSLO_OK;
 }
 
+// the group operations range_sum needs, on edwards25519 (ge) and FourQ (gq)
+inline void pt_identity(ge& r) { ge_identity(r); }
+inline void pt_identity(gq& r) { gq_identity(r); }
+inline void pt_add(ge& r, const ge& p, const ge& q) { ge_add(r, p, q); }
+inline void pt_add(gq& r, const gq& p, const gq& q) { gq_add(r, p, q); }
+inline void pt_neg(ge& r, const ge& p) { ge_neg(r, p); }
+inline void pt_neg(gq& r, const gq& p) {
+    f2_neg(r.X, p.X);
+    r.Y = p.Y;
+    r.Z = p.Z;
+    f2_neg(r.T, p.T);
+}
+
 // R~_i summed over the epochs [a, b) of the key that are not in `bad`
 // (sorted absolute epoch indices): the prefix difference minus the bad ones,
 // or the direct sum of the good ones, whichever takes fewer additions
-void range_sum(const poslo_c_key* key, uint64_t a, uint64_t b, const std::vector<uint64_t>& bad, ge& out) {
+template <class PT>
+void range_sum_of(const std::vector<PT>& prefix, const std::vector<PT>& r, uint64_t a, uint64_t b,
+                  const std::vector<uint64_t>& bad, PT& out) {
     auto lo = std::lower_bound(bad.begin(), bad.end(), a);
     auto hi = std::lower_bound(bad.begin(), bad.end(), b);
     const uint64_t nbad = (uint64_t)(hi - lo);
     if (nbad + 2 <= (b - a) - nbad) {
-        ge neg;
-        ge_neg(neg, key->prefix[a]);
-        ge_add(out, key->prefix[b], neg);
+        PT neg;
+        pt_neg(neg, prefix[a]);
+        pt_add(out, prefix[b], neg);
         for (auto it = lo; it != hi; ++it) {
-            ge_neg(neg, key->r[*it]);
-            ge_add(out, out, neg);
+            pt_neg(neg, r[*it]);
+            pt_add(out, out, neg);
         }
     } else {
-        ge_identity(out);
+        pt_identity(out);
         for (uint64_t i = a; i < b; i++) {
             if (lo != hi && *lo == i) {
                 ++lo;
                 continue;
             }
-            ge_add(out, out, key->r[i]);
+            pt_add(out, out, r[i]);
         }
     }
 }
 
-void sum_s(const uint8_t* s_epochs, uint64_t a, uint64_t b, const std::vector<uint64_t>& bad, uint64_t i0,
-           uint8_t out[32]) {
+// enc of the sum of R~_i over [a, b) minus `bad`, on the key's group
+void range_sum_enc(const poslo_c_key* key, uint64_t a, uint64_t b, const std::vector<uint64_t>& bad,
+                   uint8_t out[32]) {
+    if (key->fq) {
+        gq R;
+        range_sum_of(key->prefix_q, key->r_q, a, b, bad, R);
+        fq_encode(out, R);
+    } else {
+        ge R;
+        range_sum_of(key->prefix, key->r, a, b, bad, R);
+        ge_encode(out, R);
+    }
+}
+
+// sum of s~_i over the epochs [a, b) (positions in s_epochs) not in `bad`,
+// mod q (mod N on FourQ)
+void sum_s(const poslo_c_key* key, const uint8_t* s_epochs, uint64_t a, uint64_t b, const std::vector<uint64_t>& bad,
+           uint64_t i0, uint8_t out[32]) {
+    const uint32_t inst = key->fq ? POSLO_GROUP_FOURQ : 0u;
     uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto lo = std::lower_bound(bad.begin(), bad.end(), i0 + a);
     for (uint64_t p = a; p < b; p++) {
@@ -133,8 +189,11 @@ void sum_s(const uint8_t* s_epochs, uint64_t a, uint64_t b, const std::vector<ui
             continue;
         }
         uint32_t sp[8], tmp[8];
-        hostside::sc_from_bytes_reduce(sp, s_epochs + 32 * p);
-        sc_add(tmp, acc, sp);
+        hostside::scalar_from_bytes(inst, sp, s_epochs + 32 * p);
+        if (key->fq)
+            scN_add(tmp, acc, sp);
+        else
+            sc_add(tmp, acc, sp);
         memcpy(acc, tmp, sizeof acc);
     }
     for (int w = 0; w < 8; w++) store_le32(out + 4 * w, acc[w]);
@@ -146,28 +205,48 @@ extern "C" int poslo_c_key_load(poslo_ctx* c, const poslo_params* prm, const uin
                                 poslo_c_key** out) {
     if (!c || !params_ok(prm) || !pk || !out || prm->log2_n1 > 20) return POSLO_E_INVAL;
     *out = nullptr;
-    if (prm->inst & POSLO_GROUP_FOURQ) return POSLO_E_INVAL;  // POSLO-C: edwards25519 only
     const uint64_t n1 = 1ull << prm->log2_n1;
     if (pk_len != 32 * (1 + n1)) return POSLO_E_INVAL;
     poslo_c_key* key = new (std::nothrow) poslo_c_key();
     if (!key) return POSLO_E_NOMEM;
     key->device = c->device;
     key->log2_n1 = prm->log2_n1;
+    key->fq = (prm->inst & POSLO_GROUP_FOURQ) != 0;
     memcpy(key->y, pk, 32);
     key->r_enc.assign(pk + 32, pk + pk_len);
-    key->r.resize(n1);
-    key->prefix.resize(n1 + 1);
     std::vector<uint32_t> aff(16 * n1);
-    ge_identity(key->prefix[0]);
-    ge Y;
-    bool ok = ge_decode(Y, pk);
-    for (uint64_t i = 0; ok && i < n1; i++) {
-        ok = ge_decode(key->r[i], pk + 32 * (1 + i));
-        if (!ok) break;
-        ge_add(key->prefix[i + 1], key->prefix[i], key->r[i]);
-        for (int w = 0; w < 8; w++) {
-            aff[16 * i + w] = key->r[i].X.v[w];
-            aff[16 * i + 8 + w] = key->r[i].Y.v[w];
+    bool ok;
+    if (key->fq) {
+        key->r_q.resize(n1);
+        key->prefix_q.resize(n1 + 1);
+        gq_identity(key->prefix_q[0]);
+        gq Y;
+        ok = fq_decode(Y, pk);
+        for (uint64_t i = 0; ok && i < n1; i++) {
+            ok = fq_decode(key->r_q[i], pk + 32 * (1 + i));
+            if (!ok) break;
+            gq_add(key->prefix_q[i + 1], key->prefix_q[i], key->r_q[i]);
+            for (int w = 0; w < 4; w++) {
+                aff[16 * i + w] = key->r_q[i].X.a.v[w];
+                aff[16 * i + 4 + w] = key->r_q[i].X.b.v[w];
+                aff[16 * i + 8 + w] = key->r_q[i].Y.a.v[w];
+                aff[16 * i + 12 + w] = key->r_q[i].Y.b.v[w];
+            }
+        }
+    } else {
+        key->r.resize(n1);
+        key->prefix.resize(n1 + 1);
+        ge_identity(key->prefix[0]);
+        ge Y;
+        ok = ge_decode(Y, pk);
+        for (uint64_t i = 0; ok && i < n1; i++) {
+            ok = ge_decode(key->r[i], pk + 32 * (1 + i));
+            if (!ok) break;
+            ge_add(key->prefix[i + 1], key->prefix[i], key->r[i]);
+            for (int w = 0; w < 8; w++) {
+                aff[16 * i + w] = key->r[i].X.v[w];
+                aff[16 * i + 8 + w] = key->r[i].Y.v[w];
+            }
         }
     }
     int st = ok ? POSLO_OK : POSLO_E_ENCODING;
@@ -175,7 +254,8 @@ extern "C" int poslo_c_key_load(poslo_ctx* c, const poslo_params* prm, const uin
     if (!st && hipMalloc((void**)&key->d_r, aff.size() * 4) != hipSuccess) st = POSLO_E_NOMEM;
     if (!st && hipMemcpy(key->d_r, aff.data(), aff.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         st = POSLO_E_DEVICE;
-    if (!st) ctx_key(c, key->y, &st);  // Y's comb table resident in the context
+    if (!st) ctx_key_of(c, prm->inst, key->y, &st);  // Y's comb table resident in the context
+    if (!st && key->fq && !ctx_gtable_fq(c)) st = POSLO_E_NOMEM;
     if (st) {
         poslo_c_key_free(key);
         return st;
@@ -201,12 +281,11 @@ extern "C" int poslo_c_aver(poslo_ctx* c, const poslo_params* prm, const poslo_c
     uint64_t i0, k;
     int st = epoch_range(prm, key, m, i0, k);
     if (st) return st;
+    if (((prm->inst & POSLO_GROUP_FOURQ) != 0) != key->fq) return POSLO_E_INVAL;
     // R~ = Agg of the epochs' commitments in pk
-    ge R;
-    range_sum(key, i0, i0 + k, {}, R);
     uint8_t tag[64];
     memcpy(tag, s, 32);
-    ge_encode(tag + 32, R);
+    range_sum_enc(key, i0, i0 + k, {}, tag + 32);
     return aver_impl(c, prm, key->y, m, ds, ds_len, tag, stream, nullptr, accept, e_out);
 }
 
@@ -228,8 +307,11 @@ extern "C" int poslo_c_distill(poslo_ctx* c, const poslo_params* prm, const posl
     uint32_t n_epochs;
     if ((st = prepare_batch(c, prm, m, ds, ds_len, a, dsa, n_epochs))) return st;
     HIP_TRY(hipSetDevice(c->device));
-    const KeyEntry* ky = ctx_key(c, key->y, &st);
+    if (((prm->inst & POSLO_GROUP_FOURQ) != 0) != key->fq) return POSLO_E_INVAL;
+    const KeyEntry* ky = ctx_key_of(c, prm->inst, key->y, &st);
     if (!ky) return st;
+    const uint32_t* gtab = key->fq ? ctx_gtable_fq(c) : c->d_gtable;
+    if (!gtab) return POSLO_E_NOMEM;
     std::vector<uint32_t> bits(k, 0);
     if (k) {
         void *ek, *ds_s, *dres;
@@ -247,8 +329,14 @@ extern "C" int poslo_c_distill(poslo_ctx* c, const poslo_params* prm, const posl
         if ((st = ctx_ensure(&c->d_part, &c->part_words, (size_t)g.grid * 9))) return st;
         prof_begin(c, POSLO_KT_VERIFY, s);
         if ((st = launch_agg(c, prm, g, a, c->d_part, (uint32_t*)ek, nullptr, s))) return st;
-        hipLaunchKernelGGL(k_c_epoch_check, dim3((uint32_t)k), dim3(64), 0, s, (const uint32_t*)ek, prm->log2_n2,
-                           (const uint32_t*)ds_s, key->d_r + 16 * i0, ky->d_table, c->d_gtable, (uint32_t*)dres);
+        if (key->fq)
+            hipLaunchKernelGGL(k_c_epoch_check<true>, dim3((uint32_t)k), dim3(64), 0, s, (const uint32_t*)ek,
+                               prm->log2_n2, (const uint32_t*)ds_s, key->d_r + 16 * i0, ky->d_table, gtab,
+                               (uint32_t*)dres);
+        else
+            hipLaunchKernelGGL(k_c_epoch_check<false>, dim3((uint32_t)k), dim3(64), 0, s, (const uint32_t*)ek,
+                               prm->log2_n2, (const uint32_t*)ds_s, key->d_r + 16 * i0, ky->d_table, gtab,
+                               (uint32_t*)dres);
         HIP_TRY(hipGetLastError());
         prof_end(c, POSLO_KT_VERIFY, s);
         uint32_t bad = 0;  // POSLO++: a message longer than 31 bytes
@@ -278,16 +366,13 @@ extern "C" int poslo_c_distill(poslo_ctx* c, const poslo_params* prm, const posl
     // valid aggregate and umbrellas of U = ceil(k / n_u) epochs
     const uint64_t span = std::max<uint64_t>(1, (k + n_umbrella - 1) / n_umbrella);
     ccd->span = span;
-    ge R;
-    range_sum(key, i0, i0 + k, ccd->invalid, R);
-    sum_s(s_epochs, 0, k, ccd->invalid, i0, ccd->valid_tag);
-    ge_encode(ccd->valid_tag + 32, R);
+    range_sum_enc(key, i0, i0 + k, ccd->invalid, ccd->valid_tag + 32);
+    sum_s(key, s_epochs, 0, k, ccd->invalid, i0, ccd->valid_tag);
     for (uint64_t a0 = 0; a0 < k; a0 += span) {
         const uint64_t b0 = std::min(k, a0 + span);
         uint8_t tg[64];
-        range_sum(key, i0 + a0, i0 + b0, ccd->invalid, R);
-        sum_s(s_epochs, a0, b0, ccd->invalid, i0, tg);
-        ge_encode(tg + 32, R);
+        range_sum_enc(key, i0 + a0, i0 + b0, ccd->invalid, tg + 32);
+        sum_s(key, s_epochs, a0, b0, ccd->invalid, i0, tg);
         ccd->umb_tags.insert(ccd->umb_tags.end(), tg, tg + 64);
     }
     *out = ccd;
@@ -301,6 +386,7 @@ extern "C" int poslo_c_sebver(poslo_ctx* c, const poslo_params* prm, const poslo
     uint64_t i0, k;
     int st = epoch_range(prm, key, m, i0, k);
     if (st) return st;
+    if (((prm->inst & POSLO_GROUP_FOURQ) != 0) != key->fq) return POSLO_E_INVAL;
     if (mode == 'V' || mode == 'U')
         return sebver_impl(c, prm, key->y, m, ccd, mode, bits, cap, n_bits, stream);
     if (mode != 'I') return POSLO_E_INVAL;

@@ -6,7 +6,8 @@ the key and of FourQ's generator built by the device, e folded mod N, the
 streaming audit on FourQ; the tag
 checks (s >= N, R not a FourQ point); Distill and SeBVer V/U/I on FourQ
 (invalid sets, invalid signatures, valid and umbrella tags); the device
-signer on FourQ; and the entry points that take edwards25519 only.  Keys, signatures, ds and tags come from the oracle's
+signer on FourQ; and the entry points that take edwards25519 only (POSLO-C
+on FourQ is in test_gpu_posloc.py).  Keys, signatures, ds and tags come from the oracle's
 FourQ signer."""
 
 import functools
@@ -255,7 +256,6 @@ def test_fourq_refused_where_not_built(P, gpu):
     d = torch.from_numpy(arr.copy()).cuda()
     dsig = torch.from_numpy(sigs.reshape(-1).copy()).cuda()
     calls = {
-        "c_key_load": lambda: P.poslo_c_key_load(ctx, P.make_params(inst, 2, 4), bytes(32 * 5)),
         "server": lambda: P.Server(0, params),
     }
     for name, call in calls.items():

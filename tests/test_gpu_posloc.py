@@ -1,8 +1,8 @@
 """GPU parity of POSLO-C (coarse-grained: one signature per epoch) against
 the oracle, through the C ABI: AVer over whole epochs, Distill's invalid
 epochs, valid tag and umbrella tags, SeBVer V/U/I, the coarse CCD's byte
-export, and the argument errors.  Keys, signatures and ds come from the
-oracle's POSLO-C signer."""
+export, and the argument errors, on edwards25519 and on FourQ.  Keys,
+signatures and ds come from the oracle's POSLO-C signer."""
 
 import functools
 
@@ -49,6 +49,8 @@ CASES = [
     (1, 5, 37, 3, 3),
     (0, 5, 37, 3, 3),
     (1, 4, 64, 2, 0),
+    (1 | 8, 6, 48, 3, 4),   # the FourQ group
+    (0 | 8, 5, 37, 3, 3),
 ]
 
 
@@ -69,15 +71,15 @@ def test_c_aver_distill_sebver_equal_oracle(P, gpu, case):
         d, off = upload(torch, msgs, fixed)
         m = P.make_msgs(d, off)
         print(f"case {case} fixed {fixed}: aver", flush=True)
-        acc, e = P.poslo_c_aver(ctx, params, key, m, ds, O.posloc_agg_s(s_list))
+        acc, e = P.poslo_c_aver(ctx, params, key, m, ds, O.posloc_agg_s(s_list, inst))
         assert acc and int.from_bytes(e, "little") == O.ekeys_sum(prm, msgs, 0, ds)
         # a range of epochs against its own aggregate; a wrong aggregate
         a, b = 1, k - 1
         sub = msgs[a * n2:b * n2]
         ds_, off_ = upload(torch, sub, fixed)
         ms = P.make_msgs(ds_, off_, t0=a * n2)
-        assert P.poslo_c_aver(ctx, params, key, ms, ds, O.posloc_agg_s(s_list[a:b]))[0]
-        assert not P.poslo_c_aver(ctx, params, key, ms, ds, O.posloc_agg_s(s_list[a:b + 1]))[0]
+        assert P.poslo_c_aver(ctx, params, key, ms, ds, O.posloc_agg_s(s_list[a:b], inst))[0]
+        assert not P.poslo_c_aver(ctx, params, key, ms, ds, O.posloc_agg_s(s_list[a:b + 1], inst))[0]
     # Distill with a flipped message bit in epoch 1 and a flipped s bit in epoch k-2
     cm, cs = list(msgs), list(s_list)
     mm = bytearray(cm[n2 + n2 // 2])

@@ -179,17 +179,21 @@ def hash_calls_per_entry(inst: int, L):
 # kernel sources they were taken on: the sha256 prefix of those files must
 # match, else traffic is null.
 TRAFFIC = {
-    "aes": {"fetch_kib": 190964.4, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "aes": {"fetch_kib": 190705.8, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
             "files": ["agg_aes.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "device_verify.h",
-                      "common.h", "sc25519.h"],
-            "sha256": "e3d5aca08eff9a80", "profile": "profiles/pmc_aver_2p20x256.md"},
-    "addq": {"fetch_kib": 573536.7, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                      "common.h", "sc25519.h", "fourq.h"],
+            "sha256": "0cf0430dfcf996a8", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "aes_2p26x16": {"fetch_kib": 556440.5, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                    "files": ["agg_aes.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h",
+                              "device_verify.h", "common.h", "sc25519.h", "fourq.h"],
+                    "sha256": "0cf0430dfcf996a8", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "addq": {"fetch_kib": 573541.8, "write_kib": 32.0, "fetch_scale": 2.0, "write_scale": 1.0,
              "files": ["agg_addq.hip", "aes_perm.h", "aes128.h", "device_entry.h", "device_hash.h", "common.h",
                        "sc25519.h"],
-             "sha256": "cefb9c9c94a6d710", "profile": "profiles/pmc_aver_2p20x256.md"},
-    "sha": {"fetch_kib": 133146.0, "write_kib": 1088.0, "fetch_scale": 2.0, "write_scale": 1.0,
-            "files": ["agg_sha.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h"],
-            "sha256": "7c64ae117806ead6", "profile": "profiles/pmc_aver_2p20x256.md"},
+             "sha256": "e6f91aa883f9a3fb", "profile": "profiles/pmc_aver_2p20x256.md"},
+    "sha": {"fetch_kib": 133144.2, "write_kib": 1088.0, "fetch_scale": 2.0, "write_scale": 1.0,
+            "files": ["agg_sha.hip", "sha256.h", "device_entry.h", "device_hash.h", "common.h", "sc25519.h", "fourq.h"],
+            "sha256": "e97e85b337597797", "profile": "profiles/pmc_aver_2p20x256.md"},
 }
 
 
@@ -414,6 +418,7 @@ def bench_variants(P, torch, ctx, steps, warmup, rates):
         "kernel_ms": kt, "hashes_per_s": n / (total / steps) * hash_calls_per_entry(1, cfg["L"]),
         "roofline": {"bound": "alu", "kernel": "k_agg_ekeys_aes", "achieved": achieved, "peak": INT32_PEAK_TOPS,
                      "unit": "Tops/s (int32)", "frac": achieved / INT32_PEAK_TOPS, "ops_per_entry": ope,
+                     "traffic": traffic_bytes("aes_2p26x16"), "algorithmic_bytes": n * cfg["L"],
                      "hbm_GBs": n * cfg["L"] / (kt["agg"] / 1e3) / 1e9}}
     cfg2 = CONFIGS["c2"]
     log, total, lat, kt = bench_plain(P, torch, ctx, cfg2, 1 | 4, steps, warmup, False)

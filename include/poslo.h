@@ -87,9 +87,11 @@ enum {
  * streaming audit, poslo_ekeys (e_t mod N), poslo_distill and poslo_sebver
  * (the individual checks with FourQ's 8-bit comb tables of Y and G),
  * POSLO-C (poslo_c_key_load with FourQ commitments, poslo_c_aver,
- * poslo_c_distill, poslo_c_sebver) and the device signer
- * (poslo_gpu_keys_create, poslo_gpu_sign); the multi-signer batch and the
- * serving loop return E_INVAL. */
+ * poslo_c_distill, poslo_c_sebver), the device signer
+ * (poslo_gpu_keys_create, poslo_gpu_sign), the multi-signer batch
+ * (poslo_verify_batch, poslo_autotune_batch) and the serving loop.
+ * poslo_ctx_keys_load and poslo_ctx_keys_widen take edwards25519 keys only;
+ * FourQ keys become resident on first use. */
 #define POSLO_GROUP_FOURQ 8u
 
 /* 1 if inst is an instantiation word (SHA256, AES or AES_ADDQ, the last two

@@ -66,6 +66,9 @@ struct HotVariant {
 int batch_variant_count();
 const HotVariant& batch_variant(int v);
 int batch_default_variant(uint32_t inst);
+// instantiations the multi-signer path takes: POSLO and POSLO+ at kappa = 128,
+// on edwards25519 or FourQ
+bool batch_inst_ok(uint32_t inst);
 size_t hot_lds_bytes(const HotVariant& v);
 
 class BatchRunner {

@@ -27,6 +27,7 @@
 #include "aes_perm.h"
 #include "aes_quad.h"
 #include "batch_run.h"
+#include "device_fq.h"
 #include "device_verify.h"
 
 namespace poslo {
@@ -61,7 +62,8 @@ struct BSeeds {
     uint32_t inst;
     uint32_t* tab;
     uint32_t* counter;
-    uint32_t* rdec;  // 17 words per job: ok, x[8], y[8]
+    uint32_t* rdec;  // 17 words per job: ok, x[8], y[8] (FourQ: x and y as GF(p^2) words)
+    uint32_t fq;     // the FourQ group
 };
 
 template <int INST>
@@ -77,9 +79,21 @@ __global__ __launch_bounds__(256) void k_batch_seeds(BSeeds S) {
             sv[k] = J.tag[k];
             store_le32(rb + 4 * k, J.tag[8 + k]);
         }
+        uint32_t* o = S.rdec + (uint64_t)j * 17;
+        if (S.fq) {
+            gq R;
+            const bool ok = scN_is_canonical(sv) && fq_decode(R, rb);
+            o[0] = ok ? 1u : 0u;
+            for (int k = 0; k < 4; k++) {
+                o[1 + k] = ok ? R.X.a.v[k] : 0u;
+                o[5 + k] = ok ? R.X.b.v[k] : 0u;
+                o[9 + k] = ok ? R.Y.a.v[k] : 0u;
+                o[13 + k] = ok ? R.Y.b.v[k] : 0u;
+            }
+            return;
+        }
         ge R;
         bool ok = sc_is_canonical(sv) && ge_decode(R, rb);
-        uint32_t* o = S.rdec + (uint64_t)j * 17;
         o[0] = ok ? 1u : 0u;
         for (int k = 0; k < 8; k++) {
             o[1 + k] = ok ? R.X.v[k] : 0u;
@@ -144,6 +158,7 @@ struct BHot {
     uint32_t* e_out;     // optional: e_t mod q, 8 words per entry (job's ebase + offset)
     uint8_t* xbad;       // with e_out: 1 when x_t differs from the signature's
     uint32_t* pair_tmp;  // PAIR variants: 16 words per thread of the grid
+    uint32_t emit_raw;   // e_out gets the unreduced digest (FourQ: reduced mod N by the checks)
 };
 
 // INST 1: MDC-2-AES over the byte-addressed tables (NT = 1 or 2);
@@ -246,7 +261,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 #pragma unroll
                 for (int w = 0; w < 4; w++) d |= x[w] ^ gload_le32(sg + 4 * w);
                 uint32_t e[8];
-                sc_reduce256(e, dig);
+                if (A.emit_raw)
+#pragma unroll
+                    for (int w = 0; w < 8; w++) e[w] = dig[w];
+                else
+                    sc_reduce256(e, dig);
                 uint32_t* eo = A.e_out + (J.ebase + p2) * 8;
 #pragma unroll
                 for (int w = 0; w < 8; w++) eo[w] = e[w];
@@ -306,6 +325,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 // (many jobs at once: independent one-wave checks keep more of them resident
 // than the quad-split block check, whose registers allow four blocks per CU)
 
+// FQ: on FourQ (e mod N; rdec holds x and y as GF(p^2) words)
+template <bool FQ>
 __global__ __launch_bounds__(64) void k_batch_final(const BJob* jobs, const uint32_t* partials, const uint32_t* tg,
                                                     const uint32_t* rdec, uint32_t* result) {
     const BJob& J = jobs[blockIdx.x];
@@ -313,8 +334,25 @@ __global__ __launch_bounds__(64) void k_batch_final(const BJob* jobs, const uint
     for (uint64_t k = J.item_base + threadIdx.x; k < J.item_end; k += 64) acc288_add(acc, partials + k * 9);
     wave_reduce288(acc);  // every lane holds the sum
     uint32_t e[8], s[8];
-    sc_reduce288(e, acc);
     for (int k = 0; k < 8; k++) s[k] = J.tag[k];
+    if constexpr (FQ) {
+        scN_reduce<9>(e, acc);
+        const uint32_t* r = rdec + (uint64_t)blockIdx.x * 17;
+        if (!r[0])
+            for (int k = 0; k < 8; k++) s[k] = 0;  // s >= N: any in-range digits, the result is 0
+        gq P;
+        wave_double_scalar_fq(P, J.ty, tg, e, s);
+        if (threadIdx.x == 0) {
+            fp2 rx, ry, t0, t1;
+            unstash_f2(rx, r + 1, 1);
+            unstash_f2(ry, r + 9, 1);
+            f2_mul(t0, rx, P.Z);
+            f2_mul(t1, ry, P.Z);
+            result[blockIdx.x] = (r[0] && f2_eq(t0, P.X) && f2_eq(t1, P.Y)) ? 1u : 0u;
+        }
+        return;
+    }
+    sc_reduce288(e, acc);
     ge P;
     wave_double_scalar(P, J.ty, tg, e, s);
     if (threadIdx.x == 0) {
@@ -357,6 +395,7 @@ struct BVerify {
 // the points waiting in the workgroup's slice of the stash.  A
 // key with a resident wide table (J.tyw) takes 16 + 16 mixed additions per
 // entry instead of 32 + 16.
+template <bool FQ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_verify_pre(BVerify V) {
     uint32_t* st = V.stash + (uint64_t)blockIdx.x * kVerifyStashWords + threadIdx.x;
 #pragma unroll 1
@@ -376,8 +415,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             sg = J.sigs + q * 80;
             e = V.ekeys + (J.ebase + q) * 8;
         };
-        const uint32_t okmask = J.tyw ? verify_sig_batch<true>(ent, ne, J.tyw, V.tg, st, 64)
-                                      : verify_sig_batch<false>(ent, ne, J.ty, V.tg, st, 64);
+        uint32_t okmask;
+        if constexpr (FQ)
+            okmask = verify_sig_batch_fq<true>(ent, ne, J.ty, V.tg, st, 64);
+        else
+            okmask = J.tyw ? verify_sig_batch<true>(ent, ne, J.tyw, V.tg, st, 64)
+                           : verify_sig_batch<false>(ent, ne, J.ty, V.tg, st, 64);
 #pragma unroll 1
         for (int k = 0; k < ne; k++) {
             const uint32_t idx = threadIdx.x + 64u * (uint32_t)k;
@@ -433,7 +476,8 @@ int batch_variant_count() { return kNumHot; }
 const HotVariant& batch_variant(int v) { return kHot[v]; }
 // AES: aes_p2x32_b1024_c2048_paired_w8, the autotuner's pick on the
 // 4,096-signer log (1.52 G entries/s); SHA-256: sha_b256_c1024_sorted_w3
-int batch_default_variant(uint32_t inst) { return inst == POSLO_INST_AES ? 16 : 5; }
+int batch_default_variant(uint32_t inst) { return inst_base(inst) == POSLO_INST_AES ? 16 : 5; }
+bool batch_inst_ok(uint32_t inst) { return (inst & ~POSLO_GROUP_FOURQ) <= POSLO_INST_AES; }
 
 size_t hot_lds_bytes(const HotVariant& v) {
     size_t tw = v.inst == 1 ? (size_t)v.nt * 256 * (v.copies ? v.copies : 64) : 0;
@@ -557,8 +601,8 @@ int BatchRunner::grow_pinned(void** p, size_t* have, size_t bytes) {
 
 int BatchRunner::plan(const poslo_params* prm, const JobSpec* jobs, uint32_t njobs, const poslo_tuning& t,
                       int num_cu) {
-    if (!params_ok(prm) || prm->inst > POSLO_INST_AES || (njobs && !jobs)) return POSLO_E_INVAL;
-    if (t.variant < 0 || t.variant >= kNumHot || kHot[t.variant].inst != (int)prm->inst || t.wg_per_cu < 0 ||
+    if (!params_ok(prm) || !batch_inst_ok(prm->inst) || (njobs && !jobs)) return POSLO_E_INVAL;
+    if (t.variant < 0 || t.variant >= kNumHot || kHot[t.variant].inst != (int)inst_base(prm->inst) || t.wg_per_cu < 0 ||
         t.wg_per_cu > 64)
         return POSLO_E_INVAL;
     prm_ = *prm;
@@ -658,7 +702,7 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     S.job_of_row = (const uint32_t*)d_rows_;
     S.n_rows = rows;
     // AES rows take four lanes each
-    const uint64_t row_lanes = rows * (prm_.inst == POSLO_INST_AES ? 4 : 1);
+    const uint64_t row_lanes = rows * (inst_base(prm_.inst) == POSLO_INST_AES ? 4 : 1);
     S.row_blocks = (uint32_t)std::max<uint64_t>(1, (row_lanes + 255) / 256);
     S.njobs = njobs;
     S.log2_n2 = prm_.log2_n2;
@@ -666,6 +710,8 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     S.tab = (uint32_t*)d_tab_;
     S.counter = (uint32_t*)d_misc_;
     S.rdec = (uint32_t*)d_rdec_;
+    const bool fq = (prm_.inst & POSLO_GROUP_FOURQ) != 0;
+    S.fq = fq ? 1u : 0u;
     const uint32_t seed_grid = S.row_blocks + (njobs + 255) / 256;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(items_.size(), (uint64_t)num_cu_ * hot_wg_per_cu(hv, tune_.wg_per_cu)));
@@ -680,13 +726,15 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
     A.partials = (uint32_t*)d_part_;
     A.e_out = emit ? (uint32_t*)d_ekeys_ : nullptr;
     A.xbad = emit ? (uint8_t*)d_xbad_ : nullptr;
+    A.emit_raw = fq ? 1u : 0u;
     if (hv.pair) {
         if ((st = grow(&d_pair_, &n_pair_b_, (size_t)grid * hv.block * 64))) return st;
         A.pair_tmp = (uint32_t*)d_pair_;
     }
-    const uint32_t* tg = prof->d_gtable;
+    const uint32_t* tg = fq ? ctx_gtable_fq(prof) : prof->d_gtable;
+    if (!tg) return POSLO_E_NOMEM;
     auto launch_all = [&](hipStream_t q, bool timed) -> int {
-        if (prm_.inst == POSLO_INST_AES)
+        if (inst_base(prm_.inst) == POSLO_INST_AES)
             hipLaunchKernelGGL(k_batch_seeds<INST_AES>, dim3(seed_grid), dim3(256), 0, q, S);
         else
             hipLaunchKernelGGL(k_batch_seeds<INST_SHA256>, dim3(seed_grid), dim3(256), 0, q, S);
@@ -694,8 +742,11 @@ int BatchRunner::launch(hipStream_t s, bool use_graph, poslo_ctx* prof, bool emi
         int r = launch_hot(tune_.variant, grid, A, q);
         if (timed) prof_end(prof, POSLO_KT_BATCH_HOT, q);
         if (r) return r;
-        if (njobs)
-            hipLaunchKernelGGL(k_batch_final, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs_,
+        if (njobs && fq)
+            hipLaunchKernelGGL(k_batch_final<true>, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs_,
+                               (const uint32_t*)d_part_, tg, (const uint32_t*)d_rdec_, (uint32_t*)d_res_);
+        else if (njobs)
+            hipLaunchKernelGGL(k_batch_final<false>, dim3(njobs), dim3(64), 0, q, (const BJob*)d_jobs_,
                                (const uint32_t*)d_part_, tg, (const uint32_t*)d_rdec_, (uint32_t*)d_res_);
         return hipGetLastError() == hipSuccess ? POSLO_OK : POSLO_E_DEVICE;
     };
@@ -782,7 +833,9 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     BVerify V;
     V.jobs = (const BJob*)d_jobs_;
     V.tiles = (const BItem*)d_vtiles_;
-    V.tg = ctx_gtable_wide(prof);
+    const bool fq = (prm_.inst & POSLO_GROUP_FOURQ) != 0;
+    if (fq && !emitted_) return POSLO_E_INVAL;  // FourQ checks take the emitted digests
+    V.tg = fq ? ctx_gtable_fq(prof) : ctx_gtable_wide(prof);
     if (!V.tg) return POSLO_E_NOMEM;
     V.inst = prm_.inst;
     V.log2_n2 = prm_.log2_n2;
@@ -795,8 +848,10 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.next = next;
     V.ntiles = (uint32_t)vtiles_.size();
     prof_begin(prof, POSLO_KT_VERIFY, s);
-    if (emitted_)
-        hipLaunchKernelGGL(k_batch_verify_pre, dim3(grid), dim3(64), 0, s, V);
+    if (emitted_ && fq)
+        hipLaunchKernelGGL(k_batch_verify_pre<true>, dim3(grid), dim3(64), 0, s, V);
+    else if (emitted_)
+        hipLaunchKernelGGL(k_batch_verify_pre<false>, dim3(grid), dim3(64), 0, s, V);
     else
         hipLaunchKernelGGL(k_batch_verify, dim3((uint32_t)vtiles_.size()), dim3(256), 0, s, V);
     prof_end(prof, POSLO_KT_VERIFY, s);
@@ -870,7 +925,7 @@ std::tuple<uint32_t, uint32_t, uint32_t> shape_class(const poslo_params* prm, ui
 }
 
 // resolve keys and express the global layout as per-job views
-int make_specs(poslo_ctx* c, const poslo_batch_job* jobs, uint32_t njobs, const uint8_t* data,
+int make_specs(poslo_ctx* c, bool fourq, const poslo_batch_job* jobs, uint32_t njobs, const uint8_t* data,
                const uint64_t* offsets, uint64_t data_bytes, const uint8_t* sigs, std::vector<JobSpec>& specs) {
     std::vector<uint8_t> pks((size_t)njobs * 32);
     for (uint32_t j = 0; j < njobs; j++) {
@@ -880,14 +935,14 @@ int make_specs(poslo_ctx* c, const poslo_batch_job* jobs, uint32_t njobs, const 
         memcpy(&pks[(size_t)j * 32], jobs[j].pk, 32);
     }
     std::vector<const uint32_t*> tables;
-    int st = ctx_keys_bulk(c, pks.data(), njobs, tables, nullptr);
+    int st = ctx_keys_bulk(c, pks.data(), njobs, tables, nullptr, fourq);
     if (st) return st;
     specs.resize(njobs);
     for (uint32_t j = 0; j < njobs; j++) {
         const poslo_batch_job& in = jobs[j];
         JobSpec& sp = specs[j];
         sp.ty = tables[j];
-        sp.tyw = ctx_key_wide_resident(c, jobs[j].pk);
+        sp.tyw = fourq ? nullptr : ctx_key_wide_resident(c, jobs[j].pk);
         sp.data = data;
         sp.offsets = offsets ? offsets + in.entry_base : nullptr;
         sp.msg_len = 0;
@@ -936,7 +991,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
                                   const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes,
                                   const uint8_t* sigs, int distill, const poslo_tuning* tuning, void* stream,
                                   uint8_t* accept, uint64_t* invalid, size_t cap, size_t* n_invalid) {
-    if (!c || !params_ok(prm) || prm->inst > POSLO_INST_AES || (njobs && (!jobs || !accept)) || distill < 0 ||
+    if (!c || !params_ok(prm) || !batch_inst_ok(prm->inst) || (njobs && (!jobs || !accept)) || distill < 0 ||
         distill > 2)
         return POSLO_E_INVAL;
     if (distill && (!sigs || !n_invalid || (cap && !invalid))) return POSLO_E_INVAL;
@@ -959,7 +1014,7 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
         if (it != tuned.end()) t = it->second;
     }
     std::vector<JobSpec> specs;
-    int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, sigs, specs);
+    int st = make_specs(c, (prm->inst & POSLO_GROUP_FOURQ) != 0, jobs, njobs, data, offsets, data_bytes, sigs, specs);
     if (st) return st;
     BatchRunner& R = state_of(c).runner;
     if ((st = run_sync(c, R, prm, specs, t, s, accept, distill != 0))) return st;
@@ -984,12 +1039,13 @@ extern "C" int poslo_verify_batch(poslo_ctx* c, const poslo_params* prm, const p
 extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const poslo_batch_job* jobs, uint32_t njobs,
                                     const uint8_t* data, const uint64_t* offsets, uint64_t data_bytes, int reps,
                                     void* stream, poslo_tuning* best, double* best_ms) {
-    if (!c || !params_ok(prm) || prm->inst > POSLO_INST_AES || !best || njobs == 0 || !jobs) return POSLO_E_INVAL;
+    if (!c || !params_ok(prm) || !batch_inst_ok(prm->inst) || !best || njobs == 0 || !jobs) return POSLO_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
     if (reps < 1) reps = 3;
     std::vector<JobSpec> specs;
-    int st = make_specs(c, jobs, njobs, data, offsets, data_bytes, nullptr, specs);
+    int st = make_specs(c, (prm->inst & POSLO_GROUP_FOURQ) != 0, jobs, njobs, data, offsets, data_bytes, nullptr,
+                        specs);
     if (st) return st;
     BatchRunner& R = state_of(c).runner;
     std::vector<uint8_t> acc_ref(njobs), acc(njobs);
@@ -1005,7 +1061,7 @@ extern "C" int poslo_autotune_batch(poslo_ctx* c, const poslo_params* prm, const
         return code;
     };
     for (int v = 0; v < kNumHot; v++) {
-        if (kHot[v].inst != (int)prm->inst) continue;
+        if (kHot[v].inst != (int)inst_base(prm->inst)) continue;
         for (int wg : {0, 1, 2, 4}) {
             if (wg > 0 && wg * (kHot[v].block / 64) > 4 * kHot[v].waves_per_simd) continue;
             if (wg > 0 && (size_t)wg * (hot_lds_bytes(kHot[v]) + 512) > 160 * 1024) continue;

@@ -126,8 +126,9 @@ inline std::string fq_key_id(const uint8_t pk[32]) { return std::string((const c
 // device comb tables of many keys (built on the device for the missing
 // ones); tables[k] is key k's table.  Keys that are not point encodings get
 // nullptr and are counted in *n_bad (the call then returns E_ENCODING).
-// Keys of one call are never evicted by that call.
-int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad);
+// Keys of one call are never evicted by that call.  fourq: FourQ keys.
+int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad,
+                  bool fourq = false);
 // G's wide table for the per-entry checks (comb.h), built on first use;
 // nullptr if it cannot be allocated
 const uint32_t* ctx_gtable_wide(poslo_ctx* c);

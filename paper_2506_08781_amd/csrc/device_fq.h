@@ -96,7 +96,9 @@ PD bool fq_encodes_zinv(const gq& P, const fp2& zi, const uint32_t want[8]) {
 }
 
 // the curve part of entry checks on FourQ, as verify_sig_batch (same stash
-// layout: X, Y, Z and the running product before the entry, 32 words)
+// layout: X, Y, Z and the running product before the entry, 32 words).
+// RAW: e points at the unreduced digest, reduced mod N here.
+template <bool RAW>
 __device__ __forceinline__ bool sig_point_fq(const uint8_t* sg, const uint32_t* e, bool go, const uint32_t* ty,
                                              const uint32_t* tg, gq& P) {
     uint32_t ek[8], s[8];
@@ -104,6 +106,7 @@ __device__ __forceinline__ bool sig_point_fq(const uint8_t* sg, const uint32_t* 
         s[w] = go ? gload_le32(sg + 4 * w) : 0u;
         ek[w] = go ? e[w] : 0u;
     }
+    if constexpr (RAW) scN_reduce<8>(ek, ek);
     const bool c = go && scN_is_canonical(s);
     if (!c)
         for (int w = 0; w < 8; w++) s[w] = ek[w] = 0;  // the identity: Z stays nonzero
@@ -133,7 +136,7 @@ __device__ __forceinline__ void unstash_f2(fp2& a, const uint32_t* o, uint32_t s
     }
 }
 
-template <class ENT>
+template <bool RAW = false, class ENT>
 __device__ __forceinline__ uint32_t verify_sig_batch_fq(const ENT& ent, int ne, const uint32_t* ty,
                                                         const uint32_t* tg, uint32_t* st, uint32_t stride) {
     if (ne <= 0) return 0;
@@ -147,7 +150,7 @@ __device__ __forceinline__ uint32_t verify_sig_batch_fq(const ENT& ent, int ne, 
         const uint32_t* e;
         bool go;
         ent(k, sg, e, go);
-        if (sig_point_fq(sg, e, go, ty, tg, P)) okmask |= 1u << k;
+        if (sig_point_fq<RAW>(sg, e, go, ty, tg, P)) okmask |= 1u << k;
         if (k == 0) {
             c = P.Z;
         } else {

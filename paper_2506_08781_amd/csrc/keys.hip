@@ -288,7 +288,11 @@ int build_comb_tables(const uint8_t* pks, size_t m, uint32_t* d_tab, std::vector
     return build_tables(false, pks, m, d_tab, ok);
 }
 
-int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad) {
+int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const uint32_t*>& tables, size_t* n_bad,
+                  bool fourq) {
+    auto id_of = [&](const uint8_t* pk) {
+        return fourq ? fq_key_id(pk) : std::string((const char*)pk, 32);
+    };
     tables.assign(n, nullptr);
     if (n_bad) *n_bad = 0;
     if (n == 0) return POSLO_OK;
@@ -298,7 +302,7 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
     std::vector<std::string> missing;
     std::unordered_map<std::string, size_t> slot;
     for (size_t k = 0; k < n; k++) {
-        std::string id((const char*)pks + 32 * k, 32);
+        const std::string id = id_of(pks + 32 * k);
         auto it = c->key_index.find(id);
         if (it != c->key_index.end()) {
             c->keys.splice(c->keys.begin(), c->keys, it->second);
@@ -315,7 +319,7 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
         if (hipMalloc(&d_tab, m * (size_t)kCombWords * 4) != hipSuccess) return POSLO_E_NOMEM;
         std::shared_ptr<void> slab(d_tab, [](void* q) { hipFree(q); });
         std::vector<uint32_t> ok;
-        int st = build_comb_tables(h_pks.data(), m, (uint32_t*)d_tab, ok);
+        int st = build_tables(fourq, h_pks.data(), m, (uint32_t*)d_tab, ok);
         if (st) return st;
         // make room: evict least recently used keys not touched by this call
         size_t good = 0;
@@ -332,6 +336,7 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
             if (!ok[k]) continue;
             KeyEntry ke;
             ke.pk = missing[k];
+            ke.fourq = fourq;
             ke.d_table = (uint32_t*)d_tab + k * (size_t)kCombWords;
             ke.slab = slab;
             c->keys.push_front(ke);
@@ -340,7 +345,7 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
         }
         for (size_t k = 0; k < n; k++) {
             if (tables[k]) continue;
-            tables[k] = built[slot[std::string((const char*)pks + 32 * k, 32)]];
+            tables[k] = built[slot[id_of(pks + 32 * k)]];
         }
     }
     // duplicates of a bad key count once per occurrence

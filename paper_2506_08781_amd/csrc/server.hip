@@ -28,16 +28,18 @@
 #include <vector>
 
 #include "batch_run.h"
+#include "device_fq.h"
 #include "ge25519.h"
 #include "sc25519.h"
 
 namespace poslo {
 
-// per-key state words: s (8, reduced mod q), R = (X, Y, Z, T) (32), entries (2)
+// per-key state words: s (8, reduced mod q), R = (X, Y, Z, T) (32), entries (2);
+// on FourQ s is reduced mod N and the coordinates are GF(p^2) words
 constexpr int kStateWords = 48;
 
 __global__ void k_key_state(const BJob* jobs, const uint32_t* accept, const uint32_t* rdec,
-                            const uint32_t* slot_of_job, uint32_t njobs, uint32_t* state) {
+                            const uint32_t* slot_of_job, uint32_t njobs, uint32_t* state, uint32_t fq) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     // one lane in job order: a key's requests of one group are folded in turn
     for (uint32_t j = 0; j < njobs; j++) {
@@ -47,6 +49,29 @@ __global__ void k_key_state(const BJob* jobs, const uint32_t* accept, const uint
         for (int k = 0; k < 8; k++) {
             s[k] = st[k];
             t[k] = jobs[j].tag[k];
+        }
+        if (fq) {
+            scN_add(s, s, t);
+            gq A, R;
+            unstash_f2(A.X, st + 8, 1);
+            unstash_f2(A.Y, st + 16, 1);
+            unstash_f2(A.Z, st + 24, 1);
+            unstash_f2(A.T, st + 32, 1);
+            const uint32_t* r = rdec + (uint64_t)j * 17;
+            unstash_f2(R.X, r + 1, 1);
+            unstash_f2(R.Y, r + 9, 1);
+            f2_one(R.Z);
+            f2_mul(R.T, R.X, R.Y);
+            gq_add(A, A, R);
+            for (int k = 0; k < 8; k++) st[k] = s[k];
+            stash_f2(st + 8, 1, A.X);
+            stash_f2(st + 16, 1, A.Y);
+            stash_f2(st + 24, 1, A.Z);
+            stash_f2(st + 32, 1, A.T);
+            uint64_t e = ((uint64_t)st[41] << 32 | st[40]) + jobs[j].n;
+            st[40] = (uint32_t)e;
+            st[41] = (uint32_t)(e >> 32);
+            continue;
         }
         sc_add(s, s, t);
         ge A, R;
@@ -262,7 +287,8 @@ int poslo_server::launch_group(Slot& sl) {
     HIP_TRY(hipMemcpyAsync(sl.d_slot_of_job, slot_of_job.data(), slot_of_job.size() * 4, hipMemcpyHostToDevice, s));
     if ((st = sl.runner.launch(s, false, ctx, cfg.distill != 0))) return st;
     hipLaunchKernelGGL(k_key_state, dim3(1), dim3(64), 0, s, sl.runner.d_jobs(), sl.runner.d_accept(),
-                       sl.runner.d_rdec(), (const uint32_t*)sl.d_slot_of_job, (uint32_t)specs.size(), d_state);
+                       sl.runner.d_rdec(), (const uint32_t*)sl.d_slot_of_job, (uint32_t)specs.size(), d_state,
+                       (cfg.params.inst & POSLO_GROUP_FOURQ) ? 1u : 0u);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(sl.ev, s));
     sl.phase = 1;
@@ -434,10 +460,10 @@ void poslo_server::run() {
 }
 
 extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, poslo_server** out) {
-    if (!cfg || !out || !params_ok(&cfg->params) || cfg->params.inst > POSLO_INST_AES) return POSLO_E_INVAL;
+    if (!cfg || !out || !params_ok(&cfg->params) || !batch_inst_ok(cfg->params.inst)) return POSLO_E_INVAL;
     if (cfg->distill < 0 || cfg->distill > 2) return POSLO_E_INVAL;
     if (cfg->variant >= batch_variant_count() ||
-        (cfg->variant >= 0 && batch_variant(cfg->variant).inst != (int)cfg->params.inst))
+        (cfg->variant >= 0 && batch_variant(cfg->variant).inst != (int)inst_base(cfg->params.inst)))
         return POSLO_E_INVAL;
     *out = nullptr;
     poslo_ctx* ctx = nullptr;
@@ -480,7 +506,7 @@ extern "C" int poslo_server_register_keys(poslo_server* S, const uint32_t* ids, 
     std::lock_guard<std::mutex> reg(S->reg_mu);
     std::vector<const uint32_t*> tables;
     size_t bad = 0;
-    int st = ctx_keys_bulk(S->ctx, pks, n, tables, &bad);
+    int st = ctx_keys_bulk(S->ctx, pks, n, tables, &bad, (S->cfg.params.inst & POSLO_GROUP_FOURQ) != 0);
     if (st) return st;
     std::lock_guard<std::mutex> lk(S->mu);
     // an id registered again is replaced only while none of its requests is
@@ -645,15 +671,26 @@ extern "C" int poslo_server_key_state(poslo_server* S, uint32_t key_id, uint8_t 
     if (hipSetDevice(S->device) != hipSuccess ||
         hipMemcpy(w, S->d_state + (size_t)slot * kStateWords, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
         return POSLO_E_DEVICE;
-    ge A;
-    for (int k = 0; k < 8; k++) {
-        store_le32(tag + 4 * k, w[k]);
-        A.X.v[k] = w[8 + k];
-        A.Y.v[k] = w[16 + k];
-        A.Z.v[k] = w[24 + k];
-        A.T.v[k] = w[32 + k];
+    for (int k = 0; k < 8; k++) store_le32(tag + 4 * k, w[k]);
+    if (S->cfg.params.inst & POSLO_GROUP_FOURQ) {
+        gq A;
+        for (int k = 0; k < 4; k++) {
+            A.X.a.v[k] = w[8 + k], A.X.b.v[k] = w[12 + k];
+            A.Y.a.v[k] = w[16 + k], A.Y.b.v[k] = w[20 + k];
+            A.Z.a.v[k] = w[24 + k], A.Z.b.v[k] = w[28 + k];
+            A.T.a.v[k] = w[32 + k], A.T.b.v[k] = w[36 + k];
+        }
+        fq_encode(tag + 32, A);
+    } else {
+        ge A;
+        for (int k = 0; k < 8; k++) {
+            A.X.v[k] = w[8 + k];
+            A.Y.v[k] = w[16 + k];
+            A.Z.v[k] = w[24 + k];
+            A.T.v[k] = w[32 + k];
+        }
+        ge_encode(tag + 32, A);
     }
-    ge_encode(tag + 32, A);
     if (entries) *entries = (uint64_t)w[41] << 32 | w[40];
     return POSLO_OK;
 }

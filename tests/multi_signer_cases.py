@@ -21,7 +21,9 @@ JOBS = [(0, 0, 37), (1, 0, 1), (2, 20, 50), (0, 37, 0), (0, 37, 26), (1, 1, 90)]
 def oracle_jobs(inst):
     """Messages, keys and the oracle's signatures, tags and ds of JOBS."""
     from oracle import oracle as O
-    prm = O.Params(inst, L1, L2)
+    # FourQ: a BPV table of 64 points and subsets of 8 keep the oracle's
+    # scalar multiplications few (verification does not depend on them)
+    prm = O.Params(inst, L1, L2, v=64, k=8) if inst & O.GROUP_FOURQ else O.Params(inst, L1, L2)
     total = sum(n for _, _, n in JOBS)
     lens = synthlog.uniform_per_stream(31, np.arange(total), 0, 100)
     data, off = synthlog.messages_var(32, lens)
@@ -37,7 +39,7 @@ def oracle_jobs(inst):
             O.sig(s, b"")
         assert s.t == t0
         sg = [O.sig(s, msgs[base + p]) for p in range(n)]
-        out.append(dict(key=key, t0=t0, n=n, entry_base=base, pk=pks[key], sigs=sg, tag=O.agg(sg),
+        out.append(dict(key=key, t0=t0, n=n, entry_base=base, pk=pks[key], sigs=sg, tag=O.agg(sg, inst),
                         ds=O.ds_encode(s.ds)))
         base += n
     return prm, seeds, data, off, msgs, out

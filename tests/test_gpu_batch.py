@@ -5,7 +5,7 @@ through the C ABI.
 Small cases: several signers with jobs of uneven sizes (including empty and
 single-entry jobs, jobs starting mid-epoch and jobs of one key at different
 t), variable-length messages (0 to 100 bytes, any alignment), signed by the
-oracle.  The device signer must reproduce the oracle's signatures, tags and
+oracle, on edwards25519 and on FourQ.  The device signer must reproduce the oracle's signatures, tags and
 ds byte for byte; the batch verifier's accept bits must equal the oracle's
 AVer per job and its invalid (job, t) pairs the oracle's Distill on every
 rejected job, for every kernel variant, with and without graph replay.
@@ -81,11 +81,11 @@ def test_gpu_signer_equals_oracle(P, gpu, inst):
 
 
 def variants_of(P, inst):
-    pre = "aes" if inst == 1 else "sha"
+    pre = "aes" if inst & 3 == 1 else "sha"
     return [v for v in range(P.poslo_batch_variant_count()) if P.poslo_batch_variant_name(v).startswith(pre)]
 
 
-@pytest.mark.parametrize("inst", [1, 0])
+@pytest.mark.parametrize("inst", [1, 0, 1 | 8, 0 | 8])
 def test_verify_batch_equals_oracle(P, gpu, inst):
     torch, ctx = gpu
     jobs, data, off, sigs, want_acc, want_inv, want_all, plan = corrupted_case(inst)
@@ -137,7 +137,7 @@ def test_verify_batch_wide_keys_equal_oracle(P, gpu, inst):
         ctx.close()
 
 
-@pytest.mark.parametrize("inst", [1, 0])
+@pytest.mark.parametrize("inst", [1, 0, 1 | 8])
 def test_graph_replays_and_honest_jobs(P, gpu, inst):
     """Replays of one captured graph, with unrelated eager work and
     synchronizations between them, give the eager result every time; the

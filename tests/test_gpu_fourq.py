@@ -6,8 +6,9 @@ the key and of FourQ's generator built by the device, e folded mod N, the
 streaming audit on FourQ; the tag
 checks (s >= N, R not a FourQ point); Distill and SeBVer V/U/I on FourQ
 (invalid sets, invalid signatures, valid and umbrella tags); the device
-signer on FourQ; and the entry points that take edwards25519 only (POSLO-C
-on FourQ is in test_gpu_posloc.py).  Keys, signatures, ds and tags come from the oracle's
+signer on FourQ; and the refusal of POSLO++ on FourQ (POSLO-C, the
+multi-signer path and the serving loop on FourQ are in test_gpu_posloc.py,
+test_gpu_batch.py and test_gpu_server.py).  Keys, signatures, ds and tags come from the oracle's
 FourQ signer."""
 
 import functools
@@ -248,17 +249,20 @@ def test_fourq_device_signer_equals_oracle(P, O, gpu, inst):
         assert ds[k] == O.ds_encode(signer.ds), f"job {k}"
 
 
-def test_fourq_refused_where_not_built(P, gpu):
+def test_fourq_refuses_poslopp(P, gpu):
+    """POSLO++ (H = Add_q) is not defined on FourQ: every entry point that
+    takes the instantiation word refuses 2 | GROUP_FOURQ."""
     torch, ctx = gpu
     inst = 1 | FQ
     prm, arr, msgs, pk, sigs, ds, tag = signed(inst, 777, 48, 4, 6, 0x61, 4)
-    params = P.make_params(inst, 4, 6)
     d = torch.from_numpy(arr.copy()).cuda()
-    dsig = torch.from_numpy(sigs.reshape(-1).copy()).cuda()
-    calls = {
-        "server": lambda: P.Server(0, params),
-    }
-    for name, call in calls.items():
+    bad = P.make_params(2 | FQ, 4, 6)
+    assert P.lib().poslo_inst_valid(2 | FQ) == 0
+    for name, call in {
+        "aver": lambda: P.poslo_aver(ctx, bad, pk, P.make_msgs(d), ds, tag),
+        "ekeys": lambda: P.poslo_ekeys(ctx, bad, P.make_msgs(d), ds),
+        "server": lambda: P.Server(0, bad),
+    }.items():
         with pytest.raises(P.PosloError) as ei:
             call()
         assert ei.value.status == P.POSLO_E_INVAL, name

@@ -64,7 +64,7 @@ def make_requests(P, torch, jobs, data, off, sigs):
     return reqs
 
 
-@pytest.mark.parametrize("inst", [1, 0])
+@pytest.mark.parametrize("inst", [1, 0, 1 | 8])
 def test_server_alone_and_mixed_equal_oracle(P, gpu, inst):
     from oracle import oracle as O
     torch, ctx = gpu
@@ -94,7 +94,7 @@ def test_server_alone_and_mixed_equal_oracle(P, gpu, inst):
     for key in ids:
         acc_tags = [j["tag"] for k, j in enumerate(jobs) if j["key"] == key and exp[k][0]]
         tag, entries = srv.key_state(key)
-        assert tag == O.agg(acc_tags * 2)
+        assert tag == O.agg(acc_tags * 2, inst)
         assert entries == 2 * sum(j["n"] for k, j in enumerate(jobs) if j["key"] == key and exp[k][0])
     st = srv.stats()
     assert st.completed == st.submitted == 2 * len(jobs) and st.bytes_in_use == 0 and st.queued == 0

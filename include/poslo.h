@@ -85,7 +85,7 @@ enum {
  * if x0 != 0, else x1 mod 2).  Taken by the signer (poslo_kg, poslo_sig,
  * poslo_sig_batch, poslo_agg_inst), poslo_aver, poslo_aver_fixed, the
  * streaming audit, poslo_ekeys (e_t mod N), poslo_distill and poslo_sebver
- * (the individual checks with FourQ's 8-bit comb tables of Y and G),
+ * (the individual checks with Y's 8-bit and G's wide FourQ tables),
  * POSLO-C (poslo_c_key_load with FourQ commitments, poslo_c_aver,
  * poslo_c_distill, poslo_c_sebver), the device signer
  * (poslo_gpu_keys_create, poslo_gpu_sign), the multi-signer batch

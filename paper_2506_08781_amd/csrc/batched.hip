@@ -835,7 +835,7 @@ int BatchRunner::launch_verify(const std::vector<uint32_t>& which, hipStream_t s
     V.tiles = (const BItem*)d_vtiles_;
     const bool fq = (prm_.inst & POSLO_GROUP_FOURQ) != 0;
     if (fq && !emitted_) return POSLO_E_INVAL;  // FourQ checks take the emitted digests
-    V.tg = fq ? ctx_gtable_fq(prof) : ctx_gtable_wide(prof);
+    V.tg = fq ? ctx_gtable_wide_fq(prof) : ctx_gtable_wide(prof);
     if (!V.tg) return POSLO_E_NOMEM;
     V.inst = prm_.inst;
     V.log2_n2 = prm_.log2_n2;

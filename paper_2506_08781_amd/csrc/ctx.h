@@ -93,6 +93,7 @@ struct poslo_ctx {
     uint32_t* d_gtable = nullptr;
     uint32_t* d_gtable_wide = nullptr;  // built on first use (ctx_gtable_wide)
     uint32_t* d_gtable_fq = nullptr;    // FourQ generator's comb table, built on first use
+    uint32_t* d_gtable_wide_fq = nullptr;  // its wide table (ctx_gtable_wide_fq)
     std::mutex wide_mu;
     size_t key_cap = 4096;
     std::list<poslo::KeyEntry> keys;  // front = most recent
@@ -132,6 +133,9 @@ int ctx_keys_bulk(poslo_ctx* c, const uint8_t* pks, size_t n, std::vector<const 
 // G's wide table for the per-entry checks (comb.h), built on first use;
 // nullptr if it cannot be allocated
 const uint32_t* ctx_gtable_wide(poslo_ctx* c);
+// FourQ generator's wide table for the per-entry checks, built on first use;
+// nullptr if it cannot be allocated
+const uint32_t* ctx_gtable_wide_fq(poslo_ctx* c);
 // Y's wide table for a resident key (ctx_key first), built on first use
 // and kept for the kMaxWideKeys most recently used keys (besides those
 // widened by poslo_ctx_keys_widen); nullptr on failure

@@ -204,12 +204,14 @@ __device__ __forceinline__ void lane_double_scalar_wide(ge& P, const uint32_t* t
                                                         const uint32_t e[8], const uint32_t s[8]) {
     ge_identity(P);
     uint32_t ce = 0, cs = 0;
+    // e's windows, then s's: only one scalar is live in each loop
+    for (int w = 0; w < kCombWindows; w++) {
+        gn q;
+        comb_lookup(q, ty, w, comb_digit(e, w, ce));
+        ge_madd(P, P, q);
+    }
     for (int w = 0; w < kWideWindows; w++) {
         gn q;
-        comb_lookup(q, ty, 2 * w, comb_digit(e, 2 * w, ce));
-        ge_madd(P, P, q);
-        comb_lookup(q, ty, 2 * w + 1, comb_digit(e, 2 * w + 1, ce));
-        ge_madd(P, P, q);
         comb_lookup<kWidePerWindow>(q, tg_wide, w, wide_digit(s, w, cs));
         ge_madd(P, P, q);
     }
@@ -222,15 +224,22 @@ __device__ __forceinline__ void lane_double_scalar_wide2(ge& P, const uint32_t* 
                                                          const uint32_t e[8], const uint32_t s[8]) {
     ge_identity(P);
     uint32_t ce = 0, cs = 0;
+    // e's windows, then s's: only one scalar is live in each loop
     CombRaw r;
     comb_fetch<kWidePerWindow>(r, ty_wide, 0, wide_digit(e, 0, ce));
     for (int w = 0; w < kWideWindows; w++) {
         gn q;
         comb_apply(q, r);
-        comb_fetch<kWidePerWindow>(r, tg_wide, w, wide_digit(s, w, cs));
+        if (w + 1 < kWideWindows)
+            comb_fetch<kWidePerWindow>(r, ty_wide, w + 1, wide_digit(e, w + 1, ce));
+        else
+            comb_fetch<kWidePerWindow>(r, tg_wide, 0, wide_digit(s, 0, cs));
         ge_madd(P, P, q);
+    }
+    for (int w = 0; w < kWideWindows; w++) {
+        gn q;
         comb_apply(q, r);
-        if (w + 1 < kWideWindows) comb_fetch<kWidePerWindow>(r, ty_wide, w + 1, wide_digit(e, w + 1, ce));
+        if (w + 1 < kWideWindows) comb_fetch<kWidePerWindow>(r, tg_wide, w + 1, wide_digit(s, w + 1, cs));
         ge_madd(P, P, q);
     }
 }

@@ -14,11 +14,12 @@
 
 namespace poslo {
 
-// t[w][|d| - 1] of a FourQ comb table with the sign of d applied; the
-// identity for d = 0
+// t[w][|d| - 1] of a FourQ comb table (PER entries per window) with the
+// sign of d applied; the identity for d = 0
+template <int PER = kCombPerWindow>
 PD void fq_comb_lookup(gnq& q, const uint32_t* table, int w, int d) {
     const uint32_t m = (uint32_t)(d < 0 ? -d : d);
-    fq_load_entry(q, table + ((uint64_t)w * kCombPerWindow + (m ? m - 1 : 0)) * kCombEntryWords, d < 0);
+    fq_load_entry(q, table + ((uint64_t)w * PER + (m ? m - 1 : 0)) * kCombEntryWords, d < 0);
     if (m == 0) {
         f2_one(q.yp);
         f2_one(q.ym);
@@ -26,16 +27,21 @@ PD void fq_comb_lookup(gnq& q, const uint32_t* table, int w, int d) {
     }
 }
 
-// e*Y + s*G by one lane: 32 + 32 lookups and mixed additions; e, s < N
-__device__ __forceinline__ void lane_double_scalar_fq(gq& P, const uint32_t* ty, const uint32_t* tg,
-                                                      const uint32_t e[8], const uint32_t s[8]) {
+// e*Y + s*G by one lane with G's wide FourQ table (16 windows of 32,768
+// points, comb.h layout): 32 + 16 lookups and mixed additions; e, s < N
+__device__ __forceinline__ void lane_double_scalar_fq_wide(gq& P, const uint32_t* ty, const uint32_t* tg_wide,
+                                                           const uint32_t e[8], const uint32_t s[8]) {
     gq_identity(P);
     uint32_t ce = 0, cs = 0;
+    // e's windows, then s's: only one scalar is live in each loop
     for (int w = 0; w < kCombWindows; w++) {
         gnq q;
         fq_comb_lookup(q, ty, w, comb_digit(e, w, ce));
         gq_madd(P, P, q);
-        fq_comb_lookup(q, tg, w, comb_digit(s, w, cs));
+    }
+    for (int w = 0; w < kWideWindows; w++) {
+        gnq q;
+        fq_comb_lookup<kWidePerWindow>(q, tg_wide, w, wide_digit(s, w, cs));
         gq_madd(P, P, q);
     }
 }
@@ -96,11 +102,12 @@ PD bool fq_encodes_zinv(const gq& P, const fp2& zi, const uint32_t want[8]) {
 }
 
 // the curve part of entry checks on FourQ, as verify_sig_batch (same stash
-// layout: X, Y, Z and the running product before the entry, 32 words).
+// layout: X, Y, Z and the running product before the entry, 32 words), with
+// Y's 8-bit table and G's wide one.
 // RAW: e points at the unreduced digest, reduced mod N here.
 template <bool RAW>
 __device__ __forceinline__ bool sig_point_fq(const uint8_t* sg, const uint32_t* e, bool go, const uint32_t* ty,
-                                             const uint32_t* tg, gq& P) {
+                                             const uint32_t* tg_wide, gq& P) {
     uint32_t ek[8], s[8];
     for (int w = 0; w < 8; w++) {
         s[w] = go ? gload_le32(sg + 4 * w) : 0u;
@@ -110,7 +117,7 @@ __device__ __forceinline__ bool sig_point_fq(const uint8_t* sg, const uint32_t* 
     const bool c = go && scN_is_canonical(s);
     if (!c)
         for (int w = 0; w < 8; w++) s[w] = ek[w] = 0;  // the identity: Z stays nonzero
-    lane_double_scalar_fq(P, ty, tg, ek, s);
+    lane_double_scalar_fq_wide(P, ty, tg_wide, ek, s);
     return c;
 }
 
@@ -138,7 +145,7 @@ __device__ __forceinline__ void unstash_f2(fp2& a, const uint32_t* o, uint32_t s
 
 template <bool RAW = false, class ENT>
 __device__ __forceinline__ uint32_t verify_sig_batch_fq(const ENT& ent, int ne, const uint32_t* ty,
-                                                        const uint32_t* tg, uint32_t* st, uint32_t stride) {
+                                                        const uint32_t* tg_wide, uint32_t* st, uint32_t stride) {
     if (ne <= 0) return 0;
     uint32_t okmask = 0;
     fp2 c, c_prev;
@@ -150,7 +157,7 @@ __device__ __forceinline__ uint32_t verify_sig_batch_fq(const ENT& ent, int ne, 
         const uint32_t* e;
         bool go;
         ent(k, sg, e, go);
-        if (sig_point_fq<RAW>(sg, e, go, ty, tg, P)) okmask |= 1u << k;
+        if (sig_point_fq<RAW>(sg, e, go, ty, tg_wide, P)) okmask |= 1u << k;
         if (k == 0) {
             c = P.Z;
         } else {

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 // checks entries i + 64 k of its tile (k < ceil(len / 64)) with one shared
 // inversion, the points waiting in the wave's slice of the stash.  ty_wide:
 // v.ty is Y's wide table (else its 8-bit one).  FQ: the group is FourQ
-// (8-bit tables of Y and G, scalars mod N).
+// (Y's 8-bit table and G's wide one, scalars mod N).
 template <bool FQ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_verify_tiles(
     VerifyArgs v, const uint32_t* ekeys, const uint8_t* xbad, uint32_t ty_wide) {
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 __global__ void k_zero_word(uint32_t* p) { p[0] = 0; }
 
 // list mode (SeBVer I): flags[i] = 1 when list item i is invalid.  FQ: the
-// group is FourQ (v.tg is G's 8-bit table, scalars mod N).
+// group is FourQ (v.tg is G's wide FourQ table, scalars mod N).
 template <bool FQ>
 __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
     __shared__ uint32_t lds[4 * 256];
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kTile) void k_verify_list(VerifyArgs v) {
         }
         if (ok) {
             gq P;
-            lane_double_scalar_fq(P, v.ty, v.tg, e, sc);
+            lane_double_scalar_fq_wide(P, v.ty, v.tg, e, sc);
             fp2 zi;
             f2_inv(zi, P.Z);
             for (int k = 0; k < 8; k++) r[k] = gload_le32(sg + 32 + 4 * k);
@@ -601,7 +601,7 @@ extern "C" int poslo_distill(poslo_ctx* c, const poslo_params* prm, const uint8_
         // edwards25519: G's wide table, and Y's wide table if the key has a
         // resident one, else built for large batches (once per key, about
         // 0.3 ms) and kept in a small LRU set.  FourQ: the 8-bit tables.
-        const uint32_t* gw = fq ? gtab : ctx_gtable_wide(c);
+        const uint32_t* gw = fq ? ctx_gtable_wide_fq(c) : ctx_gtable_wide(c);
         if (!gw) return fail(POSLO_E_NOMEM);
         const uint32_t* yw =
             fq ? nullptr : n >= kWideKeyMinEntries ? ctx_key_wide(c, pk) : ctx_key_wide_resident(c, pk);
@@ -1022,7 +1022,7 @@ int poslo::sebver_impl(poslo_ctx* c, const poslo_params* prm, const uint8_t pk[3
             if (ccd->invalid[k] < m->t0 || ccd->invalid[k] - m->t0 >= m->n) return POSLO_E_INVAL;
             pos[k] = ccd->invalid[k] - m->t0;
         }
-        const uint32_t* gw = fq ? gtab : ctx_gtable_wide(c);
+        const uint32_t* gw = fq ? ctx_gtable_wide_fq(c) : ctx_gtable_wide(c);
         if (!gw) return POSLO_E_NOMEM;
         void *dpos, *dsig, *dflags;
         if ((st = scratch(c, S_IDX, ni * 8, &dpos)) || (st = scratch(c, S_SIGS, ni * 80, &dsig)) ||

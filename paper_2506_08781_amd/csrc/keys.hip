@@ -15,6 +15,7 @@
 #include "comb.h"
 #include "ctx.h"
 #include "device_ec.h"
+#include "device_fq.h"
 #include "fourq.h"
 #include "ge25519.h"
 
@@ -151,6 +152,74 @@ __global__ __launch_bounds__(kWideBuildBlock) void k_wide_build(const uint32_t* 
     }
 }
 
+// The same for FourQ (fourq.h): entries of FourQ's comb layout, GF(p^2)
+// arithmetic, one GF(p^2) inversion per kWideBuildK entries
+__global__ __launch_bounds__(kWideBuildBlock) void k_wide_build_fq(const uint32_t* t8, uint32_t* wide) {
+    __shared__ uint32_t cs[kWideBuildK * 8 * kWideBuildBlock];
+    uint32_t* my = cs + threadIdx.x;
+    const uint32_t first = (blockIdx.x * kWideBuildBlock + threadIdx.x) * kWideBuildK;
+    const int w = (int)(first / kWidePerWindow);
+    fp2 c;
+#pragma unroll 1
+    for (int k = 0; k < kWideBuildK; k++) {
+        const uint32_t m = first % kWidePerWindow + k + 1;
+        int d0 = (int)(m & 255u), d1 = (int)(m >> 8);
+        if (d0 > 128) {
+            d0 -= 256;
+            d1 += 1;
+        }
+        gq P;
+        gq_identity(P);
+        gnq q;
+        fq_comb_lookup(q, t8, 2 * w, d0);
+        gq_madd(P, P, q);
+        fq_comb_lookup(q, t8, 2 * w + 1, d1);
+        gq_madd(P, P, q);
+        uint32_t* o = wide + (uint64_t)(first + k) * kCombEntryWords;
+        stash_f2(o, 1, P.X);
+        stash_f2(o + 8, 1, P.Y);
+        stash_f2(o + 16, 1, P.Z);
+        if (k == 0)
+            c = P.Z;
+        else
+            f2_mul(c, c, P.Z);
+        stash_f2(my + 8 * k * kWideBuildBlock, kWideBuildBlock, c);
+    }
+    fp2 inv;
+    f2_inv(inv, c);
+#pragma unroll 1
+    for (int k = kWideBuildK - 1; k >= 0; k--) {
+        uint32_t* o = wide + (uint64_t)(first + k) * kCombEntryWords;
+        fp2 X, Y, Z, zi;
+        unstash_f2(X, o, 1);
+        unstash_f2(Y, o + 8, 1);
+        unstash_f2(Z, o + 16, 1);
+        if (k > 0) {
+            fp2 ck;
+            unstash_f2(ck, my + 8 * (k - 1) * kWideBuildBlock, kWideBuildBlock);
+            f2_mul(zi, inv, ck);
+            f2_mul(inv, inv, Z);
+        } else {
+            zi = inv;
+        }
+        uint32_t e[kCombEntryWords];
+        fq_comb_entry_zinv(e, X, Y, zi);
+        for (int t = 0; t < kCombEntryWords; t++) o[t] = e[t];
+    }
+}
+
+static uint32_t* build_wide_fq(const uint32_t* t8) {
+    uint32_t* d = nullptr;
+    if (hipMalloc((void**)&d, kWideWords * 4) != hipSuccess) return nullptr;
+    const uint32_t blocks = (uint32_t)(kWideWindows * kWidePerWindow / (kWideBuildK * kWideBuildBlock));
+    hipLaunchKernelGGL(k_wide_build_fq, dim3(blocks), dim3(kWideBuildBlock), 0, 0, t8, d);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+        hipFree(d);
+        return nullptr;
+    }
+    return d;
+}
+
 static uint32_t* build_wide(const uint32_t* t8) {
     uint32_t* d = nullptr;
     if (hipMalloc((void**)&d, kWideWords * 4) != hipSuccess) return nullptr;
@@ -167,6 +236,14 @@ const uint32_t* ctx_gtable_wide(poslo_ctx* c) {
     std::lock_guard<std::mutex> lk(c->wide_mu);
     if (!c->d_gtable_wide) c->d_gtable_wide = build_wide(c->d_gtable);
     return c->d_gtable_wide;
+}
+
+const uint32_t* ctx_gtable_wide_fq(poslo_ctx* c) {
+    const uint32_t* t8 = ctx_gtable_fq(c);
+    if (!t8) return nullptr;
+    std::lock_guard<std::mutex> lk(c->wide_mu);
+    if (!c->d_gtable_wide_fq) c->d_gtable_wide_fq = build_wide_fq(t8);
+    return c->d_gtable_wide_fq;
 }
 
 const uint32_t* ctx_key_wide(poslo_ctx* c, const uint8_t pk[32]) {

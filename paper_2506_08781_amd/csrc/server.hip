@@ -38,7 +38,7 @@ namespace poslo {
 // on FourQ s is reduced mod N and the coordinates are GF(p^2) words
 constexpr int kStateWords = 48;
 
-__global__ void k_key_state(const BJob* jobs, const uint32_t* accept, const uint32_t* rdec,
+__global__ __launch_bounds__(64) void k_key_state(const BJob* jobs, const uint32_t* accept, const uint32_t* rdec,
                             const uint32_t* slot_of_job, uint32_t njobs, uint32_t* state, uint32_t fq) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     // one lane in job order: a key's requests of one group are folded in turn
@@ -471,7 +471,7 @@ extern "C" int poslo_server_create(int device, const poslo_server_cfg* cfg, posl
     if (st) return st;
     ctx->key_cap = SIZE_MAX / 4;  // registered keys are never evicted
     // the per-entry checks' generator table, built now rather than by the worker
-    if (cfg->distill && !ctx_gtable_wide(ctx)) {
+    if (cfg->distill && !((cfg->params.inst & POSLO_GROUP_FOURQ) ? ctx_gtable_wide_fq(ctx) : ctx_gtable_wide(ctx))) {
         poslo_ctx_destroy(ctx);
         return POSLO_E_NOMEM;
     }

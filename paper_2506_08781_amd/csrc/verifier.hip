@@ -508,6 +508,7 @@ extern "C" void poslo_ctx_destroy(poslo_ctx* c) {
     if (c->h_result) hipHostFree(c->h_result);
     if (c->d_gtable) hipFree(c->d_gtable);
     if (c->d_gtable_wide) hipFree(c->d_gtable_wide);
+    if (c->d_gtable_wide_fq) hipFree(c->d_gtable_wide_fq);
     if (c->d_gtable_fq) hipFree(c->d_gtable_fq);
     batch_release(c);
     c->key_index.clear();

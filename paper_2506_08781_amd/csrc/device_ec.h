@@ -275,8 +275,9 @@ __device__ __forceinline__ void lds_store_fe(uint32_t* p, const fe& a) {
 constexpr int kQuadBlock = 256;               // threads of block_double_scalar_is
 constexpr int kQuadLdsWords = 64 * 4 * 8;     // its LDS: 64 points of 4 coordinates
 
-// e*Y + s*G == (rx, ry) (affine) by a whole 256-thread block, for a single
-// check where latency decides.  The quad of lanes 4k..4k+3 owns point k of
+// e*Y + s*G by a whole 256-thread block, for a single sum where latency
+// decides; the sum is left in LDS slot 0 (X, Y, Z, T at lds + 0, 8, 16, 24
+// after the closing barrier).  The quad of lanes 4k..4k+3 owns point k of
 // 64 (k < 32: window k of e on Y's comb table; k >= 32: window k - 32 of s on
 // G's), lane c holding coordinate c in the order X, Y, Z, T.  A six-level
 // tree of complete additions follows, each addition split over its quad:
@@ -288,11 +289,9 @@ constexpr int kQuadLdsWords = 64 * 4 * 8;     // its LDS: 64 points of 4 coordin
 // 2 * 121665 with its sign moved into F and G, D by 2 * 121666.  E, F, G and
 // H then all carry the factor 121666, so the result is the same point with
 // every coordinate scaled by 121666^2.  e, s < 2^253.
-// lds holds kQuadLdsWords words; every thread of the block must call it;
-// the verdict is valid in thread 0.
-__device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
-                                                       const uint32_t e[8], const uint32_t s[8], const fe& rx,
-                                                       const fe& ry) {
+// lds holds kQuadLdsWords words; every thread of the block must call it.
+__device__ __forceinline__ void block_double_scalar(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
+                                                    const uint32_t e[8], const uint32_t s[8]) {
     const int k = (int)(threadIdx.x >> 2), c = (int)(threadIdx.x & 3);
     const uint32_t* sc = k < 32 ? e : s;
     const int w = k & 31;
@@ -368,10 +367,18 @@ __device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint
         }
     }
     __syncthreads();
+}
+
+// e*Y + s*G == R for R = (rx, ry) affine, compared in projective form
+__device__ __forceinline__ bool block_double_scalar_is(uint32_t* lds, const uint32_t* ty, const uint32_t* tg,
+                                                       const uint32_t e[8], const uint32_t s[8], const fe& rx,
+                                                       const fe& ry) {
+    block_double_scalar(lds, ty, tg, e, s);
+    const int k = (int)(threadIdx.x >> 2), c = (int)(threadIdx.x & 3);
     // the sum sits in slot 0: X == x_R Z on lane 0 and Y == y_R Z on lane 1
     bool ok = true;
     if (k == 0 && c < 2) {
-        fe Z, V;
+        fe Z, V, m;
         lds_load_fe(Z, lds + 2 * 8);
         lds_load_fe(V, lds + c * 8);
         fe_mul(m, c == 0 ? rx : ry, Z);

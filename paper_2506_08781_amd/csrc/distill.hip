@@ -299,6 +299,34 @@ __device__ __forceinline__ void fold_reduce(uint32_t r[8], const uint32_t t[9]) 
         sc_reduce288(r, t);
 }
 
+// the edwards25519 outputs of a fold given the sum P = e*Y + s*G (any
+// projective scaling): the tags (mode 0, CCD^v) or the umbrella's verdict
+__device__ __forceinline__ void fold_point(const FoldArgs& f, uint32_t l, bool valid_block, const uint32_t e[8],
+                                           const uint32_t s[8], const ge& P) {
+    if (valid_block) {
+        for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
+        ge_encode(f.valid_tag + 32, P);
+    } else if (f.mode == 0) {
+        uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
+        for (int k = 0; k < 8; k++) {
+            store_le32(tag + 4 * k, s[k]);
+            f.umb_es[l * 16 + k] = e[k];
+            f.umb_es[l * 16 + 8 + k] = s[k];
+        }
+        ge_encode(tag + 32, P);
+    } else {
+        const uint32_t* c = f.chk + l * 25;
+        fe rx, ry, t0, t1;
+        for (int k = 0; k < 8; k++) {
+            rx.v[k] = c[8 + k];
+            ry.v[k] = c[16 + k];
+        }
+        fe_mul(t0, rx, P.Z);
+        fe_mul(t1, ry, P.Z);
+        f.umb_bits[l] = (c[24] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
+    }
+}
+
 template <bool FQ>
 __device__ __forceinline__ void fold_curve(const FoldArgs& f, uint32_t l, bool valid_block, const uint32_t e[8],
                                            const uint32_t s[8]) {
@@ -334,28 +362,7 @@ __device__ __forceinline__ void fold_curve(const FoldArgs& f, uint32_t l, bool v
         ge P;
         wave_double_scalar(P, f.ty, f.tg, e, s);
         if (threadIdx.x != 0) return;
-        if (valid_block) {
-            for (int k = 0; k < 8; k++) store_le32(f.valid_tag + 4 * k, s[k]);
-            ge_encode(f.valid_tag + 32, P);
-        } else if (f.mode == 0) {
-            uint8_t* tag = f.umb_tags + (uint64_t)l * 64;
-            for (int k = 0; k < 8; k++) {
-                store_le32(tag + 4 * k, s[k]);
-                f.umb_es[l * 16 + k] = e[k];
-                f.umb_es[l * 16 + 8 + k] = s[k];
-            }
-            ge_encode(tag + 32, P);
-        } else {
-            const uint32_t* c = f.chk + l * 25;
-            fe rx, ry, t0, t1;
-            for (int k = 0; k < 8; k++) {
-                rx.v[k] = c[8 + k];
-                ry.v[k] = c[16 + k];
-            }
-            fe_mul(t0, rx, P.Z);
-            fe_mul(t1, ry, P.Z);
-            f.umb_bits[l] = (c[24] && fe_equal(t0, P.X) && fe_equal(t1, P.Y)) ? 1u : 0u;
-        }
+        fold_point(f, l, valid_block, e, s, P);
     }
 }
 
@@ -391,13 +398,28 @@ __global__ __launch_bounds__(kTile) void k_umbrella_fold(FoldArgs f) {
         }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        uint32_t e[8], s[8];
-        for (int k = 0; k < 8; k++) {
-            e[k] = sh[k];
-            s[k] = sh[8 + k];
+    uint32_t e[8], s[8];
+    for (int k = 0; k < 8; k++) {
+        e[k] = sh[k];
+        s[k] = sh[8 + k];
+    }
+    if constexpr (FQ) {
+        if (threadIdx.x < 64) fold_curve<FQ>(f, l, valid_block, e, s);
+    } else {
+        // the quad-split block sum (device_ec.h), every thread of the block
+        static_assert(kTile == kQuadBlock, "the block sum takes the whole block");
+        __shared__ uint32_t pts[kQuadLdsWords];
+        uint32_t sr[8];
+        sc_reduce256(sr, s);  // mode 1 may carry an s >= q (its check then fails on the host flag)
+        block_double_scalar(pts, f.ty, f.tg, e, sr);
+        if (threadIdx.x == 0) {
+            ge P;
+            lds_load_fe(P.X, pts);
+            lds_load_fe(P.Y, pts + 8);
+            lds_load_fe(P.Z, pts + 16);
+            lds_load_fe(P.T, pts + 24);
+            fold_point(f, l, valid_block, e, s, P);
         }
-        fold_curve<FQ>(f, l, valid_block, e, s);
     }
 }
 
